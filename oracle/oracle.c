@@ -1,0 +1,473 @@
+/*
+ * Plain CPU oracle for tropical (min,+)/(max,+) linear algebra and for
+ * all-pairs shortest paths by repeated min-plus squaring.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * statement of what the GPU library must compute.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no header, constant, helper or kernel with the HIP library: its
+ * sentinels and domain bounds are declared here, independently.
+ *
+ * Arithmetic policy (the readings of the paper that this file fixes):
+ *  - Semirings (Sec. I, eqs. (1)-(4)): max-plus  x(+)y = max(x,y), x(.)y = x+y;
+ *    min-plus  x(+)y = min(x,y), x(.)y = x+y.
+ *  - int32: exact integer arithmetic carried in int64.  The absent value is a
+ *    sentinel that absorbs under (.): +INF = 0x7FFFFFFF for min-plus,
+ *    -INF = -0x7FFFFFFF for max-plus.  Finite operands of (.) must satisfy
+ *    |x| <= 2^29-1; anything else is reported as a domain error instead of
+ *    being computed.
+ *  - float32: every (.) is computed in binary64 and the (+)-reduction is done
+ *    on binary64 values; the result is rounded to binary32 once per output.
+ *    Because rounding is monotone, min_k RN32(a+b) = RN32(min_k (a+b)), and
+ *    because 53 >= 2*24+2, rounding a binary64 sum of two binary32 values to
+ *    binary32 equals rounding the exact sum (double rounding is innocuous
+ *    for one addition).  So this is the exact definition "one IEEE binary32
+ *    add per term, then min/max", evaluated without binary32 arithmetic.
+ *  - A matrix that is an input to a later step (the distance matrix of the
+ *    squaring loop) is held in binary32 between steps, as the method stores it.
+ *
+ * Layouts are row-major with leading dimensions; vectors take strides.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- this file's own constants (independent of the GPU library) ---- */
+#define OR_INF32 ((int32_t)0x7FFFFFFF)       /* min-plus absent value */
+#define OR_NINF32 ((int32_t)(-0x7FFFFFFF))   /* max-plus absent value */
+#define OR_FINITE_MAX ((1 << 29) - 1)        /* domain bound on (.) operands */
+#define OR_INF64 INT64_MAX
+#define OR_NINF64 INT64_MIN
+
+#define OR_OK 0
+#define OR_EARG 1
+#define OR_EDOMAIN 2
+#define OR_WNEGCYCLE 3
+
+#define OR_MIN_PLUS 0
+#define OR_MAX_PLUS 1
+
+/* ---------------- scalar semiring, int32 (Sec. I eqs. (1)-(4)) -------- */
+
+/* A (.) operand is legal when it is the semiring's absent value or a finite
+ * value inside the domain bound.  The other infinity is illegal. */
+static int i32_operand_ok(int sr, int32_t x) {
+    if (sr == OR_MIN_PLUS && x == OR_INF32) return 1;
+    if (sr == OR_MAX_PLUS && x == OR_NINF32) return 1;
+    return x >= -OR_FINITE_MAX && x <= OR_FINITE_MAX;
+}
+
+/* Lift an int32 element to the int64 carrier (sentinel -> int64 extreme). */
+static int64_t i32_lift(int sr, int32_t x) {
+    if (sr == OR_MIN_PLUS && x == OR_INF32) return OR_INF64;
+    if (sr == OR_MAX_PLUS && x == OR_NINF32) return OR_NINF64;
+    return (int64_t)x;
+}
+
+/* x (.) y: the absent value absorbs; otherwise the exact sum. */
+static int64_t i64_otimes(int sr, int64_t x, int64_t y) {
+    if (sr == OR_MIN_PLUS) {
+        if (x == OR_INF64 || y == OR_INF64) return OR_INF64;
+    } else {
+        if (x == OR_NINF64 || y == OR_NINF64) return OR_NINF64;
+    }
+    return x + y;
+}
+
+/* x (+) y: min for min-plus, max for max-plus. */
+static int64_t i64_oplus(int sr, int64_t x, int64_t y) {
+    if (sr == OR_MIN_PLUS) return x < y ? x : y;
+    return x > y ? x : y;
+}
+
+/* Back to int32; a finite value that does not fit is a domain error. */
+static int i64_store(int sr, int64_t v, int32_t *out) {
+    if (sr == OR_MIN_PLUS && v == OR_INF64) { *out = OR_INF32; return OR_OK; }
+    if (sr == OR_MAX_PLUS && v == OR_NINF64) { *out = OR_NINF32; return OR_OK; }
+    if (v < INT32_MIN || v > INT32_MAX) return OR_EDOMAIN;
+    *out = (int32_t)v;
+    return OR_OK;
+}
+
+/* (+)-identity of the semiring in the int64 carrier. */
+static int64_t i64_zero(int sr) { return sr == OR_MIN_PLUS ? OR_INF64 : OR_NINF64; }
+
+/* ---------------- scalar semiring, float32 via binary64 --------------- */
+
+static int f32_operand_ok(int sr, float x) {
+    if (isnan(x)) return 0;
+    if (sr == OR_MIN_PLUS && isinf(x) && x < 0) return 0;
+    if (sr == OR_MAX_PLUS && isinf(x) && x > 0) return 0;
+    return 1;
+}
+
+static double f64_oplus(int sr, double x, double y) {
+    if (sr == OR_MIN_PLUS) return y < x ? y : x;
+    return y > x ? y : x;
+}
+
+static double f64_zero(int sr) { return sr == OR_MIN_PLUS ? INFINITY : -INFINITY; }
+
+static int sr_ok(int sr) { return sr == OR_MIN_PLUS || sr == OR_MAX_PLUS; }
+
+/* ---------------- domain scans ---------------- */
+
+static int scan_i32(int sr, long rows, long cols, const int32_t *X, long ld) {
+    for (long i = 0; i < rows; ++i)
+        for (long j = 0; j < cols; ++j)
+            if (!i32_operand_ok(sr, X[i * ld + j])) return 0;
+    return 1;
+}
+
+static int scan_f32(int sr, long rows, long cols, const float *X, long ld) {
+    for (long i = 0; i < rows; ++i)
+        for (long j = 0; j < cols; ++j)
+            if (!f32_operand_ok(sr, X[i * ld + j])) return 0;
+    return 1;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_num_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* ============ Level 3: C <- C (+) A (.) B  (Sec. IV, min-plus product) ===
+ * The matrix-product listing of Sec. IV replaces + by min and x by + :
+ *     z(i,j) <- min( z(i,j), min_k ( x(i,k) + y(k,j) ) ).
+ * Max-plus is the same with max.  A is m x k, B is k x n, C is m x n.
+ * C is an accumulator: it is only (+)-combined, never an operand of (.),
+ * so any int32 value is accepted there.  Rows are independent, so they are
+ * distributed over threads; the order of the k-reduction is the definition's
+ * order and cannot change a min/max anyway.
+ */
+int or_gemm_i32(int sr, long m, long n, long k, const int32_t *A, long lda,
+                const int32_t *B, long ldb, int32_t *C, long ldc) {
+    if (!sr_ok(sr) || m < 0 || n < 0 || k < 0) return OR_EARG;
+    if (!scan_i32(sr, m, k, A, lda) || !scan_i32(sr, k, n, B, ldb)) return OR_EDOMAIN;
+    int status = OR_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < m; ++i) {
+        for (long j = 0; j < n; ++j) {
+            int64_t acc = i64_zero(sr);
+            for (long p = 0; p < k; ++p) {
+                int64_t term = i64_otimes(sr, i32_lift(sr, A[i * lda + p]),
+                                          i32_lift(sr, B[p * ldb + j]));
+                acc = i64_oplus(sr, acc, term);
+            }
+            int64_t c = i32_lift(sr, C[i * ldc + j]);
+            int32_t out;
+            if (i64_store(sr, i64_oplus(sr, c, acc), &out) != OR_OK) {
+#pragma omp atomic write
+                status = OR_EDOMAIN;
+                continue;
+            }
+            C[i * ldc + j] = out;
+        }
+    }
+    return status;
+}
+
+int or_gemm_f32(int sr, long m, long n, long k, const float *A, long lda,
+                const float *B, long ldb, float *C, long ldc) {
+    if (!sr_ok(sr) || m < 0 || n < 0 || k < 0) return OR_EARG;
+    if (!scan_f32(sr, m, k, A, lda) || !scan_f32(sr, k, n, B, ldb)) return OR_EDOMAIN;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < m; ++i) {
+        for (long j = 0; j < n; ++j) {
+            double acc = f64_zero(sr);
+            for (long p = 0; p < k; ++p) {
+                double term = (double)A[i * lda + p] + (double)B[p * ldb + j];
+                acc = f64_oplus(sr, acc, term);
+            }
+            acc = f64_oplus(sr, (double)C[i * ldc + j], acc);
+            C[i * ldc + j] = (float)acc;
+        }
+    }
+    return OR_OK;
+}
+
+/* ============ Level 2: y <- y (+) A (.) x ============ */
+int or_gemv_i32(int sr, long m, long n, const int32_t *A, long lda,
+                const int32_t *x, long incx, int32_t *y, long incy) {
+    if (!sr_ok(sr) || m < 0 || n < 0 || incx < 1 || incy < 1) return OR_EARG;
+    for (long j = 0; j < n; ++j)
+        if (!i32_operand_ok(sr, x[j * incx])) return OR_EDOMAIN;
+    if (!scan_i32(sr, m, n, A, lda)) return OR_EDOMAIN;
+    for (long i = 0; i < m; ++i) {
+        int64_t acc = i64_zero(sr);
+        for (long j = 0; j < n; ++j)
+            acc = i64_oplus(sr, acc, i64_otimes(sr, i32_lift(sr, A[i * lda + j]),
+                                                 i32_lift(sr, x[j * incx])));
+        int32_t out;
+        if (i64_store(sr, i64_oplus(sr, i32_lift(sr, y[i * incy]), acc), &out) != OR_OK)
+            return OR_EDOMAIN;
+        y[i * incy] = out;
+    }
+    return OR_OK;
+}
+
+int or_gemv_f32(int sr, long m, long n, const float *A, long lda,
+                const float *x, long incx, float *y, long incy) {
+    if (!sr_ok(sr) || m < 0 || n < 0 || incx < 1 || incy < 1) return OR_EARG;
+    if (!scan_f32(sr, m, n, A, lda)) return OR_EDOMAIN;
+    for (long j = 0; j < n; ++j)
+        if (!f32_operand_ok(sr, x[j * incx])) return OR_EDOMAIN;
+    for (long i = 0; i < m; ++i) {
+        double acc = f64_zero(sr);
+        for (long j = 0; j < n; ++j)
+            acc = f64_oplus(sr, acc, (double)A[i * lda + j] + (double)x[j * incx]);
+        y[i * incy] = (float)f64_oplus(sr, (double)y[i * incy], acc);
+    }
+    return OR_OK;
+}
+
+/* ============ Level 1 ============
+ * z = x (+) y, z = x (.) y, dot = (+)_i x_i (.) y_i (empty: the (+)-identity),
+ * y <- y (+) alpha (.) x.
+ */
+int or_vadd_i32(int sr, long n, const int32_t *x, long incx, const int32_t *y,
+                long incy, int32_t *z, long incz) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1 || incz < 1) return OR_EARG;
+    for (long i = 0; i < n; ++i) {
+        int64_t v = i64_oplus(sr, i32_lift(sr, x[i * incx]), i32_lift(sr, y[i * incy]));
+        if (i64_store(sr, v, &z[i * incz]) != OR_OK) return OR_EDOMAIN;
+    }
+    return OR_OK;
+}
+
+int or_vadd_f32(int sr, long n, const float *x, long incx, const float *y,
+                long incy, float *z, long incz) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1 || incz < 1) return OR_EARG;
+    for (long i = 0; i < n; ++i)
+        z[i * incz] = (float)f64_oplus(sr, (double)x[i * incx], (double)y[i * incy]);
+    return OR_OK;
+}
+
+int or_vmul_i32(int sr, long n, const int32_t *x, long incx, const int32_t *y,
+                long incy, int32_t *z, long incz) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1 || incz < 1) return OR_EARG;
+    for (long i = 0; i < n; ++i) {
+        if (!i32_operand_ok(sr, x[i * incx]) || !i32_operand_ok(sr, y[i * incy]))
+            return OR_EDOMAIN;
+        int64_t v = i64_otimes(sr, i32_lift(sr, x[i * incx]), i32_lift(sr, y[i * incy]));
+        if (i64_store(sr, v, &z[i * incz]) != OR_OK) return OR_EDOMAIN;
+    }
+    return OR_OK;
+}
+
+int or_vmul_f32(int sr, long n, const float *x, long incx, const float *y,
+                long incy, float *z, long incz) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1 || incz < 1) return OR_EARG;
+    for (long i = 0; i < n; ++i) {
+        if (!f32_operand_ok(sr, x[i * incx]) || !f32_operand_ok(sr, y[i * incy]))
+            return OR_EDOMAIN;
+        z[i * incz] = (float)((double)x[i * incx] + (double)y[i * incy]);
+    }
+    return OR_OK;
+}
+
+int or_dot_i32(int sr, long n, const int32_t *x, long incx, const int32_t *y,
+               long incy, int32_t *result) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1) return OR_EARG;
+    int64_t acc = i64_zero(sr);
+    for (long i = 0; i < n; ++i) {
+        if (!i32_operand_ok(sr, x[i * incx]) || !i32_operand_ok(sr, y[i * incy]))
+            return OR_EDOMAIN;
+        acc = i64_oplus(sr, acc, i64_otimes(sr, i32_lift(sr, x[i * incx]),
+                                            i32_lift(sr, y[i * incy])));
+    }
+    return i64_store(sr, acc, result);
+}
+
+int or_dot_f32(int sr, long n, const float *x, long incx, const float *y,
+               long incy, float *result) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1) return OR_EARG;
+    double acc = f64_zero(sr);
+    for (long i = 0; i < n; ++i) {
+        if (!f32_operand_ok(sr, x[i * incx]) || !f32_operand_ok(sr, y[i * incy]))
+            return OR_EDOMAIN;
+        acc = f64_oplus(sr, acc, (double)x[i * incx] + (double)y[i * incy]);
+    }
+    *result = (float)acc;
+    return OR_OK;
+}
+
+int or_axpy_i32(int sr, long n, int32_t alpha, const int32_t *x, long incx,
+                int32_t *y, long incy) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1) return OR_EARG;
+    if (!i32_operand_ok(sr, alpha)) return OR_EDOMAIN;
+    for (long i = 0; i < n; ++i) {
+        if (!i32_operand_ok(sr, x[i * incx])) return OR_EDOMAIN;
+        int64_t t = i64_otimes(sr, i32_lift(sr, alpha), i32_lift(sr, x[i * incx]));
+        int64_t v = i64_oplus(sr, i32_lift(sr, y[i * incy]), t);
+        if (i64_store(sr, v, &y[i * incy]) != OR_OK) return OR_EDOMAIN;
+    }
+    return OR_OK;
+}
+
+int or_axpy_f32(int sr, long n, float alpha, const float *x, long incx,
+                float *y, long incy) {
+    if (!sr_ok(sr) || n < 0 || incx < 1 || incy < 1) return OR_EARG;
+    if (!f32_operand_ok(sr, alpha)) return OR_EDOMAIN;
+    for (long i = 0; i < n; ++i) {
+        if (!f32_operand_ok(sr, x[i * incx])) return OR_EDOMAIN;
+        double t = (double)alpha + (double)x[i * incx];
+        y[i * incy] = (float)f64_oplus(sr, (double)y[i * incy], t);
+    }
+    return OR_OK;
+}
+
+/* ============ APSP by repeated min-plus squaring (Sec. III) ============
+ * D_0 = I (+) W, where I is the tropical identity (0 on the diagonal, +INF
+ * elsewhere); then D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1}, each step reading
+ * only the previous step's matrix.  After T = ceil(log2(n-1)) steps (0 when
+ * n <= 2) every path of up to n-1 edges has been considered.  With early
+ * exit, stop after the first step whose result equals its input bit for bit
+ * (that step is counted); every later step would be the identity map.
+ */
+int or_apsp_steps(long n) {
+    if (n <= 2) return 0;
+    int t = 0;
+    long reach = 1;
+    while (reach < n - 1) { reach *= 2; ++t; }
+    return t;
+}
+
+int or_apsp_i32(long n, const int32_t *W, long ldw, int32_t *D, long ldd,
+                int early_exit, int check_neg_cycle, int *steps_out) {
+    if (n < 0 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (steps_out) *steps_out = 0;
+    if (n == 0) return OR_OK;
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * n * n);
+    int32_t *nxt = (int32_t *)malloc(sizeof(int32_t) * n * n);
+    if (!cur || !nxt) { free(cur); free(nxt); return OR_EARG; }
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) cur[i * n + j] = W[i * ldw + j];
+    for (long i = 0; i < n; ++i)               /* I (+) W */
+        if (cur[i * n + i] > 0) cur[i * n + i] = 0;
+    int T = or_apsp_steps(n), steps = 0, status = OR_OK;
+    for (int t = 0; t < T; ++t) {
+        memcpy(nxt, cur, sizeof(int32_t) * n * n);            /* C = D */
+        status = or_gemm_i32(OR_MIN_PLUS, n, n, n, cur, n, cur, n, nxt, n);
+        if (status != OR_OK) break;
+        ++steps;
+        int same = memcmp(nxt, cur, sizeof(int32_t) * n * n) == 0;
+        int32_t *tmp = cur; cur = nxt; nxt = tmp;
+        if (early_exit && same) break;
+    }
+    if (status == OR_OK) {
+        for (long i = 0; i < n; ++i)
+            for (long j = 0; j < n; ++j) D[i * ldd + j] = cur[i * n + j];
+        if (check_neg_cycle)
+            for (long i = 0; i < n; ++i)
+                if (cur[i * n + i] < 0) { status = OR_WNEGCYCLE; break; }
+    }
+    if (steps_out) *steps_out = steps;
+    free(cur); free(nxt);
+    return status;
+}
+
+int or_apsp_f32(long n, const float *W, long ldw, float *D, long ldd,
+                int early_exit, int check_neg_cycle, int *steps_out) {
+    if (n < 0 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (steps_out) *steps_out = 0;
+    if (n == 0) return OR_OK;
+    float *cur = (float *)malloc(sizeof(float) * n * n);
+    float *nxt = (float *)malloc(sizeof(float) * n * n);
+    if (!cur || !nxt) { free(cur); free(nxt); return OR_EARG; }
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) cur[i * n + j] = W[i * ldw + j];
+    for (long i = 0; i < n; ++i)
+        if (cur[i * n + i] > 0.0f) cur[i * n + i] = 0.0f;
+    int T = or_apsp_steps(n), steps = 0, status = OR_OK;
+    for (int t = 0; t < T; ++t) {
+        memcpy(nxt, cur, sizeof(float) * n * n);
+        status = or_gemm_f32(OR_MIN_PLUS, n, n, n, cur, n, cur, n, nxt, n);
+        if (status != OR_OK) break;
+        ++steps;
+        int same = memcmp(nxt, cur, sizeof(float) * n * n) == 0;
+        float *tmp = cur; cur = nxt; nxt = tmp;
+        if (early_exit && same) break;
+    }
+    if (status == OR_OK) {
+        for (long i = 0; i < n; ++i)
+            for (long j = 0; j < n; ++j) D[i * ldd + j] = cur[i * n + j];
+        if (check_neg_cycle)
+            for (long i = 0; i < n; ++i)
+                if (cur[i * n + i] < 0.0f) { status = OR_WNEGCYCLE; break; }
+    }
+    if (steps_out) *steps_out = steps;
+    free(cur); free(nxt);
+    return status;
+}
+
+/* ============ Sequential Floyd-Warshall (Sec. IV, Algorithm 2) ==========
+ * The paper's CPU method: for every pivot z, relax every pair (x,y) through
+ * z.  The paper marks absent edges with 0 and skips x == y; here absent is
+ * +INF and the diagonal starts at min(W_ii, 0), which is the same relaxation
+ * without the ambiguity of a zero-weight edge.  Single-threaded, as in the
+ * paper's CPU measurement.  The double version is for fp32-valued inputs
+ * (exact when every path sum is an integer below 2^24).
+ */
+int or_fw_i32(long n, const int32_t *W, long ldw, int32_t *D, long ldd) {
+    if (n < 0 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (!scan_i32(OR_MIN_PLUS, n, n, W, ldw)) return OR_EDOMAIN;
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n * n : 1));
+    if (!d) return OR_EARG;
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) d[i * n + j] = i32_lift(OR_MIN_PLUS, W[i * ldw + j]);
+    for (long i = 0; i < n; ++i)
+        if (d[i * n + i] > 0) d[i * n + i] = 0;
+    for (long z = 0; z < n; ++z)
+        for (long x = 0; x < n; ++x) {
+            if (d[x * n + z] == OR_INF64) continue;
+            for (long y = 0; y < n; ++y) {
+                if (d[z * n + y] == OR_INF64) continue;
+                int64_t s = d[x * n + z] + d[z * n + y];
+                if (s < d[x * n + y]) d[x * n + y] = s;
+            }
+        }
+    int status = OR_OK;
+    for (long i = 0; i < n && status == OR_OK; ++i)
+        for (long j = 0; j < n; ++j)
+            if (i64_store(OR_MIN_PLUS, d[i * n + j], &D[i * ldd + j]) != OR_OK) {
+                status = OR_EDOMAIN;
+                break;
+            }
+    free(d);
+    return status;
+}
+
+int or_fw_f64(long n, const double *W, long ldw, double *D, long ldd) {
+    if (n < 0 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) D[i * ldd + j] = W[i * ldw + j];
+    for (long i = 0; i < n; ++i)
+        if (D[i * ldd + i] > 0.0) D[i * ldd + i] = 0.0;
+    for (long z = 0; z < n; ++z)
+        for (long x = 0; x < n; ++x) {
+            double dxz = D[x * ldd + z];
+            if (isinf(dxz)) continue;
+            for (long y = 0; y < n; ++y) {
+                double s = dxz + D[z * ldd + y];
+                if (s < D[x * ldd + y]) D[x * ldd + y] = s;
+            }
+        }
+    return OR_OK;
+}

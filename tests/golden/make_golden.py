@@ -1,0 +1,47 @@
+"""Write the stored expected values under tests/golden/ using only the oracle.
+
+Run:  python tests/golden/make_golden.py
+Every value here comes from oracle/ applied to inputs from the seeded
+generators; nothing is taken from the GPU path.
+"""
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_1701_04733_amd import workloads as wl  # noqa: E402
+
+
+def sha(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def main():
+    out = {}
+    # Small APSP workload: ER digraph n=256, p=0.05, int32 weights U{1..100}, seed 1.
+    W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)
+    D, steps, st = oracle.apsp(W)
+    out["apsp_er256_i32_seed1"] = {
+        "recipe": "er_digraph_i32(256, 0.05, 1, 100, seed=1); fixed T squarings",
+        "input_sha256": sha(W), "steps": steps, "status": st, "D_sha256": sha(D),
+        "D_row0_first16": D[0, :16].tolist(),
+        "reachable_pairs": int((D != oracle.INF32).sum()),
+    }
+    # Early exit on the same graph.
+    D2, steps2, _ = oracle.apsp(W, early_exit=True)
+    out["apsp_er256_i32_seed1_early_exit"] = {"steps": steps2, "D_sha256": sha(D2)}
+    with open(os.path.join(HERE, "apsp_er256.json"), "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,486 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself (IEEE binary32 arithmetic done by numpy, scipy's Dijkstra, brute-force
+path enumeration, closed forms, algebraic identities of the semiring), chosen
+so that a dropped term, a wrong sign or index, a swapped min/max or a
+transposed operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import INF32, NINF32, FINITE_MAX
+from paper_1701_04733_amd import workloads as wl
+
+SR = ["min", "max"]
+DT = ["i32", "f32"]
+
+
+def _np_dtype(dt):
+    return np.int32 if dt == "i32" else np.float32
+
+
+def _absent(dt, sr):
+    if dt == "i32":
+        return INF32 if sr == "min" else NINF32
+    return np.float32(np.inf if sr == "min" else -np.inf)
+
+
+def _identity(n, dt, sr):
+    """Tropical identity: (.)-one (0) on the diagonal, (+)-zero elsewhere."""
+    I = np.full((n, n), _absent(dt, sr), dtype=_np_dtype(dt))
+    np.fill_diagonal(I, 0)
+    return I
+
+
+def _fp32_product_numpy(sr, A, B, C):
+    """Per-term IEEE binary32 adds (numpy float32 arithmetic) then min/max.
+
+    This is the textbook definition evaluated in binary32 by a library, a
+    different computation from the oracle's binary64 evaluation."""
+    S = A[:, :, None] + B[None, :, :]           # float32 + float32 -> float32 (RN)
+    assert S.dtype == np.float32
+    red = S.min(axis=1) if sr == "min" else S.max(axis=1)
+    return np.minimum(C, red) if sr == "min" else np.maximum(C, red)
+
+
+def _i32_product_numpy(sr, A, B, C):
+    """int64 numpy broadcast with the absent value masked in afterwards."""
+    A64, B64 = A.astype(np.int64), B.astype(np.int64)
+    S = A64[:, :, None] + B64[None, :, :]
+    absent = INF32 if sr == "min" else NINF32
+    touch = (A == absent)[:, :, None] | (B == absent)[None, :, :]
+    big = np.int64(1) << 40
+    S = np.where(touch, big if sr == "min" else -big, S)
+    red = S.min(axis=1) if sr == "min" else S.max(axis=1)
+    red = np.where(np.abs(red) >= big, absent, red)
+    out = np.minimum(C.astype(np.int64), red) if sr == "min" else np.maximum(C.astype(np.int64), red)
+    return out.astype(np.int32)
+
+
+# ------------------------------------------------------------------ GEMM ---
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (17, 9, 33), (40, 31, 64)])
+def test_gemm_f32_equals_binary32_per_term(sr, shape):
+    m, n, k = shape
+    A = wl.signed_operand((m, k), "f32", sr, seed=11)
+    B = wl.signed_operand((k, n), "f32", sr, seed=12)
+    C = wl.signed_operand((m, n), "f32", sr, seed=13, inf_frac=0.3)
+    got = oracle.gemm(sr, A, B, C)
+    want = _fp32_product_numpy(sr, A, B, C)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_gemm_f32_rounding_cases():
+    """Sums that round in binary32 (ties-to-even, overflow to inf, subnormals)."""
+    big = np.float32(3.0e38)
+    tiny = np.float32(1e-45)                       # smallest subnormal
+    one = np.float32(1.0)
+    eps_half = np.float32(2.0 ** -24)              # exactly half an ulp of 1.0
+    A = np.array([[one, big, tiny, np.float32(1.5) * eps_half]], dtype=np.float32)
+    k = A.shape[1]
+    for j, bval in enumerate([eps_half, big, tiny, one]):
+        B = np.full((k, 1), np.inf, dtype=np.float32)
+        B[j, 0] = bval
+        C = np.full((1, 1), np.inf, dtype=np.float32)
+        got = oracle.gemm("min", A, B, C)[0, 0]
+        with np.errstate(over="ignore"):
+            want = np.float32(A[0, j] + bval)      # binary32 add
+        assert got.view(np.uint32) == want.view(np.uint32)
+    # 1 + 2^-24 is a tie and rounds to even (1.0); 3e38+3e38 overflows to inf
+    assert oracle.gemm("min", np.array([[one]], np.float32), np.array([[eps_half]], np.float32),
+                       np.array([[np.inf]], np.float32))[0, 0] == one
+    assert np.isinf(oracle.gemm("min", np.array([[big]], np.float32), np.array([[big]], np.float32),
+                                np.array([[np.inf]], np.float32))[0, 0])
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (4, 6, 5), (19, 23, 29), (33, 8, 70)])
+def test_gemm_i32_equals_int64_numpy(sr, shape):
+    m, n, k = shape
+    A = wl.signed_operand((m, k), "i32", sr, seed=21)
+    B = wl.signed_operand((k, n), "i32", sr, seed=22)
+    C = wl.signed_operand((m, n), "i32", sr, seed=23, inf_frac=0.3)
+    assert np.array_equal(oracle.gemm(sr, A, B, C), _i32_product_numpy(sr, A, B, C))
+
+
+@pytest.mark.parametrize("sr", SR)
+def test_gemm_i32_sentinel_absorbs_at_domain_edge(sr):
+    absent = INF32 if sr == "min" else NINF32
+    far = -FINITE_MAX if sr == "min" else FINITE_MAX   # pulls hardest against absorption
+    A = np.array([[absent, far]], dtype=np.int32)
+    B = np.array([[far], [absent]], dtype=np.int32)
+    C = np.array([[absent]], dtype=np.int32)
+    assert oracle.gemm(sr, A, B, C)[0, 0] == absent
+    # the extreme finite sums are exact
+    A2 = np.array([[far]], dtype=np.int32)
+    assert oracle.gemm(sr, A2, A2, np.array([[absent]], np.int32))[0, 0] == 2 * far
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_identity_and_absorbing(sr, dt):
+    A = wl.signed_operand((13, 13), dt, sr, seed=31)
+    I = _identity(13, dt, sr)
+    Z = np.full((13, 13), _absent(dt, sr), dtype=_np_dtype(dt))
+    same = lambda x, y: np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert same(oracle.gemm(sr, A, I, Z), A)
+    assert same(oracle.gemm(sr, I, A, Z), A)
+    assert same(oracle.gemm(sr, A, Z, Z), Z)
+    assert same(oracle.gemm(sr, Z, A, Z), Z)
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_k1_outer_sum(sr, dt):
+    a = wl.signed_operand((7, 1), dt, sr, seed=41, inf_frac=0.2)
+    b = wl.signed_operand((1, 11), dt, sr, seed=42, inf_frac=0.2)
+    C = wl.semiring_identity_matrix((7, 11), dt, sr)
+    got = oracle.gemm(sr, a, b, C)
+    absent = _absent(dt, sr)
+    for i in range(7):
+        for j in range(11):
+            if a[i, 0] == absent or b[0, j] == absent:
+                assert got[i, j] == absent
+            elif dt == "i32":
+                assert int(got[i, j]) == int(a[i, 0]) + int(b[0, j])
+            else:
+                assert got[i, j].view(np.uint32) == np.float32(a[i, 0] + b[0, j]).view(np.uint32)
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_k0_leaves_c(sr, dt):
+    C = wl.signed_operand((5, 4), dt, sr, seed=51)
+    A = np.zeros((5, 0), dtype=_np_dtype(dt))
+    B = np.zeros((0, 4), dtype=_np_dtype(dt))
+    assert np.array_equal(oracle.gemm(sr, A, B, C).view(np.uint32), C.view(np.uint32))
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_transpose_identity(sr, dt):
+    A = wl.signed_operand((9, 14), dt, sr, seed=61)
+    B = wl.signed_operand((14, 6), dt, sr, seed=62)
+    C = wl.signed_operand((9, 6), dt, sr, seed=63, inf_frac=0.5)
+    left = oracle.gemm(sr, A, B, C).T
+    right = oracle.gemm(sr, np.ascontiguousarray(B.T), np.ascontiguousarray(A.T),
+                        np.ascontiguousarray(C.T))
+    assert np.array_equal(left.view(np.uint32), right.view(np.uint32))
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_max_min_duality(dt):
+    A = wl.signed_operand((12, 10), dt, "max", seed=71)
+    B = wl.signed_operand((10, 15), dt, "max", seed=72)
+    C = wl.signed_operand((12, 15), dt, "max", seed=73, inf_frac=0.4)
+    # -(-0x7FFFFFFF) == 0x7FFFFFFF: the sentinels are exact negatives
+    mx = oracle.gemm("max", A, B, C)
+    mn = oracle.gemm("min", -A, -B, -C)
+    if dt == "i32":
+        assert np.array_equal(mx, -mn)
+    else:
+        # only the sign of an exactly-cancelled zero may differ: compare values
+        assert np.array_equal(mx, -mn)
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_leading_dimensions(sr, dt):
+    """Views with padded rows (lda > k etc.) give the same result."""
+    A = wl.signed_operand((6, 20), dt, sr, seed=81)
+    B = wl.signed_operand((20, 30), dt, sr, seed=82)
+    C = wl.semiring_identity_matrix((6, 9), dt, sr)
+    got = oracle.gemm(sr, A[:, 3:11], B[3:11, 5:14], C)
+    want = oracle.gemm(sr, A[:, 3:11].copy(), B[3:11, 5:14].copy(), C)
+    ref = (_i32_product_numpy if dt == "i32" else _fp32_product_numpy)(
+        sr, A[:, 3:11].copy(), B[3:11, 5:14].copy(), C)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_gemm_domain_errors():
+    ok = np.zeros((2, 2), np.int32)
+    for bad in (np.iinfo(np.int32).min, FINITE_MAX + 1, -(FINITE_MAX + 1), NINF32):
+        A = ok.copy()
+        A[0, 1] = bad
+        with pytest.raises(oracle.OracleError):
+            oracle.gemm("min", A, ok, np.full((2, 2), INF32, np.int32))
+    F = np.zeros((2, 2), np.float32)
+    for sr, bad in (("min", -np.inf), ("max", np.inf), ("min", np.nan)):
+        A = F.copy()
+        A[1, 1] = bad
+        with pytest.raises(oracle.OracleError):
+            oracle.gemm(sr, A, F, F.copy())
+
+
+# ------------------------------------------------------- gemv / level 1 ---
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemv_is_one_column_gemm(sr, dt):
+    A = wl.signed_operand((17, 23), dt, sr, seed=91)
+    x = wl.signed_operand((23,), dt, sr, seed=92)
+    y = wl.signed_operand((17,), dt, sr, seed=93, inf_frac=0.3)
+    got = oracle.gemv(sr, A, x, y)
+    ref = (_i32_product_numpy if dt == "i32" else _fp32_product_numpy)(
+        sr, A, x.reshape(-1, 1), y.reshape(-1, 1))[:, 0]
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_level1(sr, dt):
+    x = wl.signed_operand((257,), dt, sr, seed=101)
+    y = wl.signed_operand((257,), dt, sr, seed=102)
+    absent = _absent(dt, sr)
+    red = np.minimum if sr == "min" else np.maximum
+    assert np.array_equal(oracle.vadd(sr, x, y), red(x, y))
+    z = oracle.vmul(sr, x, y)
+    d = oracle.dot(sr, x, y)
+    if dt == "f32":
+        want = x + y                                   # binary32 adds
+        assert np.array_equal(z.view(np.uint32), want.view(np.uint32))
+        wd = want.min() if sr == "min" else want.max()
+        assert np.float32(d).view(np.uint32) == np.float32(wd).view(np.uint32)
+    else:
+        s = x.astype(np.int64) + y.astype(np.int64)
+        s[(x == absent) | (y == absent)] = absent
+        assert np.array_equal(z.astype(np.int64), s)
+        assert int(d) == int(s.min() if sr == "min" else s.max())
+    alpha = 5 if dt == "i32" else np.float32(0.375)
+    ax = oracle.axpy(sr, alpha, x, y)
+    t = oracle.vmul(sr, np.full_like(x, alpha), x)
+    assert np.array_equal(ax.view(np.uint32), red(y, t).view(np.uint32))
+    # empty dot is the (+)-identity
+    e = oracle.dot(sr, x[:0], y[:0])
+    assert e == absent
+
+
+# ----------------------------------------------------------------- APSP ---
+
+@pytest.mark.parametrize("n,T", [(0, 0), (1, 0), (2, 0), (3, 1), (4, 2), (5, 2), (16, 4),
+                                 (17, 4), (18, 5), (256, 8), (257, 8), (258, 9), (512, 9),
+                                 (16384, 14)])
+def test_squaring_count(n, T):
+    assert oracle.apsp_steps(n) == T
+    if n > 2:
+        # smallest T with 2^T >= n-1: paths of up to n-1 edges are covered
+        assert 2 ** T >= n - 1 and 2 ** (T - 1) < n - 1
+
+
+def _to_scipy(W):
+    from scipy.sparse.csgraph import csgraph_from_dense
+    Wf = W.astype(np.float64)
+    if W.dtype == np.int32:
+        Wf[W == INF32] = np.inf
+    np.fill_diagonal(Wf, np.inf)           # self loops never help (non-negative)
+    return csgraph_from_dense(Wf, null_value=np.inf)
+
+
+def _dijkstra(W, indices=None):
+    from scipy.sparse.csgraph import dijkstra
+    return dijkstra(_to_scipy(W), directed=True, indices=indices)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_apsp_tiny_bruteforce(seed):
+    g = np.random.default_rng(seed)
+    n = int(g.integers(1, 8))
+    W = wl.er_digraph_i32(n, 0.4, 0, 9, seed=100 + seed)      # includes zero weights
+    D, steps, _ = oracle.apsp(W)
+    bf = oracle.brute_force_apsp(W.tolist(), INF32)
+    assert D.tolist() == bf
+    assert steps == oracle.apsp_steps(n)
+
+
+@pytest.mark.parametrize("n,p", [(16, 0.2), (64, 0.05), (128, 0.05), (200, 0.02)])
+def test_apsp_i32_vs_fw_and_dijkstra(n, p):
+    W = wl.er_digraph_i32(n, p, 1, 100, seed=n)
+    D, _, _ = oracle.apsp(W)
+    assert np.array_equal(D, oracle.floyd_warshall(W))
+    dj = _dijkstra(W)
+    want = np.where(np.isinf(dj), INF32, dj).astype(np.int64)
+    assert np.array_equal(D.astype(np.int64), want)
+
+
+def test_apsp_naive_products_agree():
+    """The n-1 plain products D <- D (.) (I (+) W) of Sec. III give the same
+    distances as repeated squaring."""
+    n = 40
+    W = wl.er_digraph_i32(n, 0.06, 1, 50, seed=7)
+    W0 = W.copy()
+    np.fill_diagonal(W0, 0)
+    D = W0.copy()
+    Z = np.full((n, n), INF32, np.int32)
+    for _ in range(n - 2):
+        D = oracle.gemm("min", D, W0, Z)
+    Dsq, _, _ = oracle.apsp(W)
+    assert np.array_equal(D, Dsq)
+
+
+def test_apsp_one_step_short_is_wrong():
+    """A directed path needs all T squarings: with T-1 it is not solved."""
+    n = 18                                        # n-1 = 17 > 2^4, so T = 5
+    W = np.full((n, n), INF32, np.int32)
+    np.fill_diagonal(W, 0)
+    for i in range(n - 1):
+        W[i, i + 1] = 1
+    D, steps, _ = oracle.apsp(W)
+    assert steps == 5 and D[0, n - 1] == n - 1
+    cur = W.copy()
+    for _ in range(4):
+        cur = oracle.gemm("min", cur, cur, cur)
+    assert cur[0, n - 1] == INF32
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_apsp_closed_forms(dt):
+    npdt = _np_dtype(dt)
+    absent = _absent(dt, "min")
+    # directed cycle, unit weights: d(i,j) = (j - i) mod n
+    n = 37
+    W = np.full((n, n), absent, npdt)
+    for i in range(n):
+        W[i, (i + 1) % n] = 1
+    D, _, _ = oracle.apsp(W)
+    i, j = np.indices((n, n))
+    assert np.array_equal(D, ((j - i) % n).astype(npdt))
+    # directed path: j - i above the diagonal, absent below
+    P = np.full((n, n), absent, npdt)
+    for a in range(n - 1):
+        P[a, a + 1] = 1
+    D, _, _ = oracle.apsp(P)
+    assert np.array_equal(D, np.where(j >= i, j - i, absent).astype(npdt))
+    # complete graph of ones: 1 off the diagonal, one step reaches the fixpoint
+    K = np.ones((n, n), npdt)
+    D, steps, _ = oracle.apsp(K, early_exit=True)
+    assert np.array_equal(D, np.where(i == j, 0, 1).astype(npdt)) and steps == 1
+    # undirected 6x7 grid, unit weights: Manhattan distance
+    r, c = 6, 7
+    G = np.full((r * c, r * c), absent, npdt)
+    for y in range(r):
+        for x in range(c):
+            u = y * c + x
+            if x + 1 < c:
+                G[u, u + 1] = G[u + 1, u] = 1
+            if y + 1 < r:
+                G[u, u + c] = G[u + c, u] = 1
+    D, _, _ = oracle.apsp(G)
+    yy, xx = np.divmod(np.arange(r * c), c)
+    man = np.abs(yy[:, None] - yy[None, :]) + np.abs(xx[:, None] - xx[None, :])
+    assert np.array_equal(D, man.astype(npdt))
+    # two components: absent blocks between them
+    B = np.full((10, 10), absent, npdt)
+    B[:5, :5] = 2
+    B[5:, 5:] = 3
+    D, _, _ = oracle.apsp(B)
+    assert (D[:5, 5:] == absent).all() and (D[5:, :5] == absent).all()
+
+
+def test_apsp_f32_integer_weights_exact():
+    n = 60
+    Wi = wl.er_digraph_i32(n, 0.08, 1, 1000, seed=9)
+    Wf = np.where(Wi == INF32, np.inf, Wi).astype(np.float32)
+    D, _, _ = oracle.apsp(Wf)
+    fw = oracle.floyd_warshall(Wf)
+    assert np.array_equal(D.astype(np.float64), fw)
+    Di, _, _ = oracle.apsp(Wi)
+    assert np.array_equal(np.where(Di == INF32, np.inf, Di), D.astype(np.float64))
+
+
+def test_apsp_f32_rounding_bound_vs_dijkstra():
+    """Each distance is a depth-<=T tree of rounded adds of non-negative
+    weights, so (1-u)^T d* <= d32 <= (1+u)^T d* with u = 2^-24."""
+    n = 300
+    r, c, w = wl.sparse_digraph_f32_exp(n, 6.0, seed=4)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    D, steps, _ = oracle.apsp(W, early_exit=True)
+    T = oracle.apsp_steps(n)
+    exact = _dijkstra(W)
+    fin = np.isfinite(exact)
+    assert np.array_equal(fin, np.isfinite(D))
+    u = 2.0 ** -24
+    d = D.astype(np.float64)[fin]
+    e = exact[fin]
+    assert np.all(d <= e * (1 + u) ** T + 1e-300)
+    assert np.all(d >= e * (1 - u) ** T - 1e-300)
+    assert 1 <= steps <= T
+
+
+def test_apsp_early_exit_equals_fixed_T():
+    W = wl.er_digraph_i32(150, 0.1, 1, 100, seed=3)
+    Dfix, sfix, _ = oracle.apsp(W)
+    Dee, see, _ = oracle.apsp(W, early_exit=True)
+    assert np.array_equal(Dfix, Dee) and see <= sfix
+    Wf = np.where(W == INF32, np.inf, W * np.float32(0.37)).astype(np.float32)
+    Ffix, _, _ = oracle.apsp(Wf)
+    Fee, _, _ = oracle.apsp(Wf, early_exit=True)
+    assert np.array_equal(Ffix.view(np.uint32), Fee.view(np.uint32))
+
+
+def test_apsp_invariants_small_config():
+    """n=256 ER graph, p=0.05, weights in [1,100]: diagonal 0, bounded by
+    I (+) W, fixpoint and triangle inequality exact, reachability = BFS."""
+    from scipy.sparse.csgraph import breadth_first_order  # noqa: F401
+    W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)
+    D, steps, st = oracle.apsp(W, check_neg_cycle=True)
+    assert st == oracle.OK and steps == 8
+    assert (np.diag(D) == 0).all()
+    W0 = W.copy()
+    np.fill_diagonal(W0, 0)
+    assert (D.astype(np.int64) <= W0.astype(np.int64)).all()
+    assert np.array_equal(oracle.gemm("min", D, D, D), D)    # fixpoint
+    # reachability equals the boolean transitive closure
+    R = (W0 != INF32)
+    for _ in range(9):
+        R = R | ((R.astype(np.int32) @ R.astype(np.int32)) > 0)
+    assert np.array_equal(R, D != INF32)
+
+
+def test_apsp_negative_cycle_flag():
+    # a two-edge cycle of weight 1 + (-3) is seen by the first squaring
+    W = np.array([[0, 1, INF32], [-3, 0, INF32], [INF32, 2, 0]], np.int32)
+    _, _, st = oracle.apsp(W, check_neg_cycle=True)
+    assert st == oracle.WNEGCYCLE
+    _, _, st = oracle.apsp(np.abs(W), check_neg_cycle=True)
+    assert st == oracle.OK
+
+
+def test_generators_reproducible():
+    a = wl.er_digraph_i32(64, 0.05, 1, 100, seed=1)
+    b = wl.er_digraph_i32(64, 0.05, 1, 100, seed=1)
+    assert np.array_equal(a, b) and (np.diag(a) == 0).all()
+    g1 = wl.batched_graphs_i32(count=8)
+    g2 = wl.batched_graphs_i32(count=8)
+    assert all(np.array_equal(x, y) for x, y in zip(g1, g2))
+    assert all(16 <= x.shape[0] <= 512 for x in g1)
+
+
+def _read_hand_example():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "hand_4node.txt")
+    mats, cur = {}, None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line in ("W", "D"):
+            cur = line
+            mats[cur] = []
+            continue
+        mats[cur].append([INF32 if t == "INF" else int(t) for t in line.split()])
+    return np.array(mats["W"], np.int32), np.array(mats["D"], np.int32)
+
+
+def test_hand_worked_example():
+    W, Dw = _read_hand_example()
+    D, steps, _ = oracle.apsp(W)
+    assert steps == 2 and np.array_equal(D, Dw)
+    assert oracle.brute_force_apsp(W.tolist(), INF32) == Dw.tolist()
+    # and as floats
+    Wf = np.where(W == INF32, np.inf, W).astype(np.float32)
+    Df, _, _ = oracle.apsp(Wf)
+    assert np.array_equal(Df, Dw.astype(np.float32))
