@@ -1,0 +1,178 @@
+/*
+ * btas.h -- Basic Tropical Algebra Subroutines for AMD Instinct MI355X (gfx950).
+ *
+ * A BLAS-style C ABI for tropical linear algebra over the max-plus and
+ * min-plus semirings (Sec. I, eqs. (1)-(4)):
+ *     max-plus:  x (+) y = max(x, y),   x (.) y = x + y
+ *     min-plus:  x (+) y = min(x, y),   x (.) y = x + y
+ * and for all-pairs shortest paths by repeated min-plus squaring of the
+ * weighted adjacency matrix (Sec. III).  The library is motivated as the
+ * tropical counterpart of the standard vector and matrix routines of BLAS
+ * (Abstract; Sec. II); no signatures are given there, so these follow BLAS
+ * conventions.
+ *
+ * General rules
+ *  - Every call returns btas_status_t; nothing throws across the ABI.
+ *  - Matrices are row-major with a leading dimension (elements between the
+ *    starts of consecutive rows), as the adjacency matrix of Sec. IV is
+ *    indexed.  Column-major callers use (A (.) B)^T = B^T (.) A^T.
+ *  - Matrix and vector pointers are DEVICE pointers owned by the caller; the
+ *    library never frees or retains them past the call's stream work.  Only
+ *    btas_tropical_axpy's alpha and the *_out / counts arguments explicitly
+ *    documented as host memory are host pointers.
+ *  - Element types: BTAS_INT32 (int32_t) and BTAS_FLOAT32 (IEEE binary32).
+ *  - Absent values (the (+)-identity): for int32, BTAS_I32_INF in min-plus and
+ *    BTAS_I32_NEG_INF in max-plus; they absorb under (.) (saturating, never
+ *    wrapping).  For float32, +inf / -inf.  Finite int32 operands of (.) must
+ *    satisfy |x| <= BTAS_I32_FINITE_MAX; float32 operands must not be NaN and
+ *    must not be the other semiring's infinity.  Out-of-domain input gives
+ *    unspecified values (no fault); with the environment variable
+ *    BTAS_VALIDATE=1 it is detected and reported as BTAS_ERR_DOMAIN before
+ *    any output is written.
+ *  - float32: each (.) is one IEEE binary32 round-to-nearest-even addition,
+ *    denormals preserved, no contraction; since min/max are exact and
+ *    rounding is monotone the result does not depend on reduction order and
+ *    is bit-reproducible.
+ *  - Calls are asynchronous on the handle's stream unless stated otherwise.
+ *    A handle must be used by one host thread at a time.
+ *  - Errors: arguments are checked before anything is launched (as BLAS's
+ *    xerbla does); btas_last_error(h) then names the offending argument.
+ *    A HIP launch or synchronisation failure is BTAS_ERR_DEVICE.
+ *  - Degenerate sizes: a zero output size is a no-op returning BTAS_OK; a
+ *    zero reduction length leaves the accumulator unchanged (the (+) over an
+ *    empty set is the identity).
+ */
+#ifndef BTAS_H
+#define BTAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { BTAS_MIN_PLUS = 0, BTAS_MAX_PLUS = 1 } btas_semiring_t;
+typedef enum { BTAS_INT32 = 0, BTAS_FLOAT32 = 1 } btas_dtype_t;
+
+typedef enum {
+    BTAS_OK = 0,
+    BTAS_ERR_INVALID_ARG = 1, /* bad size, leading dimension, stride, enum or null pointer */
+    BTAS_ERR_ALIAS = 2,       /* output overlaps an input where that is not allowed       */
+    BTAS_ERR_DOMAIN = 3,      /* BTAS_VALIDATE=1 found an element outside the domain      */
+    BTAS_ERR_OOM = 4,         /* device workspace allocation failed                      */
+    BTAS_ERR_DEVICE = 5,      /* HIP runtime error (launch, copy, synchronisation)         */
+    BTAS_ERR_UNSUPPORTED = 6, /* combination not provided (e.g. max-plus APSP)             */
+    BTAS_WARN_NEG_CYCLE = 7   /* APSP result has some D_ii < 0 (result unspecified)        */
+} btas_status_t;
+
+#define BTAS_I32_INF ((int32_t)0x7FFFFFFF)      /* min-plus absent value, +INF  */
+#define BTAS_I32_NEG_INF ((int32_t)-0x7FFFFFFF) /* max-plus absent value, -INF  */
+#define BTAS_I32_FINITE_MAX ((1 << 29) - 1)     /* |finite (.) operand| bound   */
+
+typedef struct btas_ctx *btas_handle_t;
+
+/* Create a handle bound to HIP device `device` (made current for the call).
+ * The handle starts on the default (null) stream and owns its workspace.
+ * h: host pointer receiving the handle.  Errors: INVALID_ARG (null h, bad
+ * device), DEVICE. */
+btas_status_t btas_create(btas_handle_t *h, int device);
+
+/* Release the handle and its workspace (synchronises its stream first). */
+btas_status_t btas_destroy(btas_handle_t h);
+
+/* Use `hip_stream` (a hipStream_t, borrowed, not owned; NULL = default
+ * stream) for all later work of this handle. */
+btas_status_t btas_set_stream(btas_handle_t h, void *hip_stream);
+
+/* Block the host until the handle's stream has drained. */
+btas_status_t btas_synchronize(btas_handle_t h);
+
+/* Static text for a status code. */
+const char *btas_status_string(btas_status_t s);
+
+/* Text describing the last failure on this handle ("" if none).  Valid until
+ * the next call on the handle. */
+const char *btas_last_error(btas_handle_t h);
+
+/* Library version string. */
+const char *btas_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Level 3 -- tropical matrix product with accumulate (Sec. IV, min-plus form
+ * of the matrix-product listing):  C <- C (+) A (.) B, i.e.
+ *     c_ij <- c_ij (+) ( (+)_p  a_ip (.) b_pj ).
+ * A is m x k (lda >= max(1,k)), B is k x n (ldb >= max(1,n)), C is m x n
+ * (ldc >= max(1,n)), all row-major device arrays of dtype `dt`.  C is read
+ * and written; it must not overlap A or B (BTAS_ERR_ALIAS).  Pass C filled
+ * with the absent value for a plain product.  Any int32 value is accepted in
+ * C (it is only (+)-combined).
+ */
+btas_status_t btas_tropical_gemm(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt,
+                                 int m, int n, int k,
+                                 const void *A, int lda, const void *B, int ldb,
+                                 void *C, int ldc);
+
+/* Level 2 -- y <- y (+) A (.) x, i.e. y_i <- y_i (+) (+)_j a_ij (.) x_j.
+ * A is m x n row-major (lda >= max(1,n)); x has n elements with stride incx
+ * >= 1; y has m elements with stride incy >= 1.  y must not overlap A or x. */
+btas_status_t btas_tropical_gemv(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt,
+                                 int m, int n, const void *A, int lda,
+                                 const void *x, int incx, void *y, int incy);
+
+/* Level 1 (strides >= 1, n >= 0).  z may equal x or y exactly (elementwise
+ * in place) but must not partially overlap them. */
+/* z_i = x_i (+) y_i */
+btas_status_t btas_tropical_vadd(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                 const void *x, int incx, const void *y, int incy,
+                                 void *z, int incz);
+/* z_i = x_i (.) y_i */
+btas_status_t btas_tropical_vmul(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                 const void *x, int incx, const void *y, int incy,
+                                 void *z, int incz);
+/* *result_dev = (+)_i x_i (.) y_i  (one element of dtype dt in device
+ * memory; n = 0 stores the absent value). */
+btas_status_t btas_tropical_dot(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                const void *x, int incx, const void *y, int incy,
+                                void *result_dev);
+/* y_i <- y_i (+) alpha (.) x_i; alpha_host points to one host element of
+ * dtype dt, read during the call. */
+btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                 const void *alpha_host, const void *x, int incx,
+                                 void *y, int incy);
+
+/* ---------------------------------------------------------------------------
+ * All-pairs shortest paths by repeated min-plus squaring (Sec. III).
+ *   D_0 = I (+) W   (I: 0 on the diagonal, absent elsewhere; so D_ii =
+ *                    min(W_ii, 0)),
+ *   D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1}   for t = 1..T,
+ *   T   = ceil(log2(n-1)) for n > 2, else 0,
+ * each step reading only the previous step's matrix (out-of-place).  W and D
+ * are n x n row-major device matrices (ldw, ldd >= max(1,n)); D may equal W
+ * (in place) but must not partially overlap it.  Only min-plus is provided
+ * (BTAS_ERR_UNSUPPORTED is never returned for valid dtypes).
+ * Flags:
+ *   BTAS_APSP_EARLY_EXIT: stop after the first step whose output equals its
+ *     input bit for bit (that step is counted).  Same result as fixed T.
+ *     Reads a device flag back after every step (host synchronisation).
+ *   BTAS_APSP_CHECK_NEG_CYCLE: after the last step, return
+ *     BTAS_WARN_NEG_CYCLE if some D_ii < 0 (synchronises).
+ * steps_out: host int receiving the number of squarings executed (may be
+ * NULL; when non-NULL the call synchronises).  Integer contract: all finite
+ * path lengths must stay within +-BTAS_I32_FINITE_MAX.  The handle keeps an
+ * n x n workspace matrix between calls (grown on demand).
+ */
+#define BTAS_APSP_EARLY_EXIT 1u
+#define BTAS_APSP_CHECK_NEG_CYCLE 2u
+btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n,
+                                 const void *W, int ldw, void *D, int ldd,
+                                 unsigned flags, int *steps_out);
+
+/* Number of squarings T for n vertices (0 for n <= 2). */
+int btas_apsp_num_steps(int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTAS_H */

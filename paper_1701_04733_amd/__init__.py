@@ -1,0 +1,301 @@
+"""Python binding of libbtas: tropical GEMM / gemv / level-1 and APSP on MI355X.
+
+Thin ctypes marshalling over the C ABI declared in ``include/btas.h``: torch
+tensors supply device pointers, leading dimensions and the current HIP
+stream; every step of the computation runs in the HIP kernels of libbtas.
+There is no CPU fallback: if ``libbtas.so`` is missing or no GPU is present,
+calls raise.
+
+Semirings (Sec. I, eqs. (1)-(4)): ``"min"`` (min-plus) and ``"max"``
+(max-plus).  Element types: ``torch.int32`` (saturating +-INF sentinels
+``I32_INF`` / ``I32_NEG_INF``) and ``torch.float32`` (IEEE +-inf).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = [
+    "I32_INF", "I32_NEG_INF", "I32_FINITE_MAX", "BtasError", "lib", "library_path",
+    "Handle", "default_handle", "tropical_gemm", "tropical_gemv", "vadd", "vmul", "dot",
+    "axpy", "apsp", "apsp_num_steps", "version",
+]
+
+I32_INF = 0x7FFFFFFF
+I32_NEG_INF = -0x7FFFFFFF
+I32_FINITE_MAX = (1 << 29) - 1
+
+MIN_PLUS, MAX_PLUS = 0, 1
+INT32, FLOAT32 = 0, 1
+APSP_EARLY_EXIT, APSP_CHECK_NEG_CYCLE = 1, 2
+
+STATUS = {0: "BTAS_OK", 1: "BTAS_ERR_INVALID_ARG", 2: "BTAS_ERR_ALIAS", 3: "BTAS_ERR_DOMAIN",
+          4: "BTAS_ERR_OOM", 5: "BTAS_ERR_DEVICE", 6: "BTAS_ERR_UNSUPPORTED",
+          7: "BTAS_WARN_NEG_CYCLE"}
+OK, WARN_NEG_CYCLE = 0, 7
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libbtas.so")
+_LIB = None
+_LOCK = threading.Lock()
+
+
+class BtasError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib():
+    """Load libbtas.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    with _LOCK:
+        if _LIB is not None:
+            return _LIB
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"libbtas.so not found at {library_path}; run "
+                               "python -m paper_1701_04733_amd.build")
+        L = ctypes.CDLL(library_path)
+        P, I, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint
+        L.btas_create.argtypes = [ctypes.POINTER(P), I]
+        L.btas_destroy.argtypes = [P]
+        L.btas_set_stream.argtypes = [P, P]
+        L.btas_synchronize.argtypes = [P]
+        L.btas_status_string.argtypes = [I]
+        L.btas_status_string.restype = ctypes.c_char_p
+        L.btas_last_error.argtypes = [P]
+        L.btas_last_error.restype = ctypes.c_char_p
+        L.btas_version.restype = ctypes.c_char_p
+        L.btas_tropical_gemm.argtypes = [P, I, I, I, I, I, P, I, P, I, P, I]
+        L.btas_tropical_gemv.argtypes = [P, I, I, I, I, P, I, P, I, P, I]
+        for name in ("btas_tropical_vadd", "btas_tropical_vmul"):
+            getattr(L, name).argtypes = [P, I, I, I, P, I, P, I, P, I]
+        L.btas_tropical_dot.argtypes = [P, I, I, I, P, I, P, I, P]
+        L.btas_tropical_axpy.argtypes = [P, I, I, I, P, P, I, P, I]
+        L.btas_apsp_squaring.argtypes = [P, I, I, P, I, P, I, U, ctypes.POINTER(I)]
+        L.btas_apsp_num_steps.argtypes = [I]
+        _LIB = L
+    return _LIB
+
+
+def version() -> str:
+    return lib().btas_version().decode()
+
+
+def apsp_num_steps(n: int) -> int:
+    """T = ceil(log2(n-1)) for n > 2, else 0 (Sec. III)."""
+    return lib().btas_apsp_num_steps(int(n))
+
+
+class Handle:
+    """One libbtas handle bound to a device; follows torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = lib().btas_create(ctypes.byref(h), self.device)
+        if st != OK:
+            raise BtasError(st, f"btas_create(device={device}) failed")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def bind_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        lib().btas_set_stream(self._h, ctypes.c_void_p(s.cuda_stream))
+
+    def check(self, st: int, allow=(OK,)) -> int:
+        if st not in allow:
+            msg = lib().btas_last_error(self._h).decode()
+            raise BtasError(st, msg)
+        return st
+
+    def synchronize(self):
+        self.check(lib().btas_synchronize(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().btas_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_HANDLES: dict = {}
+
+
+def default_handle(device: int | None = None) -> Handle:
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    h = _HANDLES.get(device)
+    if h is None:
+        h = _HANDLES[device] = Handle(device)
+    h.bind_stream()
+    return h
+
+
+# ------------------------------------------------------------ marshalling ---
+
+def _sr(semiring) -> int:
+    if semiring in ("min", MIN_PLUS):
+        return MIN_PLUS
+    if semiring in ("max", MAX_PLUS):
+        return MAX_PLUS
+    raise ValueError(f"semiring must be 'min' or 'max', not {semiring!r}")
+
+
+def _dt(t) -> int:
+    import torch
+    if t.dtype == torch.int32:
+        return INT32
+    if t.dtype == torch.float32:
+        return FLOAT32
+    raise TypeError(f"btas supports int32 and float32 tensors, not {t.dtype}")
+
+
+def _mat(t, name):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be a matrix")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.size(1) > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride (row-major with leading dimension)")
+    ld = t.stride(0) if t.size(0) > 1 else max(1, t.size(1))
+    return ctypes.c_void_p(t.data_ptr()), max(1, ld)
+
+
+def _vec(t, name):
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be a vector")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return ctypes.c_void_p(t.data_ptr()), max(1, t.stride(0))
+
+
+def _handle_for(t, handle):
+    return handle if handle is not None else default_handle(t.device.index or 0)
+
+
+def tropical_gemm(A, B, C=None, semiring="min", handle=None):
+    """C <- C (+) A (.) B on the device (C allocated as the (+)-identity if None)."""
+    import torch
+    sr = _sr(semiring)
+    if C is None:
+        fill = (I32_INF if sr == MIN_PLUS else I32_NEG_INF) if A.dtype == torch.int32 else \
+            (float("inf") if sr == MIN_PLUS else float("-inf"))
+        C = torch.full((A.size(0), B.size(1)), fill, dtype=A.dtype, device=A.device)
+    if A.dtype != B.dtype or A.dtype != C.dtype:
+        raise TypeError("A, B and C must share a dtype")
+    h = _handle_for(C, handle)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    m, k = A.shape
+    if B.size(0) != k or C.shape != (m, B.size(1)):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    h.check(lib().btas_tropical_gemm(h.ptr, sr, _dt(A), m, B.size(1), k, pa, lda, pb, ldb, pc, ldc))
+    return C
+
+
+def tropical_gemv(A, x, y, semiring="min", handle=None):
+    """y <- y (+) A (.) x on the device."""
+    h = _handle_for(y, handle)
+    pa, lda = _mat(A, "A")
+    px, incx = _vec(x, "x")
+    py, incy = _vec(y, "y")
+    m, n = A.shape
+    if x.numel() != n or y.numel() != m:
+        raise ValueError("shape mismatch")
+    h.check(lib().btas_tropical_gemv(h.ptr, _sr(semiring), _dt(A), m, n, pa, lda, px, incx, py, incy))
+    return y
+
+
+def _binary(name, x, y, z, semiring, handle):
+    import torch
+    if z is None:
+        z = torch.empty_like(x)
+    h = _handle_for(z, handle)
+    px, ix = _vec(x, "x")
+    py, iy = _vec(y, "y")
+    pz, iz = _vec(z, "z")
+    if not (x.numel() == y.numel() == z.numel()):
+        raise ValueError("length mismatch")
+    h.check(getattr(lib(), name)(h.ptr, _sr(semiring), _dt(x), x.numel(), px, ix, py, iy, pz, iz))
+    return z
+
+
+def vadd(x, y, z=None, semiring="min", handle=None):
+    """z = x (+) y."""
+    return _binary("btas_tropical_vadd", x, y, z, semiring, handle)
+
+
+def vmul(x, y, z=None, semiring="min", handle=None):
+    """z = x (.) y."""
+    return _binary("btas_tropical_vmul", x, y, z, semiring, handle)
+
+
+def dot(x, y, semiring="min", out=None, handle=None):
+    """(+)_i x_i (.) y_i, returned as a one-element device tensor."""
+    import torch
+    if out is None:
+        out = torch.empty(1, dtype=x.dtype, device=x.device)
+    h = _handle_for(x, handle)
+    px, ix = _vec(x, "x")
+    py, iy = _vec(y, "y")
+    if x.numel() != y.numel():
+        raise ValueError("length mismatch")
+    h.check(lib().btas_tropical_dot(h.ptr, _sr(semiring), _dt(x), x.numel(), px, ix, py, iy,
+                                    ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def axpy(alpha, x, y, semiring="min", handle=None):
+    """y <- y (+) alpha (.) x (alpha is a host scalar)."""
+    import torch
+    h = _handle_for(y, handle)
+    if x.dtype == torch.int32:
+        a = ctypes.c_int32(int(alpha))
+    else:
+        a = ctypes.c_float(float(alpha))
+    px, ix = _vec(x, "x")
+    py, iy = _vec(y, "y")
+    if x.numel() != y.numel():
+        raise ValueError("length mismatch")
+    h.check(lib().btas_tropical_axpy(h.ptr, _sr(semiring), _dt(x), x.numel(),
+                                     ctypes.cast(ctypes.byref(a), ctypes.c_void_p), px, ix, py, iy))
+    return y
+
+
+def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True, handle=None):
+    """All-pairs shortest paths by repeated min-plus squaring of I (+) W.
+
+    Returns (D, steps, status); status is OK or WARN_NEG_CYCLE.  With
+    ``return_steps=False`` and no flags the call stays asynchronous and steps
+    is None.  ``out`` may be W itself (in place).
+    """
+    import torch
+    n = W.size(0)
+    if W.shape != (n, n):
+        raise ValueError("W must be square")
+    if out is None:
+        out = torch.empty_like(W)
+    h = _handle_for(W, handle)
+    pw, ldw = _mat(W, "W")
+    pd, ldd = _mat(out, "D")
+    flags = (APSP_EARLY_EXIT if early_exit else 0) | (APSP_CHECK_NEG_CYCLE if check_neg_cycle else 0)
+    steps = ctypes.c_int(0)
+    sp = ctypes.byref(steps) if (return_steps or flags) else None
+    st = h.check(lib().btas_apsp_squaring(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
+                 allow=(OK, WARN_NEG_CYCLE))
+    return out, (steps.value if sp is not None else None), st

@@ -1,0 +1,450 @@
+// C ABI of libbtas: handles, argument validation and dispatch to the HIP
+// kernels.  See include/btas.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "btas.h"
+#include "kernels.h"
+
+struct btas_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    bool validate = false;
+    void* ws = nullptr;  // APSP ping-pong partner matrix
+    size_t ws_bytes = 0;
+    void* partials = nullptr;  // dot reduction partials
+    int* dflags = nullptr;     // device flags [8]
+    int* hflags = nullptr;     // pinned host mirror [8]
+};
+
+namespace {
+
+const char* kVersion = "btas-gfx950 0.1.0";
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+btas_status_t fail(btas_handle_t h, btas_status_t st, const char* fmt, ...) {
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->last_error = buf;
+    }
+    return st;
+}
+
+btas_status_t device_fail(btas_handle_t h, const char* where, hipError_t e) {
+    return fail(h, BTAS_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+bool sr_ok(btas_semiring_t sr) { return sr == BTAS_MIN_PLUS || sr == BTAS_MAX_PLUS; }
+bool dt_ok(btas_dtype_t dt) { return dt == BTAS_INT32 || dt == BTAS_FLOAT32; }
+
+// Byte span [lo, hi) touched by a row-major rows x cols matrix with leading
+// dimension ld (4-byte elements); empty when rows or cols is 0.
+struct Span {
+    uintptr_t lo = 0, hi = 0;
+    bool empty() const { return hi <= lo; }
+};
+Span mat_span(const void* p, long rows, long cols, long ld) {
+    Span s;
+    if (rows <= 0 || cols <= 0 || p == nullptr) return s;
+    s.lo = (uintptr_t)p;
+    s.hi = s.lo + (uintptr_t)(((rows - 1) * ld + cols) * 4);
+    return s;
+}
+Span vec_span(const void* p, long n, long inc) {
+    Span s;
+    if (n <= 0 || p == nullptr) return s;
+    s.lo = (uintptr_t)p;
+    s.hi = s.lo + (uintptr_t)(((n - 1) * inc + 1) * 4);
+    return s;
+}
+bool overlap(const Span& a, const Span& b) {
+    return !a.empty() && !b.empty() && a.lo < b.hi && b.lo < a.hi;
+}
+
+btas_status_t check_common(btas_handle_t h, const char* fn, btas_semiring_t sr,
+                           btas_dtype_t dt) {
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!sr_ok(sr)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (semiring=%d) unknown", fn, (int)sr);
+    if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (dtype=%d) unknown", fn, (int)dt);
+    return BTAS_OK;
+}
+
+btas_status_t sync_flags(btas_handle_t h, const char* fn, int count) {
+    hipError_t e = hipMemcpyAsync(h->hflags, h->dflags, sizeof(int) * count,
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    return BTAS_OK;
+}
+
+// BTAS_VALIDATE=1: scan operands of (.) for out-of-domain values.
+btas_status_t validate_operands(btas_handle_t h, const char* fn, int sr, int dt,
+                                const void* const* ptrs, const long* rows, const long* cols,
+                                const long* lds, int count) {
+    if (!h->validate) return BTAS_OK;
+    hipError_t e = btas::launch_clear_flags(h->dflags, 1, h->stream);
+    for (int i = 0; i < count && e == hipSuccess; ++i)
+        e = btas::launch_domain_scan(sr, dt, (int)rows[i], (int)cols[i], ptrs[i], lds[i],
+                                     h->dflags, h->stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    btas_status_t st = sync_flags(h, fn, 1);
+    if (st != BTAS_OK) return st;
+    if (h->hflags[0]) return fail(h, BTAS_ERR_DOMAIN, "%s: an input element is outside the semiring's domain", fn);
+    return BTAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* btas_version(void) { return kVersion; }
+
+const char* btas_status_string(btas_status_t s) {
+    switch (s) {
+        case BTAS_OK: return "BTAS_OK";
+        case BTAS_ERR_INVALID_ARG: return "BTAS_ERR_INVALID_ARG";
+        case BTAS_ERR_ALIAS: return "BTAS_ERR_ALIAS";
+        case BTAS_ERR_DOMAIN: return "BTAS_ERR_DOMAIN";
+        case BTAS_ERR_OOM: return "BTAS_ERR_OOM";
+        case BTAS_ERR_DEVICE: return "BTAS_ERR_DEVICE";
+        case BTAS_ERR_UNSUPPORTED: return "BTAS_ERR_UNSUPPORTED";
+        case BTAS_WARN_NEG_CYCLE: return "BTAS_WARN_NEG_CYCLE";
+    }
+    return "BTAS_UNKNOWN_STATUS";
+}
+
+const char* btas_last_error(btas_handle_t h) { return h ? h->last_error.c_str() : "null handle"; }
+
+int btas_apsp_num_steps(int n) {
+    if (n <= 2) return 0;
+    int t = 0;
+    long reach = 1;
+    while (reach < (long)n - 1) {
+        reach *= 2;
+        ++t;
+    }
+    return t;
+}
+
+btas_status_t btas_create(btas_handle_t* out, int device) {
+    if (!out) return BTAS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return BTAS_ERR_INVALID_ARG;
+    DeviceGuard g(device);
+    if (!g.ok) return BTAS_ERR_DEVICE;
+    btas_ctx* h = new btas_ctx;
+    h->device = device;
+    const char* v = getenv("BTAS_VALIDATE");
+    h->validate = v && v[0] == '1';
+    if (hipMalloc(&h->dflags, 8 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&h->hflags, 8 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&h->partials, (size_t)btas::dot_partials_needed(0) * 4) != hipSuccess) {
+        if (h->dflags) (void)hipFree(h->dflags);
+        if (h->hflags) (void)hipHostFree(h->hflags);
+        if (h->partials) (void)hipFree(h->partials);
+        delete h;
+        return BTAS_ERR_OOM;
+    }
+    *out = h;
+    return BTAS_OK;
+}
+
+btas_status_t btas_destroy(btas_handle_t h) {
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    DeviceGuard g(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->dflags) (void)hipFree(h->dflags);
+    if (h->hflags) (void)hipHostFree(h->hflags);
+    delete h;
+    return BTAS_OK;
+}
+
+btas_status_t btas_set_stream(btas_handle_t h, void* stream) {
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)stream;
+    return BTAS_OK;
+}
+
+btas_status_t btas_synchronize(btas_handle_t h) {
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, "btas_synchronize", e);
+}
+
+// ------------------------------------------------------------- level 3 ---
+btas_status_t btas_tropical_gemm(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int m,
+                                 int n, int k, const void* A, int lda, const void* B, int ldb,
+                                 void* C, int ldc) {
+    const char* fn = "btas_tropical_gemm";
+    btas_status_t st = check_common(h, fn, sr, dt);
+    if (st != BTAS_OK) return st;
+    if (m < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (m=%d) < 0", fn, m);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (n=%d) < 0", fn, n);
+    if (k < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 6 (k=%d) < 0", fn, k);
+    if (lda < (k > 1 ? k : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (lda=%d) < max(1,k=%d)", fn, lda, k);
+    if (ldb < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 10 (ldb=%d) < max(1,n=%d)", fn, ldb, n);
+    if (ldc < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 12 (ldc=%d) < max(1,n=%d)", fn, ldc, n);
+    if ((long)m * k > 0 && !A) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (A) is null", fn);
+    if ((long)k * n > 0 && !B) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (B) is null", fn);
+    if ((long)m * n > 0 && !C) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 11 (C) is null", fn);
+    const Span sc = mat_span(C, m, n, ldc);
+    if (overlap(sc, mat_span(A, m, k, lda)) || overlap(sc, mat_span(B, k, n, ldb)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: C overlaps A or B", fn);
+    if (m == 0 || n == 0 || k == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    const void* ps[2] = {A, B};
+    const long rows[2] = {m, k}, cols[2] = {k, n}, lds[2] = {lda, ldb};
+    st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 2);
+    if (st != BTAS_OK) return st;
+    btas::GemmArgs a{m, n, k, A, lda, B, ldb, C, ldc, C, ldc, nullptr};
+    hipError_t e = btas::launch_gemm(sr, dt, a, -1, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+// ------------------------------------------------------------- level 2 ---
+btas_status_t btas_tropical_gemv(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int m,
+                                 int n, const void* A, int lda, const void* x, int incx, void* y,
+                                 int incy) {
+    const char* fn = "btas_tropical_gemv";
+    btas_status_t st = check_common(h, fn, sr, dt);
+    if (st != BTAS_OK) return st;
+    if (m < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (m=%d) < 0", fn, m);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (n=%d) < 0", fn, n);
+    if (lda < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (lda=%d) < max(1,n=%d)", fn, lda, n);
+    if (incx < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (incx=%d) < 1", fn, incx);
+    if (incy < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 11 (incy=%d) < 1", fn, incy);
+    if ((long)m * n > 0 && !A) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 6 (A) is null", fn);
+    if (n > 0 && m > 0 && !x) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (x) is null", fn);
+    if (m > 0 && !y) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 10 (y) is null", fn);
+    const Span sy = vec_span(y, m, incy);
+    if (overlap(sy, mat_span(A, m, n, lda)) || overlap(sy, vec_span(x, n, incx)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: y overlaps A or x", fn);
+    if (m == 0 || n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    const void* ps[2] = {A, x};
+    const long rows[2] = {m, n}, cols[2] = {n, 1}, lds[2] = {lda, incx};
+    st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 2);
+    if (st != BTAS_OK) return st;
+    hipError_t e = btas::launch_gemv(sr, dt, m, n, A, lda, x, incx, y, incy, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+// ------------------------------------------------------------- level 1 ---
+static btas_status_t vec_binary(btas_handle_t h, const char* fn, int op, btas_semiring_t sr,
+                                btas_dtype_t dt, int n, const void* x, int incx, const void* y,
+                                int incy, void* z, int incz) {
+    btas_status_t st = check_common(h, fn, sr, dt);
+    if (st != BTAS_OK) return st;
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (n=%d) < 0", fn, n);
+    if (incx < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 6 (incx=%d) < 1", fn, incx);
+    if (incy < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (incy=%d) < 1", fn, incy);
+    if (incz < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 10 (incz=%d) < 1", fn, incz);
+    if (n > 0 && (!x || !y || !z)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: null vector pointer", fn);
+    const Span sz = vec_span(z, n, incz);
+    const bool same_x = z == x && incz == incx, same_y = z == y && incz == incy;
+    if ((!same_x && overlap(sz, vec_span(x, n, incx))) || (!same_y && overlap(sz, vec_span(y, n, incy))))
+        return fail(h, BTAS_ERR_ALIAS, "%s: z partially overlaps x or y", fn);
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    if (op == 1) {
+        const void* ps[2] = {x, y};
+        const long rows[2] = {n, n}, cols[2] = {1, 1}, lds[2] = {incx, incy};
+        st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 2);
+        if (st != BTAS_OK) return st;
+    }
+    hipError_t e = btas::launch_vec_binary(op, sr, dt, n, x, incx, y, incy, z, incz, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+btas_status_t btas_tropical_vadd(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                 const void* x, int incx, const void* y, int incy, void* z,
+                                 int incz) {
+    return vec_binary(h, "btas_tropical_vadd", 0, sr, dt, n, x, incx, y, incy, z, incz);
+}
+
+btas_status_t btas_tropical_vmul(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                 const void* x, int incx, const void* y, int incy, void* z,
+                                 int incz) {
+    return vec_binary(h, "btas_tropical_vmul", 1, sr, dt, n, x, incx, y, incy, z, incz);
+}
+
+btas_status_t btas_tropical_dot(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                const void* x, int incx, const void* y, int incy,
+                                void* result_dev) {
+    const char* fn = "btas_tropical_dot";
+    btas_status_t st = check_common(h, fn, sr, dt);
+    if (st != BTAS_OK) return st;
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (n=%d) < 0", fn, n);
+    if (incx < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 6 (incx=%d) < 1", fn, incx);
+    if (incy < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (incy=%d) < 1", fn, incy);
+    if (n > 0 && (!x || !y)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: null vector pointer", fn);
+    if (!result_dev) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (result) is null", fn);
+    DeviceGuard g(h->device);
+    const void* ps[2] = {x, y};
+    const long rows[2] = {n, n}, cols[2] = {1, 1}, lds[2] = {incx, incy};
+    st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 2);
+    if (st != BTAS_OK) return st;
+    hipError_t e = btas::launch_dot(sr, dt, n, x, incx, y, incy, h->partials, result_dev, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                 const void* alpha_host, const void* x, int incx, void* y,
+                                 int incy) {
+    const char* fn = "btas_tropical_axpy";
+    btas_status_t st = check_common(h, fn, sr, dt);
+    if (st != BTAS_OK) return st;
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (n=%d) < 0", fn, n);
+    if (!alpha_host) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (alpha) is null", fn);
+    if (incx < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (incx=%d) < 1", fn, incx);
+    if (incy < 1) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (incy=%d) < 1", fn, incy);
+    if (n > 0 && (!x || !y)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: null vector pointer", fn);
+    if (overlap(vec_span(y, n, incy), vec_span(x, n, incx)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: y overlaps x", fn);
+    uint32_t abits;
+    std::memcpy(&abits, alpha_host, 4);
+    if (h->validate) {
+        // host-side check of the scalar operand
+        bool ok;
+        if (dt == BTAS_FLOAT32) {
+            float a;
+            std::memcpy(&a, &abits, 4);
+            ok = a == a && !(sr == BTAS_MIN_PLUS && a == -__builtin_inff()) &&
+                 !(sr == BTAS_MAX_PLUS && a == __builtin_inff());
+        } else {
+            const int32_t a = (int32_t)abits;
+            const int32_t absent = sr == BTAS_MIN_PLUS ? BTAS_I32_INF : BTAS_I32_NEG_INF;
+            ok = a == absent || (a >= -BTAS_I32_FINITE_MAX && a <= BTAS_I32_FINITE_MAX);
+        }
+        if (!ok) return fail(h, BTAS_ERR_DOMAIN, "%s: alpha is outside the semiring's domain", fn);
+    }
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    const void* ps[1] = {x};
+    const long rows[1] = {n}, cols[1] = {1}, lds[1] = {incx};
+    st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 1);
+    if (st != BTAS_OK) return st;
+    hipError_t e = btas::launch_axpy(sr, dt, n, abits, x, incx, y, incy, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+// ----------------------------------------------------------------- APSP ---
+btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const void* W, int ldw,
+                                 void* D, int ldd, unsigned flags, int* steps_out) {
+    const char* fn = "btas_apsp_squaring";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (steps_out) *steps_out = 0;
+    if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
+    if (ldw < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (ldw=%d) < max(1,n=%d)", fn, ldw, n);
+    if (ldd < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (ldd=%d) < max(1,n=%d)", fn, ldd, n);
+    if (flags & ~(BTAS_APSP_EARLY_EXIT | BTAS_APSP_CHECK_NEG_CYCLE))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (flags=0x%x) has unknown bits", fn, flags);
+    if (n > 0 && (!W || !D)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W or D is null", fn);
+    const bool in_place = W == D && ldw == ldd;
+    if (!in_place && overlap(mat_span(W, n, n, ldw), mat_span(D, n, n, ldd)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: D partially overlaps W", fn);
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    {
+        const void* ps[1] = {W};
+        const long rows[1] = {n}, cols[1] = {n}, lds[1] = {ldw};
+        btas_status_t st = validate_operands(h, fn, BTAS_MIN_PLUS, dt, ps, rows, cols, lds, 1);
+        if (st != BTAS_OK) return st;
+    }
+    const int T = btas_apsp_num_steps(n);
+    const size_t need = (size_t)n * n * 4;
+    if (T > 0 && h->ws_bytes < need) {
+        if (h->ws) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(h->ws);
+            h->ws = nullptr;
+            h->ws_bytes = 0;
+        }
+        if (hipMalloc(&h->ws, need) != hipSuccess)
+            return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
+        h->ws_bytes = need;
+    }
+    const bool early = flags & BTAS_APSP_EARLY_EXIT;
+    // Ping-pong between D and the workspace, starting where an even/odd
+    // number of fixed steps ends in D.
+    void* bufs[2] = {D, h->ws};
+    long lds[2] = {ldd, n};
+    int cur = (T % 2 == 0) ? 0 : 1;
+    hipError_t e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], h->stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    int steps = 0;
+    for (int t = 0; t < T; ++t) {
+        const int nxt = cur ^ 1;
+        if (early) {
+            e = btas::launch_clear_flags(h->dflags, 1, h->stream);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+        }
+        btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
+                         bufs[nxt], lds[nxt], early ? h->dflags : nullptr};
+        e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        ++steps;
+        cur = nxt;
+        if (early) {
+            btas_status_t st = sync_flags(h, fn, 1);
+            if (st != BTAS_OK) return st;
+            if (h->hflags[0] == 0) break;
+        }
+    }
+    if (cur != 0) {
+        e = btas::launch_copy_matrix(n, n, bufs[cur], lds[cur], D, ldd, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+    }
+    btas_status_t result = BTAS_OK;
+    if (flags & BTAS_APSP_CHECK_NEG_CYCLE) {
+        e = btas::launch_clear_flags(h->dflags, 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_neg_diag_check(dt, n, D, ldd, h->dflags, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        btas_status_t st = sync_flags(h, fn, 1);
+        if (st != BTAS_OK) return st;
+        if (h->hflags[0]) result = fail(h, BTAS_WARN_NEG_CYCLE, "%s: negative cycle (some D_ii < 0)", fn);
+    }
+    if (steps_out) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        *steps_out = steps;
+    }
+    return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Small elementwise kernels around the squaring loop: D_0 = I (+) W, flag
+// resets, the negative-cycle check, strided matrix copies and the optional
+// domain scan.  All are O(n^2) and HBM-bound.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "semiring.h"
+
+namespace btas {
+
+// D_0 = I (+) W (Sec. III starts the squaring from the adjacency matrix; the
+// tropical identity puts 0 on the diagonal, so D_ii = min(W_ii, 0)).
+template <typename T>
+__global__ __launch_bounds__(256) void apsp_init_kernel(int n, const T* W, long ldw, T* D,
+                                                         long ldd) {
+    const long total = (long)n * n;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, j = e - i * n;
+        T w = W[i * ldw + j];
+        if (i == j && w > (T)0) w = (T)0;
+        D[i * ldd + j] = w;
+    }
+}
+
+static unsigned blocks_for(long total) {
+    long b = (total + 1023) / 1024;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (unsigned)b;
+}
+
+hipError_t launch_apsp_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
+                            hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = blocks_for((long)n * n);
+    if (dt == BTAS_FLOAT32)
+        hipLaunchKernelGGL(apsp_init_kernel<float>, dim3(g), dim3(256), 0, s, n, (const float*)W,
+                           ldw, (float*)dst, ldd);
+    else
+        hipLaunchKernelGGL(apsp_init_kernel<int32_t>, dim3(g), dim3(256), 0, s, n,
+                           (const int32_t*)W, ldw, (int32_t*)dst, ldd);
+    return hipGetLastError();
+}
+
+__global__ void clear_flags_kernel(int* flag, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) flag[i] = 0;
+}
+
+hipError_t launch_clear_flags(int* flag, int count, hipStream_t s) {
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, s, flag, count);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void neg_diag_kernel(int n, const T* D, long ldd, int* flag) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (D[(long)i * ldd + i] < (T)0) *flag = 1;
+}
+
+hipError_t launch_neg_diag_check(int dt, int n, const void* D, long ldd, int* flag,
+                                 hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (dt == BTAS_FLOAT32)
+        hipLaunchKernelGGL(neg_diag_kernel<float>, dim3(g), dim3(256), 0, s, n, (const float*)D,
+                           ldd, flag);
+    else
+        hipLaunchKernelGGL(neg_diag_kernel<int32_t>, dim3(g), dim3(256), 0, s, n,
+                           (const int32_t*)D, ldd, flag);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void copy_matrix_kernel(int m, int n, const uint32_t* src,
+                                                           long lds, uint32_t* dst, long ldd) {
+    const long total = (long)m * n;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, j = e - i * n;
+        dst[i * ldd + j] = src[i * lds + j];
+    }
+}
+
+hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst, long ldd,
+                              hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_matrix_kernel, dim3(blocks_for((long)m * n)), dim3(256), 0, s, m, n,
+                       (const uint32_t*)src, lds, (uint32_t*)dst, ldd);
+    return hipGetLastError();
+}
+
+// Legal (.) operands: the semiring's absent value or a finite value within
+// +-BTAS_I32_FINITE_MAX (int32); anything but NaN and the other infinity
+// (float32).
+template <typename T, int SR>
+__device__ __forceinline__ bool operand_ok(T x);
+
+template <>
+__device__ __forceinline__ bool operand_ok<int32_t, BTAS_MIN_PLUS>(int32_t x) {
+    return x == BTAS_I32_INF || (x >= -BTAS_I32_FINITE_MAX && x <= BTAS_I32_FINITE_MAX);
+}
+template <>
+__device__ __forceinline__ bool operand_ok<int32_t, BTAS_MAX_PLUS>(int32_t x) {
+    return x == BTAS_I32_NEG_INF || (x >= -BTAS_I32_FINITE_MAX && x <= BTAS_I32_FINITE_MAX);
+}
+template <>
+__device__ __forceinline__ bool operand_ok<float, BTAS_MIN_PLUS>(float x) {
+    return !(x != x) && x != -__builtin_inff();
+}
+template <>
+__device__ __forceinline__ bool operand_ok<float, BTAS_MAX_PLUS>(float x) {
+    return !(x != x) && x != __builtin_inff();
+}
+
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void domain_scan_kernel(int m, int n, const T* X, long ld,
+                                                           int* flag) {
+    const long total = (long)m * n;
+    bool bad = false;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, j = e - i * n;
+        bad |= !operand_ok<T, SR>(X[i * ld + j]);
+    }
+    if (bad) *flag = 1;
+}
+
+hipError_t launch_domain_scan(int sr, int dt, int m, int n, const void* X, long ld, int* flag,
+                              hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    const dim3 g(blocks_for((long)m * n)), b(256);
+    if (dt == BTAS_FLOAT32) {
+        if (sr == BTAS_MIN_PLUS)
+            hipLaunchKernelGGL((domain_scan_kernel<float, 0>), g, b, 0, s, m, n, (const float*)X,
+                               ld, flag);
+        else
+            hipLaunchKernelGGL((domain_scan_kernel<float, 1>), g, b, 0, s, m, n, (const float*)X,
+                               ld, flag);
+    } else {
+        if (sr == BTAS_MIN_PLUS)
+            hipLaunchKernelGGL((domain_scan_kernel<int32_t, 0>), g, b, 0, s, m, n,
+                               (const int32_t*)X, ld, flag);
+        else
+            hipLaunchKernelGGL((domain_scan_kernel<int32_t, 1>), g, b, 0, s, m, n,
+                               (const int32_t*)X, ld, flag);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace btas

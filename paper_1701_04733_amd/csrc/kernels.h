@@ -1,0 +1,64 @@
+// Host-side launchers of the tropical kernels (internal to libbtas).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "btas.h"
+
+namespace btas {
+
+// Cout <- Cin (+) A (.) B ; `changed` (device int, may be null) is set to 1
+// when some output differs bitwise from its Cin value.
+struct GemmArgs {
+    int m, n, k;
+    const void* A;
+    long lda;
+    const void* B;
+    long ldb;
+    const void* Cin;
+    long ldci;
+    void* Cout;
+    long ldco;
+    int* changed;
+};
+
+enum { GEMM_CFG_L = 0, GEMM_CFG_M = 1, GEMM_CFG_S = 2, GEMM_NUM_CFGS = 3 };
+
+int pick_gemm_cfg(int m, int n, int k);
+hipError_t launch_gemm(int sr, int dt, const GemmArgs& a, int cfg, hipStream_t s);
+
+// y <- y (+) A (.) x
+hipError_t launch_gemv(int sr, int dt, int m, int n, const void* A, long lda, const void* x,
+                       long incx, void* y, long incy, hipStream_t s);
+
+// Level 1.  op: 0 = vadd (z = x (+) y), 1 = vmul (z = x (.) y).
+hipError_t launch_vec_binary(int op, int sr, int dt, int n, const void* x, long incx,
+                             const void* y, long incy, void* z, long incz, hipStream_t s);
+// y <- y (+) alpha (.) x ; alpha passed by bits.
+hipError_t launch_axpy(int sr, int dt, int n, uint32_t alpha_bits, const void* x, long incx,
+                       void* y, long incy, hipStream_t s);
+// result <- (+)_i x_i (.) y_i via a two-pass reduction through `partials`
+// (at least dot_partials_needed(n) elements of 4 bytes).
+int dot_partials_needed(int n);
+hipError_t launch_dot(int sr, int dt, int n, const void* x, long incx, const void* y, long incy,
+                      void* partials, void* result, hipStream_t s);
+
+// APSP helpers.
+// dst <- I (+) W  (copy with dst_ii = min(W_ii, 0)); dst may equal W.
+hipError_t launch_apsp_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
+                            hipStream_t s);
+// flag[0..count) <- 0 (a kernel, not a memset, so it is safe inside graphs).
+hipError_t launch_clear_flags(int* flag, int count, hipStream_t s);
+// flag <- 1 if some D_ii < 0.
+hipError_t launch_neg_diag_check(int dt, int n, const void* D, long ldd, int* flag,
+                                 hipStream_t s);
+// Copy an n-column, m-row matrix between leading dimensions (4-byte elements).
+hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst, long ldd,
+                              hipStream_t s);
+// Domain scan (BTAS_VALIDATE=1): flag <- 1 if some element of the m x n matrix
+// is not a legal (.) operand of the semiring.
+hipError_t launch_domain_scan(int sr, int dt, int m, int n, const void* X, long ld, int* flag,
+                              hipStream_t s);
+
+}  // namespace btas

@@ -1,0 +1,248 @@
+// Tropical level-2 (gemv) and level-1 (vadd, vmul, axpy, dot) kernels.
+//
+// "Standard vector and matrix operations" of the library (Abstract; Sec. III)
+// over the semirings of Sec. I, eqs. (1)-(4).  All of these are HBM-bound
+// (at most one (.) and one (+) per element loaded), so the design goal is
+// coalesced 128-bit streaming: one wave per output row for gemv with the
+// vector x re-read from cache, grid-stride elementwise loops for level 1 and
+// a deterministic two-pass reduction for dot (min/max are exact, so the
+// reduction order never changes the bits).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "semiring.h"
+
+namespace btas {
+
+template <typename T>
+using v4 = T __attribute__((ext_vector_type(4)));
+
+template <typename T, int SR>
+__device__ __forceinline__ T wave_reduce(T v) {
+    using R = Ring<SR, T>;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = R::add(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------- gemv ---
+// One wave per row of A: y_i <- y_i (+) (+)_j a_ij (.) x_j.
+template <typename T, int SR, bool VEC>
+__global__ __launch_bounds__(256) void tropical_gemv_kernel(int m, int n,
+                                                             const T* __restrict__ A, long lda,
+                                                             const T* __restrict__ x, long incx,
+                                                             T* __restrict__ y, long incy) {
+    using R = Ring<SR, T>;
+    const int lane = threadIdx.x & 63;
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const T* a = A + row * lda;
+    T acc = R::absent();
+    int j0 = 0;
+    if (VEC) {
+        const int nv = n / 4;
+        const v4<T>* a4 = reinterpret_cast<const v4<T>*>(a);
+        const v4<T>* x4 = reinterpret_cast<const v4<T>*>(x);
+        for (int v = lane; v < nv; v += 64) {
+            const v4<T> av = __builtin_nontemporal_load(a4 + v);
+            const v4<T> xv = x4[v];
+            acc = R::add3(acc, R::mul(av[0], xv[0]), R::mul(av[1], xv[1]));
+            acc = R::add3(acc, R::mul(av[2], xv[2]), R::mul(av[3], xv[3]));
+        }
+        j0 = nv * 4;
+    }
+    for (int j = j0 + lane; j < n; j += 64) acc = R::add(acc, R::mul(a[j], x[(long)j * incx]));
+    acc = wave_reduce<T, SR>(acc);
+    if (lane == 0) y[row * incy] = R::add(y[row * incy], R::finish(acc));
+}
+
+template <typename T, int SR>
+static hipError_t gemv_typed(int m, int n, const void* A, long lda, const void* x, long incx,
+                             void* y, long incy, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    const bool vec = incx == 1 && lda % 4 == 0 && (((uintptr_t)A | (uintptr_t)x) % 16 == 0);
+    dim3 grid((unsigned)((m + 3) / 4)), block(256);
+    if (vec)
+        hipLaunchKernelGGL((tropical_gemv_kernel<T, SR, true>), grid, block, 0, s, m, n,
+                           (const T*)A, lda, (const T*)x, incx, (T*)y, incy);
+    else
+        hipLaunchKernelGGL((tropical_gemv_kernel<T, SR, false>), grid, block, 0, s, m, n,
+                           (const T*)A, lda, (const T*)x, incx, (T*)y, incy);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv(int sr, int dt, int m, int n, const void* A, long lda, const void* x,
+                       long incx, void* y, long incy, hipStream_t s) {
+    if (dt == BTAS_FLOAT32)
+        return sr == BTAS_MIN_PLUS
+                   ? gemv_typed<float, BTAS_MIN_PLUS>(m, n, A, lda, x, incx, y, incy, s)
+                   : gemv_typed<float, BTAS_MAX_PLUS>(m, n, A, lda, x, incx, y, incy, s);
+    return sr == BTAS_MIN_PLUS
+               ? gemv_typed<int32_t, BTAS_MIN_PLUS>(m, n, A, lda, x, incx, y, incy, s)
+               : gemv_typed<int32_t, BTAS_MAX_PLUS>(m, n, A, lda, x, incx, y, incy, s);
+}
+
+// ------------------------------------------------------------- level 1 ---
+static inline unsigned grid_for(long n, int per_thread) {
+    long blocks = (n + 256L * per_thread - 1) / (256L * per_thread);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    return (unsigned)blocks;
+}
+
+template <typename T, int SR, int OP>
+__global__ __launch_bounds__(256) void tropical_vec_binary_kernel(long n, const T* x, long incx,
+                                                                   const T* y, long incy, T* z,
+                                                                   long incz) {
+    using R = Ring<SR, T>;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const T a = x[i * incx], b = y[i * incy];
+        z[i * incz] = OP == 0 ? R::add(a, b) : R::finish(R::mul(a, b));
+    }
+}
+
+template <typename T, int SR, int OP>
+__global__ __launch_bounds__(256) void tropical_vec_binary_v4_kernel(long nv, const v4<T>* x,
+                                                                      const v4<T>* y,
+                                                                      v4<T>* z) {
+    using R = Ring<SR, T>;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
+         i += (long)gridDim.x * blockDim.x) {
+        const v4<T> a = __builtin_nontemporal_load(x + i), b = __builtin_nontemporal_load(y + i);
+        v4<T> r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = OP == 0 ? R::add(a[e], b[e]) : R::finish(R::mul(a[e], b[e]));
+        __builtin_nontemporal_store(r, z + i);
+    }
+}
+
+template <typename T, int SR, int OP>
+static hipError_t vec_binary_typed(long n, const void* x, long incx, const void* y, long incy,
+                                   void* z, long incz, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const bool vec = incx == 1 && incy == 1 && incz == 1 &&
+                     (((uintptr_t)x | (uintptr_t)y | (uintptr_t)z) % 16 == 0);
+    long head = 0;
+    if (vec) {
+        const long nv = n / 4;
+        if (nv > 0)
+            hipLaunchKernelGGL((tropical_vec_binary_v4_kernel<T, SR, OP>), dim3(grid_for(nv, 4)),
+                               dim3(256), 0, s, nv, (const v4<T>*)x, (const v4<T>*)y,
+                               (v4<T>*)z);
+        head = nv * 4;
+    }
+    if (head < n)
+        hipLaunchKernelGGL((tropical_vec_binary_kernel<T, SR, OP>), dim3(grid_for(n - head, 4)),
+                           dim3(256), 0, s, n - head, (const T*)x + head * incx, incx,
+                           (const T*)y + head * incy, incy, (T*)z + head * incz, incz);
+    return hipGetLastError();
+}
+
+hipError_t launch_vec_binary(int op, int sr, int dt, int n, const void* x, long incx,
+                             const void* y, long incy, void* z, long incz, hipStream_t s) {
+#define BTAS_VB(T, SRV, OPV) vec_binary_typed<T, SRV, OPV>(n, x, incx, y, incy, z, incz, s)
+    if (dt == BTAS_FLOAT32) {
+        if (sr == BTAS_MIN_PLUS) return op == 0 ? BTAS_VB(float, 0, 0) : BTAS_VB(float, 0, 1);
+        return op == 0 ? BTAS_VB(float, 1, 0) : BTAS_VB(float, 1, 1);
+    }
+    if (sr == BTAS_MIN_PLUS) return op == 0 ? BTAS_VB(int32_t, 0, 0) : BTAS_VB(int32_t, 0, 1);
+    return op == 0 ? BTAS_VB(int32_t, 1, 0) : BTAS_VB(int32_t, 1, 1);
+#undef BTAS_VB
+}
+
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void tropical_axpy_kernel(long n, T alpha, const T* x,
+                                                             long incx, T* y, long incy) {
+    using R = Ring<SR, T>;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        y[i * incy] = R::add(y[i * incy], R::finish(R::mul(alpha, x[i * incx])));
+}
+
+hipError_t launch_axpy(int sr, int dt, int n, uint32_t alpha_bits, const void* x, long incx,
+                       void* y, long incy, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    dim3 g(grid_for(n, 4)), b(256);
+    if (dt == BTAS_FLOAT32) {
+        const float a = __builtin_bit_cast(float, alpha_bits);
+        if (sr == BTAS_MIN_PLUS)
+            hipLaunchKernelGGL((tropical_axpy_kernel<float, 0>), g, b, 0, s, (long)n, a,
+                               (const float*)x, incx, (float*)y, incy);
+        else
+            hipLaunchKernelGGL((tropical_axpy_kernel<float, 1>), g, b, 0, s, (long)n, a,
+                               (const float*)x, incx, (float*)y, incy);
+    } else {
+        const int32_t a = (int32_t)alpha_bits;
+        if (sr == BTAS_MIN_PLUS)
+            hipLaunchKernelGGL((tropical_axpy_kernel<int32_t, 0>), g, b, 0, s, (long)n, a,
+                               (const int32_t*)x, incx, (int32_t*)y, incy);
+        else
+            hipLaunchKernelGGL((tropical_axpy_kernel<int32_t, 1>), g, b, 0, s, (long)n, a,
+                               (const int32_t*)x, incx, (int32_t*)y, incy);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dot ---
+static constexpr int DOT_MAX_BLOCKS = 1024;
+
+int dot_partials_needed(int /*n*/) { return DOT_MAX_BLOCKS; }
+
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void tropical_dot_partial_kernel(long n, const T* x, long incx,
+                                                                    const T* y, long incy,
+                                                                    T* partials) {
+    using R = Ring<SR, T>;
+    __shared__ T red[4];
+    T acc = R::absent();
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        acc = R::add(acc, R::mul(x[i * incx], y[i * incy]));
+    acc = wave_reduce<T, SR>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = R::add(R::add(red[0], red[1]), R::add(red[2], red[3]));
+}
+
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void tropical_dot_final_kernel(int np, const T* partials,
+                                                                  T* result) {
+    using R = Ring<SR, T>;
+    __shared__ T red[4];
+    T acc = R::absent();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc = R::add(acc, partials[i]);
+    acc = wave_reduce<T, SR>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *result = R::finish(R::add(R::add(red[0], red[1]), R::add(red[2], red[3])));
+}
+
+template <typename T, int SR>
+static hipError_t dot_typed(int n, const void* x, long incx, const void* y, long incy,
+                            void* partials, void* result, hipStream_t s) {
+    int blocks = 0;
+    if (n > 0) {
+        blocks = (int)grid_for(n, 8);
+        if (blocks > DOT_MAX_BLOCKS) blocks = DOT_MAX_BLOCKS;
+        hipLaunchKernelGGL((tropical_dot_partial_kernel<T, SR>), dim3(blocks), dim3(256), 0, s,
+                           (long)n, (const T*)x, incx, (const T*)y, incy, (T*)partials);
+    }
+    hipLaunchKernelGGL((tropical_dot_final_kernel<T, SR>), dim3(1), dim3(256), 0, s, blocks,
+                       (const T*)partials, (T*)result);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(int sr, int dt, int n, const void* x, long incx, const void* y, long incy,
+                      void* partials, void* result, hipStream_t s) {
+    if (dt == BTAS_FLOAT32)
+        return sr == BTAS_MIN_PLUS
+                   ? dot_typed<float, 0>(n, x, incx, y, incy, partials, result, s)
+                   : dot_typed<float, 1>(n, x, incx, y, incy, partials, result, s);
+    return sr == BTAS_MIN_PLUS ? dot_typed<int32_t, 0>(n, x, incx, y, incy, partials, result, s)
+                               : dot_typed<int32_t, 1>(n, x, incx, y, incy, partials, result, s);
+}
+
+}  // namespace btas

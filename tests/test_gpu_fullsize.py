@@ -1,0 +1,78 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times.  The oracle cannot redo these products in seconds, so it
+checks sampled outputs one row at a time (8192^3 GEMM), or properties that
+hold at any size plus single-source references (n=16384 APSP)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SEED_A, SEED_B = 2, 3
+
+
+def _bits(x):
+    x = np.ascontiguousarray(x).copy()
+    if x.dtype == np.float32:
+        x[x == 0] = 0.0
+    return x.view(np.uint32)
+
+
+@pytest.mark.parametrize("dt", ["f32", "i32"])
+@pytest.mark.parametrize("sr", ["min", "max"])
+def test_gemm_8192_sampled_rows(dev, sr, dt):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    n = 8192
+    A = wl.gemm_operand((n, n), dt, sr, seed=SEED_A)
+    B = wl.gemm_operand((n, n), dt, sr, seed=SEED_B)
+    C = wl.semiring_identity_matrix((n, n), dt, sr)
+    tA, tB, tC = (torch.from_numpy(x).to(dev) for x in (A, B, C))
+    btas.tropical_gemm(tA, tB, tC, semiring=sr)
+    rows = [0, 1, 127, 128, 4095, 5000, 8190, 8191]
+    got = tC[rows].cpu().numpy()
+    want = oracle.gemm(sr, A[rows], B, C[rows])
+    for i, r in enumerate(rows):
+        assert np.array_equal(_bits(got[i]), _bits(want[i])), f"row {r}"
+    # a column sample too (transposes the roles of the tiles)
+    cols = [0, 4097, 8191]
+    gotc = tC[:, cols].cpu().numpy()
+    sample_rows = np.arange(0, n, 97)
+    for j, c in enumerate(cols):
+        want = oracle.gemm(sr, A[sample_rows], B[:, c:c + 1].copy(), C[sample_rows, c:c + 1].copy())[:, 0]
+        assert np.array_equal(_bits(gotc[sample_rows, j]), _bits(want)), f"col {c}"
+
+
+def test_apsp_16384_f32_properties(dev):
+    """n=16384, mean out-degree 16, exponential(1) weights, early exit."""
+    import torch
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra
+
+    import paper_1701_04733_amd as btas
+    n = 16384
+    r, c, w = wl.sparse_digraph_f32_exp(n, 16.0, seed=4)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    tW = torch.from_numpy(W).to(dev)
+    del W
+    D, steps, _ = btas.apsp(tW, early_exit=True)
+    T = oracle.apsp_steps(n)
+    assert 1 <= steps <= T
+    assert (torch.diagonal(D) == 0).all()
+    sources = [0, 1, 8191, 16383]
+    rows = D[sources].cpu().numpy().astype(np.float64)
+    G = csr_matrix((w.astype(np.float64), (r, c)), shape=(n, n))
+    exact = dijkstra(G, directed=True, indices=sources)
+    fin = np.isfinite(exact)
+    assert np.array_equal(fin, np.isfinite(rows))
+    u = 2.0 ** -24
+    assert np.all(rows[fin] <= exact[fin] * (1 + u) ** T)
+    assert np.all(rows[fin] >= exact[fin] * (1 - u) ** T)
+    # Early exit fired before T, so D is a fixpoint: D_i (+) D_i (.) D == D_i exactly.
+    if steps < T:
+        Dn = D.cpu().numpy()
+        again = oracle.gemm("min", Dn[sources], Dn, Dn[sources])
+        assert np.array_equal(_bits(again), _bits(Dn[sources]))

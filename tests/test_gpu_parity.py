@@ -1,0 +1,322 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element on the same seeded inputs.  The bar is bit equality for
+both int32 and float32 (each float32 term is one rounded add and min/max are
+exact, so there is nothing for a tolerance to absorb); the only
+normalisation is -0 -> +0 before comparing float bits.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SR = ["min", "max"]
+DT = ["i32", "f32"]
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def btas(dev):
+    import paper_1701_04733_amd as b
+    b.lib()
+    return b
+
+
+def to_dev(x, dev):
+    torch = torch_mod()
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def to_np(t):
+    torch = torch_mod()
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def bits(x):
+    x = np.ascontiguousarray(x)
+    if x.dtype == np.float32:
+        y = x.copy()
+        y[y == 0] = 0.0                                   # -0 -> +0
+        return y.view(np.uint32)
+    return x.view(np.uint32)
+
+
+def assert_same(got, want, what=""):
+    gb, wb = bits(got), bits(want)
+    if not np.array_equal(gb, wb):
+        bad = np.argwhere(gb != wb)
+        i = tuple(bad[0])
+        raise AssertionError(f"{what}: {len(bad)} mismatches; first at {i}: got {got[i]!r} want {want[i]!r}")
+
+
+def operands(m, n, k, dt, sr, seed, frac=0.1, signed=False):
+    gen = wl.signed_operand if signed else wl.gemm_operand
+    A = gen((m, k), dt, sr, seed=seed, inf_frac=frac)
+    B = gen((k, n), dt, sr, seed=seed + 1, inf_frac=frac)
+    return A, B
+
+
+SHAPES = [(1, 1, 1), (2, 3, 1), (3, 7, 2), (7, 31, 65), (31, 64, 127), (64, 64, 64),
+          (65, 127, 129), (127, 129, 257), (129, 257, 31), (257, 65, 1000), (300, 290, 77)]
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gemm_shapes(btas, dev, sr, dt, shape):
+    m, n, k = shape
+    A, B = operands(m, n, k, dt, sr, seed=1000 + m + n + k, signed=True)
+    C = wl.signed_operand((m, n), dt, sr, seed=7 + m, inf_frac=0.3)
+    want = oracle.gemm(sr, A, B, C)
+    Ct = to_dev(C, dev)
+    btas.tropical_gemm(to_dev(A, dev), to_dev(B, dev), Ct, semiring=sr)
+    assert_same(to_np(Ct), want, f"{sr}/{dt}/{shape}")
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("frac", [0.0, 0.1, 1.0])
+def test_gemm_large_tiles_ragged(btas, dev, sr, dt, frac):
+    """Shape large enough for the 128x128 tiling, with ragged m, n and k."""
+    m, n, k = 2945, 2890, 133
+    A, B = operands(m, n, k, dt, sr, seed=77, frac=frac)
+    C = wl.semiring_identity_matrix((m, n), dt, sr)
+    want = oracle.gemm(sr, A, B, C)
+    Ct = to_dev(C, dev)
+    btas.tropical_gemm(to_dev(A, dev), to_dev(B, dev), Ct, semiring=sr)
+    assert_same(to_np(Ct), want, f"{sr}/{dt}/frac={frac}")
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_leading_dimensions_and_alignment(btas, dev, sr, dt):
+    """Sub-views with padded rows, including leading dimensions that are not a
+    multiple of 4 elements and base pointers only 4-byte aligned."""
+    torch = torch_mod()
+    m, n, k = 70, 45, 53
+    bigA = wl.signed_operand((m + 3, k + 7), dt, sr, seed=5)
+    bigB = wl.signed_operand((k + 2, n + 9), dt, sr, seed=6)
+    bigC = wl.signed_operand((m + 1, n + 5), dt, sr, seed=8, inf_frac=0.5)
+    A, B, C = bigA[1:1 + m, 3:3 + k], bigB[2:2 + k, 1:1 + n], bigC[1:1 + m, 1:1 + n]
+    want = oracle.gemm(sr, A.copy(), B.copy(), C.copy())
+    tA, tB, tC = to_dev(bigA, dev), to_dev(bigB, dev), to_dev(bigC, dev)
+    vC = tC[1:1 + m, 1:1 + n]
+    btas.tropical_gemm(tA[1:1 + m, 3:3 + k], tB[2:2 + k, 1:1 + n], vC, semiring=sr)
+    got = to_np(tC)
+    assert_same(got[1:1 + m, 1:1 + n], want, "view")
+    # the padding around C is untouched
+    mask = np.ones(got.shape, bool)
+    mask[1:1 + m, 1:1 + n] = False
+    assert np.array_equal(bits(got)[mask], bits(bigC)[mask])
+    del torch
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_degenerate_sizes(btas, dev, sr, dt):
+    torch = torch_mod()
+    C = wl.signed_operand((5, 4), dt, sr, seed=3)
+    Ct = to_dev(C, dev)
+    A = to_dev(np.zeros((5, 0), C.dtype), dev)
+    B = to_dev(np.zeros((0, 4), C.dtype), dev)
+    btas.tropical_gemm(A, B, Ct, semiring=sr)                # k = 0: C unchanged
+    assert_same(to_np(Ct), C, "k=0")
+    E = to_dev(np.zeros((0, 4), C.dtype), dev)
+    btas.tropical_gemm(to_dev(np.zeros((0, 3), C.dtype), dev),
+                       to_dev(np.zeros((3, 4), C.dtype), dev), E, semiring=sr)  # m = 0
+    del torch
+
+
+def test_gemm_determinism_and_identity(btas, dev):
+    torch = torch_mod()
+    n = 515
+    A = wl.signed_operand((n, n), "f32", "min", seed=9)
+    I = np.full((n, n), np.inf, np.float32)
+    np.fill_diagonal(I, 0)
+    tA, tI = to_dev(A, dev), to_dev(I, dev)
+    outs = [to_np(btas.tropical_gemm(tA, tI, semiring="min")) for _ in range(5)]
+    for o in outs:
+        assert_same(o, A, "A (.) I")
+    outs = [to_np(btas.tropical_gemm(tI, tA, semiring="min")) for _ in range(3)]
+    for o in outs:
+        assert_same(o, A, "I (.) A")
+    del torch
+
+
+def test_gemm_errors(btas, dev):
+    torch = torch_mod()
+    A = torch.zeros((8, 8), dtype=torch.int32, device=dev)
+    with pytest.raises(btas.BtasError, match="ALIAS"):
+        btas.tropical_gemm(A, A, A)
+    with pytest.raises(btas.BtasError, match="ALIAS"):
+        btas.tropical_gemm(A[:4], A[:, :4], A[4:, 4:])
+    h = btas.default_handle()
+    L = btas.lib()
+    st = L.btas_tropical_gemm(h.ptr, 0, 0, 4, 4, 4, A.data_ptr(), 3, A.data_ptr(), 8,
+                              A.data_ptr() + 256, 8)
+    assert st == 1 and b"lda" in L.btas_last_error(h.ptr)
+    st = L.btas_tropical_gemm(h.ptr, 5, 0, 4, 4, 4, A.data_ptr(), 4, A.data_ptr(), 4, None, 4)
+    assert st == 1 and b"semiring" in L.btas_last_error(h.ptr)
+    st = L.btas_tropical_gemm(h.ptr, 0, 0, -1, 4, 4, None, 4, None, 4, None, 4)
+    assert st == 1 and b"m=-1" in L.btas_last_error(h.ptr)
+
+
+# ------------------------------------------------------- gemv / level 1 ---
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("mn", [(1, 1), (5, 3), (64, 257), (1000, 999), (333, 4096)])
+def test_gemv(btas, dev, sr, dt, mn):
+    m, n = mn
+    A = wl.signed_operand((m, n), dt, sr, seed=m)
+    x = wl.signed_operand((n,), dt, sr, seed=n + 1)
+    y = wl.signed_operand((m,), dt, sr, seed=3, inf_frac=0.3)
+    want = oracle.gemv(sr, A, x, y)
+    ty = to_dev(y, dev)
+    btas.tropical_gemv(to_dev(A, dev), to_dev(x, dev), ty, semiring=sr)
+    assert_same(to_np(ty), want, "gemv")
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemv_strided(btas, dev, sr, dt):
+    m, n = 77, 91
+    A = wl.signed_operand((m, n + 3), dt, sr, seed=1)
+    x = wl.signed_operand((2 * n,), dt, sr, seed=2)
+    y = wl.signed_operand((3 * m,), dt, sr, seed=3)
+    want = y.copy()
+    want[::3] = oracle.gemv(sr, A[:, :n].copy(), x[::2].copy(), y[::3].copy())
+    tA, tx, ty = to_dev(A, dev), to_dev(x, dev), to_dev(y, dev)
+    btas.tropical_gemv(tA[:, :n], tx[::2], ty[::3], semiring=sr)
+    assert_same(to_np(ty), want, "strided gemv")
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("n", [0, 1, 3, 1023, 100003])
+def test_level1(btas, dev, sr, dt, n):
+    torch = torch_mod()
+    x = wl.signed_operand((n,), dt, sr, seed=n + 5)
+    y = wl.signed_operand((n,), dt, sr, seed=n + 6)
+    tx, ty = to_dev(x, dev), to_dev(y, dev)
+    assert_same(to_np(btas.vadd(tx, ty, semiring=sr)), oracle.vadd(sr, x, y), "vadd")
+    assert_same(to_np(btas.vmul(tx, ty, semiring=sr)), oracle.vmul(sr, x, y), "vmul")
+    d = to_np(btas.dot(tx, ty, semiring=sr))[0]
+    assert_same(np.array([d]), np.array([oracle.dot(sr, x, y)], dtype=x.dtype), "dot")
+    alpha = 17 if dt == "i32" else 0.625
+    ty2 = to_dev(y, dev)
+    btas.axpy(alpha, tx, ty2, semiring=sr)
+    assert_same(to_np(ty2), oracle.axpy(sr, alpha, x, y), "axpy")
+    if n > 4:
+        # strided views
+        z = torch.empty(n // 2, dtype=tx.dtype, device=dev)
+        btas.vmul(tx[::2][: n // 2], ty[1::2][: n // 2], z, semiring=sr)
+        assert_same(to_np(z), oracle.vmul(sr, x[::2][: n // 2].copy(), y[1::2][: n // 2].copy()), "vmul strided")
+
+
+# ----------------------------------------------------------------- APSP ---
+
+def test_apsp_small_config_golden(btas, dev):
+    """n=256 ER digraph (p=0.05, weights U{1..100}, seed 1), T=8 squarings."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "apsp_er256.json")))
+    W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)
+    assert hashlib.sha256(W.tobytes()).hexdigest() == gold["apsp_er256_i32_seed1"]["input_sha256"]
+    D, steps, _ = btas.apsp(to_dev(W, dev))
+    Dn = to_np(D)
+    assert steps == 8
+    assert hashlib.sha256(Dn.tobytes()).hexdigest() == gold["apsp_er256_i32_seed1"]["D_sha256"]
+    want, _, _ = oracle.apsp(W)
+    assert_same(Dn, want, "apsp n=256")
+    D2, steps2, _ = btas.apsp(to_dev(W, dev), early_exit=True)
+    assert steps2 == gold["apsp_er256_i32_seed1_early_exit"]["steps"]
+    assert_same(to_np(D2), want, "apsp n=256 early exit")
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 16, 32, 64, 128, 200, 201, 512])
+def test_apsp_sizes(btas, dev, dt, n):
+    Wi = wl.er_digraph_i32(n, min(1.0, 3.0 / n), 1, 1000, seed=n)
+    if dt == "f32":
+        g = wl.rng(n + 1)
+        W = np.where(Wi == wl.I32_INF, np.inf, g.exponential(1.0, (n, n))).astype(np.float32)
+        np.fill_diagonal(W, 0)
+    else:
+        W = Wi
+    want, wsteps, _ = oracle.apsp(W)
+    D, steps, _ = btas.apsp(to_dev(W, dev))
+    assert steps == wsteps
+    assert_same(to_np(D), want, f"apsp {dt} n={n}")
+    want_e, wsteps_e, _ = oracle.apsp(W, early_exit=True)
+    D, steps, _ = btas.apsp(to_dev(W, dev), early_exit=True)
+    assert steps == wsteps_e
+    assert_same(to_np(D), want_e, f"apsp early {dt} n={n}")
+    assert_same(want_e, want, "early == fixed")
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_apsp_in_place_and_padded(btas, dev, dt):
+    torch = torch_mod()
+    n = 133
+    Wi = wl.er_digraph_i32(n, 0.05, 1, 50, seed=11)
+    W = Wi if dt == "i32" else np.where(Wi == wl.I32_INF, np.inf, Wi * 0.3).astype(np.float32)
+    want, _, _ = oracle.apsp(W)
+    t = to_dev(W, dev)
+    btas.apsp(t, out=t)                                    # in place, T = 8 (even)
+    assert_same(to_np(t), want, "in place")
+    n2 = 100                                               # T = 7 (odd)
+    W2 = W[:n2, :n2].copy()
+    want2, _, _ = oracle.apsp(W2)
+    big = torch.full((n2, n2 + 5), 7, dtype=t.dtype, device=dev)
+    big[:, :n2] = to_dev(W2, dev)
+    out = torch.zeros((n2 + 1, n2 + 3), dtype=t.dtype, device=dev)
+    btas.apsp(big[:, :n2], out=out[:n2, :n2])
+    assert_same(to_np(out)[:n2, :n2], want2, "padded")
+    in_place_pad = big[:, :n2]
+    btas.apsp(in_place_pad, out=in_place_pad)
+    assert_same(to_np(big)[:, :n2], want2, "padded in place")
+
+
+def test_apsp_neg_cycle_and_errors(btas, dev):
+    INF = wl.I32_INF
+    W = np.array([[0, 1, INF], [-3, 0, INF], [INF, 2, 0]], np.int32)
+    _, _, st = btas.apsp(to_dev(W, dev), check_neg_cycle=True)
+    assert st == btas.WARN_NEG_CYCLE
+    _, _, st = btas.apsp(to_dev(np.abs(W), dev), check_neg_cycle=True)
+    assert st == btas.OK
+    torch = torch_mod()
+    M = torch.zeros((8, 9), dtype=torch.int32, device=dev)
+    with pytest.raises(btas.BtasError, match="ALIAS"):
+        btas.apsp(M[:, :8], out=M[:, 1:9])
+
+
+def test_validate_mode_detects_domain(btas, dev, monkeypatch):
+    """BTAS_VALIDATE=1 handles reject out-of-domain operands before writing."""
+    torch = torch_mod()
+    monkeypatch.setenv("BTAS_VALIDATE", "1")
+    h = btas.Handle(0)
+    h.bind_stream()
+    A = torch.zeros((4, 4), dtype=torch.int32, device=dev)
+    A[1, 2] = (1 << 29)                                     # one past the bound
+    B = torch.zeros((4, 4), dtype=torch.int32, device=dev)
+    C = torch.full((4, 4), 5, dtype=torch.int32, device=dev)
+    with pytest.raises(btas.BtasError, match="DOMAIN"):
+        btas.tropical_gemm(A, B, C, handle=h)
+    assert (C == 5).all()
+    A[1, 2] = btas.I32_INF
+    btas.tropical_gemm(A, B, C, handle=h)
+    F = torch.zeros((3, 3), dtype=torch.float32, device=dev)
+    F[0, 0] = float("nan")
+    with pytest.raises(btas.BtasError, match="DOMAIN"):
+        btas.tropical_gemm(F, F.clone(), torch.zeros_like(F), handle=h)
+    h.close()
