@@ -31,11 +31,15 @@ if ROOT not in sys.path:
 N = 8192
 VARIANTS = [("min", "f32"), ("max", "f32"), ("min", "i32"), ("max", "i32")]
 
-# MI355X: 256 CUs x 64 VALU lanes per clock (4 SIMD16) x 2.4 GHz peak engine clock.
-CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
-LANE_INSTR_PER_S = CUS * LANES * CLOCK_HZ            # 39.32e12
-INSTR_PER_TERM = 1.5                                  # 1 add per term + 1 three-input min per 2 terms
-PEAK_TOPS = LANE_INSTR_PER_S / INSTR_PER_TERM * 2 / 1e12   # 52.43 tropical Top/s
+# MI355X VALU issue peak from unit counts: fp32 vector 157.3 TFLOP/s =
+# 256 CUs x 128 fp32 lanes x 2 (an FMA counts twice) x 2.4 GHz, i.e. 78.64e12
+# lane-slots per second.  A tropical term (one (.) and one (+)) needs at least
+# 1.5 slots with the instructions this build uses: one add, plus half of a
+# three-input min/max that folds two terms.  Two tropical ops per term.
+CUS, FP32_LANES, CLOCK_HZ = 256, 128, 2.4e9
+SLOTS_PER_S = CUS * FP32_LANES * CLOCK_HZ             # 78.64e12
+SLOTS_PER_TERM = 1.5
+PEAK_TOPS = SLOTS_PER_S / SLOTS_PER_TERM * 2 / 1e12   # 104.86 tropical Top/s
 
 
 def parse():

@@ -169,6 +169,8 @@ def _mat(t, name):
         raise ValueError(f"{name} must be a matrix")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
+    if t.numel() == 0:
+        return ctypes.c_void_p(t.data_ptr() or None), max(1, t.size(1))
     if t.size(1) > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride (row-major with leading dimension)")
     ld = t.stride(0) if t.size(0) > 1 else max(1, t.size(1))
@@ -180,6 +182,8 @@ def _vec(t, name):
         raise ValueError(f"{name} must be a vector")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
+    if t.numel() == 0:
+        return ctypes.c_void_p(t.data_ptr() or None), 1
     return ctypes.c_void_p(t.data_ptr()), max(1, t.stride(0))
 
 
