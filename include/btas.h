@@ -171,6 +171,40 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n,
 /* Number of squarings T for n vertices (0 for n <= 2). */
 int btas_apsp_num_steps(int n);
 
+/* ---------------------------------------------------------------------------
+ * Batched APSP: `count` independent solves of btas_apsp_squaring (fixed
+ * T(n_i) squarings each, same bits as one call per graph), executed as ONE
+ * hipGraph launch on the handle's stream.  The paper names host-device
+ * transfer and latency as what limits matrix-product formulations (Sec. V);
+ * this entry point keeps all graphs resident and issues no host round trip
+ * between squarings.
+ *   n, W, ldw, D, ldd: HOST arrays of length count; W[i] and D[i] are device
+ *   pointers to n[i] x n[i] row-major matrices with leading dimensions
+ *   ldw[i], ldd[i] >= max(1, n[i]).  Every W[i] is read before any D[j] is
+ *   written, so D[i] may equal W[i]; two outputs must not overlap
+ *   (BTAS_ERR_ALIAS).  flags must be 0 (early exit is not offered here;
+ *   it would not change the result).
+ * The first call with a given argument set builds a plan (device workspace of
+ * two padded n_i x n_i buffers per graph, work lists, per-size-bucket tile
+ * shapes chosen by timing both candidate shapes on this device, the captured
+ * graph) and synchronises; later calls with identical arguments only launch
+ * the graph (asynchronous).  The environment variable BTAS_BATCHED_TILE=128
+ * or 64 forces one tile shape; BTAS_AUTOTUNE=0 uses a cost model instead of
+ * timing.
+ */
+btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int count,
+                                         const int *n, const void *const *W, const int *ldw,
+                                         void *const *D, const int *ldd, unsigned flags);
+
+/* Describe the handle's current batched plan: number of kernel launches in
+ * its graph and the algorithmic work, sum_i T(n_i) * n_i^3 terms (host
+ * outputs, either may be NULL).  INVALID_ARG if no plan exists. */
+btas_status_t btas_batched_plan_info(btas_handle_t h, int *num_launches, double *total_terms);
+
+/* Output-tile edge (128 or 64) the handle uses for graphs of n vertices of
+ * dtype dt, or -1 if that size bucket has not been planned yet. */
+int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n);
+
 #ifdef __cplusplus
 }
 #endif

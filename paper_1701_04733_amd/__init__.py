@@ -19,7 +19,7 @@ import threading
 __all__ = [
     "I32_INF", "I32_NEG_INF", "I32_FINITE_MAX", "BtasError", "lib", "library_path",
     "Handle", "default_handle", "tropical_gemm", "tropical_gemv", "vadd", "vmul", "dot",
-    "axpy", "apsp", "apsp_num_steps", "version",
+    "axpy", "apsp", "apsp_num_steps", "version", "apsp_batched", "BatchedAPSP",
 ]
 
 I32_INF = 0x7FFFFFFF
@@ -77,6 +77,11 @@ def lib():
         L.btas_tropical_axpy.argtypes = [P, I, I, I, P, P, I, P, I]
         L.btas_apsp_squaring.argtypes = [P, I, I, P, I, P, I, U, ctypes.POINTER(I)]
         L.btas_apsp_num_steps.argtypes = [I]
+        IP = ctypes.POINTER(I)
+        PP = ctypes.POINTER(P)
+        L.btas_apsp_squaring_batched.argtypes = [P, I, I, IP, PP, IP, PP, IP, U]
+        L.btas_batched_plan_info.argtypes = [P, IP, ctypes.POINTER(ctypes.c_double)]
+        L.btas_batched_tile_choice.argtypes = [P, I, I]
         _LIB = L
     return _LIB
 
@@ -303,3 +308,59 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     st = h.check(lib().btas_apsp_squaring(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
                  allow=(OK, WARN_NEG_CYCLE))
     return out, (steps.value if sp is not None else None), st
+
+
+class BatchedAPSP:
+    """Repeated solves of one fixed set of graphs (same tensors every call).
+
+    The first ``run()`` plans and captures the hipGraph; later calls replay it.
+    ``Ws`` and ``Ds`` are lists of square device tensors of one dtype; D[i]
+    may be W[i] itself.
+    """
+
+    def __init__(self, Ws, Ds=None, handle=None):
+        import torch
+        if not Ws:
+            raise ValueError("need at least one graph")
+        self.Ws = list(Ws)
+        self.Ds = list(Ds) if Ds is not None else [torch.empty_like(w) for w in self.Ws]
+        dts = {_dt(w) for w in self.Ws} | {_dt(d) for d in self.Ds}
+        if len(dts) != 1:
+            raise TypeError("all graphs must share one dtype")
+        self.dt = dts.pop()
+        self.h = handle if handle is not None else default_handle(self.Ws[0].device.index or 0)
+        cnt = len(self.Ws)
+        if len(self.Ds) != cnt:
+            raise ValueError("Ws and Ds differ in length")
+        IA = ctypes.c_int * cnt
+        PA = ctypes.c_void_p * cnt
+        ns, pw, lw, pd, ld = [], [], [], [], []
+        for w, d in zip(self.Ws, self.Ds):
+            n = w.size(0)
+            if w.shape != (n, n) or d.shape != (n, n):
+                raise ValueError("graphs must be square and D must match W")
+            a, b = _mat(w, "W")
+            c, e = _mat(d, "D")
+            ns.append(n); pw.append(a.value); lw.append(b); pd.append(c.value); ld.append(e)
+        self._args = (IA(*ns), PA(*pw), IA(*lw), PA(*pd), IA(*ld))
+
+    def run(self):
+        n, pw, lw, pd, ld = self._args
+        self.h.check(lib().btas_apsp_squaring_batched(self.h.ptr, self.dt, len(self.Ws), n, pw, lw,
+                                                      pd, ld, 0))
+        return self.Ds
+
+    def plan_info(self):
+        launches = ctypes.c_int(0)
+        terms = ctypes.c_double(0)
+        self.h.check(lib().btas_batched_plan_info(self.h.ptr, ctypes.byref(launches),
+                                                  ctypes.byref(terms)))
+        return {"launches": launches.value, "terms": terms.value}
+
+    def tile_choice(self, n: int) -> int:
+        return lib().btas_batched_tile_choice(self.h.ptr, self.dt, int(n))
+
+
+def apsp_batched(Ws, Ds=None, handle=None):
+    """Solve every graph in ``Ws`` by repeated squaring in one graph launch."""
+    return BatchedAPSP(Ws, Ds, handle).run()

@@ -9,78 +9,17 @@
 #include <string>
 
 #include "btas.h"
+#include "context.h"
 #include "kernels.h"
 
-struct btas_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string last_error;
-    bool validate = false;
-    void* ws = nullptr;  // APSP ping-pong partner matrix
-    size_t ws_bytes = 0;
-    void* partials = nullptr;  // dot reduction partials
-    int* dflags = nullptr;     // device flags [8]
-    int* hflags = nullptr;     // pinned host mirror [8]
-};
+using namespace btas;
 
 namespace {
 
 const char* kVersion = "btas-gfx950 0.1.0";
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-btas_status_t fail(btas_handle_t h, btas_status_t st, const char* fmt, ...) {
-    if (h) {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
-        h->last_error = buf;
-    }
-    return st;
-}
-
-btas_status_t device_fail(btas_handle_t h, const char* where, hipError_t e) {
-    return fail(h, BTAS_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
-}
-
 bool sr_ok(btas_semiring_t sr) { return sr == BTAS_MIN_PLUS || sr == BTAS_MAX_PLUS; }
 bool dt_ok(btas_dtype_t dt) { return dt == BTAS_INT32 || dt == BTAS_FLOAT32; }
-
-// Byte span [lo, hi) touched by a row-major rows x cols matrix with leading
-// dimension ld (4-byte elements); empty when rows or cols is 0.
-struct Span {
-    uintptr_t lo = 0, hi = 0;
-    bool empty() const { return hi <= lo; }
-};
-Span mat_span(const void* p, long rows, long cols, long ld) {
-    Span s;
-    if (rows <= 0 || cols <= 0 || p == nullptr) return s;
-    s.lo = (uintptr_t)p;
-    s.hi = s.lo + (uintptr_t)(((rows - 1) * ld + cols) * 4);
-    return s;
-}
-Span vec_span(const void* p, long n, long inc) {
-    Span s;
-    if (n <= 0 || p == nullptr) return s;
-    s.lo = (uintptr_t)p;
-    s.hi = s.lo + (uintptr_t)(((n - 1) * inc + 1) * 4);
-    return s;
-}
-bool overlap(const Span& a, const Span& b) {
-    return !a.empty() && !b.empty() && a.lo < b.hi && b.lo < a.hi;
-}
 
 btas_status_t check_common(btas_handle_t h, const char* fn, btas_semiring_t sr,
                            btas_dtype_t dt) {
@@ -104,14 +43,15 @@ btas_status_t validate_operands(btas_handle_t h, const char* fn, int sr, int dt,
                                 const void* const* ptrs, const long* rows, const long* cols,
                                 const long* lds, int count) {
     if (!h->validate) return BTAS_OK;
-    hipError_t e = btas::launch_clear_flags(h->dflags, 1, h->stream);
+    int* flag = h->dflags + FLAG_CHECK;
+    hipError_t e = btas::launch_clear_flags(flag, 1, h->stream);
     for (int i = 0; i < count && e == hipSuccess; ++i)
-        e = btas::launch_domain_scan(sr, dt, (int)rows[i], (int)cols[i], ptrs[i], lds[i],
-                                     h->dflags, h->stream);
+        e = btas::launch_domain_scan(sr, dt, (int)rows[i], (int)cols[i], ptrs[i], lds[i], flag,
+                                     h->stream);
     if (e != hipSuccess) return device_fail(h, fn, e);
-    btas_status_t st = sync_flags(h, fn, 1);
+    btas_status_t st = sync_flags(h, fn, FLAG_CHECK + 1);
     if (st != BTAS_OK) return st;
-    if (h->hflags[0]) return fail(h, BTAS_ERR_DOMAIN, "%s: an input element is outside the semiring's domain", fn);
+    if (h->hflags[FLAG_CHECK]) return fail(h, BTAS_ERR_DOMAIN, "%s: an input element is outside the semiring's domain", fn);
     return BTAS_OK;
 }
 
@@ -137,16 +77,7 @@ const char* btas_status_string(btas_status_t s) {
 
 const char* btas_last_error(btas_handle_t h) { return h ? h->last_error.c_str() : "null handle"; }
 
-int btas_apsp_num_steps(int n) {
-    if (n <= 2) return 0;
-    int t = 0;
-    long reach = 1;
-    while (reach < (long)n - 1) {
-        reach *= 2;
-        ++t;
-    }
-    return t;
-}
+int btas_apsp_num_steps(int n) { return btas::apsp_steps(n); }
 
 btas_status_t btas_create(btas_handle_t* out, int device) {
     if (!out) return BTAS_ERR_INVALID_ARG;
@@ -160,8 +91,8 @@ btas_status_t btas_create(btas_handle_t* out, int device) {
     h->device = device;
     const char* v = getenv("BTAS_VALIDATE");
     h->validate = v && v[0] == '1';
-    if (hipMalloc(&h->dflags, 8 * sizeof(int)) != hipSuccess ||
-        hipHostMalloc((void**)&h->hflags, 8 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+    if (hipMalloc(&h->dflags, kNumFlags * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&h->hflags, kNumFlags * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&h->partials, (size_t)btas::dot_partials_needed(0) * 4) != hipSuccess) {
         if (h->dflags) (void)hipFree(h->dflags);
         if (h->hflags) (void)hipHostFree(h->hflags);
@@ -177,6 +108,8 @@ btas_status_t btas_destroy(btas_handle_t h) {
     if (!h) return BTAS_ERR_INVALID_ARG;
     DeviceGuard g(h->device);
     (void)hipStreamSynchronize(h->stream);
+    h->batch_plan.reset();
+    if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
     if (h->ws) (void)hipFree(h->ws);
     if (h->partials) (void)hipFree(h->partials);
     if (h->dflags) (void)hipFree(h->dflags);
@@ -226,8 +159,18 @@ btas_status_t btas_tropical_gemm(btas_handle_t h, btas_semiring_t sr, btas_dtype
     const long rows[2] = {m, k}, cols[2] = {k, n}, lds[2] = {lda, ldb};
     st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 2);
     if (st != BTAS_OK) return st;
-    btas::GemmArgs a{m, n, k, A, lda, B, ldb, C, ldc, C, ldc, nullptr};
-    hipError_t e = btas::launch_gemm(sr, dt, a, -1, h->stream);
+    int* wide = nullptr;
+    hipError_t e = hipSuccess;
+    if (dt == BTAS_INT32) {
+        // Decide on the device whether the binary32-exact path applies.
+        wide = h->dflags + FLAG_GEMM_WIDE;
+        e = btas::launch_clear_flags(wide, 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_range_scan(sr, m, k, A, lda, wide, h->stream);
+        if (e == hipSuccess) e = btas::launch_range_scan(sr, k, n, B, ldb, wide, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+    }
+    btas::GemmArgs a{m, n, k, A, lda, B, ldb, C, ldc, C, ldc, nullptr, wide, nullptr};
+    e = btas::launch_gemm(sr, dt, a, -1, h->stream);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
 }
 
@@ -405,25 +348,32 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     void* bufs[2] = {D, h->ws};
     long lds[2] = {ldd, n};
     int cur = (T % 2 == 0) ? 0 : 1;
-    hipError_t e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], h->stream);
+    // int32: slot FLAG_STEP_WIDE + t records whether D_t left the binary32-exact
+    // range; the init kernel fills slot 0 and step t reads slot t-1, writes slot t.
+    int* wide = dt == BTAS_INT32 ? h->dflags + FLAG_STEP_WIDE : nullptr;
+    hipError_t e = hipSuccess;
+    if (wide) e = btas::launch_clear_flags(wide, T + 1, h->stream);
+    if (e == hipSuccess) e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], wide, h->stream);
     if (e != hipSuccess) return device_fail(h, fn, e);
     int steps = 0;
     for (int t = 0; t < T; ++t) {
         const int nxt = cur ^ 1;
+        int* changed = h->dflags + FLAG_CHANGED;
         if (early) {
-            e = btas::launch_clear_flags(h->dflags, 1, h->stream);
+            e = btas::launch_clear_flags(changed, 1, h->stream);
             if (e != hipSuccess) return device_fail(h, fn, e);
         }
         btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
-                         bufs[nxt], lds[nxt], early ? h->dflags : nullptr};
+                         bufs[nxt], lds[nxt], early ? changed : nullptr,
+                         wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr};
         e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
         ++steps;
         cur = nxt;
         if (early) {
-            btas_status_t st = sync_flags(h, fn, 1);
+            btas_status_t st = sync_flags(h, fn, FLAG_CHANGED + 1);
             if (st != BTAS_OK) return st;
-            if (h->hflags[0] == 0) break;
+            if (h->hflags[FLAG_CHANGED] == 0) break;
         }
     }
     if (cur != 0) {
@@ -432,12 +382,13 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     }
     btas_status_t result = BTAS_OK;
     if (flags & BTAS_APSP_CHECK_NEG_CYCLE) {
-        e = btas::launch_clear_flags(h->dflags, 1, h->stream);
-        if (e == hipSuccess) e = btas::launch_neg_diag_check(dt, n, D, ldd, h->dflags, h->stream);
+        int* flag = h->dflags + FLAG_CHECK;
+        e = btas::launch_clear_flags(flag, 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_neg_diag_check(dt, n, D, ldd, flag, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
-        btas_status_t st = sync_flags(h, fn, 1);
+        btas_status_t st = sync_flags(h, fn, FLAG_CHECK + 1);
         if (st != BTAS_OK) return st;
-        if (h->hflags[0]) result = fail(h, BTAS_WARN_NEG_CYCLE, "%s: negative cycle (some D_ii < 0)", fn);
+        if (h->hflags[FLAG_CHECK]) result = fail(h, BTAS_WARN_NEG_CYCLE, "%s: negative cycle (some D_ii < 0)", fn);
     }
     if (steps_out) {
         e = hipStreamSynchronize(h->stream);

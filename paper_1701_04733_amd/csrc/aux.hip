@@ -3,6 +3,9 @@
 // domain scan.  All are O(n^2) and HBM-bound.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "gemm_tile.h"
 #include "kernels.h"
 #include "semiring.h"
 
@@ -12,15 +15,19 @@ namespace btas {
 // tropical identity puts 0 on the diagonal, so D_ii = min(W_ii, 0)).
 template <typename T>
 __global__ __launch_bounds__(256) void apsp_init_kernel(int n, const T* W, long ldw, T* D,
-                                                         long ldd) {
+                                                         long ldd, int* wide) {
     const long total = (long)n * n;
+    bool w_wide = false;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
         const long i = e / n, j = e - i * n;
         T w = W[i * ldw + j];
         if (i == j && w > (T)0) w = (T)0;
         D[i * ldd + j] = w;
+        if constexpr (std::is_same_v<T, int32_t>)
+            w_wide |= w != BTAS_I32_INF && (w > FP32_EXACT_MAX || w < -FP32_EXACT_MAX);
     }
+    if (wide != nullptr && w_wide) *wide = 1;
 }
 
 static unsigned blocks_for(long total) {
@@ -31,15 +38,42 @@ static unsigned blocks_for(long total) {
 }
 
 hipError_t launch_apsp_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
-                            hipStream_t s) {
+                            int* wide, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const unsigned g = blocks_for((long)n * n);
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL(apsp_init_kernel<float>, dim3(g), dim3(256), 0, s, n, (const float*)W,
-                           ldw, (float*)dst, ldd);
+                           ldw, (float*)dst, ldd, nullptr);
     else
         hipLaunchKernelGGL(apsp_init_kernel<int32_t>, dim3(g), dim3(256), 0, s, n,
-                           (const int32_t*)W, ldw, (int32_t*)dst, ldd);
+                           (const int32_t*)W, ldw, (int32_t*)dst, ldd, wide);
+    return hipGetLastError();
+}
+
+template <int SR>
+__global__ __launch_bounds__(256) void range_scan_kernel(int m, int n, const int32_t* X, long ld,
+                                                          int* flag) {
+    const long total = (long)m * n;
+    bool wide = false;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, j = e - i * n;
+        const int32_t x = X[i * ld + j];
+        wide |= x != Ring<SR, int32_t>::absent() && (x > FP32_EXACT_MAX || x < -FP32_EXACT_MAX);
+    }
+    if (wide) *flag = 1;
+}
+
+hipError_t launch_range_scan(int sr, int m, int n, const void* X, long ld, int* flag,
+                             hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    const dim3 g(blocks_for((long)m * n)), b(256);
+    if (sr == BTAS_MIN_PLUS)
+        hipLaunchKernelGGL(range_scan_kernel<BTAS_MIN_PLUS>, g, b, 0, s, m, n, (const int32_t*)X,
+                           ld, flag);
+    else
+        hipLaunchKernelGGL(range_scan_kernel<BTAS_MAX_PLUS>, g, b, 0, s, m, n, (const int32_t*)X,
+                           ld, flag);
     return hipGetLastError();
 }
 

@@ -1,0 +1,186 @@
+// Grouped kernels for many independent APSP solves (batched and served).
+//
+// Each graph g owns two padded n_g x n_g buffers (leading dimension a multiple
+// of 4, 256-byte aligned) and squares back and forth between them, as in the
+// single-solve driver (Sec. III: D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1}).  One
+// launch of the grouped step kernel performs one squaring for a whole list of
+// output tiles drawn from many graphs; work items name (graph, tile row, tile
+// column, tile shape) and each graph carries its own step parity, so graphs
+// at different steps (served requests) can share a launch.  Small elementwise
+// kernels map W -> I (+) W into the internal buffer and copy the final matrix
+// out to the caller's layout.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "batched.h"
+#include "gemm_tile.h"
+
+namespace btas {
+
+// int32 graphs whose finite weights satisfy 2^T * max|w| <= FP32_EXACT_MAX
+// keep every finite distance of every step inside the binary32-exact range
+// (a step's entries are sums of at most 2^t weights), so their squarings run
+// on the binary32 pipeline.  The init kernel records max|w| per graph.
+template <typename T>
+__device__ __forceinline__ bool graph_is_narrow(const BatchGraph& g, const int* maxabs, int gi) {
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (maxabs == nullptr) return false;
+        const long bound = (long)FP32_EXACT_MAX >> (g.T < 31 ? g.T : 31);
+        return (long)maxabs[gi] <= bound;
+    } else {
+        return false;
+    }
+}
+
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __restrict__ graphs,
+                                                            const BatchItem* __restrict__ items,
+                                                            const int* __restrict__ maxabs,
+                                                            int* __restrict__ changed) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const BatchItem it = items[blockIdx.x];
+    const BatchGraph g = graphs[it.graph];
+    const int s = it.step;                      // squaring index, 1-based
+    const T* src = (const T*)g.buf[(g.parity + s - 1) & 1];
+    T* dst = (T*)g.buf[(g.parity + s) & 1];
+    int* chg = changed != nullptr ? changed + it.graph : nullptr;
+    TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
+    const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
+    if (it.kind == BATCH_TILE_128) {
+        const int m0 = it.tm * CfgL::BM, n0 = it.tn * CfgL::BN;
+        if constexpr (std::is_same_v<T, int32_t>) {
+            if (narrow) {
+                GemmTile<CfgL, T, float, SR, true>::run(a, m0, n0, smem_raw);
+                return;
+            }
+        }
+        GemmTile<CfgL, T, T, SR, true>::run(a, m0, n0, smem_raw);
+    } else {
+        const int m0 = it.tm * CfgM::BM, n0 = it.tn * CfgM::BN;
+        if constexpr (std::is_same_v<T, int32_t>) {
+            if (narrow) {
+                GemmTile<CfgM, T, float, SR, true>::run(a, m0, n0, smem_raw);
+                return;
+            }
+        }
+        GemmTile<CfgM, T, T, SR, true>::run(a, m0, n0, smem_raw);
+    }
+}
+
+static_assert(CfgL::NT == 256 && CfgM::NT == 256, "grouped kernel mixes both tile shapes");
+
+hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
+                               int nitems, const int* maxabs, int* changed, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const size_t lds = CfgL::lds_bytes > CfgM::lds_bytes ? CfgL::lds_bytes : CfgM::lds_bytes;
+    if (dt == BTAS_FLOAT32)
+        hipLaunchKernelGGL((grouped_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems), dim3(256), lds,
+                           s, graphs, items, nullptr, changed);
+    else
+        hipLaunchKernelGGL((grouped_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems), dim3(256),
+                           lds, s, graphs, items, maxabs, changed);
+    return hipGetLastError();
+}
+
+// Job owning workgroup `b` (jobs sorted by first_block).
+__device__ __forceinline__ int find_job(const BatchCopy* jobs, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].first_block <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- init: buf[parity] <- I (+) W, and max |finite w| per graph (int32) ----
+template <typename T>
+__global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __restrict__ graphs,
+                                                            const BatchCopy* __restrict__ jobs,
+                                                            int njobs, int* __restrict__ maxabs) {
+    const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
+    const BatchGraph g = graphs[jb.graph];
+    const int n = g.n;
+    const T* W = (const T*)jb.ext;
+    T* D = (T*)g.buf[g.parity & 1];
+    const long total = (long)n * n;
+    const long stride = (long)jb.nblocks * blockDim.x;
+    int mx = 0;
+    for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
+         e += stride) {
+        const long i = e / n, j = e - i * n;
+        T w = W[i * jb.ld_ext + j];
+        if (i == j && w > (T)0) w = (T)0;
+        D[i * g.ld + j] = w;
+        if constexpr (std::is_same_v<T, int32_t>) {
+            if (w != BTAS_I32_INF) {
+                const int aw = w < 0 ? (w == INT32_MIN ? INT32_MAX : -w) : w;
+                mx = aw > mx ? aw : mx;
+            }
+        }
+    }
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (maxabs != nullptr) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const int o = __shfl_xor(mx, off, 64);
+                mx = o > mx ? o : mx;
+            }
+            if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(maxabs + jb.graph, mx);
+        }
+    }
+}
+
+// ---- final copy: D_ext <- buf[(parity + T) & 1] ----
+__global__ __launch_bounds__(256) void grouped_copy_out_kernel(const BatchGraph* __restrict__ graphs,
+                                                                const BatchCopy* __restrict__ jobs,
+                                                                int njobs) {
+    const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
+    const BatchGraph g = graphs[jb.graph];
+    const int n = g.n;
+    const uint32_t* S = (const uint32_t*)g.buf[(g.parity + g.T) & 1];
+    uint32_t* D = (uint32_t*)const_cast<void*>(jb.ext);
+    const long total = (long)n * n;
+    const long stride = (long)jb.nblocks * blockDim.x;
+    for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
+         e += stride) {
+        const long i = e / n, j = e - i * n;
+        D[i * jb.ld_ext + j] = S[i * g.ld + j];
+    }
+}
+
+__global__ void clear_ints_kernel(int* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_clear_ints(int* p, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int blocks = (count + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(clear_ints_kernel, dim3(blocks), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_grouped_init(int dt, const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
+                               int total_blocks, int* maxabs, hipStream_t s) {
+    if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
+    if (dt == BTAS_FLOAT32)
+        hipLaunchKernelGGL(grouped_init_kernel<float>, dim3(total_blocks), dim3(256), 0, s, graphs,
+                           jobs, njobs, nullptr);
+    else
+        hipLaunchKernelGGL(grouped_init_kernel<int32_t>, dim3(total_blocks), dim3(256), 0, s,
+                           graphs, jobs, njobs, maxabs);
+    return hipGetLastError();
+}
+
+hipError_t launch_grouped_copy_out(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
+                                   int total_blocks, hipStream_t s) {
+    if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grouped_copy_out_kernel, dim3(total_blocks), dim3(256), 0, s, graphs, jobs,
+                       njobs);
+    return hipGetLastError();
+}
+
+}  // namespace btas

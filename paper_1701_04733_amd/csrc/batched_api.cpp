@@ -1,0 +1,326 @@
+// btas_apsp_squaring_batched: many independent APSP solves in one hipGraph.
+//
+// Plan (built once per distinct argument set, cached on the handle):
+//  * every graph gets two padded internal buffers; D_0 = I (+) W is written
+//    into the first, T(n) squarings alternate between them, the last one is
+//    copied to the caller's D;
+//  * graphs are ordered by decreasing T(n), then n, so the work list of
+//    squaring t is a prefix of the graph order and its largest tiles come
+//    first (longest-processing-time-first within each launch);
+//  * each size bucket (half-octaves of n) uses the tile shape (128x128 or
+//    64x64 output tiles) that the autotuner measured fastest for that bucket
+//    on this device, timed on the plan's own buffers and work lists;
+//  * init, every squaring launch and the copy-out are captured into one
+//    hipGraph on the handle's auxiliary stream and replayed on the caller's
+//    stream, so a batched solve is a single graph launch with no host
+//    round trip between squarings.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "batched.h"
+#include "context.h"
+
+namespace btas {
+
+struct BatchPlan {
+    uint64_t key = 0;
+    int dt = 0;
+    int count = 0;
+    void* ws = nullptr;
+    BatchGraph* d_graphs = nullptr;
+    BatchItem* d_items = nullptr;
+    BatchCopy* d_init = nullptr;
+    BatchCopy* d_out = nullptr;
+    int* d_maxabs = nullptr;
+    int init_blocks = 0, njobs = 0;
+    std::vector<int> step_off, step_cnt;  // launch t (1-based) covers [off, off+cnt)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double terms = 0;                     // sum over graphs of T(n) * n^3
+};
+
+void destroy_batch_plan(BatchPlan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (void* q : {(void*)p->d_graphs, (void*)p->d_items, (void*)p->d_init, (void*)p->d_out,
+                    (void*)p->d_maxabs, p->ws})
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+namespace {
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+int size_bucket(int n) {
+    // half-octave buckets: 2*floor(log2 n) + (upper half of the octave)
+    if (n <= 1) return 0;
+    int lg = 31 - __builtin_clz((unsigned)n);
+    const int half = (n - (1 << lg)) * 2 >= (1 << lg) ? 1 : 0;
+    return 2 * lg + half;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int tiles_of(int n, int kind) {
+    const int t = kind == BATCH_TILE_128 ? 128 : 64;
+    return (n + t - 1) / t;
+}
+
+// Cost model used when autotuning is off: padded tile area, with the 64-wide
+// tiles (4x4 per thread) charged 15% more per element than 128-wide ones.
+int model_kind(int n) {
+    const double a128 = std::pow((double)tiles_of(n, BATCH_TILE_128) * 128, 2);
+    const double a64 = std::pow((double)tiles_of(n, BATCH_TILE_64) * 64, 2) * 1.15;
+    return a128 <= a64 ? BATCH_TILE_128 : BATCH_TILE_64;
+}
+
+struct HostGraph {
+    int idx;  // caller's index
+    int n, T, ld;
+};
+
+void append_items(std::vector<BatchItem>& items, int graph_slot, int n, int kind, int step) {
+    const int t = tiles_of(n, kind);
+    for (int tm = 0; tm < t; ++tm)
+        for (int tn = 0; tn < t; ++tn) items.push_back({graph_slot, tm, tn, kind, step, 0});
+}
+
+btas_status_t upload(btas_handle_t h, const char* fn, void** dst, const void* src, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(dst, bytes) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate %zu bytes of descriptors", fn, bytes);
+    hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+}  // namespace
+}  // namespace btas
+
+using namespace btas;
+
+extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int count,
+                                                    const int* n, const void* const* W,
+                                                    const int* ldw, void* const* D,
+                                                    const int* ldd, unsigned flags) {
+    const char* fn = "btas_apsp_squaring_batched";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (dt != BTAS_INT32 && dt != BTAS_FLOAT32)
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
+    if (count < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (count=%d) < 0", fn, count);
+    if (flags != 0)
+        return fail(h, BTAS_ERR_UNSUPPORTED, "%s: flags=0x%x; batched solves run the fixed T(n) squarings "
+                    "(early exit would give the same bits)", fn, flags);
+    if (count == 0) return BTAS_OK;
+    if (!n || !W || !ldw || !D || !ldd)
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: a host array argument is null", fn);
+    std::vector<Span> dspans;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: n[%d]=%d < 0", fn, i, n[i]);
+        if (ldw[i] < std::max(1, n[i]))
+            return fail(h, BTAS_ERR_INVALID_ARG, "%s: ldw[%d]=%d < max(1,n)", fn, i, ldw[i]);
+        if (ldd[i] < std::max(1, n[i]))
+            return fail(h, BTAS_ERR_INVALID_ARG, "%s: ldd[%d]=%d < max(1,n)", fn, i, ldd[i]);
+        if (n[i] > 0 && (!W[i] || !D[i]))
+            return fail(h, BTAS_ERR_INVALID_ARG, "%s: W[%d] or D[%d] is null", fn, i, i);
+        if (n[i] > 0) dspans.push_back(mat_span(D[i], n[i], n[i], ldd[i]));
+    }
+    // Outputs must not overlap each other (each W is read before any D is written).
+    std::sort(dspans.begin(), dspans.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < dspans.size(); ++i)
+        if (dspans[i].lo < dspans[i - 1].hi)
+            return fail(h, BTAS_ERR_ALIAS, "%s: two output matrices overlap", fn);
+
+    DeviceGuard guard(h->device);
+    uint64_t key = mix(0x42ull, (uint64_t)dt);
+    key = mix(key, (uint64_t)count);
+    for (int i = 0; i < count; ++i) {
+        key = mix(key, (uint64_t)n[i]);
+        key = mix(key, ((uint64_t)(uint32_t)ldw[i] << 32) | (uint32_t)ldd[i]);
+        key = mix(key, (uint64_t)(uintptr_t)W[i]);
+        key = mix(key, (uint64_t)(uintptr_t)D[i]);
+    }
+
+    hipError_t e = hipSuccess;
+    if (!h->aux_stream) {
+        e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+    }
+
+    BatchPlan* plan = h->batch_plan.get();
+    if (!plan || plan->key != key) {
+        if (plan) {
+            // The previous plan's graph may still run on the caller's stream.
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+        }
+        h->batch_plan.reset();
+        std::unique_ptr<BatchPlan, BatchPlanDeleter> p(new BatchPlan);
+        p->key = key;
+        p->dt = dt;
+        p->count = count;
+        // Order graphs: decreasing T, then decreasing n; drop n == 0.
+        std::vector<HostGraph> hg;
+        for (int i = 0; i < count; ++i)
+            if (n[i] > 0) hg.push_back({i, n[i], apsp_steps(n[i]), (int)round_up(n[i], 4)});
+        std::stable_sort(hg.begin(), hg.end(), [](const HostGraph& a, const HostGraph& b) {
+            return a.T != b.T ? a.T > b.T : a.n > b.n;
+        });
+        const int ng = (int)hg.size();
+        // Workspace: two 256-byte aligned buffers per graph.
+        std::vector<size_t> off(ng);
+        size_t total = 0;
+        for (int g = 0; g < ng; ++g) {
+            off[g] = total;
+            total += 2 * round_up((size_t)hg[g].n * hg[g].ld * 4, 256);
+        }
+        if (total > 0 && hipMalloc(&p->ws, total) != hipSuccess)
+            return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte batch workspace", fn, total);
+        std::vector<BatchGraph> graphs(ng);
+        for (int g = 0; g < ng; ++g) {
+            const size_t half = round_up((size_t)hg[g].n * hg[g].ld * 4, 256);
+            char* base = (char*)p->ws + off[g];
+            graphs[g] = {{base, base + half}, hg[g].n, hg[g].ld, hg[g].T, 0};
+            p->terms += (double)hg[g].T * hg[g].n * (double)hg[g].n * hg[g].n;
+        }
+        btas_status_t st = upload(h, fn, (void**)&p->d_graphs, graphs.data(), sizeof(BatchGraph) * ng);
+        if (st != BTAS_OK) return st;
+        if (hipMalloc((void**)&p->d_maxabs, sizeof(int) * std::max(ng, 1)) != hipSuccess)
+            return fail(h, BTAS_ERR_OOM, "%s: cannot allocate flags", fn);
+
+        // Tile shape per size bucket: forced, modelled, or measured.
+        const char* force = getenv("BTAS_BATCHED_TILE");
+        const char* tune_env = getenv("BTAS_AUTOTUNE");
+        const bool tune = !(tune_env && tune_env[0] == '0');
+        std::map<int, std::vector<int>> buckets;  // bucket -> graph slots
+        for (int g = 0; g < ng; ++g)
+            if (hg[g].T > 0) buckets[size_bucket(hg[g].n)].push_back(g);
+        std::map<int, int> kind_of_bucket;
+        for (auto& kv : buckets) {
+            int kind;
+            const int rep = hg[kv.second.front()].n;  // largest n of the bucket
+            if (force && std::strcmp(force, "128") == 0) kind = BATCH_TILE_128;
+            else if (force && std::strcmp(force, "64") == 0) kind = BATCH_TILE_64;
+            else if (!tune) kind = model_kind(rep);
+            else {
+                auto it = h->tile_choice.find({(int)dt, kv.first});
+                if (it != h->tile_choice.end()) {
+                    kind = it->second;
+                } else {
+                    // Time one squaring of the whole bucket with each shape on the
+                    // plan's (not yet initialised) buffers: the kernels' speed does
+                    // not depend on the values, and the binary32 path is the one
+                    // taken for in-range int32 data.
+                    (void)launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
+                    float ms_of[2] = {1e30f, 1e30f};
+                    for (int cand : {BATCH_TILE_128, BATCH_TILE_64}) {
+                        std::vector<BatchItem> its;
+                        for (int g : kv.second) append_items(its, g, hg[g].n, cand, 1);
+                        BatchItem* d_its = nullptr;
+                        st = upload(h, fn, (void**)&d_its, its.data(), sizeof(BatchItem) * its.size());
+                        if (st != BTAS_OK) return st;
+                        hipEvent_t e0, e1;
+                        (void)hipEventCreate(&e0);
+                        (void)hipEventCreate(&e1);
+                        for (int rep_i = 0; rep_i < 3 && e == hipSuccess; ++rep_i) {
+                            (void)hipEventRecord(e0, h->aux_stream);
+                            e = launch_grouped_step(dt, p->d_graphs, d_its, (int)its.size(),
+                                                    p->d_maxabs, nullptr, h->aux_stream);
+                            (void)hipEventRecord(e1, h->aux_stream);
+                            if (e == hipSuccess) e = hipEventSynchronize(e1);
+                            float t = 0;
+                            (void)hipEventElapsedTime(&t, e0, e1);
+                            if (rep_i > 0) ms_of[cand] = std::min(ms_of[cand], t);  // first run warms up
+                        }
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                        (void)hipFree(d_its);
+                        if (e != hipSuccess) return device_fail(h, fn, e);
+                    }
+                    kind = ms_of[BATCH_TILE_64] < ms_of[BATCH_TILE_128] ? BATCH_TILE_64 : BATCH_TILE_128;
+                    h->tile_choice[{(int)dt, kv.first}] = kind;
+                }
+            }
+            kind_of_bucket[kv.first] = kind;
+        }
+
+        // Work lists: launch t holds the tiles of every graph with T >= t.
+        std::vector<BatchItem> items;
+        const int Tmax = ng > 0 ? hg[0].T : 0;
+        for (int t = 1; t <= Tmax; ++t) {
+            p->step_off.push_back((int)items.size());
+            for (int g = 0; g < ng && hg[g].T >= t; ++g)
+                append_items(items, g, hg[g].n, kind_of_bucket[size_bucket(hg[g].n)], t);
+            p->step_cnt.push_back((int)items.size() - p->step_off.back());
+        }
+        st = upload(h, fn, (void**)&p->d_items, items.data(), sizeof(BatchItem) * items.size());
+        if (st != BTAS_OK) return st;
+        // Copy jobs (caller order is irrelevant: one job per graph).
+        std::vector<BatchCopy> init(ng), out(ng);
+        int blocks = 0;
+        for (int g = 0; g < ng; ++g) {
+            const int nb = copy_blocks_for(hg[g].n);
+            init[g] = {g, blocks, nb, 0, (long)ldw[hg[g].idx], W[hg[g].idx]};
+            out[g] = {g, blocks, nb, 0, (long)ldd[hg[g].idx], D[hg[g].idx]};
+            blocks += nb;
+        }
+        p->init_blocks = blocks;
+        p->njobs = ng;
+        st = upload(h, fn, (void**)&p->d_init, init.data(), sizeof(BatchCopy) * ng);
+        if (st == BTAS_OK) st = upload(h, fn, (void**)&p->d_out, out.data(), sizeof(BatchCopy) * ng);
+        if (st != BTAS_OK) return st;
+
+        // Capture the whole solve.
+        e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        if (dt == BTAS_INT32) e = launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
+        if (e == hipSuccess)
+            e = launch_grouped_init(dt, p->d_graphs, p->d_init, ng, blocks,
+                                    dt == BTAS_INT32 ? p->d_maxabs : nullptr, h->aux_stream);
+        for (int t = 0; t < Tmax && e == hipSuccess; ++t)
+            e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
+                                    dt == BTAS_INT32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream);
+        if (e == hipSuccess) e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return device_fail(h, fn, e != hipSuccess ? e : e2);
+        }
+        p->graph = graph;
+        e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        h->batch_plan = std::move(p);
+        plan = h->batch_plan.get();
+    }
+    e = hipGraphLaunch(plan->exec, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+extern "C" btas_status_t btas_batched_plan_info(btas_handle_t h, int* num_launches,
+                                                double* total_terms) {
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    const BatchPlan* p = h->batch_plan.get();
+    if (!p) return fail(h, BTAS_ERR_INVALID_ARG, "btas_batched_plan_info: no batched plan yet");
+    if (num_launches) *num_launches = (int)p->step_cnt.size() + (p->dt == BTAS_INT32 ? 3 : 2);
+    if (total_terms) *total_terms = p->terms;
+    return BTAS_OK;
+}
+
+extern "C" int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n) {
+    if (!h) return -1;
+    auto it = h->tile_choice.find({(int)dt, size_bucket(n)});
+    if (it == h->tile_choice.end()) return -1;
+    return it->second == BATCH_TILE_128 ? 128 : 64;
+}

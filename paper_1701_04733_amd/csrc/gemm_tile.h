@@ -1,0 +1,278 @@
+// One output macro-tile of the tropical product, shared by the single-GEMM
+// kernel and the grouped (batched / served APSP) kernel.
+//
+//   Cout[m0.., n0..] <- Cin (+) A (.) B     over a BM x BN tile, k fully reduced.
+//
+// The paper's matrix product (Sec. IV, min-plus form of the matrix-product
+// listing) assigns sub-matrices of the output to threads; here a workgroup
+// owns a BM x BN tile and each thread a TM x TN register tile, with A and B
+// panels staged through LDS.
+//
+// Storage type T (the caller's element type) and compute type CT may differ:
+// int32 data whose finite values all satisfy |x| <= 2^23-1 is computed on the
+// binary32 pipeline (CT = float), which is exact because every such value and
+// every sum of two of them (|s| <= 2^24-2) is an exactly representable
+// binary32 integer, and the absent values map to +-inf.  That path issues the
+// (.) as a 2-operand float add, which gfx950 dual-issues, instead of a
+// saturating integer add with a clamp modifier, which it does not.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "semiring.h"
+
+namespace btas {
+
+template <typename T>
+using v4 = T __attribute__((ext_vector_type(4)));
+
+// Largest magnitude of a finite int32 element that the binary32 path accepts.
+constexpr int32_t FP32_EXACT_MAX = (1 << 23) - 1;
+
+template <int BM_, int BN_, int BK_, int TM_, int TN_>
+struct GemmCfg {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, TM = TM_, TN = TN_;
+    static constexpr int TXN = BN / TN;          // threads along n
+    static constexpr int TYN = BM / TM;          // threads along m
+    static constexpr int NT = TXN * TYN;         // threads per workgroup
+    static constexpr int RG = TM / 4;            // 4-row groups per thread
+    static constexpr int CG = TN / 4;            // 4-col groups per thread
+    static constexpr int APAD = 4, BPAD = 4;
+    static constexpr int LDA_S = BK + APAD;      // LDS row stride of the A tile
+    static constexpr int LDB_S = BN + BPAD;      // LDS row stride of the B tile
+    static constexpr int A_VECS = BM * BK / 4;   // 4-vectors in an A tile
+    static constexpr int B_VECS = BK * BN / 4;
+    static constexpr int LA = A_VECS / NT;       // per-thread vector loads
+    static constexpr int LB = B_VECS / NT;
+    static_assert(TM % 4 == 0 && TN % 4 == 0, "register tile is built from 4-wide groups");
+    static_assert(BK % 4 == 0, "k-block is consumed in quads");
+    static_assert(A_VECS % NT == 0 && B_VECS % NT == 0, "tile loads must split evenly");
+    static constexpr size_t lds_bytes = 2 * (BM * LDA_S + BK * LDB_S) * 4;
+};
+
+using CfgL = GemmCfg<128, 128, 16, 8, 8>;  // large problems: 256 threads, 8x8 per thread
+using CfgM = GemmCfg<64, 64, 16, 4, 4>;    // mid-size: 256 threads, 4x4 per thread
+using CfgS = GemmCfg<32, 32, 16, 4, 4>;    // small / latency-bound: 64 threads
+
+// Element conversion between storage and compute types.
+template <typename T, typename CT, int SR>
+struct Conv {
+    __device__ __forceinline__ static CT in(T x) { return x; }
+    __device__ __forceinline__ static T out(CT acc) { return Ring<SR, T>::finish(acc); }
+};
+
+template <int SR>
+struct Conv<int32_t, float, SR> {
+    __device__ __forceinline__ static float in(int32_t x) {
+        return x == Ring<SR, int32_t>::absent() ? Ring<SR, float>::absent() : (float)x;
+    }
+    // acc is an exact integer of magnitude < 2^24, or the absent infinity.
+    __device__ __forceinline__ static int32_t out(float acc) {
+        return __builtin_isinf(acc) ? Ring<SR, int32_t>::absent() : (int32_t)acc;
+    }
+};
+
+template <typename T>
+struct TileArgs {
+    int m, n, k;
+    const T* A;
+    long lda;
+    const T* B;
+    long ldb;
+    const T* Cin;
+    long ldci;
+    T* Cout;
+    long ldco;
+    int* changed;   // set to 1 if an output differs bitwise from Cin (may be null)
+    int* wide_out;  // int32: set to 1 if a finite output exceeds FP32_EXACT_MAX (may be null)
+};
+
+template <typename Cfg, typename T, typename CT, int SR, bool VEC>
+struct GemmTile {
+    using R = Ring<SR, CT>;
+    using Cv = Conv<T, CT, SR>;
+
+    // HBM -> registers (converted to the compute type) for one k-block.
+    __device__ __forceinline__ static void load_global(v4<CT> (&ra)[Cfg::LA], v4<CT> (&rb)[Cfg::LB],
+                                                       const TileArgs<T>& a, int m0, int n0,
+                                                       int k0, bool interior, int tid) {
+        const CT z = R::absent();
+#pragma unroll
+        for (int i = 0; i < Cfg::LA; ++i) {
+            const int l = tid + i * Cfg::NT;
+            const int row = l / (Cfg::BK / 4);
+            const int kq = l % (Cfg::BK / 4);
+            const int gr = m0 + row, gc = k0 + kq * 4;
+            if (VEC && interior) {
+                const v4<T> x = *reinterpret_cast<const v4<T>*>(a.A + (long)gr * a.lda + gc);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ra[i][e] = Cv::in(x[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    ra[i][e] = (gr < a.m && gc + e < a.k) ? Cv::in(a.A[(long)gr * a.lda + gc + e]) : z;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Cfg::LB; ++i) {
+            const int l = tid + i * Cfg::NT;
+            const int row = l / (Cfg::BN / 4);
+            const int nq = l % (Cfg::BN / 4);
+            const int gr = k0 + row, gc = n0 + nq * 4;
+            if (VEC && interior) {
+                const v4<T> x = *reinterpret_cast<const v4<T>*>(a.B + (long)gr * a.ldb + gc);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) rb[i][e] = Cv::in(x[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    rb[i][e] = (gr < a.k && gc + e < a.n) ? Cv::in(a.B[(long)gr * a.ldb + gc + e]) : z;
+            }
+        }
+    }
+
+    // registers -> LDS buffer.
+    __device__ __forceinline__ static void store_lds(const v4<CT> (&ra)[Cfg::LA],
+                                                     const v4<CT> (&rb)[Cfg::LB], CT* As, CT* Bs,
+                                                     int tid) {
+#pragma unroll
+        for (int i = 0; i < Cfg::LA; ++i) {
+            const int l = tid + i * Cfg::NT;
+            const int row = l / (Cfg::BK / 4);
+            const int kq = l % (Cfg::BK / 4);
+            *reinterpret_cast<v4<CT>*>(As + row * Cfg::LDA_S + kq * 4) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < Cfg::LB; ++i) {
+            const int l = tid + i * Cfg::NT;
+            const int row = l / (Cfg::BN / 4);
+            const int nq = l % (Cfg::BN / 4);
+            *reinterpret_cast<v4<CT>*>(Bs + row * Cfg::LDB_S + nq * 4) = rb[i];
+        }
+    }
+
+    // Consume one LDS k-block into the register tile.  The quad loop is kept
+    // rolled so that only one quad's operands are live (about 150 VGPRs for
+    // the 8x8 tile, three waves per SIMD); each quad folds two k-steps per
+    // three-input min/max.
+    __device__ __forceinline__ static void compute(CT (&acc)[Cfg::TM][Cfg::TN], const CT* As,
+                                                   const CT* Bs, int tx, int ty) {
+#pragma unroll 1
+        for (int q = 0; q < Cfg::BK / 4; ++q) {
+            v4<CT> av[Cfg::TM];
+#pragma unroll
+            for (int r = 0; r < Cfg::TM; ++r) {
+                const int row = (r / 4) * (Cfg::BM / Cfg::RG) + ty * 4 + (r % 4);
+                av[r] = *reinterpret_cast<const v4<CT>*>(As + row * Cfg::LDA_S + q * 4);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; kk += 2) {
+                CT b0[Cfg::TN], b1[Cfg::TN];
+#pragma unroll
+                for (int g = 0; g < Cfg::CG; ++g) {
+                    const int col = g * (Cfg::BN / Cfg::CG) + tx * 4;
+                    const v4<CT> x0 = *reinterpret_cast<const v4<CT>*>(
+                        Bs + (q * 4 + kk) * Cfg::LDB_S + col);
+                    const v4<CT> x1 = *reinterpret_cast<const v4<CT>*>(
+                        Bs + (q * 4 + kk + 1) * Cfg::LDB_S + col);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        b0[g * 4 + e] = x0[e];
+                        b1[g * 4 + e] = x1[e];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < Cfg::TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < Cfg::TN; ++c)
+                        acc[r][c] = R::add3(acc[r][c], R::mul(av[r][kk], b0[c]),
+                                            R::mul(av[r][kk + 1], b1[c]));
+            }
+        }
+    }
+
+    // The whole tile: k loop with double-buffered LDS, then the epilogue.
+    __device__ __forceinline__ static void run(const TileArgs<T>& a, int m0, int n0,
+                                               unsigned char* smem) {
+        using RT = Ring<SR, T>;
+        CT* As0 = reinterpret_cast<CT*>(smem);
+        CT* Bs0 = As0 + Cfg::BM * Cfg::LDA_S;
+        CT* As1 = Bs0 + Cfg::BK * Cfg::LDB_S;
+        CT* Bs1 = As1 + Cfg::BM * Cfg::LDA_S;
+        const int tid = threadIdx.x;
+        const int tx = tid % Cfg::TXN, ty = tid / Cfg::TXN;
+        const bool mn_interior = (m0 + Cfg::BM <= a.m) && (n0 + Cfg::BN <= a.n);
+
+        CT acc[Cfg::TM][Cfg::TN];
+#pragma unroll
+        for (int r = 0; r < Cfg::TM; ++r)
+#pragma unroll
+            for (int c = 0; c < Cfg::TN; ++c) acc[r][c] = R::absent();
+
+        const int nkb = (a.k + Cfg::BK - 1) / Cfg::BK;
+        v4<CT> ra[Cfg::LA], rb[Cfg::LB];
+        if (nkb > 0) {
+            load_global(ra, rb, a, m0, n0, 0, mn_interior && Cfg::BK <= a.k, tid);
+            store_lds(ra, rb, As0, Bs0, tid);
+        }
+        __syncthreads();
+        for (int kb = 0; kb < nkb; ++kb) {
+            const bool even = (kb & 1) == 0;
+            const bool more = kb + 1 < nkb;
+            if (more) {
+                const int k0 = (kb + 1) * Cfg::BK;
+                load_global(ra, rb, a, m0, n0, k0, mn_interior && k0 + Cfg::BK <= a.k, tid);
+            }
+            compute(acc, even ? As0 : As1, even ? Bs0 : Bs1, tx, ty);
+            if (more) store_lds(ra, rb, even ? As1 : As0, even ? Bs1 : Bs0, tid);
+            __syncthreads();
+        }
+
+        // Epilogue: finish the accumulator, (+)-combine with Cin, store Cout.
+        bool diff = false, wide = false;
+#pragma unroll
+        for (int r = 0; r < Cfg::TM; ++r) {
+            const int row = m0 + (r / 4) * (Cfg::BM / Cfg::RG) + ty * 4 + (r % 4);
+            if (row >= a.m) continue;
+#pragma unroll
+            for (int g = 0; g < Cfg::CG; ++g) {
+                const int col = n0 + g * (Cfg::BN / Cfg::CG) + tx * 4;
+                if (VEC && mn_interior) {
+                    const v4<T> old = *reinterpret_cast<const v4<T>*>(a.Cin + (long)row * a.ldci + col);
+                    v4<T> nv;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        nv[e] = RT::add(old[e], Cv::out(acc[r][g * 4 + e]));
+                        diff |= bits_of(nv[e]) != bits_of(old[e]);
+                        wide |= is_wide(nv[e]);
+                    }
+                    *reinterpret_cast<v4<T>*>(a.Cout + (long)row * a.ldco + col) = nv;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (col + e >= a.n) break;
+                        const T old = a.Cin[(long)row * a.ldci + col + e];
+                        const T nv = RT::add(old, Cv::out(acc[r][g * 4 + e]));
+                        diff |= bits_of(nv) != bits_of(old);
+                        wide |= is_wide(nv);
+                        a.Cout[(long)row * a.ldco + col + e] = nv;
+                    }
+                }
+            }
+        }
+        if (a.changed != nullptr && __any(diff) && (threadIdx.x & 63) == 0) *a.changed = 1;
+        if (a.wide_out != nullptr && __any(wide) && (threadIdx.x & 63) == 0) *a.wide_out = 1;
+    }
+
+    __device__ __forceinline__ static bool is_wide(T x) {
+        if constexpr (std::is_same_v<T, int32_t>) {
+            return x != Ring<SR, T>::absent() && (x > FP32_EXACT_MAX || x < -FP32_EXACT_MAX);
+        } else {
+            return false;
+        }
+    }
+};
+
+}  // namespace btas

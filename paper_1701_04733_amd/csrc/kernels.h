@@ -21,6 +21,12 @@ struct GemmArgs {
     void* Cout;
     long ldco;
     int* changed;
+    // int32 only (ignored for float32): wide_in points at a device flag that
+    // is 0 when every finite element of A and B fits in +-FP32_EXACT_MAX (the
+    // product then runs exactly on the binary32 pipeline); wide_out, if not
+    // null, is set to 1 when a finite output element does not fit.
+    const int* wide_in;
+    int* wide_out;
 };
 
 enum { GEMM_CFG_L = 0, GEMM_CFG_M = 1, GEMM_CFG_S = 2, GEMM_NUM_CFGS = 3 };
@@ -45,9 +51,15 @@ hipError_t launch_dot(int sr, int dt, int n, const void* x, long incx, const voi
                       void* partials, void* result, hipStream_t s);
 
 // APSP helpers.
-// dst <- I (+) W  (copy with dst_ii = min(W_ii, 0)); dst may equal W.
+// dst <- I (+) W  (copy with dst_ii = min(W_ii, 0)); dst may equal W.  For
+// int32, `wide` (may be null) is set to 1 if a finite element of dst exceeds
+// +-FP32_EXACT_MAX.
 hipError_t launch_apsp_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
-                            hipStream_t s);
+                            int* wide, hipStream_t s);
+// int32: flag <- 1 if a finite element (not the semiring's absent value) of the
+// m x n matrix exceeds +-FP32_EXACT_MAX.
+hipError_t launch_range_scan(int sr, int m, int n, const void* X, long ld, int* flag,
+                             hipStream_t s);
 // flag[0..count) <- 0 (a kernel, not a memset, so it is safe inside graphs).
 hipError_t launch_clear_flags(int* flag, int count, hipStream_t s);
 // flag <- 1 if some D_ii < 0.

@@ -1,0 +1,115 @@
+"""Batched APSP (one hipGraph launch for many graphs) against the oracle and
+against the plain one-solve-per-call path: bit-identical results."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(x):
+    x = np.ascontiguousarray(x).copy()
+    if x.dtype == np.float32:
+        x[x == 0] = 0.0
+    return x.view(np.uint32)
+
+
+def _mixed_graphs(dt, count, seed, lo=1, hi=300):
+    g = wl.rng(seed)
+    out = []
+    for i in range(count):
+        n = int(g.integers(lo, hi + 1))
+        W = wl.er_digraph_i32(n, min(1.0, 4.0 / max(n, 1)), 1, 1000, seed=seed * 1000 + i)
+        if dt == "f32":
+            w2 = wl.rng(seed * 7 + i).exponential(1.0, (n, n))
+            W = np.where(W == wl.I32_INF, np.inf, w2).astype(np.float32)
+            np.fill_diagonal(W, 0)
+        out.append(W)
+    return out
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+def test_batched_matches_oracle(dev, dt):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = _mixed_graphs(dt, 37, seed=3)
+    Ws += [np.zeros((0, 0), Ws[0].dtype)]                    # an empty graph is allowed
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    runner = btas.BatchedAPSP(tW)
+    Ds = runner.run()
+    torch.cuda.synchronize()
+    for W, D in zip(Ws, Ds):
+        if W.shape[0] == 0:
+            continue
+        want, _, _ = oracle.apsp(W)
+        assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"n={W.shape[0]}"
+    # replay of the captured graph gives the same bits
+    for D in Ds:
+        D.fill_(0)
+    Ds2 = runner.run()
+    torch.cuda.synchronize()
+    for W, D in zip(Ws, Ds2):
+        if W.shape[0]:
+            want, _, _ = oracle.apsp(W)
+            assert np.array_equal(_bits(D.cpu().numpy()), _bits(want))
+    info = runner.plan_info()
+    assert info["launches"] >= 2
+
+
+@pytest.mark.parametrize("tile", ["128", "64"])
+def test_batched_tile_shapes_same_bits(dev, tile, monkeypatch):
+    """Every tile shape the autotuner may pick gives the same bits."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    monkeypatch.setenv("BTAS_BATCHED_TILE", tile)
+    h = btas.Handle(0)
+    h.bind_stream()
+    Ws = _mixed_graphs("i32", 12, seed=9, lo=60, hi=520)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    r = btas.BatchedAPSP(tW, handle=h)
+    Ds = r.run()
+    torch.cuda.synchronize()
+    for W, D in zip(Ws, Ds):
+        want, _, _ = oracle.apsp(W)
+        assert np.array_equal(D.cpu().numpy(), want)
+    h.close()
+
+
+def test_batched_in_place_and_errors(dev):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = _mixed_graphs("i32", 5, seed=4, lo=2, hi=90)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    btas.apsp_batched(tW, tW)                                    # D[i] is W[i]
+    torch.cuda.synchronize()
+    for W, D in zip(Ws, tW):
+        want, _, _ = oracle.apsp(W)
+        assert np.array_equal(D.cpu().numpy(), want)
+    big = torch.zeros((10, 10), dtype=torch.int32, device=dev)
+    with pytest.raises(btas.BtasError, match="ALIAS"):
+        btas.apsp_batched([big[:5, :5].clone(), big[:5, :5].clone()], [big[:5, :5], big[2:7, 2:7]])
+
+
+def test_batched_full_config_vs_plain_and_oracle(dev):
+    """4096 graphs, n log-uniform in [16,512], p = 8/n, weights U{1..1000}:
+    every result equals the plain per-graph path bit for bit, and a sample of
+    graphs equals the oracle."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = wl.batched_graphs_i32(count=4096, seed=5)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    Ds = btas.apsp_batched(tW)
+    plain = [btas.apsp(w, return_steps=False)[0] for w in tW]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(Ds, plain)):
+        assert torch.equal(a, b), f"graph {i} (n={Ws[i].shape[0]}) differs from the plain path"
+    sample = list(range(0, 4096, 128)) + [int(np.argmax([w.shape[0] for w in Ws]))]
+    for i in sample:
+        want, _, _ = oracle.apsp(Ws[i])
+        assert np.array_equal(Ds[i].cpu().numpy(), want), f"graph {i}"

@@ -320,3 +320,42 @@ def test_validate_mode_detects_domain(btas, dev, monkeypatch):
     with pytest.raises(btas.BtasError, match="DOMAIN"):
         btas.tropical_gemm(F, F.clone(), torch.zeros_like(F), handle=h)
     h.close()
+
+
+# ------------------------------------- int32 on the binary32-exact path ---
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("edge", [(1 << 23) - 1, 1 << 23, (1 << 29) - 1])
+def test_gemm_i32_exact_range_boundary(btas, dev, sr, edge):
+    """Operands whose largest finite magnitude is just inside / just outside
+    the range computed on the binary32 pipeline give the oracle's bits."""
+    m, n, k = 300, 260, 270
+    g = wl.rng(edge % 1000 + (sr == "max"))
+    A = g.integers(-edge, edge, size=(m, k), endpoint=True).astype(np.int32)
+    B = g.integers(-edge, edge, size=(k, n), endpoint=True).astype(np.int32)
+    A[0, 0], B[0, 0] = edge, -edge                         # hit the extremes exactly
+    absent = wl.I32_INF if sr == "min" else wl.I32_NEG_INF
+    A[g.random((m, k)) < 0.1] = absent
+    B[g.random((k, n)) < 0.1] = absent
+    C = wl.signed_operand((m, n), "i32", sr, seed=4, inf_frac=0.5)
+    want = oracle.gemm(sr, A, B, C)
+    Ct = to_dev(C, dev)
+    btas.tropical_gemm(to_dev(A, dev), to_dev(B, dev), Ct, semiring=sr)
+    assert_same(to_np(Ct), want, f"edge={edge}")
+
+
+def test_apsp_i32_distances_cross_exact_range(btas, dev):
+    """A path graph with heavy edges: early squarings stay within +-(2^23-1),
+    later ones exceed it and must switch to the integer pipeline."""
+    n = 150
+    W = np.full((n, n), wl.I32_INF, np.int32)
+    np.fill_diagonal(W, 0)
+    g = wl.rng(12)
+    for i in range(n - 1):
+        W[i, i + 1] = int(g.integers(1 << 19, 1 << 20))
+    W[g.random((n, n)) < 0.01] = 1 << 21
+    np.fill_diagonal(W, 0)
+    want, _, _ = oracle.apsp(W)
+    assert want[0, n - 1] > (1 << 23)
+    D, _, _ = btas.apsp(to_dev(W, dev))
+    assert_same(to_np(D), want, "crossing")
