@@ -50,7 +50,14 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=128,
                    help="rows of the 8192^3 min-plus fp32 product timed on the oracle")
-    p.add_argument("--extras", action="store_true", help="also time the APSP workloads")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the APSP workloads (small, large, batched, served)")
+    p.add_argument("--served-count", type=int, default=300,
+                   help="requests per arrival rate in the served workload")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="run one plain 256 MiB device copy first (reference for HBM counters)")
+    p.add_argument("--served-rates", default="300,3000",
+                   help="comma-separated Poisson arrival rates (req/s) for the served workload")
     return p.parse_args()
 
 
@@ -66,6 +73,165 @@ def cpu_baseline(A, B, C, rows):
             "sample": f"min-plus fp32 rows 0..{rows - 1} of the 8192^3 product "
                       f"({rows}x{N}x{N} terms), {dt:.2f} s",
             "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_apsp_small(dev, reps=200):
+    """One APSP on an ER digraph, n=256, p=0.05, int32 weights U{1..100}, T=8:
+    per-solve latency of the plain path (init + 8 GEMM launches) and of the
+    same solve as one captured hipGraph launch."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    W = torch.from_numpy(wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)).to(dev)
+    D = torch.empty_like(W)
+    g = btas.BatchedAPSP([W], [D])
+    out = {"workload": "APSP n=256 ER p=0.05 int32 U{1..100}, T=8 squarings"}
+    for name, fn in (("plain", lambda: btas.apsp(W, out=D, return_steps=False)), ("graph", g.run)):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        thr = reps / (time.perf_counter() - t0)
+        out[name] = {"latency_us_p50": round(float(np.percentile(lat, 50)) * 1e6, 1),
+                     "latency_us_p99": round(float(np.percentile(lat, 99)) * 1e6, 1),
+                     "solves_per_s": round(thr, 1)}
+    return out
+
+
+def bench_apsp_large(dev):
+    """One APSP, n=16384 fp32, mean out-degree 16, exponential(1) weights,
+    early exit (capped at T=14)."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    n = 16384
+    W = torch.from_numpy(wl.apsp_large_f32(n, 16.0, seed=4)).to(dev)
+    D = torch.empty_like(W)
+    btas.apsp(W[:2048, :2048].contiguous(), early_exit=True)  # warm the kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, steps, _ = btas.apsp(W, out=D, early_exit=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ops = 2.0 * n ** 3 * steps
+    return {"workload": "APSP n=16384 fp32, out-degree 16, exp(1) weights, early exit",
+            "seconds": round(sec, 4), "steps": steps, "T": btas.apsp_num_steps(n),
+            "Gop/s": round(ops / sec / 1e9, 1), "frac_valu_peak": round(ops / sec / 1e12 / PEAK_TOPS, 4)}
+
+
+def bench_batched(dev, reps=5):
+    """4096 independent graphs, n log-uniform in [16,512], p = 8/n, int32
+    weights U{1..1000}: one hipGraph launch vs 4096 plain solves."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    Ws = [torch.from_numpy(w).to(dev) for w in wl.batched_graphs_i32(count=4096, seed=5)]
+    r = btas.BatchedAPSP(Ws)
+    r.run()
+    torch.cuda.synchronize()
+    info = r.plan_info()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = _events()
+        e0.record()
+        r.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    bm = float(np.median(ms))
+    outs = [torch.empty_like(w) for w in Ws]
+    for w, o in zip(Ws[:64], outs):
+        btas.apsp(w, out=o, return_steps=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w, o in zip(Ws, outs):
+        btas.apsp(w, out=o, return_steps=False)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(r.Ds, outs))
+    return {"workload": "batched APSP, 4096 graphs, n log-uniform [16,512], p=8/n, int32 U{1..1000}",
+            "batched_ms": round(bm, 3), "batched_solves_per_s": round(4096 / (bm / 1e3), 1),
+            "batched_Gop/s": round(2 * info["terms"] / (bm / 1e3) / 1e9, 1),
+            "frac_valu_peak": round(2 * info["terms"] / (bm / 1e3) / 1e12 / PEAK_TOPS, 4),
+            "graph_kernel_launches": info["launches"],
+            "plain_ms": round(plain * 1e3, 3), "plain_solves_per_s": round(4096 / plain, 1),
+            "speedup_vs_plain": round(plain * 1e3 / bm, 2), "bit_identical_to_plain": same}
+
+
+def _serve_trace(reqs, mode):
+    import threading
+
+    import numpy as np
+
+    import paper_1701_04733_amd as btas
+    srv = btas.Server("f32", budget_bytes=64 << 30, mode=mode)
+    ids = [None] * len(reqs)
+    lat = []
+    ready = threading.Event()
+
+    def reaper():
+        for i in range(len(reqs)):
+            while ids[i] is None:
+                time.sleep(0.0002)
+            srv.wait(ids[i], -1)
+            a, _, d = srv.times(ids[i])
+            lat.append((a, d))
+            srv.release(ids[i])
+        ready.set()
+
+    th = threading.Thread(target=reaper, daemon=True)
+    th.start()
+    base = srv.now() + 0.05
+    for i, r in enumerate(reqs):
+        target = base + r.arrival_s
+        while True:
+            left = target - srv.now()
+            if left <= 0:
+                break
+            time.sleep(left if left > 0.002 else 0)
+        ids[i] = srv.submit(r.n, r.rows, r.cols, r.w, arrival=target)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    L = np.array([d - a for a, d in lat]) * 1e3
+    span = max(d for _, d in lat) - min(a for a, _ in lat)
+    return {"p50_ms": round(float(np.percentile(L, 50)), 2), "p99_ms": round(float(np.percentile(L, 99)), 2),
+            "mean_ms": round(float(L.mean()), 2), "solves_per_s": round(len(reqs) / span, 1),
+            "launches": st["launches"], "pool_peak_GiB": round(st["pool_peak_bytes"] / 2**30, 2)}
+
+
+def bench_served(rates, count):
+    """Open-loop Poisson trace of fp32 APSP requests (n log-uniform in
+    [32,4096], out-degree 12, weights in (0,10], COO in, densified on the
+    device, fixed T(n)), served with continuous batching and with the plain
+    FIFO one-solve-per-launch path on the same trace."""
+    from paper_1701_04733_amd import workloads as wl
+    out = {"workload": f"served APSP fp32, {count} requests per rate, n log-uniform [32,4096], "
+                       "out-degree 12, HBM budget 64 GiB"}
+    for rate in rates:
+        reqs = wl.served_requests(count, float(rate))
+        out[f"rate_{rate}"] = {"continuous": _serve_trace(reqs, "continuous"),
+                               "fifo": _serve_trace(reqs, "fifo")}
+    return out
 
 
 def main():
@@ -93,6 +259,13 @@ def main():
         del A, B, C
     torch.cuda.synchronize()
     h = btas.default_handle(0)
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                       # reads and writes 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
 
     def run_step(events=None):
         for v in VARIANTS:
@@ -152,6 +325,18 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host["A"], host["B"], host["C"], args.cpu_rows)
+    del host, tensors
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        extras = {}
+        extras["apsp_small"] = bench_apsp_small(dev)
+        extras["apsp_large"] = bench_apsp_large(dev)
+        torch.cuda.empty_cache()
+        extras["batched"] = bench_batched(dev)
+        torch.cuda.empty_cache()
+        rates = [int(x) for x in args.served_rates.split(",") if x]
+        extras["served"] = bench_served(rates, args.served_count)
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 

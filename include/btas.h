@@ -205,6 +205,74 @@ btas_status_t btas_batched_plan_info(btas_handle_t h, int *num_launches, double 
  * dtype dt, or -1 if that size bucket has not been planned yet. */
 int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop for APSP solves of mixed sizes.  The paper points to
+ * latency and host-device traffic as the limits of matrix-product methods
+ * (Sec. V); the server keeps every request's distance matrix on the device
+ * from admission to release and overlaps the squarings (Sec. III) of all
+ * admitted requests in shared launches.
+ *
+ * A server owns an engine thread, a stream and a device memory pool of
+ * budget_bytes.  Requests are admitted in arrival order while the pool can
+ * hold their two padded n x n matrices and edges; admitted requests are
+ * densified on the device (D_0 = I (+) W from the COO edge list; duplicate
+ * edges keep the lightest) and then advanced one squaring at a time:
+ *   BTAS_SERVE_CONTINUOUS: every engine iteration issues ONE grouped launch
+ *     holding, for each active request, the next tiles of its current
+ *     squaring up to quantum_terms (tile rows x tile cols x n) of work
+ *     (<= 0 selects 2e10); requests admitted while others run join the next
+ *     iteration (continuous batching);
+ *   BTAS_SERVE_FIFO: one request at a time, each squaring one plain GEMM
+ *     launch (the one-solve-per-launch baseline).
+ * Results are identical in both modes and to btas_apsp_squaring.  Times are
+ * seconds on the server's steady clock (btas_server_now).  The server is
+ * thread-safe: submit/wait/result/release may be called from any thread.
+ */
+typedef struct btas_server *btas_server_t;
+#define BTAS_SERVE_CONTINUOUS 0
+#define BTAS_SERVE_FIFO 1
+
+typedef struct {
+    long iterations;        /* engine iterations run                        */
+    long launches;          /* kernel launches issued for squarings          */
+    double busy_seconds;    /* engine time spent with work on the device     */
+    size_t pool_bytes, pool_used_bytes, pool_peak_bytes;
+    int active, pending;    /* requests on the device / waiting for memory   */
+} btas_server_stats_t;
+
+/* dt: element type of every request.  Errors: INVALID_ARG, OOM (pool), DEVICE. */
+btas_status_t btas_server_create(btas_server_t *srv, int device, btas_dtype_t dt,
+                                 size_t budget_bytes, int mode, double quantum_terms);
+/* Stops the engine after its current iteration and frees everything. */
+btas_status_t btas_server_destroy(btas_server_t srv);
+/* Seconds since the server was created. */
+double btas_server_now(btas_server_t srv);
+/* Queue one solve.  rows/cols/w: HOST arrays of nnz edges (copied before
+ * return; 0 <= rows, cols < n else INVALID_ARG; weights must be legal (.)
+ * operands else DOMAIN).  flags: 0 or BTAS_APSP_EARLY_EXIT.  arrival: the
+ * request's arrival time on the server clock (latency is measured from it;
+ * < 0 means now).  *id receives the request id.  OOM if the request can never
+ * fit the pool. */
+btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_t *rows,
+                                 const int32_t *cols, const void *w, unsigned flags,
+                                 double arrival, int64_t *id);
+/* Wait until request id is done (timeout_s < 0: forever); *done = 1 if so. */
+btas_status_t btas_server_wait(btas_server_t srv, int64_t id, double timeout_s, int *done);
+/* Device pointer, leading dimension and executed squarings of a finished
+ * request's distance matrix; valid until btas_server_release. */
+btas_status_t btas_server_result(btas_server_t srv, int64_t id, const void **D_dev, int *ldd,
+                                 int *steps);
+/* Copy a finished request's n x n distance matrix to the device matrix D
+ * (leading dimension ldd >= n); synchronous.  Do not release the request
+ * concurrently. */
+btas_status_t btas_server_copy_result(btas_server_t srv, int64_t id, void *D, int ldd);
+/* Arrival, admission and completion times of a request (-1 if not yet). */
+btas_status_t btas_server_times(btas_server_t srv, int64_t id, double *arrival,
+                                double *admitted, double *done);
+/* Return a finished request's memory to the pool. */
+btas_status_t btas_server_release(btas_server_t srv, int64_t id);
+btas_status_t btas_server_stats(btas_server_t srv, btas_server_stats_t *out);
+
 #ifdef __cplusplus
 }
 #endif

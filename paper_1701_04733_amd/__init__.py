@@ -19,7 +19,7 @@ import threading
 __all__ = [
     "I32_INF", "I32_NEG_INF", "I32_FINITE_MAX", "BtasError", "lib", "library_path",
     "Handle", "default_handle", "tropical_gemm", "tropical_gemv", "vadd", "vmul", "dot",
-    "axpy", "apsp", "apsp_num_steps", "version", "apsp_batched", "BatchedAPSP",
+    "axpy", "apsp", "apsp_num_steps", "version", "apsp_batched", "BatchedAPSP", "Server",
 ]
 
 I32_INF = 0x7FFFFFFF
@@ -39,6 +39,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbtas.so")
 _LIB = None
 _LOCK = threading.Lock()
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_long), ("launches", ctypes.c_long),
+                ("busy_seconds", ctypes.c_double), ("pool_bytes", ctypes.c_size_t),
+                ("pool_used_bytes", ctypes.c_size_t), ("pool_peak_bytes", ctypes.c_size_t),
+                ("active", ctypes.c_int), ("pending", ctypes.c_int)]
 
 
 class BtasError(RuntimeError):
@@ -82,6 +89,19 @@ def lib():
         L.btas_apsp_squaring_batched.argtypes = [P, I, I, IP, PP, IP, PP, IP, U]
         L.btas_batched_plan_info.argtypes = [P, IP, ctypes.POINTER(ctypes.c_double)]
         L.btas_batched_tile_choice.argtypes = [P, I, I]
+        L.btas_server_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.c_size_t, I, ctypes.c_double]
+        L.btas_server_destroy.argtypes = [P]
+        L.btas_server_now.argtypes = [P]
+        L.btas_server_now.restype = ctypes.c_double
+        I64 = ctypes.c_int64
+        L.btas_server_submit.argtypes = [P, I, I, P, P, P, U, ctypes.c_double, ctypes.POINTER(I64)]
+        L.btas_server_wait.argtypes = [P, I64, ctypes.c_double, IP]
+        L.btas_server_result.argtypes = [P, I64, ctypes.POINTER(P), IP, IP]
+        L.btas_server_copy_result.argtypes = [P, I64, P, I]
+        D = ctypes.c_double
+        L.btas_server_times.argtypes = [P, I64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.btas_server_release.argtypes = [P, I64]
+        L.btas_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
         _LIB = L
     return _LIB
 
@@ -364,3 +384,98 @@ class BatchedAPSP:
 def apsp_batched(Ws, Ds=None, handle=None):
     """Solve every graph in ``Ws`` by repeated squaring in one graph launch."""
     return BatchedAPSP(Ws, Ds, handle).run()
+
+
+class Server:
+    """APSP request server (continuous batching or the FIFO baseline).
+
+    Requests are COO edge lists (host numpy arrays); distance matrices stay on
+    the device until ``release``.  Thread-safe: a client thread may submit
+    while another waits and releases.
+    """
+
+    def __init__(self, dtype="f32", budget_bytes=64 << 30, mode="continuous",
+                 quantum_terms=0.0, device=0):
+        self.dt = FLOAT32 if dtype in ("f32", "float32") else INT32
+        self.np_dtype = "float32" if self.dt == FLOAT32 else "int32"
+        m = {"continuous": 0, "fifo": 1}[mode]
+        p = ctypes.c_void_p()
+        st = lib().btas_server_create(ctypes.byref(p), int(device), self.dt, int(budget_bytes), m,
+                                      float(quantum_terms))
+        if st != OK:
+            raise BtasError(st, "btas_server_create failed")
+        self._s = p
+
+    def now(self) -> float:
+        return lib().btas_server_now(self._s)
+
+    def submit(self, n, rows, cols, w, early_exit=False, arrival=-1.0) -> int:
+        import numpy as np
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        w = np.ascontiguousarray(w, dtype=self.np_dtype)
+        if not (rows.size == cols.size == w.size):
+            raise ValueError("rows, cols and w differ in length")
+        rid = ctypes.c_int64(0)
+        st = lib().btas_server_submit(self._s, int(n), rows.size, rows.ctypes.data, cols.ctypes.data,
+                                      w.ctypes.data, APSP_EARLY_EXIT if early_exit else 0,
+                                      float(arrival), ctypes.byref(rid))
+        if st != OK:
+            raise BtasError(st, f"btas_server_submit(n={n}) failed")
+        return rid.value
+
+    def wait(self, rid, timeout=-1.0) -> bool:
+        done = ctypes.c_int(0)
+        st = lib().btas_server_wait(self._s, int(rid), float(timeout), ctypes.byref(done))
+        if st != OK:
+            raise BtasError(st, f"request {rid} failed")
+        return bool(done.value)
+
+    def steps(self, rid) -> int:
+        s = ctypes.c_int(0)
+        st = lib().btas_server_result(self._s, int(rid), None, None, ctypes.byref(s))
+        if st != OK:
+            raise BtasError(st, f"request {rid} has no result")
+        return s.value
+
+    def result_into(self, rid, out):
+        """Copy request rid's distance matrix into the device matrix ``out``."""
+        p, ld = _mat(out, "out")
+        st = lib().btas_server_copy_result(self._s, int(rid), p, ld)
+        if st != OK:
+            raise BtasError(st, f"request {rid} has no result")
+        return out
+
+    def times(self, rid):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = lib().btas_server_times(self._s, int(rid), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        if st != OK:
+            raise BtasError(st, f"unknown request {rid}")
+        return a.value, b.value, c.value
+
+    def release(self, rid):
+        st = lib().btas_server_release(self._s, int(rid))
+        if st != OK:
+            raise BtasError(st, f"cannot release request {rid}")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        lib().btas_server_stats(self._s, ctypes.byref(s))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            lib().btas_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -61,5 +61,15 @@ inline int copy_blocks_for(int n) {
     return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
 }
 hipError_t launch_clear_ints(int* p, int count, hipStream_t s);
+// D (n x n, leading dimension ld) <- I (+) W for a COO edge list W given by
+// device arrays rows/cols/w of length nnz (indices already range-checked);
+// duplicate edges keep the smallest weight.
+hipError_t launch_densify(int dt, void* D, int n, int ld, int nnz, const int32_t* rows,
+                          const int32_t* cols, const void* w, hipStream_t s);
+
+inline int batch_tiles_of(int n, int kind) {
+    const int t = kind == BATCH_TILE_128 ? 128 : 64;
+    return (n + t - 1) / t;
+}
 
 }  // namespace btas

@@ -150,6 +150,63 @@ __global__ __launch_bounds__(256) void grouped_copy_out_kernel(const BatchGraph*
     }
 }
 
+// ---- served requests: densify a COO edge list into I (+) W ----
+template <typename T>
+__global__ __launch_bounds__(256) void fill_identity_kernel(T* D, int n, int ld) {
+    const long total = (long)n * n;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, j = e - i * n;
+        D[i * ld + j] = i == j ? (T)0 : Ring<BTAS_MIN_PLUS, T>::absent();
+    }
+}
+
+__device__ __forceinline__ void atomic_min_elem(int32_t* p, int32_t v) { atomicMin(p, v); }
+
+__device__ __forceinline__ void atomic_min_elem(float* p, float v) {
+    unsigned* ip = reinterpret_cast<unsigned*>(p);
+    unsigned old = *ip;
+    while (v < __uint_as_float(old)) {
+        const unsigned seen = atomicCAS(ip, old, __float_as_uint(v));
+        if (seen == old) break;
+        old = seen;
+    }
+}
+
+// D[r][c] <- min(D[r][c], w) for every edge (duplicates keep the lightest).
+// Indices were range-checked on the host.
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_min_kernel(T* D, int ld, int nnz,
+                                                           const int32_t* __restrict__ rows,
+                                                           const int32_t* __restrict__ cols,
+                                                           const T* __restrict__ w) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x)
+        atomic_min_elem(D + (long)rows[e] * ld + cols[e], w[e]);
+}
+
+hipError_t launch_densify(int dt, void* D, int n, int ld, int nnz, const int32_t* rows,
+                          const int32_t* cols, const void* w, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long blocks = ((long)n * n + 1023) / 1024;
+    if (blocks > 16384) blocks = 16384;
+    int eb = (nnz + 255) / 256;
+    if (eb > 4096) eb = 4096;
+    if (dt == BTAS_FLOAT32) {
+        hipLaunchKernelGGL(fill_identity_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (float*)D, n, ld);
+        if (nnz > 0)
+            hipLaunchKernelGGL(scatter_min_kernel<float>, dim3(eb), dim3(256), 0, s, (float*)D, ld,
+                               nnz, rows, cols, (const float*)w);
+    } else {
+        hipLaunchKernelGGL(fill_identity_kernel<int32_t>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (int32_t*)D, n, ld);
+        if (nnz > 0)
+            hipLaunchKernelGGL(scatter_min_kernel<int32_t>, dim3(eb), dim3(256), 0, s,
+                               (int32_t*)D, ld, nnz, rows, cols, (const int32_t*)w);
+    }
+    return hipGetLastError();
+}
+
 __global__ void clear_ints_kernel(int* p, int count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
         p[i] = 0;

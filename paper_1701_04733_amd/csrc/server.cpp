@@ -1,0 +1,598 @@
+// Serving engine for APSP requests: admission by a device-memory budget,
+// device-resident distance matrices, and continuous batching at squaring
+// granularity (Sec. III squarings of many requests share each launch).
+//
+// One engine thread owns a non-blocking stream and loops:
+//   1. admit pending requests in arrival order while the memory pool has room
+//      for their two padded n x n buffers and their COO edges; upload the edges
+//      and densify I (+) W on the device;
+//   2. build one work list: for every active request, the next tiles of its
+//      current squaring, at most `quantum` terms' worth per request (a large
+//      request's squaring is spread over several launches, so small requests
+//      never wait for a whole large squaring: round-robin processor sharing);
+//   3. launch the grouped step kernel once for the whole list, wait for it;
+//   4. advance requests whose squaring completed; finish those that ran T(n)
+//      squarings (or, with early exit, one that changed nothing); signal
+//      waiters.
+// In FIFO mode the engine instead runs one request at a time with the plain
+// single-solve path (one GEMM launch per squaring): the baseline that the
+// continuous mode is compared against on the same request trace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <string>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "batched.h"
+#include "btas.h"
+#include "kernels.h"
+
+namespace btas {
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int steps_for(int n) {
+    if (n <= 2) return 0;
+    int t = 0;
+    long reach = 1;
+    while (reach < (long)n - 1) {
+        reach *= 2;
+        ++t;
+    }
+    return t;
+}
+
+// First-fit allocator over one device allocation; offsets are 256-aligned.
+class DevicePool {
+   public:
+    bool init(size_t bytes) {
+        size_ = align_up(bytes, 256);
+        if (hipMalloc(&base_, size_) != hipSuccess) {
+            base_ = nullptr;
+            return false;
+        }
+        free_[0] = size_;
+        return true;
+    }
+    ~DevicePool() {
+        if (base_) (void)hipFree(base_);
+    }
+    // Returns an offset or SIZE_MAX.
+    size_t alloc(size_t bytes) {
+        bytes = align_up(bytes, 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(bytes, 256);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    char* at(size_t off) const { return (char*)base_ + off; }
+    size_t size() const { return size_; }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+
+   private:
+    void* base_ = nullptr;
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+enum ReqState { PENDING = 0, ACTIVE = 1, DONE = 2, FAILED = 3 };
+
+struct Request {
+    int64_t id = 0;
+    int n = 0, T = 0, ld = 0, nnz = 0, kind = BATCH_TILE_128, ntiles = 0;
+    bool early = false;
+    int maxabs = 0;
+    std::vector<int32_t> rows, cols;
+    std::vector<uint32_t> w;
+    double arrival = 0, admitted = -1, done = -1;
+    int state = PENDING;
+    size_t off = SIZE_MAX, bytes = 0;   // matrices
+    size_t coo_off = SIZE_MAX, coo_bytes = 0;
+    void* buf[2] = {nullptr, nullptr};
+    int step = 0;       // completed squarings
+    int next_tile = 0;  // first tile of the current squaring not yet launched
+    int changed_acc = 0;  // some entry changed in the current squaring (early exit)
+};
+
+}  // namespace
+
+struct Server {
+    int device = 0;
+    int dt = BTAS_FLOAT32;
+    int mode = 0;
+    double quantum = 2e10;
+    hipStream_t stream = nullptr;
+    DevicePool pool;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> pending;
+    std::vector<Request*> active;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> all;
+    int64_t next_id = 1;
+    bool stop = false;
+    std::string error;
+    std::thread engine;
+
+    // engine-private staging (pinned host + device mirrors), grown on demand
+    BatchGraph* h_graphs = nullptr;
+    BatchItem* h_items = nullptr;
+    int* h_maxabs = nullptr;
+    int* h_changed = nullptr;
+    BatchGraph* d_graphs = nullptr;
+    BatchItem* d_items = nullptr;
+    int* d_maxabs = nullptr;
+    int* d_changed = nullptr;
+    size_t cap_graphs = 0, cap_items = 0;
+    // statistics
+    std::atomic<long> launches{0}, iterations{0};
+    double busy_s = 0;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    bool grow(size_t ng, size_t ni) {
+        if (ng > cap_graphs) {
+            size_t c = std::max(ng, cap_graphs * 2 + 64);
+            free_graph_staging();
+            if (hipHostMalloc((void**)&h_graphs, c * sizeof(BatchGraph), 0) != hipSuccess ||
+                hipHostMalloc((void**)&h_maxabs, c * sizeof(int), 0) != hipSuccess ||
+                hipHostMalloc((void**)&h_changed, c * sizeof(int), 0) != hipSuccess ||
+                hipMalloc((void**)&d_graphs, c * sizeof(BatchGraph)) != hipSuccess ||
+                hipMalloc((void**)&d_maxabs, c * sizeof(int)) != hipSuccess ||
+                hipMalloc((void**)&d_changed, c * sizeof(int)) != hipSuccess)
+                return false;
+            cap_graphs = c;
+        }
+        if (ni > cap_items) {
+            size_t c = std::max(ni, cap_items * 2 + 1024);
+            free_item_staging();
+            if (hipHostMalloc((void**)&h_items, c * sizeof(BatchItem), 0) != hipSuccess ||
+                hipMalloc((void**)&d_items, c * sizeof(BatchItem)) != hipSuccess)
+                return false;
+            cap_items = c;
+        }
+        return true;
+    }
+
+    // Called only between iterations, when the stream has drained.
+    void free_graph_staging() {
+        for (void** p : {(void**)&h_graphs, (void**)&h_maxabs, (void**)&h_changed})
+            if (*p) (void)hipHostFree(*p), *p = nullptr;
+        for (void** p : {(void**)&d_graphs, (void**)&d_maxabs, (void**)&d_changed})
+            if (*p) (void)hipFree(*p), *p = nullptr;
+        cap_graphs = 0;
+    }
+    void free_item_staging() {
+        if (h_items) (void)hipHostFree(h_items), h_items = nullptr;
+        if (d_items) (void)hipFree(d_items), d_items = nullptr;
+        cap_items = 0;
+    }
+    void free_staging() {
+        free_graph_staging();
+        free_item_staging();
+    }
+
+    // Caller holds mu.  Admit pending requests in arrival order while the pool
+    // has room.  FIFO mode admits only when nothing is active.
+    bool admit_locked(std::vector<Request*>& admitted) {
+        while (!pending.empty()) {
+            if (mode == BTAS_SERVE_FIFO && (!active.empty() || !admitted.empty())) break;
+            Request* r = pending.front();
+            const size_t half = align_up((size_t)r->n * r->ld * 4, 256);
+            const size_t off = pool.alloc(2 * half);
+            if (off == SIZE_MAX) break;
+            const size_t coo = align_up((size_t)r->nnz * 4, 256) * 3;
+            const size_t coff = r->nnz > 0 ? pool.alloc(coo) : SIZE_MAX;
+            if (r->nnz > 0 && coff == SIZE_MAX) {
+                pool.release(off, 2 * half);
+                break;
+            }
+            r->off = off;
+            r->bytes = 2 * half;
+            r->coo_off = coff;
+            r->coo_bytes = coo;
+            r->buf[0] = pool.at(off);
+            r->buf[1] = pool.at(off + half);
+            pending.pop_front();
+            admitted.push_back(r);
+        }
+        return !admitted.empty();
+    }
+
+    // Upload edges and densify on the engine stream (engine thread only).
+    hipError_t densify(Request* r) {
+        if (r->nnz > 0) {
+            const size_t seg = align_up((size_t)r->nnz * 4, 256);
+            char* base = pool.at(r->coo_off);
+            hipError_t e = hipMemcpyAsync(base, r->rows.data(), r->nnz * 4, hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(base + seg, r->cols.data(), r->nnz * 4, hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(base + 2 * seg, r->w.data(), r->nnz * 4, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return e;
+            return launch_densify(dt, r->buf[0], r->n, r->ld, r->nnz, (const int32_t*)base,
+                                  (const int32_t*)(base + seg), base + 2 * seg, stream);
+        }
+        return launch_densify(dt, r->buf[0], r->n, r->ld, 0, nullptr, nullptr, nullptr, stream);
+    }
+
+    void finish_locked(Request* r, double t) {
+        r->state = DONE;
+        r->done = t;
+        active.erase(std::remove(active.begin(), active.end(), r), active.end());
+    }
+
+    void fail_all_locked(const std::string& msg) {
+        error = msg;
+        for (Request* r : active) r->state = FAILED;
+        for (Request* r : pending) r->state = FAILED;
+        active.clear();
+        pending.clear();
+        cv_done.notify_all();
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            cv_work.wait(lk, [&] { return stop || !active.empty() || !pending.empty(); });
+            if (stop) break;
+            std::vector<Request*> admitted;
+            admit_locked(admitted);
+            if (active.empty() && admitted.empty()) {
+                // Head request does not fit yet: wait for a release.
+                cv_work.wait(lk);
+                continue;
+            }
+            lk.unlock();
+            const double it_start = now();
+            hipError_t e = hipSuccess;
+            for (Request* r : admitted)
+                if (e == hipSuccess) e = densify(r);
+            std::vector<Request*> launched;   // requests with tiles in this launch
+            std::vector<int> completes;       // 1 if the launch finishes their squaring
+            int nitems = 0, ngraphs = 0;
+            if (e == hipSuccess && mode == BTAS_SERVE_CONTINUOUS) {
+                std::vector<Request*> work;
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    work = active;
+                }
+                for (Request* r : admitted) work.push_back(r);
+                size_t need_items = 0;
+                for (Request* r : work) need_items += (size_t)(r->ntiles - r->next_tile);
+                if (!grow(work.size() + 1, need_items + 1)) e = hipErrorOutOfMemory;
+                for (size_t i = 0; e == hipSuccess && i < work.size(); ++i) {
+                    Request* r = work[i];
+                    if (r->step >= r->T) continue;
+                    const int tile = r->kind == BATCH_TILE_128 ? 128 : 64;
+                    const double per_tile = (double)tile * tile * r->n;
+                    int take = (int)std::max(1.0, quantum / per_tile);
+                    take = std::min(take, r->ntiles - r->next_tile);
+                    const int gi = ngraphs++;
+                    h_graphs[gi] = {{r->buf[0], r->buf[1]}, r->n, r->ld, r->T, 0};
+                    h_maxabs[gi] = r->maxabs;
+                    h_changed[gi] = 0;
+                    const int per_row = batch_tiles_of(r->n, r->kind);
+                    for (int t = r->next_tile; t < r->next_tile + take; ++t)
+                        h_items[nitems++] = {gi, t / per_row, t % per_row, r->kind, r->step + 1, 0};
+                    r->next_tile += take;
+                    launched.push_back(r);
+                    completes.push_back(r->next_tile == r->ntiles);
+                }
+                if (e == hipSuccess && nitems > 0) {
+                    e = hipMemcpyAsync(d_graphs, h_graphs, ngraphs * sizeof(BatchGraph), hipMemcpyHostToDevice, stream);
+                    if (e == hipSuccess) e = hipMemcpyAsync(d_maxabs, h_maxabs, ngraphs * sizeof(int), hipMemcpyHostToDevice, stream);
+                    if (e == hipSuccess) e = hipMemcpyAsync(d_items, h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream);
+                    // changed flags accumulate over the launches of one squaring:
+                    // they are kept per request on the host (see below)
+                    if (e == hipSuccess) e = hipMemcpyAsync(d_changed, h_changed, ngraphs * sizeof(int), hipMemcpyHostToDevice, stream);
+                    if (e == hipSuccess)
+                        e = launch_grouped_step(dt, d_graphs, d_items, nitems,
+                                                dt == BTAS_INT32 ? d_maxabs : nullptr, d_changed, stream);
+                    if (e == hipSuccess) e = hipMemcpyAsync(h_changed, d_changed, ngraphs * sizeof(int), hipMemcpyDeviceToHost, stream);
+                    launches++;
+                }
+            } else if (e == hipSuccess && mode == BTAS_SERVE_FIFO) {
+                // Plain path: every squaring of the admitted request as one GEMM launch.
+                for (Request* r : admitted) {
+                    int cur = 0;
+                    for (int t = 0; t < r->T && e == hipSuccess; ++t) {
+                        GemmArgs a{r->n, r->n, r->n, r->buf[cur], r->ld, r->buf[cur], r->ld,
+                                   r->buf[cur], r->ld, r->buf[cur ^ 1], r->ld, nullptr, nullptr, nullptr};
+                        e = launch_gemm(BTAS_MIN_PLUS, dt, a, -1, stream);
+                        cur ^= 1;
+                        launches++;
+                    }
+                    r->step = r->T;
+                }
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            const double t_end = now();
+            busy_s += t_end - it_start;
+            iterations++;
+            lk.lock();
+            if (e != hipSuccess) {
+                fail_all_locked(std::string("engine: HIP error ") + hipGetErrorString(e));
+                continue;
+            }
+            for (Request* r : admitted) {
+                if (r->coo_off != SIZE_MAX) {
+                    pool.release(r->coo_off, r->coo_bytes);
+                    r->coo_off = SIZE_MAX;
+                }
+                r->admitted = it_start;
+                r->state = ACTIVE;
+                active.push_back(r);
+            }
+            for (size_t i = 0; i < launched.size(); ++i) {
+                Request* r = launched[i];
+                r->changed_acc |= h_changed[i];
+                if (!completes[i]) continue;
+                const bool changed = r->changed_acc != 0;
+                r->changed_acc = 0;
+                r->step += 1;
+                r->next_tile = 0;
+                if (r->step >= r->T || (r->early && !changed)) {
+                    r->T = r->step;  // squarings actually executed
+                    finish_locked(r, t_end);
+                }
+            }
+            for (Request* r : admitted)
+                if (r->state == ACTIVE && r->step >= r->T) finish_locked(r, t_end);
+            cv_done.notify_all();
+        }
+    }
+};
+
+}  // namespace btas
+
+using btas::Server;
+
+struct btas_server {
+    Server s;
+};
+
+extern "C" {
+
+btas_status_t btas_server_create(btas_server_t* out, int device, btas_dtype_t dt,
+                                 size_t budget_bytes, int mode, double quantum_terms) {
+    if (!out) return BTAS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (dt != BTAS_INT32 && dt != BTAS_FLOAT32) return BTAS_ERR_INVALID_ARG;
+    if (mode != BTAS_SERVE_CONTINUOUS && mode != BTAS_SERVE_FIFO) return BTAS_ERR_INVALID_ARG;
+    if (budget_bytes < 4096) return BTAS_ERR_INVALID_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return BTAS_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return BTAS_ERR_DEVICE;
+    std::unique_ptr<btas_server> srv(new btas_server);
+    Server& s = srv->s;
+    s.device = device;
+    s.dt = dt;
+    s.mode = mode;
+    if (quantum_terms > 0) s.quantum = quantum_terms;
+    if (!s.pool.init(budget_bytes)) return BTAS_ERR_OOM;
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return BTAS_ERR_DEVICE;
+    s.engine = std::thread([p = &s] { p->run(); });
+    *out = srv.release();
+    return BTAS_OK;
+}
+
+btas_status_t btas_server_destroy(btas_server_t srv) {
+    if (!srv) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    {
+        std::lock_guard<std::mutex> g(s.mu);
+        s.stop = true;
+    }
+    s.cv_work.notify_all();
+    if (s.engine.joinable()) s.engine.join();
+    (void)hipSetDevice(s.device);
+    if (s.stream) {
+        (void)hipStreamSynchronize(s.stream);
+        (void)hipStreamDestroy(s.stream);
+    }
+    s.free_staging();
+    delete srv;
+    return BTAS_OK;
+}
+
+double btas_server_now(btas_server_t srv) { return srv ? srv->s.now() : -1.0; }
+
+btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_t* rows,
+                                 const int32_t* cols, const void* w, unsigned flags,
+                                 double arrival, int64_t* id_out) {
+    if (!srv || n < 0 || nnz < 0 || (nnz > 0 && (!rows || !cols || !w)) || !id_out)
+        return BTAS_ERR_INVALID_ARG;
+    if (flags & ~(unsigned)BTAS_APSP_EARLY_EXIT) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    try {
+    std::unique_ptr<btas::Request> r(new btas::Request);
+    r->n = n;
+    r->T = btas::steps_for(n);
+    r->ld = (int)btas::align_up(std::max(n, 1), 4);
+    r->nnz = nnz;
+    r->early = flags & BTAS_APSP_EARLY_EXIT;
+    r->rows.assign(rows, rows + nnz);
+    r->cols.assign(cols, cols + nnz);
+    r->w.resize(nnz);
+    if (nnz) std::memcpy(r->w.data(), w, (size_t)nnz * 4);
+    for (int e = 0; e < nnz; ++e)  // the densify kernel writes D[rows[e]][cols[e]]
+        if (rows[e] < 0 || rows[e] >= n || cols[e] < 0 || cols[e] >= n) return BTAS_ERR_INVALID_ARG;
+    int mx = 0;
+    if (s.dt == BTAS_INT32) {
+        for (int e = 0; e < nnz; ++e) {
+            const int32_t v = (int32_t)r->w[e];
+            if (v == BTAS_I32_INF) continue;
+            if (v < -BTAS_I32_FINITE_MAX || v > BTAS_I32_FINITE_MAX) return BTAS_ERR_DOMAIN;
+            mx = std::max(mx, v < 0 ? -v : v);
+        }
+    } else {
+        for (int e = 0; e < nnz; ++e) {
+            float v;
+            std::memcpy(&v, &r->w[e], 4);
+            if (v != v || v == -__builtin_inff()) return BTAS_ERR_DOMAIN;
+        }
+    }
+    r->maxabs = mx;
+    // Tile shape: padded-area model (64-wide tiles charged 15% more per element).
+    const double a128 = std::pow((double)btas::batch_tiles_of(n, btas::BATCH_TILE_128) * 128, 2);
+    const double a64 = std::pow((double)btas::batch_tiles_of(n, btas::BATCH_TILE_64) * 64, 2) * 1.15;
+    r->kind = a128 <= a64 ? btas::BATCH_TILE_128 : btas::BATCH_TILE_64;
+    const int per_row = btas::batch_tiles_of(n, r->kind);
+    r->ntiles = per_row * per_row;
+    const size_t need = 2 * btas::align_up((size_t)n * r->ld * 4, 256) +
+                        3 * btas::align_up((size_t)nnz * 4, 256);
+    if (need > s.pool.size()) return BTAS_ERR_OOM;
+    {
+        std::lock_guard<std::mutex> g(s.mu);
+        if (!s.error.empty()) return BTAS_ERR_DEVICE;
+        r->id = s.next_id++;
+        r->arrival = arrival >= 0 ? arrival : s.now();
+        *id_out = r->id;
+        s.pending.push_back(r.get());
+        s.all[r->id] = std::move(r);
+    }
+    s.cv_work.notify_all();
+    return BTAS_OK;
+    } catch (...) {
+        return BTAS_ERR_OOM;
+    }
+}
+
+btas_status_t btas_server_wait(btas_server_t srv, int64_t id, double timeout_s, int* done) {
+    if (!srv) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    std::unique_lock<std::mutex> lk(s.mu);
+    auto it = s.all.find(id);
+    if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+    btas::Request* r = it->second.get();
+    auto ready = [&] { return r->state == btas::DONE || r->state == btas::FAILED; };
+    if (timeout_s < 0) s.cv_done.wait(lk, ready);
+    else s.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+    if (done) *done = r->state == btas::DONE;
+    return r->state == btas::FAILED ? BTAS_ERR_DEVICE : BTAS_OK;
+}
+
+btas_status_t btas_server_result(btas_server_t srv, int64_t id, const void** D_dev, int* ldd,
+                                 int* steps) {
+    if (!srv) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    std::lock_guard<std::mutex> g(s.mu);
+    auto it = s.all.find(id);
+    if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+    btas::Request* r = it->second.get();
+    if (r->state != btas::DONE) return BTAS_ERR_INVALID_ARG;
+    if (D_dev) *D_dev = r->buf[r->T & 1];
+    if (ldd) *ldd = r->ld;
+    if (steps) *steps = r->T;
+    return BTAS_OK;
+}
+
+btas_status_t btas_server_copy_result(btas_server_t srv, int64_t id, void* D, int ldd) {
+    if (!srv || !D) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    const void* src;
+    int n, ld;
+    {
+        std::lock_guard<std::mutex> g(s.mu);
+        auto it = s.all.find(id);
+        if (it == s.all.end() || it->second->state != btas::DONE) return BTAS_ERR_INVALID_ARG;
+        btas::Request* r = it->second.get();
+        src = r->buf[r->T & 1];
+        n = r->n;
+        ld = r->ld;
+    }
+    if (n == 0) return BTAS_OK;
+    if (ldd < n) return BTAS_ERR_INVALID_ARG;
+    (void)hipSetDevice(s.device);
+    hipError_t e = hipMemcpy2D(D, (size_t)ldd * 4, src, (size_t)ld * 4, (size_t)n * 4, n,
+                               hipMemcpyDeviceToDevice);
+    return e == hipSuccess ? BTAS_OK : BTAS_ERR_DEVICE;
+}
+
+btas_status_t btas_server_times(btas_server_t srv, int64_t id, double* arrival, double* admitted,
+                                double* done) {
+    if (!srv) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    std::lock_guard<std::mutex> g(s.mu);
+    auto it = s.all.find(id);
+    if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+    btas::Request* r = it->second.get();
+    if (arrival) *arrival = r->arrival;
+    if (admitted) *admitted = r->admitted;
+    if (done) *done = r->done;
+    return BTAS_OK;
+}
+
+btas_status_t btas_server_release(btas_server_t srv, int64_t id) {
+    if (!srv) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    {
+        std::lock_guard<std::mutex> g(s.mu);
+        auto it = s.all.find(id);
+        if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+        btas::Request* r = it->second.get();
+        if (r->state != btas::DONE && r->state != btas::FAILED) return BTAS_ERR_INVALID_ARG;
+        if (r->off != SIZE_MAX) s.pool.release(r->off, r->bytes);
+        s.all.erase(it);
+    }
+    s.cv_work.notify_all();
+    return BTAS_OK;
+}
+
+btas_status_t btas_server_stats(btas_server_t srv, btas_server_stats_t* out) {
+    if (!srv || !out) return BTAS_ERR_INVALID_ARG;
+    Server& s = srv->s;
+    std::lock_guard<std::mutex> g(s.mu);
+    out->iterations = s.iterations.load();
+    out->launches = s.launches.load();
+    out->busy_seconds = s.busy_s;
+    out->pool_bytes = s.pool.size();
+    out->pool_used_bytes = s.pool.used();
+    out->pool_peak_bytes = s.pool.peak();
+    out->active = (int)s.active.size();
+    out->pending = (int)s.pending.size();
+    return s.error.empty() ? BTAS_OK : BTAS_ERR_DEVICE;
+}
+
+}  // extern "C"

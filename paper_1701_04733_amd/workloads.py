@@ -97,21 +97,20 @@ def er_digraph_i32(n: int, p: float, w_lo: int, w_hi: int, seed) -> np.ndarray:
 
 
 def _sparse_rows(g: np.random.Generator, n: int, p: float):
-    """Per-row sorted column lists of an ER digraph without self loops."""
-    degs = g.binomial(n - 1, p, size=n) if n > 1 else np.zeros(n, dtype=np.int64)
-    rows, cols = [], []
-    for i in range(n):
-        d = int(degs[i])
-        if d == 0:
-            continue
-        c = g.choice(n - 1, size=d, replace=False)
-        c = np.where(c >= i, c + 1, c)
-        c.sort()
-        rows.append(np.full(d, i, dtype=np.int64))
-        cols.append(c.astype(np.int64))
-    if rows:
-        return np.concatenate(rows), np.concatenate(cols)
-    return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    """Edges (rows, cols) of an ER digraph without self loops, sorted.
+
+    The edge count is Binomial(n(n-1), p) and the edge set a uniform subset of
+    that size of the n(n-1) ordered pairs, which is the same law as one
+    independent coin per pair."""
+    if n < 2:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    pairs = n * (n - 1)
+    m = int(g.binomial(pairs, p))
+    idx = np.sort(g.choice(pairs, size=m, replace=False))
+    r = idx // (n - 1)
+    c = idx % (n - 1)
+    c = c + (c >= r)
+    return r.astype(np.int64), c.astype(np.int64)
 
 
 def sparse_digraph_f32_exp(n: int, mean_degree: float, seed, mean_weight: float = 1.0):

@@ -1,0 +1,140 @@
+"""Served APSP: every request's result equals the oracle, and is the same bits
+alone and in a mix of concurrently served requests; admission respects the
+memory budget; early exit gives the fixed-T result."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(x):
+    x = np.ascontiguousarray(x).copy()
+    if x.dtype == np.float32:
+        x[x == 0] = 0.0
+    return x.view(np.uint32)
+
+
+def _requests(count, seed, lo=32, hi=600):
+    return wl.served_requests(count, rate=1000.0, lo=lo, hi=hi, seed=seed)
+
+
+def _dense(req, dtype=np.float32):
+    if dtype == np.float32:
+        return wl.coo_to_dense_f32(req.n, req.rows, req.cols, req.w)
+    W = np.full((req.n, req.n), wl.I32_INF, np.int32)
+    W[req.rows, req.cols] = req.w
+    np.fill_diagonal(W, 0)
+    return W
+
+
+def _fetch(srv, rid, n, dev, dtype):
+    import torch
+    out = torch.empty((n, n), dtype=dtype, device=dev)
+    srv.result_into(rid, out)
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["continuous", "fifo"])
+def test_served_mix_matches_oracle_and_alone(dev, mode):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    reqs = _requests(24, seed=31)
+    with btas.Server("f32", budget_bytes=4 << 30, mode=mode, quantum_terms=2e8) as srv:
+        ids = [srv.submit(r.n, r.rows, r.cols, r.w) for r in reqs]      # all at once: a mix
+        mixed = {}
+        for r, rid in zip(reqs, ids):
+            assert srv.wait(rid, timeout=120)
+            mixed[r.rid] = _fetch(srv, rid, r.n, dev, torch.float32)
+            assert srv.steps(rid) == oracle.apsp_steps(r.n)
+            srv.release(rid)
+        st = srv.stats()
+        assert st["active"] == 0 and st["pending"] == 0 and st["pool_used_bytes"] == 0
+        if mode == "continuous":
+            assert st["launches"] < sum(oracle.apsp_steps(r.n) for r in reqs)  # shared launches
+    with btas.Server("f32", budget_bytes=4 << 30, mode="continuous") as alone_srv:
+        for r in reqs:
+            rid = alone_srv.submit(r.n, r.rows, r.cols, r.w)
+            assert alone_srv.wait(rid, timeout=120)
+            alone = _fetch(alone_srv, rid, r.n, dev, torch.float32)
+            alone_srv.release(rid)
+            assert np.array_equal(_bits(alone), _bits(mixed[r.rid])), f"request {r.rid} n={r.n}"
+            want, _, _ = oracle.apsp(_dense(r))
+            assert np.array_equal(_bits(alone), _bits(want)), f"request {r.rid} vs oracle"
+
+
+def test_served_early_exit_same_bits(dev):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    reqs = _requests(10, seed=32, lo=40, hi=400)
+    with btas.Server("f32", budget_bytes=2 << 30) as srv:
+        fixed = [srv.submit(r.n, r.rows, r.cols, r.w) for r in reqs]
+        early = [srv.submit(r.n, r.rows, r.cols, r.w, early_exit=True) for r in reqs]
+        for r, a, b in zip(reqs, fixed, early):
+            assert srv.wait(a, 120) and srv.wait(b, 120)
+            da = _fetch(srv, a, r.n, dev, torch.float32)
+            db = _fetch(srv, b, r.n, dev, torch.float32)
+            assert np.array_equal(_bits(da), _bits(db))
+            want, wsteps, _ = oracle.apsp(_dense(r), early_exit=True)
+            assert srv.steps(b) == wsteps <= srv.steps(a)
+            srv.release(a)
+            srv.release(b)
+
+
+def test_served_budget_admission(dev):
+    """A budget that holds only a couple of requests at a time still serves all
+    of them, never exceeding the pool."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    reqs = _requests(12, seed=33, lo=200, hi=300)
+    per = max(2 * ((r.n + 3) // 4 * 4) * r.n * 4 for r in reqs)
+    budget = 3 * per
+    with btas.Server("f32", budget_bytes=budget) as srv:
+        ids = [srv.submit(r.n, r.rows, r.cols, r.w) for r in reqs]
+        spans = []
+        for r, rid in zip(reqs, ids):
+            assert srv.wait(rid, 120)
+            got = _fetch(srv, rid, r.n, dev, torch.float32)
+            spans.append(srv.times(rid)[1:])
+            srv.release(rid)
+            want, _, _ = oracle.apsp(_dense(r))
+            assert np.array_equal(_bits(got), _bits(want))
+        st = srv.stats()
+        assert st["pool_peak_bytes"] <= st["pool_bytes"] <= budget + 256
+        # no more requests were resident at once than the budget holds
+        least = min(2 * ((r.n + 3) // 4 * 4) * r.n * 4 for r in reqs)
+        events = sorted([(a, 1) for a, _ in spans] + [(d, -1) for _, d in spans])
+        live = peak = 0
+        for _, e in events:
+            live += e
+            peak = max(peak, live)
+        assert peak <= budget // least
+
+
+def test_served_int32_and_errors(dev):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    g = wl.rng(7)
+    with btas.Server("i32", budget_bytes=1 << 30) as srv:
+        for n in (1, 2, 3, 57, 130):
+            r, c = wl._sparse_rows(g, n, min(1.0, 5.0 / max(n, 1)))
+            w = g.integers(1, 100, size=r.size, endpoint=True).astype(np.int32)
+            rid = srv.submit(n, r, c, w)
+            assert srv.wait(rid, 60)
+            got = _fetch(srv, rid, n, dev, torch.int32)
+            W = np.full((n, n), wl.I32_INF, np.int32)
+            W[r, c] = w
+            np.fill_diagonal(W, 0)
+            want, _, _ = oracle.apsp(W)
+            assert np.array_equal(got, want)
+            srv.release(rid)
+        with pytest.raises(btas.BtasError, match="INVALID_ARG"):
+            srv.submit(4, np.array([0, 4]), np.array([1, 2]), np.array([1, 1], np.int32))
+        with pytest.raises(btas.BtasError, match="DOMAIN"):
+            srv.submit(4, np.array([0]), np.array([1]), np.array([1 << 29], np.int32))
