@@ -82,8 +82,9 @@ def _events():
 
 def bench_apsp_small(dev, reps=200):
     """One APSP on an ER digraph, n=256, p=0.05, int32 weights U{1..100}, T=8:
-    per-solve latency of the plain path (init + 8 GEMM launches) and of the
-    same solve as one captured hipGraph launch."""
+    per-solve latency of the plain path (init + 8 split-K squarings), of the
+    same sequence captured as one hipGraph launch, and of the batched path
+    with a single graph."""
     import numpy as np
     import torch
 
@@ -93,7 +94,9 @@ def bench_apsp_small(dev, reps=200):
     D = torch.empty_like(W)
     g = btas.BatchedAPSP([W], [D])
     out = {"workload": "APSP n=256 ER p=0.05 int32 U{1..100}, T=8 squarings"}
-    for name, fn in (("plain", lambda: btas.apsp(W, out=D, return_steps=False)), ("graph", g.run)):
+    for name, fn in (("plain", lambda: btas.apsp(W, out=D, return_steps=False)),
+                     ("graph", lambda: btas.apsp(W, out=D, return_steps=False, graph=True)),
+                     ("batched_one_graph", g.run)):
         for _ in range(10):
             fn()
         torch.cuda.synchronize()

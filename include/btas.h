@@ -157,6 +157,10 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     Reads a device flag back after every step (host synchronisation).
  *   BTAS_APSP_CHECK_NEG_CYCLE: after the last step, return
  *     BTAS_WARN_NEG_CYCLE if some D_ii < 0 (synchronises).
+ *   BTAS_APSP_GRAPH: capture the whole fixed-T solve into a hipGraph on the
+ *     first call with a given (dtype, n, W, ldw, D, ldd) and replay it on later
+ *     calls (one launch per solve; for latency-bound small n).  The handle
+ *     keeps one such graph.  Not combinable with EARLY_EXIT.
  * steps_out: host int receiving the number of squarings executed (may be
  * NULL; when non-NULL the call synchronises).  Integer contract: all finite
  * path lengths must stay within +-BTAS_I32_FINITE_MAX.  The handle keeps an
@@ -164,6 +168,7 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  */
 #define BTAS_APSP_EARLY_EXIT 1u
 #define BTAS_APSP_CHECK_NEG_CYCLE 2u
+#define BTAS_APSP_GRAPH 4u
 btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n,
                                  const void *W, int ldw, void *D, int ldd,
                                  unsigned flags, int *steps_out);

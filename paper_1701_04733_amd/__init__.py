@@ -28,7 +28,7 @@ I32_FINITE_MAX = (1 << 29) - 1
 
 MIN_PLUS, MAX_PLUS = 0, 1
 INT32, FLOAT32 = 0, 1
-APSP_EARLY_EXIT, APSP_CHECK_NEG_CYCLE = 1, 2
+APSP_EARLY_EXIT, APSP_CHECK_NEG_CYCLE, APSP_GRAPH = 1, 2, 4
 
 STATUS = {0: "BTAS_OK", 1: "BTAS_ERR_INVALID_ARG", 2: "BTAS_ERR_ALIAS", 3: "BTAS_ERR_DOMAIN",
           4: "BTAS_ERR_OOM", 5: "BTAS_ERR_DEVICE", 6: "BTAS_ERR_UNSUPPORTED",
@@ -306,7 +306,8 @@ def axpy(alpha, x, y, semiring="min", handle=None):
     return y
 
 
-def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True, handle=None):
+def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True, graph=False,
+         handle=None):
     """All-pairs shortest paths by repeated min-plus squaring of I (+) W.
 
     Returns (D, steps, status); status is OK or WARN_NEG_CYCLE.  With
@@ -322,9 +323,10 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     h = _handle_for(W, handle)
     pw, ldw = _mat(W, "W")
     pd, ldd = _mat(out, "D")
-    flags = (APSP_EARLY_EXIT if early_exit else 0) | (APSP_CHECK_NEG_CYCLE if check_neg_cycle else 0)
+    flags = (APSP_EARLY_EXIT if early_exit else 0) | (APSP_CHECK_NEG_CYCLE if check_neg_cycle else 0) \
+        | (APSP_GRAPH if graph else 0)
     steps = ctypes.c_int(0)
-    sp = ctypes.byref(steps) if (return_steps or flags) else None
+    sp = ctypes.byref(steps) if (return_steps or (flags & ~APSP_GRAPH)) else None
     st = h.check(lib().btas_apsp_squaring(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
                  allow=(OK, WARN_NEG_CYCLE))
     return out, (steps.value if sp is not None else None), st

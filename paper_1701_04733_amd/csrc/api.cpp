@@ -55,6 +55,32 @@ btas_status_t validate_operands(btas_handle_t h, const char* fn, int sr, int dt,
     return BTAS_OK;
 }
 
+// The fixed-T squaring sequence (no host synchronisation): flag resets, D_0 =
+// I (+) W, T squarings ping-ponging between D and the workspace so that the
+// last one lands in D.
+hipError_t enqueue_fixed_apsp(btas_handle_t h, btas_dtype_t dt, int n, const void* W, int ldw,
+                              void* D, int ldd, int T, hipStream_t s) {
+    void* bufs[2] = {D, h->ws};
+    long lds[2] = {ldd, n};
+    int cur = (T % 2 == 0) ? 0 : 1;
+    // int32: slot FLAG_STEP_WIDE + t records whether D_t left the binary32-exact
+    // range; the init kernel fills slot 0 and step t reads slot t-1, writes slot t.
+    int* wide = dt == BTAS_INT32 ? h->dflags + FLAG_STEP_WIDE : nullptr;
+    hipError_t e = hipSuccess;
+    if (wide) e = btas::launch_clear_flags(wide, T + 1, s);
+    if (e == hipSuccess) e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], wide, s);
+    for (int t = 0; t < T && e == hipSuccess; ++t) {
+        const int nxt = cur ^ 1;
+        btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
+                         bufs[nxt], lds[nxt], nullptr,
+                         wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr,
+                         h->skws, h->skws_bytes};
+        e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, s);
+        cur = nxt;
+    }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -109,8 +135,11 @@ btas_status_t btas_destroy(btas_handle_t h) {
     DeviceGuard g(h->device);
     (void)hipStreamSynchronize(h->stream);
     h->batch_plan.reset();
+    if (h->apsp_exec) (void)hipGraphExecDestroy(h->apsp_exec);
+    if (h->apsp_graph) (void)hipGraphDestroy(h->apsp_graph);
     if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->skws) (void)hipFree(h->skws);
     if (h->partials) (void)hipFree(h->partials);
     if (h->dflags) (void)hipFree(h->dflags);
     if (h->hflags) (void)hipHostFree(h->hflags);
@@ -169,7 +198,10 @@ btas_status_t btas_tropical_gemm(btas_handle_t h, btas_semiring_t sr, btas_dtype
         if (e == hipSuccess) e = btas::launch_range_scan(sr, k, n, B, ldb, wide, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
     }
-    btas::GemmArgs a{m, n, k, A, lda, B, ldb, C, ldc, C, ldc, nullptr, wide, nullptr};
+    if (ensure_splitk(h, btas::gemm_splitk_bytes(m, n, k)) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
+    btas::GemmArgs a{m, n, k, A, lda, B, ldb, C, ldc, C, ldc, nullptr, wide, nullptr,
+                     h->skws, h->skws_bytes};
     e = btas::launch_gemm(sr, dt, a, -1, h->stream);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
 }
@@ -315,8 +347,10 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (ldw=%d) < max(1,n=%d)", fn, ldw, n);
     if (ldd < (n > 1 ? n : 1))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (ldd=%d) < max(1,n=%d)", fn, ldd, n);
-    if (flags & ~(BTAS_APSP_EARLY_EXIT | BTAS_APSP_CHECK_NEG_CYCLE))
+    if (flags & ~(BTAS_APSP_EARLY_EXIT | BTAS_APSP_CHECK_NEG_CYCLE | BTAS_APSP_GRAPH))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (flags=0x%x) has unknown bits", fn, flags);
+    if ((flags & BTAS_APSP_EARLY_EXIT) && (flags & BTAS_APSP_GRAPH))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: EARLY_EXIT and GRAPH cannot be combined", fn);
     if (n > 0 && (!W || !D)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W or D is null", fn);
     const bool in_place = W == D && ldw == ldd;
     if (!in_place && overlap(mat_span(W, n, n, ldw), mat_span(D, n, n, ldd)))
@@ -342,43 +376,84 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
             return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
         h->ws_bytes = need;
     }
+    if (T > 0 && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
     const bool early = flags & BTAS_APSP_EARLY_EXIT;
-    // Ping-pong between D and the workspace, starting where an even/odd
-    // number of fixed steps ends in D.
-    void* bufs[2] = {D, h->ws};
-    long lds[2] = {ldd, n};
-    int cur = (T % 2 == 0) ? 0 : 1;
-    // int32: slot FLAG_STEP_WIDE + t records whether D_t left the binary32-exact
-    // range; the init kernel fills slot 0 and step t reads slot t-1, writes slot t.
-    int* wide = dt == BTAS_INT32 ? h->dflags + FLAG_STEP_WIDE : nullptr;
     hipError_t e = hipSuccess;
-    if (wide) e = btas::launch_clear_flags(wide, T + 1, h->stream);
-    if (e == hipSuccess) e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], wide, h->stream);
-    if (e != hipSuccess) return device_fail(h, fn, e);
     int steps = 0;
-    for (int t = 0; t < T; ++t) {
-        const int nxt = cur ^ 1;
-        int* changed = h->dflags + FLAG_CHANGED;
-        if (early) {
+    if (!early && (flags & BTAS_APSP_GRAPH)) {
+        // One hipGraph per argument set: capture once on the auxiliary stream,
+        // replay on the handle's stream.
+        uint64_t key = 0x9E37ull;
+        for (uint64_t v : {(uint64_t)dt, (uint64_t)n, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
+                           (uint64_t)(uintptr_t)D, (uint64_t)ldd, (uint64_t)(uintptr_t)h->ws,
+                           (uint64_t)(uintptr_t)h->skws, (uint64_t)h->skws_bytes})
+            key = (key ^ (v + 0x9E3779B97F4A7C15ull + (key << 6) + (key >> 2)));
+        if (!h->apsp_exec || h->apsp_key != key) {
+            if (h->apsp_exec) {
+                e = hipStreamSynchronize(h->stream);
+                (void)hipGraphExecDestroy(h->apsp_exec);
+                (void)hipGraphDestroy(h->apsp_graph);
+                h->apsp_exec = nullptr;
+                h->apsp_graph = nullptr;
+                if (e != hipSuccess) return device_fail(h, fn, e);
+            }
+            if (!h->aux_stream) {
+                e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return device_fail(h, fn, e);
+            }
+            e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+            e = enqueue_fixed_apsp(h, dt, n, W, ldw, D, ldd, T, h->aux_stream);
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&h->apsp_exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                h->apsp_exec = nullptr;
+                return device_fail(h, fn, e);
+            }
+            h->apsp_graph = graph;
+            h->apsp_key = key;
+        }
+        e = hipGraphLaunch(h->apsp_exec, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        steps = T;
+    } else if (!early) {
+        e = enqueue_fixed_apsp(h, dt, n, W, ldw, D, ldd, T, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        steps = T;
+    } else {
+        // Early exit: the same sequence, reading the change flag after each squaring.
+        void* bufs[2] = {D, h->ws};
+        long lds[2] = {ldd, n};
+        int cur = (T % 2 == 0) ? 0 : 1;
+        int* wide = dt == BTAS_INT32 ? h->dflags + FLAG_STEP_WIDE : nullptr;
+        if (wide) e = btas::launch_clear_flags(wide, T + 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], wide, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        for (int t = 0; t < T; ++t) {
+            const int nxt = cur ^ 1;
+            int* changed = h->dflags + FLAG_CHANGED;
             e = btas::launch_clear_flags(changed, 1, h->stream);
             if (e != hipSuccess) return device_fail(h, fn, e);
-        }
-        btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
-                         bufs[nxt], lds[nxt], early ? changed : nullptr,
-                         wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr};
-        e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, h->stream);
-        if (e != hipSuccess) return device_fail(h, fn, e);
-        ++steps;
-        cur = nxt;
-        if (early) {
+            btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
+                             bufs[nxt], lds[nxt], changed,
+                             wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr,
+                             h->skws, h->skws_bytes};
+            e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, h->stream);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+            ++steps;
+            cur = nxt;
             btas_status_t st = sync_flags(h, fn, FLAG_CHANGED + 1);
             if (st != BTAS_OK) return st;
             if (h->hflags[FLAG_CHANGED] == 0) break;
         }
-    }
-    if (cur != 0) {
-        e = btas::launch_copy_matrix(n, n, bufs[cur], lds[cur], D, ldd, h->stream);
-        if (e != hipSuccess) return device_fail(h, fn, e);
+        if (cur != 0) {
+            e = btas::launch_copy_matrix(n, n, bufs[cur], lds[cur], D, ldd, h->stream);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+        }
     }
     btas_status_t result = BTAS_OK;
     if (flags & BTAS_APSP_CHECK_NEG_CYCLE) {

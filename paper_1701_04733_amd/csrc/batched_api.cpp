@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -249,6 +250,15 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                         if (e != hipSuccess) return device_fail(h, fn, e);
                     }
                     kind = ms_of[BATCH_TILE_64] < ms_of[BATCH_TILE_128] ? BATCH_TILE_64 : BATCH_TILE_128;
+                    if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1') {
+                        double terms = 0;
+                        for (int g : kv.second) terms += (double)hg[g].n * hg[g].n * hg[g].n;
+                        fprintf(stderr, "[btas] autotune dt=%d bucket=%d n<=%d graphs=%zu: 128-tile %.3f ms, "
+                                "64-tile %.3f ms (%.1f / %.1f Tterm/s) -> %d\n", (int)dt, kv.first, rep,
+                                kv.second.size(), ms_of[BATCH_TILE_128], ms_of[BATCH_TILE_64],
+                                terms / ms_of[BATCH_TILE_128] / 1e9, terms / ms_of[BATCH_TILE_64] / 1e9,
+                                kind == BATCH_TILE_128 ? 128 : 64);
+                    }
                     h->tile_choice[{(int)dt, kv.first}] = kind;
                 }
             }

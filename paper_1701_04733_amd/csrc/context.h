@@ -30,10 +30,15 @@ struct btas_ctx {
     void* ws = nullptr;                  // APSP ping-pong partner matrix
     size_t ws_bytes = 0;
     void* partials = nullptr;            // dot reduction partials
+    void* skws = nullptr;                // split-K partial products
+    size_t skws_bytes = 0;
     int* dflags = nullptr;               // device flags [kNumFlags], see the FLAG_* slots
     int* hflags = nullptr;               // pinned host mirror
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> tile shape
+    hipGraph_t apsp_graph = nullptr;     // last captured single-solve graph (BTAS_APSP_GRAPH)
+    hipGraphExec_t apsp_exec = nullptr;
+    uint64_t apsp_key = 0;
 };
 
 namespace btas {
@@ -95,6 +100,22 @@ inline Span vec_span(const void* p, long n, long inc) {
 }
 inline bool overlap(const Span& a, const Span& b) {
     return !a.empty() && !b.empty() && a.lo < b.hi && b.lo < a.hi;
+}
+
+// Grow the split-K workspace to `need` bytes (0: nothing to do).  The old
+// buffer may still be read by queued work, so the stream is drained first.
+inline hipError_t ensure_splitk(btas_handle_t h, size_t need) {
+    if (need <= h->skws_bytes) return hipSuccess;
+    if (h->skws) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return e;
+        (void)hipFree(h->skws);
+        h->skws = nullptr;
+        h->skws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->skws, need);
+    if (e == hipSuccess) h->skws_bytes = need;
+    return e;
 }
 
 inline int apsp_steps(int n) {

@@ -26,6 +26,7 @@
 //    the host never waits for it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "gemm_tile.h"
@@ -65,6 +66,77 @@ __global__ __launch_bounds__(Cfg::NT) void tropical_gemm_kernel(TileArgs<T> a,
     GemmTile<Cfg, T, T, SR, VEC>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
 }
 
+// Split-K: blockIdx.x = tile * S + chunk; the chunk's partial product goes to
+// ws[chunk] (m x n, leading dimension n), Cin is not read.
+template <typename Cfg, typename T, int SR, bool VEC>
+__global__ __launch_bounds__(Cfg::NT) void tropical_gemm_splitk_kernel(TileArgs<T> a, int S, int kc,
+                                                                        T* ws, const int* wide_in) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nbm = (a.m + Cfg::BM - 1) / Cfg::BM;
+    const int nbn = (a.n + Cfg::BN - 1) / Cfg::BN;
+    const int tile = blockIdx.x / S, chunk = blockIdx.x - tile * S;
+    const int tm = tile / nbn, tn = tile - tm * nbn;
+    (void)nbm;
+    const int k0 = chunk * kc;
+    TileArgs<T> p = a;
+    p.A = a.A + k0;
+    p.B = a.B + (long)k0 * a.ldb;
+    p.k = min(kc, a.k - k0);
+    p.Cin = nullptr;
+    p.ldci = 0;
+    p.Cout = ws + (long)chunk * a.m * a.n;
+    p.ldco = a.n;
+    p.changed = nullptr;
+    p.wide_out = nullptr;
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (wide_in != nullptr && *wide_in == 0) {
+            GemmTile<Cfg, T, float, SR, VEC>::run(p, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
+            return;
+        }
+    }
+    GemmTile<Cfg, T, T, SR, VEC>::run(p, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
+}
+
+// Cout = Cin (+) (+)_s ws[s]; sets the changed / wide flags like the tile epilogue.
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(int m, int n, int S, const T* ws,
+                                                             const T* Cin, long ldci, T* Cout,
+                                                             long ldco, int* changed, int* wide_out) {
+    using R = Ring<SR, T>;
+    const long total = (long)m * n;
+    bool diff = false, wide = false;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, j = e - i * n;
+        T acc = R::absent();
+        for (int s = 0; s < S; ++s) acc = R::add(acc, ws[(long)s * total + e]);
+        const T old = Cin[i * ldci + j];
+        const T nv = R::add(old, acc);
+        Cout[i * ldco + j] = nv;
+        diff |= bits_of(nv) != bits_of(old);
+        if constexpr (std::is_same_v<T, int32_t>)
+            wide |= nv != R::absent() && (nv > FP32_EXACT_MAX || nv < -FP32_EXACT_MAX);
+    }
+    if (changed != nullptr && __any(diff) && (threadIdx.x & 63) == 0) *changed = 1;
+    if (wide_out != nullptr && __any(wide) && (threadIdx.x & 63) == 0) *wide_out = 1;
+}
+
+// Chunks for a split-K launch of Cfg (0 or 1: no split).  Aim at about 512
+// workgroups with at least 32 k per chunk.
+template <typename Cfg>
+static int splitk_chunks(int m, int n, int k) {
+    const long tiles = (long)((m + Cfg::BM - 1) / Cfg::BM) * ((n + Cfg::BN - 1) / Cfg::BN);
+    if (tiles >= 256 || k < 128) return 1;
+    long S = (512 + tiles - 1) / tiles;
+    S = std::min<long>(S, k / 32);
+    return (int)std::max<long>(1, std::min<long>(S, 64));
+}
+
+size_t gemm_splitk_bytes(int m, int n, int k) {
+    const int S = splitk_chunks<CfgS>(m, n, k);
+    return S > 1 ? (size_t)S * m * n * 4 : 0;
+}
+
 template <typename Cfg, typename T, int SR>
 static hipError_t launch_cfg(const GemmArgs& g, hipStream_t s) {
     const int nbm = (g.m + Cfg::BM - 1) / Cfg::BM;
@@ -77,6 +149,28 @@ static hipError_t launch_cfg(const GemmArgs& g, hipStream_t s) {
                                             (uintptr_t)g.Cin | (uintptr_t)g.Cout) % 16 == 0);
     TileArgs<T> a{g.m, g.n, g.k, (const T*)g.A, g.lda, (const T*)g.B, g.ldb, (const T*)g.Cin,
                   g.ldci, (T*)g.Cout, g.ldco, g.changed, g.wide_out};
+    int S = splitk_chunks<Cfg>(g.m, g.n, g.k);
+    if (S > 1 && (g.ws == nullptr || (size_t)S * g.m * g.n * 4 > g.ws_bytes)) S = 1;
+    if (S > 1) {
+        // chunk length: a multiple of BK, so every chunk but the last is full
+        int kc = (g.k + S - 1) / S;
+        kc = (kc + Cfg::BK - 1) / Cfg::BK * Cfg::BK;
+        S = (g.k + kc - 1) / kc;
+        const bool vec_s = vec && g.n % 4 == 0 && (uintptr_t)g.ws % 16 == 0;
+        dim3 grid((unsigned)(nb * S)), block(Cfg::NT);
+        if (vec_s)
+            hipLaunchKernelGGL((tropical_gemm_splitk_kernel<Cfg, T, SR, true>), grid, block,
+                               Cfg::lds_bytes, s, a, S, kc, (T*)g.ws, g.wide_in);
+        else
+            hipLaunchKernelGGL((tropical_gemm_splitk_kernel<Cfg, T, SR, false>), grid, block,
+                               Cfg::lds_bytes, s, a, S, kc, (T*)g.ws, g.wide_in);
+        long rb = ((long)g.m * g.n + 1023) / 1024;
+        rb = std::max<long>(1, std::min<long>(rb, 4096));
+        hipLaunchKernelGGL((splitk_reduce_kernel<T, SR>), dim3((unsigned)rb), dim3(256), 0, s, g.m,
+                           g.n, S, (const T*)g.ws, (const T*)g.Cin, g.ldci, (T*)g.Cout, g.ldco,
+                           g.changed, g.wide_out);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)nb), block(Cfg::NT);
     if (vec)
         hipLaunchKernelGGL((tropical_gemm_kernel<Cfg, T, SR, true>), grid, block, Cfg::lds_bytes,

@@ -81,7 +81,7 @@ struct TileArgs {
     long lda;
     const T* B;
     long ldb;
-    const T* Cin;
+    const T* Cin;   // null: the accumulator starts from the absent value (split-K partials)
     long ldci;
     T* Cout;
     long ldco;
@@ -240,7 +240,13 @@ struct GemmTile {
             for (int g = 0; g < Cfg::CG; ++g) {
                 const int col = n0 + g * (Cfg::BN / Cfg::CG) + tx * 4;
                 if (VEC && mn_interior) {
-                    const v4<T> old = *reinterpret_cast<const v4<T>*>(a.Cin + (long)row * a.ldci + col);
+                    v4<T> old;
+                    if (a.Cin != nullptr) {
+                        old = *reinterpret_cast<const v4<T>*>(a.Cin + (long)row * a.ldci + col);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) old[e] = RT::absent();
+                    }
                     v4<T> nv;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
@@ -253,7 +259,7 @@ struct GemmTile {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (col + e >= a.n) break;
-                        const T old = a.Cin[(long)row * a.ldci + col + e];
+                        const T old = a.Cin != nullptr ? a.Cin[(long)row * a.ldci + col + e] : RT::absent();
                         const T nv = RT::add(old, Cv::out(acc[r][g * 4 + e]));
                         diff |= bits_of(nv) != bits_of(old);
                         wide |= is_wide(nv);

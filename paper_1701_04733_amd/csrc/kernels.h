@@ -27,7 +27,16 @@ struct GemmArgs {
     // null, is set to 1 when a finite output element does not fit.
     const int* wide_in;
     int* wide_out;
+    // Optional split-K workspace (device, ws_bytes bytes).  When the output has
+    // too few tiles to fill the GPU and k is long, the k range is cut into S
+    // chunks whose partial products go to ws and a reduce pass (+)-combines
+    // them with Cin.  Exact: (+) is associative, commutative and idempotent.
+    void* ws;
+    size_t ws_bytes;
 };
+
+// Split-K workspace that launch_gemm may use for an m x n x k product.
+size_t gemm_splitk_bytes(int m, int n, int k);
 
 enum { GEMM_CFG_L = 0, GEMM_CFG_M = 1, GEMM_CFG_S = 2, GEMM_NUM_CFGS = 3 };
 

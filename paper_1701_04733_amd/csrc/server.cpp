@@ -126,9 +126,71 @@ struct Request {
     size_t off = SIZE_MAX, bytes = 0;   // matrices
     size_t coo_off = SIZE_MAX, coo_bytes = 0;
     void* buf[2] = {nullptr, nullptr};
-    int step = 0;       // completed squarings
-    int next_tile = 0;  // first tile of the current squaring not yet launched
-    int changed_acc = 0;  // some entry changed in the current squaring (early exit)
+    int planned = 0;      // squarings whose tiles have all been enqueued
+    int next_tile = 0;    // first tile of squaring planned+1 not yet enqueued
+    int done_steps = 0;   // squarings known complete
+    bool hold = false;    // early exit: wait for the last squaring's flag before planning more
+    int changed_acc = 0;  // some entry changed in the squaring in flight (early exit)
+};
+
+// Host-pinned and device copies of one launch's descriptors.
+struct Staging {
+    BatchGraph* h_graphs = nullptr;
+    BatchItem* h_items = nullptr;
+    int* h_maxabs = nullptr;
+    int* h_changed = nullptr;
+    BatchGraph* d_graphs = nullptr;
+    BatchItem* d_items = nullptr;
+    int* d_maxabs = nullptr;
+    int* d_changed = nullptr;
+    size_t cap_graphs = 0, cap_items = 0;
+
+    void free_graphs() {
+        for (void** p : {(void**)&h_graphs, (void**)&h_maxabs, (void**)&h_changed})
+            if (*p) (void)hipHostFree(*p), *p = nullptr;
+        for (void** p : {(void**)&d_graphs, (void**)&d_maxabs, (void**)&d_changed})
+            if (*p) (void)hipFree(*p), *p = nullptr;
+        cap_graphs = 0;
+    }
+    void free_items() {
+        if (h_items) (void)hipHostFree(h_items), h_items = nullptr;
+        if (d_items) (void)hipFree(d_items), d_items = nullptr;
+        cap_items = 0;
+    }
+    // Only called when no launch that uses this staging set is in flight.
+    bool reserve(size_t ng, size_t ni) {
+        if (ng > cap_graphs) {
+            const size_t c = std::max(ng, cap_graphs * 2 + 64);
+            free_graphs();
+            if (hipHostMalloc((void**)&h_graphs, c * sizeof(BatchGraph), 0) != hipSuccess ||
+                hipHostMalloc((void**)&h_maxabs, c * sizeof(int), 0) != hipSuccess ||
+                hipHostMalloc((void**)&h_changed, c * sizeof(int), 0) != hipSuccess ||
+                hipMalloc((void**)&d_graphs, c * sizeof(BatchGraph)) != hipSuccess ||
+                hipMalloc((void**)&d_maxabs, c * sizeof(int)) != hipSuccess ||
+                hipMalloc((void**)&d_changed, c * sizeof(int)) != hipSuccess)
+                return false;
+            cap_graphs = c;
+        }
+        if (ni > cap_items) {
+            const size_t c = std::max(ni, cap_items * 2 + 1024);
+            free_items();
+            if (hipHostMalloc((void**)&h_items, c * sizeof(BatchItem), 0) != hipSuccess ||
+                hipMalloc((void**)&d_items, c * sizeof(BatchItem)) != hipSuccess)
+                return false;
+            cap_items = c;
+        }
+        return true;
+    }
+};
+
+// One enqueued unit of device work and what its completion means.
+struct Launch {
+    int slot = -1;                       // staging set used (-1: none)
+    hipEvent_t ev = nullptr;
+    std::vector<Request*> graphs;        // graph index -> request
+    std::vector<char> ends_step;         // launch holds the last tiles of that squaring
+    std::vector<Request*> densified;     // admitted just before this launch
+    std::vector<Request*> whole;         // FIFO mode: solved entirely by this launch
 };
 
 }  // namespace
@@ -145,23 +207,18 @@ struct Server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> pending;
-    std::vector<Request*> active;
+    std::vector<Request*> active;        // admitted, not finished, in admission order
     std::unordered_map<int64_t, std::unique_ptr<Request>> all;
     int64_t next_id = 1;
     bool stop = false;
+    bool admission_blocked = false;      // the head of `pending` did not fit the pool
     std::string error;
     std::thread engine;
 
-    // engine-private staging (pinned host + device mirrors), grown on demand
-    BatchGraph* h_graphs = nullptr;
-    BatchItem* h_items = nullptr;
-    int* h_maxabs = nullptr;
-    int* h_changed = nullptr;
-    BatchGraph* d_graphs = nullptr;
-    BatchItem* d_items = nullptr;
-    int* d_maxabs = nullptr;
-    int* d_changed = nullptr;
-    size_t cap_graphs = 0, cap_items = 0;
+    static constexpr int kDepth = 2;     // launches in flight
+    Staging staging[kDepth];
+    std::deque<Launch> inflight;
+    std::vector<hipEvent_t> free_events;
     // statistics
     std::atomic<long> launches{0}, iterations{0};
     double busy_s = 0;
@@ -170,61 +227,46 @@ struct Server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
-    bool grow(size_t ng, size_t ni) {
-        if (ng > cap_graphs) {
-            size_t c = std::max(ng, cap_graphs * 2 + 64);
-            free_graph_staging();
-            if (hipHostMalloc((void**)&h_graphs, c * sizeof(BatchGraph), 0) != hipSuccess ||
-                hipHostMalloc((void**)&h_maxabs, c * sizeof(int), 0) != hipSuccess ||
-                hipHostMalloc((void**)&h_changed, c * sizeof(int), 0) != hipSuccess ||
-                hipMalloc((void**)&d_graphs, c * sizeof(BatchGraph)) != hipSuccess ||
-                hipMalloc((void**)&d_maxabs, c * sizeof(int)) != hipSuccess ||
-                hipMalloc((void**)&d_changed, c * sizeof(int)) != hipSuccess)
-                return false;
-            cap_graphs = c;
+    void free_staging() {
+        for (Staging& st : staging) {
+            st.free_graphs();
+            st.free_items();
         }
-        if (ni > cap_items) {
-            size_t c = std::max(ni, cap_items * 2 + 1024);
-            free_item_staging();
-            if (hipHostMalloc((void**)&h_items, c * sizeof(BatchItem), 0) != hipSuccess ||
-                hipMalloc((void**)&d_items, c * sizeof(BatchItem)) != hipSuccess)
-                return false;
-            cap_items = c;
-        }
-        return true;
+        for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+        free_events.clear();
     }
 
-    // Called only between iterations, when the stream has drained.
-    void free_graph_staging() {
-        for (void** p : {(void**)&h_graphs, (void**)&h_maxabs, (void**)&h_changed})
-            if (*p) (void)hipHostFree(*p), *p = nullptr;
-        for (void** p : {(void**)&d_graphs, (void**)&d_maxabs, (void**)&d_changed})
-            if (*p) (void)hipFree(*p), *p = nullptr;
-        cap_graphs = 0;
-    }
-    void free_item_staging() {
-        if (h_items) (void)hipHostFree(h_items), h_items = nullptr;
-        if (d_items) (void)hipFree(d_items), d_items = nullptr;
-        cap_items = 0;
-    }
-    void free_staging() {
-        free_graph_staging();
-        free_item_staging();
+    hipEvent_t get_event() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
     }
 
     // Caller holds mu.  Admit pending requests in arrival order while the pool
-    // has room.  FIFO mode admits only when nothing is active.
-    bool admit_locked(std::vector<Request*>& admitted) {
+    // has room.  FIFO mode admits one request only when nothing else is on the
+    // device.
+    void admit_locked(std::vector<Request*>& admitted) {
+        admission_blocked = false;
         while (!pending.empty()) {
-            if (mode == BTAS_SERVE_FIFO && (!active.empty() || !admitted.empty())) break;
+            if (mode == BTAS_SERVE_FIFO && (!active.empty() || !inflight.empty() || !admitted.empty()))
+                break;
             Request* r = pending.front();
             const size_t half = align_up((size_t)r->n * r->ld * 4, 256);
             const size_t off = pool.alloc(2 * half);
-            if (off == SIZE_MAX) break;
+            if (off == SIZE_MAX) {
+                admission_blocked = true;
+                break;
+            }
             const size_t coo = align_up((size_t)r->nnz * 4, 256) * 3;
             const size_t coff = r->nnz > 0 ? pool.alloc(coo) : SIZE_MAX;
             if (r->nnz > 0 && coff == SIZE_MAX) {
                 pool.release(off, 2 * half);
+                admission_blocked = true;
                 break;
             }
             r->off = off;
@@ -233,10 +275,12 @@ struct Server {
             r->coo_bytes = coo;
             r->buf[0] = pool.at(off);
             r->buf[1] = pool.at(off + half);
+            r->state = ACTIVE;
+            r->admitted = now();
             pending.pop_front();
+            active.push_back(r);
             admitted.push_back(r);
         }
-        return !admitted.empty();
     }
 
     // Upload edges and densify on the engine stream (engine thread only).
@@ -254,10 +298,190 @@ struct Server {
         return launch_densify(dt, r->buf[0], r->n, r->ld, 0, nullptr, nullptr, nullptr, stream);
     }
 
-    void finish_locked(Request* r, double t) {
+    bool plannable(const Request* r) const { return !r->hold && r->planned < r->T; }
+
+    // Fill a launch with, for every active request that can advance, the next
+    // tiles of its next squaring (at most `quantum` terms of work each).
+    // Planning assumes that every enqueued launch completes, which stream
+    // order guarantees; only early-exit requests wait for their flag.
+    hipError_t plan_and_enqueue(Launch& L, const std::vector<Request*>& order) {
+        Staging& st = staging[L.slot];
+        size_t ng = 0, ni = 0;
+        for (Request* r : order)
+            if (plannable(r)) {
+                ++ng;
+                ni += (size_t)(r->ntiles - r->next_tile);
+            }
+        if (!st.reserve(ng + 1, ni + 1)) return hipErrorOutOfMemory;
+        int nitems = 0;
+        for (Request* r : order) {
+            if (!plannable(r)) continue;
+            const int tile = r->kind == BATCH_TILE_128 ? 128 : 64;
+            const double per_tile = (double)tile * tile * r->n;
+            int take = (int)std::max(1.0, quantum / per_tile);
+            take = std::min(take, r->ntiles - r->next_tile);
+            const int gi = (int)L.graphs.size();
+            st.h_graphs[gi] = {{r->buf[0], r->buf[1]}, r->n, r->ld, r->T, 0};
+            st.h_maxabs[gi] = r->maxabs;
+            st.h_changed[gi] = 0;
+            const int per_row = batch_tiles_of(r->n, r->kind);
+            for (int t = r->next_tile; t < r->next_tile + take; ++t)
+                st.h_items[nitems++] = {gi, t / per_row, t % per_row, r->kind, r->planned + 1, 0};
+            r->next_tile += take;
+            const bool ends = r->next_tile == r->ntiles;
+            if (ends) {
+                r->planned += 1;
+                r->next_tile = 0;
+                if (r->early) r->hold = true;
+            }
+            L.graphs.push_back(r);
+            L.ends_step.push_back(ends);
+        }
+        if (nitems == 0) return hipSuccess;
+        const int g = (int)L.graphs.size();
+        hipError_t e = hipMemcpyAsync(st.d_graphs, st.h_graphs, g * sizeof(BatchGraph), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(st.d_maxabs, st.h_maxabs, g * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(st.d_changed, st.h_changed, g * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(st.d_items, st.h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = launch_grouped_step(dt, st.d_graphs, st.d_items, nitems,
+                                    dt == BTAS_INT32 ? st.d_maxabs : nullptr, st.d_changed, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(st.h_changed, st.d_changed, g * sizeof(int), hipMemcpyDeviceToHost, stream);
+        launches++;
+        return e;
+    }
+
+    // FIFO mode: the plain path, every squaring one GEMM launch.
+    hipError_t enqueue_whole(Request* r) {
+        hipError_t e = hipSuccess;
+        int cur = 0;
+        for (int t = 0; t < r->T && e == hipSuccess; ++t) {
+            GemmArgs a{r->n, r->n, r->n, r->buf[cur], r->ld, r->buf[cur], r->ld,
+                       r->buf[cur], r->ld, r->buf[cur ^ 1], r->ld, nullptr, nullptr, nullptr};
+            e = launch_gemm(BTAS_MIN_PLUS, dt, a, -1, stream);
+            cur ^= 1;
+            launches++;
+        }
+        r->planned = r->T;
+        return e;
+    }
+
+    void finish_locked(Request* r, double t, int steps) {
         r->state = DONE;
         r->done = t;
+        r->T = steps;  // squarings executed; the result is in buf[steps & 1]
         active.erase(std::remove(active.begin(), active.end(), r), active.end());
+    }
+
+    // Wait for the oldest launch and apply what its completion means.
+    hipError_t retire_oldest() {
+        Launch L = std::move(inflight.front());
+        inflight.pop_front();
+        hipError_t e = hipEventSynchronize(L.ev);
+        const double t = now();
+        free_events.push_back(L.ev);
+        std::lock_guard<std::mutex> g(mu);
+        if (e != hipSuccess) return e;
+        for (Request* r : L.densified) {
+            if (r->coo_off != SIZE_MAX) {
+                pool.release(r->coo_off, r->coo_bytes);
+                r->coo_off = SIZE_MAX;
+            }
+            if (r->T == 0) finish_locked(r, t, 0);
+        }
+        for (Request* r : L.whole) finish_locked(r, t, r->T);
+        const int* chg = L.slot >= 0 ? staging[L.slot].h_changed : nullptr;
+        for (size_t i = 0; i < L.graphs.size(); ++i) {
+            Request* r = L.graphs[i];
+            if (r->early) r->changed_acc |= chg[i];
+            if (!L.ends_step[i]) continue;
+            r->done_steps += 1;
+            bool stop_early = false;
+            if (r->early) {
+                stop_early = r->changed_acc == 0;
+                r->changed_acc = 0;
+                r->hold = false;
+            }
+            if (r->done_steps >= r->T || stop_early) finish_locked(r, t, r->done_steps);
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+        return hipSuccess;
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        while (true) {
+            std::vector<Request*> admitted, order;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                auto has_plannable = [&] {
+                    if (mode == BTAS_SERVE_FIFO) return false;
+                    for (Request* r : active)
+                        if (plannable(r)) return true;
+                    return false;
+                };
+                cv_work.wait(lk, [&] {
+                    return stop || !inflight.empty() || has_plannable() ||
+                           (!pending.empty() && !admission_blocked);
+                });
+                if (stop) break;
+                admit_locked(admitted);
+                order = active;
+            }
+            const double it_start = now();
+            hipError_t e = hipSuccess;
+            for (Request* r : admitted)
+                if (e == hipSuccess) e = densify(r);
+            Launch L;
+            L.densified = admitted;
+            bool any = !admitted.empty();
+            if (e == hipSuccess && mode == BTAS_SERVE_CONTINUOUS) {
+                // A staging set is free once the launch that used it retired.
+                if (inflight.size() >= (size_t)kDepth) e = retire_oldest();
+                if (e == hipSuccess) {
+                    L.slot = (int)(launches.load() % kDepth);
+                    for (const Launch& o : inflight)
+                        if (o.slot == L.slot) L.slot ^= 1;
+                    e = plan_and_enqueue(L, order);
+                    any = any || !L.graphs.empty();
+                }
+            } else if (e == hipSuccess && mode == BTAS_SERVE_FIFO) {
+                for (Request* r : admitted)
+                    if (e == hipSuccess && r->T > 0) {
+                        e = enqueue_whole(r);
+                        L.whole.push_back(r);
+                    }
+            }
+            if (e == hipSuccess && any) {
+                L.ev = get_event();
+                if (L.ev == nullptr) e = hipErrorOutOfMemory;
+                else e = hipEventRecord(L.ev, stream);
+                if (e == hipSuccess) inflight.push_back(std::move(L));
+            }
+            // Keep at most kDepth launches in flight; when nothing new can be
+            // planned, wait for the oldest so that its requests advance.
+            bool more = false;
+            if (e == hipSuccess && !inflight.empty()) {
+                std::lock_guard<std::mutex> g(mu);
+                if (mode == BTAS_SERVE_CONTINUOUS)
+                    for (Request* r : active)
+                        if (plannable(r)) more = true;
+            }
+            if (e == hipSuccess && !inflight.empty() && (!more || inflight.size() >= (size_t)kDepth))
+                e = retire_oldest();
+            busy_s += now() - it_start;
+            iterations++;
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(stream);
+                inflight.clear();
+                std::lock_guard<std::mutex> g(mu);
+                fail_all_locked(std::string("engine: HIP error ") + hipGetErrorString(e));
+                break;
+            }
+        }
+        // Drain before the stream and pool go away.
+        while (!inflight.empty()) (void)retire_oldest();
     }
 
     void fail_all_locked(const std::string& msg) {
@@ -267,119 +491,6 @@ struct Server {
         active.clear();
         pending.clear();
         cv_done.notify_all();
-    }
-
-    void run() {
-        (void)hipSetDevice(device);
-        std::unique_lock<std::mutex> lk(mu);
-        while (true) {
-            cv_work.wait(lk, [&] { return stop || !active.empty() || !pending.empty(); });
-            if (stop) break;
-            std::vector<Request*> admitted;
-            admit_locked(admitted);
-            if (active.empty() && admitted.empty()) {
-                // Head request does not fit yet: wait for a release.
-                cv_work.wait(lk);
-                continue;
-            }
-            lk.unlock();
-            const double it_start = now();
-            hipError_t e = hipSuccess;
-            for (Request* r : admitted)
-                if (e == hipSuccess) e = densify(r);
-            std::vector<Request*> launched;   // requests with tiles in this launch
-            std::vector<int> completes;       // 1 if the launch finishes their squaring
-            int nitems = 0, ngraphs = 0;
-            if (e == hipSuccess && mode == BTAS_SERVE_CONTINUOUS) {
-                std::vector<Request*> work;
-                {
-                    std::lock_guard<std::mutex> g(mu);
-                    work = active;
-                }
-                for (Request* r : admitted) work.push_back(r);
-                size_t need_items = 0;
-                for (Request* r : work) need_items += (size_t)(r->ntiles - r->next_tile);
-                if (!grow(work.size() + 1, need_items + 1)) e = hipErrorOutOfMemory;
-                for (size_t i = 0; e == hipSuccess && i < work.size(); ++i) {
-                    Request* r = work[i];
-                    if (r->step >= r->T) continue;
-                    const int tile = r->kind == BATCH_TILE_128 ? 128 : 64;
-                    const double per_tile = (double)tile * tile * r->n;
-                    int take = (int)std::max(1.0, quantum / per_tile);
-                    take = std::min(take, r->ntiles - r->next_tile);
-                    const int gi = ngraphs++;
-                    h_graphs[gi] = {{r->buf[0], r->buf[1]}, r->n, r->ld, r->T, 0};
-                    h_maxabs[gi] = r->maxabs;
-                    h_changed[gi] = 0;
-                    const int per_row = batch_tiles_of(r->n, r->kind);
-                    for (int t = r->next_tile; t < r->next_tile + take; ++t)
-                        h_items[nitems++] = {gi, t / per_row, t % per_row, r->kind, r->step + 1, 0};
-                    r->next_tile += take;
-                    launched.push_back(r);
-                    completes.push_back(r->next_tile == r->ntiles);
-                }
-                if (e == hipSuccess && nitems > 0) {
-                    e = hipMemcpyAsync(d_graphs, h_graphs, ngraphs * sizeof(BatchGraph), hipMemcpyHostToDevice, stream);
-                    if (e == hipSuccess) e = hipMemcpyAsync(d_maxabs, h_maxabs, ngraphs * sizeof(int), hipMemcpyHostToDevice, stream);
-                    if (e == hipSuccess) e = hipMemcpyAsync(d_items, h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream);
-                    // changed flags accumulate over the launches of one squaring:
-                    // they are kept per request on the host (see below)
-                    if (e == hipSuccess) e = hipMemcpyAsync(d_changed, h_changed, ngraphs * sizeof(int), hipMemcpyHostToDevice, stream);
-                    if (e == hipSuccess)
-                        e = launch_grouped_step(dt, d_graphs, d_items, nitems,
-                                                dt == BTAS_INT32 ? d_maxabs : nullptr, d_changed, stream);
-                    if (e == hipSuccess) e = hipMemcpyAsync(h_changed, d_changed, ngraphs * sizeof(int), hipMemcpyDeviceToHost, stream);
-                    launches++;
-                }
-            } else if (e == hipSuccess && mode == BTAS_SERVE_FIFO) {
-                // Plain path: every squaring of the admitted request as one GEMM launch.
-                for (Request* r : admitted) {
-                    int cur = 0;
-                    for (int t = 0; t < r->T && e == hipSuccess; ++t) {
-                        GemmArgs a{r->n, r->n, r->n, r->buf[cur], r->ld, r->buf[cur], r->ld,
-                                   r->buf[cur], r->ld, r->buf[cur ^ 1], r->ld, nullptr, nullptr, nullptr};
-                        e = launch_gemm(BTAS_MIN_PLUS, dt, a, -1, stream);
-                        cur ^= 1;
-                        launches++;
-                    }
-                    r->step = r->T;
-                }
-            }
-            if (e == hipSuccess) e = hipStreamSynchronize(stream);
-            const double t_end = now();
-            busy_s += t_end - it_start;
-            iterations++;
-            lk.lock();
-            if (e != hipSuccess) {
-                fail_all_locked(std::string("engine: HIP error ") + hipGetErrorString(e));
-                continue;
-            }
-            for (Request* r : admitted) {
-                if (r->coo_off != SIZE_MAX) {
-                    pool.release(r->coo_off, r->coo_bytes);
-                    r->coo_off = SIZE_MAX;
-                }
-                r->admitted = it_start;
-                r->state = ACTIVE;
-                active.push_back(r);
-            }
-            for (size_t i = 0; i < launched.size(); ++i) {
-                Request* r = launched[i];
-                r->changed_acc |= h_changed[i];
-                if (!completes[i]) continue;
-                const bool changed = r->changed_acc != 0;
-                r->changed_acc = 0;
-                r->step += 1;
-                r->next_tile = 0;
-                if (r->step >= r->T || (r->early && !changed)) {
-                    r->T = r->step;  // squarings actually executed
-                    finish_locked(r, t_end);
-                }
-            }
-            for (Request* r : admitted)
-                if (r->state == ACTIVE && r->step >= r->T) finish_locked(r, t_end);
-            cv_done.notify_all();
-        }
     }
 };
 
@@ -489,6 +600,7 @@ btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_
         r->id = s.next_id++;
         r->arrival = arrival >= 0 ? arrival : s.now();
         *id_out = r->id;
+        s.admission_blocked = false;
         s.pending.push_back(r.get());
         s.all[r->id] = std::move(r);
     }
@@ -575,6 +687,7 @@ btas_status_t btas_server_release(btas_server_t srv, int64_t id) {
         if (r->state != btas::DONE && r->state != btas::FAILED) return BTAS_ERR_INVALID_ARG;
         if (r->off != SIZE_MAX) s.pool.release(r->off, r->bytes);
         s.all.erase(it);
+        s.admission_blocked = false;
     }
     s.cv_work.notify_all();
     return BTAS_OK;

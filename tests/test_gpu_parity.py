@@ -68,7 +68,9 @@ def operands(m, n, k, dt, sr, seed, frac=0.1, signed=False):
 
 
 SHAPES = [(1, 1, 1), (2, 3, 1), (3, 7, 2), (7, 31, 65), (31, 64, 127), (64, 64, 64),
-          (65, 127, 129), (127, 129, 257), (129, 257, 31), (257, 65, 1000), (300, 290, 77)]
+          (65, 127, 129), (127, 129, 257), (129, 257, 31), (257, 65, 1000), (300, 290, 77),
+          # few output tiles, long k: split-K chunks plus a ragged last chunk
+          (64, 64, 4096), (100, 37, 1000), (17, 250, 777), (256, 256, 256)]
 
 
 @pytest.mark.parametrize("sr", SR)
@@ -360,3 +362,25 @@ def test_apsp_i32_distances_cross_exact_range(btas, dev):
     assert want[0, n - 1] > (1 << 23)
     D, _, _ = btas.apsp(to_dev(W, dev))
     assert_same(to_np(D), want, "crossing")
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_apsp_graph_mode_replays_current_inputs(btas, dev, dt):
+    """The captured solve is replayed on the current contents of W."""
+    for n in (5, 100, 256):
+        outs = []
+        t = out = None
+        for seed in (1, 2, 3):
+            Wi = wl.er_digraph_i32(n, min(1.0, 6.0 / n), 1, 100, seed=seed * 100 + n)
+            W = Wi if dt == "i32" else np.where(Wi == wl.I32_INF, np.inf, Wi * 0.5).astype(np.float32)
+            if t is None:
+                t = to_dev(W, dev)
+                out = torch_mod().empty_like(t)
+            else:
+                t.copy_(to_dev(W, dev))
+            btas.apsp(t, out=out, graph=True, return_steps=False)
+            want, _, _ = oracle.apsp(W)
+            assert_same(to_np(out), want, f"graph n={n} seed={seed}")
+            outs.append(want)
+    with pytest.raises(btas.BtasError, match="INVALID_ARG"):
+        btas.apsp(t, early_exit=True, graph=True)
