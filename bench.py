@@ -180,6 +180,48 @@ def bench_batched(dev, reps=5):
             "speedup_vs_plain": round(plain * 1e3 / bm, 2), "bit_identical_to_plain": same}
 
 
+def bench_level12(dev, reps=10):
+    """HBM-bound routines: gemv y <- y (+) A (.) x at 8192x8192 and the level-1
+    ops on 2^26-element vectors (fp32 min-plus), against 8 TB/s."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    g = torch.Generator(device=dev).manual_seed(7)
+    out = {"workload": "fp32 min-plus: gemv 8192x8192, level 1 on 2^26 elements", "peak_GB/s": 8000.0}
+
+    def timed(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = _events()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        return {"us": round(ms * 1e3, 1), "GB/s": round(nbytes / (ms / 1e3) / 1e9, 1),
+                "frac_hbm_peak": round(nbytes / (ms / 1e3) / 8e12, 4)}
+
+    A = torch.rand((8192, 8192), generator=g, device=dev)
+    x = torch.rand(8192, generator=g, device=dev)
+    y = torch.full((8192,), float("inf"), device=dev)
+    out["gemv"] = timed(lambda: btas.tropical_gemv(A, x, y), A.numel() * 4 + 8192 * 12)
+    del A
+    n = 1 << 26
+    u = torch.rand(n, generator=g, device=dev)
+    v = torch.rand(n, generator=g, device=dev)
+    w = torch.empty_like(u)
+    r = torch.empty(1, device=dev)
+    out["vadd"] = timed(lambda: btas.vadd(u, v, w), 12 * n)
+    out["vmul"] = timed(lambda: btas.vmul(u, v, w), 12 * n)
+    out["dot"] = timed(lambda: btas.dot(u, v, out=r), 8 * n)
+    out["axpy"] = timed(lambda: btas.axpy(0.5, u, w), 12 * n)
+    return out
+
+
 def _serve_trace(reqs, mode):
     import threading
 
@@ -332,6 +374,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         extras = {}
+        extras["level12"] = bench_level12(dev)
         extras["apsp_small"] = bench_apsp_small(dev)
         extras["apsp_large"] = bench_apsp_large(dev)
         torch.cuda.empty_cache()

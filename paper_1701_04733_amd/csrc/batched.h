@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "btas.h"
 
 namespace btas {
@@ -24,11 +26,56 @@ enum { BATCH_TILE_128 = 0, BATCH_TILE_64 = 1 };
 // One output tile of one squaring of one graph.
 struct BatchItem {
     int graph;
-    int tm, tn;  // tile coordinates in units of the tile shape
-    int kind;    // BATCH_TILE_128 or BATCH_TILE_64
+    int m0, n0;  // first output row / column of the tile
+    int kind;    // BATCH_TILE_128 (128x128 outputs) or BATCH_TILE_64 (64x64)
     int step;    // squaring index s >= 1
     int pad;
 };
+
+// How a graph's n x n output is cut into tiles.
+enum { SHAPE_128 = 0, SHAPE_64 = 1, SHAPE_MIXED = 2, NUM_SHAPES = 3 };
+
+struct TileRef {
+    int m0, n0, kind;
+};
+
+// Tiles covering [0,n)^2.  SHAPE_MIXED uses 128x128 tiles on the
+// floor(n/128)*128 core and 64x64 tiles on the remainder strips, which keeps
+// most work on the larger tile while padding the ragged edge only to 64.
+inline std::vector<TileRef> tile_plan(int n, int shape) {
+    std::vector<TileRef> out;
+    if (n <= 0) return out;
+    if (shape == SHAPE_128 || shape == SHAPE_64) {
+        const int t = shape == SHAPE_128 ? 128 : 64;
+        const int kind = shape == SHAPE_128 ? BATCH_TILE_128 : BATCH_TILE_64;
+        for (int i = 0; i < n; i += t)
+            for (int j = 0; j < n; j += t) out.push_back({i, j, kind});
+        return out;
+    }
+    const int core = n / 128 * 128;
+    // 64-wide segments: the core split in halves plus the remainder
+    for (int i = 0; i < core; i += 128)
+        for (int j = 0; j < core; j += 128) out.push_back({i, j, BATCH_TILE_128});
+    for (int i = 0; i < n; i += 64)
+        for (int j = 0; j < n; j += 64)
+            if (i >= core || j >= core) out.push_back({i, j, BATCH_TILE_64});
+    return out;
+}
+
+// Padded output area of a plan, 64x64 tiles weighted by `w64` (their lower
+// efficiency per element); the model used when tiles are not timed.
+inline double tile_plan_cost(int n, int shape, double w64 = 1.15) {
+    double c = 0;
+    for (const TileRef& t : tile_plan(n, shape)) c += t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0 * w64;
+    return c;
+}
+
+inline int model_shape(int n) {
+    int best = SHAPE_128;
+    for (int s : {SHAPE_64, SHAPE_MIXED})
+        if (tile_plan_cost(n, s) < tile_plan_cost(n, best)) best = s;
+    return best;
+}
 
 // An external matrix (the caller's W or D) paired with a graph.  Jobs of one
 // launch own consecutive ranges of workgroups: [first_block, first_block + nblocks).
@@ -67,9 +114,6 @@ hipError_t launch_clear_ints(int* p, int count, hipStream_t s);
 hipError_t launch_densify(int dt, void* D, int n, int ld, int nnz, const int32_t* rows,
                           const int32_t* cols, const void* w, hipStream_t s);
 
-inline int batch_tiles_of(int n, int kind) {
-    const int t = kind == BATCH_TILE_128 ? 128 : 64;
-    return (n + t - 1) / t;
-}
+
 
 }  // namespace btas

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
     TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
     const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
     if (it.kind == BATCH_TILE_128) {
-        const int m0 = it.tm * CfgL::BM, n0 = it.tn * CfgL::BN;
+        const int m0 = it.m0, n0 = it.n0;
         if constexpr (std::is_same_v<T, int32_t>) {
             if (narrow) {
                 GemmTile<CfgL, T, float, SR, true>::run(a, m0, n0, smem_raw);
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
         }
         GemmTile<CfgL, T, T, SR, true>::run(a, m0, n0, smem_raw);
     } else {
-        const int m0 = it.tm * CfgM::BM, n0 = it.tn * CfgM::BN;
+        const int m0 = it.m0, n0 = it.n0;
         if constexpr (std::is_same_v<T, int32_t>) {
             if (narrow) {
                 GemmTile<CfgM, T, float, SR, true>::run(a, m0, n0, smem_raw);

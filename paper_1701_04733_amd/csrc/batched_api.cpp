@@ -73,28 +73,14 @@ int size_bucket(int n) {
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-int tiles_of(int n, int kind) {
-    const int t = kind == BATCH_TILE_128 ? 128 : 64;
-    return (n + t - 1) / t;
-}
-
-// Cost model used when autotuning is off: padded tile area, with the 64-wide
-// tiles (4x4 per thread) charged 15% more per element than 128-wide ones.
-int model_kind(int n) {
-    const double a128 = std::pow((double)tiles_of(n, BATCH_TILE_128) * 128, 2);
-    const double a64 = std::pow((double)tiles_of(n, BATCH_TILE_64) * 64, 2) * 1.15;
-    return a128 <= a64 ? BATCH_TILE_128 : BATCH_TILE_64;
-}
-
 struct HostGraph {
     int idx;  // caller's index
     int n, T, ld;
 };
 
-void append_items(std::vector<BatchItem>& items, int graph_slot, int n, int kind, int step) {
-    const int t = tiles_of(n, kind);
-    for (int tm = 0; tm < t; ++tm)
-        for (int tn = 0; tn < t; ++tn) items.push_back({graph_slot, tm, tn, kind, step, 0});
+void append_items(std::vector<BatchItem>& items, int graph_slot, int n, int shape, int step) {
+    for (const TileRef& t : tile_plan(n, shape))
+        items.push_back({graph_slot, t.m0, t.n0, t.kind, step, 0});
 }
 
 btas_status_t upload(btas_handle_t h, const char* fn, void** dst, const void* src, size_t bytes) {
@@ -211,9 +197,10 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         for (auto& kv : buckets) {
             int kind;
             const int rep = hg[kv.second.front()].n;  // largest n of the bucket
-            if (force && std::strcmp(force, "128") == 0) kind = BATCH_TILE_128;
-            else if (force && std::strcmp(force, "64") == 0) kind = BATCH_TILE_64;
-            else if (!tune) kind = model_kind(rep);
+            if (force && std::strcmp(force, "128") == 0) kind = SHAPE_128;
+            else if (force && std::strcmp(force, "64") == 0) kind = SHAPE_64;
+            else if (force && std::strcmp(force, "mixed") == 0) kind = SHAPE_MIXED;
+            else if (!tune) kind = model_shape(rep);
             else {
                 auto it = h->tile_choice.find({(int)dt, kv.first});
                 if (it != h->tile_choice.end()) {
@@ -224,8 +211,8 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                     // not depend on the values, and the binary32 path is the one
                     // taken for in-range int32 data.
                     (void)launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
-                    float ms_of[2] = {1e30f, 1e30f};
-                    for (int cand : {BATCH_TILE_128, BATCH_TILE_64}) {
+                    float ms_of[NUM_SHAPES] = {1e30f, 1e30f, 1e30f};
+                    for (int cand : {SHAPE_128, SHAPE_64, SHAPE_MIXED}) {
                         std::vector<BatchItem> its;
                         for (int g : kv.second) append_items(its, g, hg[g].n, cand, 1);
                         BatchItem* d_its = nullptr;
@@ -249,15 +236,16 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                         (void)hipFree(d_its);
                         if (e != hipSuccess) return device_fail(h, fn, e);
                     }
-                    kind = ms_of[BATCH_TILE_64] < ms_of[BATCH_TILE_128] ? BATCH_TILE_64 : BATCH_TILE_128;
+                    kind = SHAPE_128;
+                    for (int cand : {SHAPE_64, SHAPE_MIXED})
+                        if (ms_of[cand] < ms_of[kind]) kind = cand;
                     if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1') {
                         double terms = 0;
                         for (int g : kv.second) terms += (double)hg[g].n * hg[g].n * hg[g].n;
-                        fprintf(stderr, "[btas] autotune dt=%d bucket=%d n<=%d graphs=%zu: 128-tile %.3f ms, "
-                                "64-tile %.3f ms (%.1f / %.1f Tterm/s) -> %d\n", (int)dt, kv.first, rep,
-                                kv.second.size(), ms_of[BATCH_TILE_128], ms_of[BATCH_TILE_64],
-                                terms / ms_of[BATCH_TILE_128] / 1e9, terms / ms_of[BATCH_TILE_64] / 1e9,
-                                kind == BATCH_TILE_128 ? 128 : 64);
+                        fprintf(stderr, "[btas] autotune dt=%d bucket=%d n<=%d graphs=%zu: 128: %.3f ms "
+                                "(%.1f Tterm/s), 64: %.3f ms (%.1f), mixed: %.3f ms (%.1f) -> shape %d\n",
+                                (int)dt, kv.first, rep, kv.second.size(), ms_of[0], terms / ms_of[0] / 1e9,
+                                ms_of[1], terms / ms_of[1] / 1e9, ms_of[2], terms / ms_of[2] / 1e9, kind);
                     }
                     h->tile_choice[{(int)dt, kv.first}] = kind;
                 }
@@ -332,5 +320,5 @@ extern "C" int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n)
     if (!h) return -1;
     auto it = h->tile_choice.find({(int)dt, size_bucket(n)});
     if (it == h->tile_choice.end()) return -1;
-    return it->second == BATCH_TILE_128 ? 128 : 64;
+    return it->second == SHAPE_128 ? 128 : it->second == SHAPE_64 ? 64 : 0;
 }

@@ -37,6 +37,7 @@
 #include "batched.h"
 #include "btas.h"
 #include "kernels.h"
+#include "range_alloc.h"
 
 namespace btas {
 namespace {
@@ -54,69 +55,38 @@ int steps_for(int n) {
     return t;
 }
 
-// First-fit allocator over one device allocation; offsets are 256-aligned.
+// The memory pool: one device allocation carved by a RangeAllocator.
 class DevicePool {
    public:
     bool init(size_t bytes) {
-        size_ = align_up(bytes, 256);
-        if (hipMalloc(&base_, size_) != hipSuccess) {
+        ranges_.reset(bytes);
+        if (hipMalloc(&base_, ranges_.size()) != hipSuccess) {
             base_ = nullptr;
             return false;
         }
-        free_[0] = size_;
         return true;
     }
     ~DevicePool() {
         if (base_) (void)hipFree(base_);
     }
-    // Returns an offset or SIZE_MAX.
-    size_t alloc(size_t bytes) {
-        bytes = align_up(bytes, 256);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const size_t off = it->first, rest = it->second - bytes;
-                free_.erase(it);
-                if (rest) free_[off + bytes] = rest;
-                used_ += bytes;
-                peak_ = std::max(peak_, used_);
-                return off;
-            }
-        }
-        return SIZE_MAX;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align_up(bytes, 256);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+    size_t alloc(size_t bytes) { return ranges_.alloc(bytes); }
+    void release(size_t off, size_t bytes) { ranges_.release(off, bytes); }
     char* at(size_t off) const { return (char*)base_ + off; }
-    size_t size() const { return size_; }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
+    size_t size() const { return ranges_.size(); }
+    size_t used() const { return ranges_.used(); }
+    size_t peak() const { return ranges_.peak(); }
 
    private:
     void* base_ = nullptr;
-    size_t size_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;
+    RangeAllocator ranges_;
 };
 
 enum ReqState { PENDING = 0, ACTIVE = 1, DONE = 2, FAILED = 3 };
 
 struct Request {
     int64_t id = 0;
-    int n = 0, T = 0, ld = 0, nnz = 0, kind = BATCH_TILE_128, ntiles = 0;
+    int n = 0, T = 0, ld = 0, nnz = 0, ntiles = 0;
+    std::vector<TileRef> tiles;  // output tiles of one squaring
     bool early = false;
     int maxabs = 0;
     std::vector<int32_t> rows, cols;
@@ -316,18 +286,16 @@ struct Server {
         int nitems = 0;
         for (Request* r : order) {
             if (!plannable(r)) continue;
-            const int tile = r->kind == BATCH_TILE_128 ? 128 : 64;
-            const double per_tile = (double)tile * tile * r->n;
-            int take = (int)std::max(1.0, quantum / per_tile);
-            take = std::min(take, r->ntiles - r->next_tile);
             const int gi = (int)L.graphs.size();
             st.h_graphs[gi] = {{r->buf[0], r->buf[1]}, r->n, r->ld, r->T, 0};
             st.h_maxabs[gi] = r->maxabs;
             st.h_changed[gi] = 0;
-            const int per_row = batch_tiles_of(r->n, r->kind);
-            for (int t = r->next_tile; t < r->next_tile + take; ++t)
-                st.h_items[nitems++] = {gi, t / per_row, t % per_row, r->kind, r->planned + 1, 0};
-            r->next_tile += take;
+            double work = 0;  // terms scheduled for this request in this launch
+            while (r->next_tile < r->ntiles && (work == 0 || work < quantum)) {
+                const TileRef& t = r->tiles[r->next_tile++];
+                st.h_items[nitems++] = {gi, t.m0, t.n0, t.kind, r->planned + 1, 0};
+                work += (t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0) * r->n;
+            }
             const bool ends = r->next_tile == r->ntiles;
             if (ends) {
                 r->planned += 1;
@@ -585,12 +553,9 @@ btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_
         }
     }
     r->maxabs = mx;
-    // Tile shape: padded-area model (64-wide tiles charged 15% more per element).
-    const double a128 = std::pow((double)btas::batch_tiles_of(n, btas::BATCH_TILE_128) * 128, 2);
-    const double a64 = std::pow((double)btas::batch_tiles_of(n, btas::BATCH_TILE_64) * 64, 2) * 1.15;
-    r->kind = a128 <= a64 ? btas::BATCH_TILE_128 : btas::BATCH_TILE_64;
-    const int per_row = btas::batch_tiles_of(n, r->kind);
-    r->ntiles = per_row * per_row;
+    // Tile plan: padded-area model (64x64 tiles charged 15% more per element).
+    r->tiles = btas::tile_plan(n, btas::model_shape(n));
+    r->ntiles = (int)r->tiles.size();
     const size_t need = 2 * btas::align_up((size_t)n * r->ld * 4, 256) +
                         3 * btas::align_up((size_t)nnz * 4, 256);
     if (need > s.pool.size()) return BTAS_ERR_OOM;
