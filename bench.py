@@ -61,6 +61,33 @@ def parse():
     return p.parse_args()
 
 
+GEMM_SOURCES = ["paper_1701_04733_amd/csrc/gemm.hip", "paper_1701_04733_amd/csrc/gemm_tile.h",
+                "paper_1701_04733_amd/csrc/semiring.h"]
+COUNTERS = "profiles/tropical_gemm_8192_hbm_counters.txt"
+
+
+def measured_traffic(tag="min-plus/f32"):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None if the GEMM sources changed since it was taken."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for p in GEMM_SOURCES:
+            with open(os.path.join(ROOT, p), "rb") as f:
+                h.update(f.read())
+        fields = {}
+        with open(os.path.join(ROOT, COUNTERS)) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        if fields.get("sources_sha256") != h.hexdigest():
+            return None
+        return float(fields[f"traffic_bytes_per_launch[{tag}]"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(A, B, C, rows):
     """The oracle as it stands, on a bounded slab of the min-plus fp32 product."""
     import oracle
@@ -366,7 +393,9 @@ def main():
         "variants": variants,
         "roofline": {"bound": "alu", "kernel": "tropical_gemm_kernel<128x128x16,8x8> min-plus fp32",
                      "achieved": round(achieved, 2), "peak": round(PEAK_TOPS, 2), "unit": "Top/s",
-                     "frac": round(achieved / PEAK_TOPS, 4), "traffic": None},
+                     "frac": round(achieved / PEAK_TOPS, 4), "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": 4 * N * N * 4},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host["A"], host["B"], host["C"], args.cpu_rows)

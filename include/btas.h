@@ -225,7 +225,7 @@ int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n);
  *   BTAS_SERVE_CONTINUOUS: every engine iteration issues ONE grouped launch
  *     holding, for each active request, the next tiles of its current
  *     squaring up to quantum_terms (tile rows x tile cols x n) of work
- *     (<= 0 selects 2e10); requests admitted while others run join the next
+ *     (<= 0 selects 6e10); requests admitted while others run join the next
  *     iteration (continuous batching);
  *   BTAS_SERVE_FIFO: one request at a time, each squaring one plain GEMM
  *     launch (the one-solve-per-launch baseline).

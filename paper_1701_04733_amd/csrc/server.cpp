@@ -36,6 +36,7 @@
 
 #include "batched.h"
 #include "btas.h"
+#include "gemm_tile.h"
 #include "kernels.h"
 #include "range_alloc.h"
 
@@ -169,7 +170,7 @@ struct Server {
     int device = 0;
     int dt = BTAS_FLOAT32;
     int mode = 0;
-    double quantum = 2e10;
+    double quantum = 6e10;
     hipStream_t stream = nullptr;
     DevicePool pool;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -186,6 +187,13 @@ struct Server {
     std::thread engine;
 
     static constexpr int kDepth = 2;     // launches in flight
+    // Below this many tiles a grouped launch cannot fill the GPU; requests at
+    // the start of a squaring then get the single-GEMM path instead (split-K
+    // for small n, XCD-swizzled large tiles for big n).
+    static constexpr int kMinGroupedItems = 256;
+    void* splitk_ws = nullptr;           // split-K partials of the single-GEMM path
+    size_t splitk_bytes = 0;
+    int* d_zero = nullptr;               // a device 0: "operands fit the binary32 path"
     Staging staging[kDepth];
     std::deque<Launch> inflight;
     std::vector<hipEvent_t> free_events;
@@ -198,6 +206,8 @@ struct Server {
     }
 
     void free_staging() {
+        if (splitk_ws) (void)hipFree(splitk_ws), splitk_ws = nullptr;
+        if (d_zero) (void)hipFree(d_zero), d_zero = nullptr;
         for (Staging& st : staging) {
             st.free_graphs();
             st.free_items();
@@ -283,39 +293,66 @@ struct Server {
                 ni += (size_t)(r->ntiles - r->next_tile);
             }
         if (!st.reserve(ng + 1, ni + 1)) return hipErrorOutOfMemory;
+        // Few tiles in total: requests at a squaring boundary take the
+        // single-GEMM path, one launch per request.
+        const bool few = ni < (size_t)kMinGroupedItems;
         int nitems = 0;
+        std::vector<Request*> single;
         for (Request* r : order) {
             if (!plannable(r)) continue;
             const int gi = (int)L.graphs.size();
             st.h_graphs[gi] = {{r->buf[0], r->buf[1]}, r->n, r->ld, r->T, 0};
             st.h_maxabs[gi] = r->maxabs;
             st.h_changed[gi] = 0;
-            double work = 0;  // terms scheduled for this request in this launch
-            while (r->next_tile < r->ntiles && (work == 0 || work < quantum)) {
-                const TileRef& t = r->tiles[r->next_tile++];
-                st.h_items[nitems++] = {gi, t.m0, t.n0, t.kind, r->planned + 1, 0};
-                work += (t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0) * r->n;
+            if (few && r->next_tile == 0) {
+                single.push_back(r);
+                r->next_tile = r->ntiles;
+            } else {
+                double work = 0;  // terms scheduled for this request in this launch
+                while (r->next_tile < r->ntiles && (work == 0 || work < quantum)) {
+                    const TileRef& t = r->tiles[r->next_tile++];
+                    st.h_items[nitems++] = {gi, t.m0, t.n0, t.kind, r->planned + 1, 0};
+                    work += (t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0) * r->n;
+                }
             }
             const bool ends = r->next_tile == r->ntiles;
-            if (ends) {
+            L.graphs.push_back(r);
+            L.ends_step.push_back(ends);
+        }
+        const int g = (int)L.graphs.size();
+        if (g == 0) return hipSuccess;
+        hipError_t e = hipMemcpyAsync(st.d_changed, st.h_changed, g * sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && nitems > 0) {
+            e = hipMemcpyAsync(st.d_graphs, st.h_graphs, g * sizeof(BatchGraph), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(st.d_maxabs, st.h_maxabs, g * sizeof(int), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(st.d_items, st.h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess)
+                e = launch_grouped_step(dt, st.d_graphs, st.d_items, nitems,
+                                        dt == BTAS_INT32 ? st.d_maxabs : nullptr, st.d_changed, stream);
+            launches++;
+        }
+        for (size_t i = 0; e == hipSuccess && i < L.graphs.size(); ++i) {
+            Request* r = L.graphs[i];
+            if (std::find(single.begin(), single.end(), r) == single.end()) continue;
+            const int s = r->planned + 1;  // squaring s reads buf[(s-1)&1], writes buf[s&1]
+            void* src = r->buf[(s - 1) & 1];
+            void* dst = r->buf[s & 1];
+            // int32 operands within 2^T * max|w| <= FP32_EXACT_MAX stay on the binary32 path
+            const bool narrow = dt == BTAS_INT32 &&
+                                (long)r->maxabs <= ((long)FP32_EXACT_MAX >> (r->T < 31 ? r->T : 31));
+            GemmArgs a{r->n, r->n, r->n, src, r->ld, src, r->ld, src, r->ld, dst, r->ld,
+                       st.d_changed + i, narrow ? d_zero : nullptr, nullptr, splitk_ws, splitk_bytes};
+            e = launch_gemm(BTAS_MIN_PLUS, dt, a, -1, stream);
+            launches++;
+        }
+        for (size_t i = 0; i < L.graphs.size(); ++i)
+            if (L.ends_step[i]) {
+                Request* r = L.graphs[i];
                 r->planned += 1;
                 r->next_tile = 0;
                 if (r->early) r->hold = true;
             }
-            L.graphs.push_back(r);
-            L.ends_step.push_back(ends);
-        }
-        if (nitems == 0) return hipSuccess;
-        const int g = (int)L.graphs.size();
-        hipError_t e = hipMemcpyAsync(st.d_graphs, st.h_graphs, g * sizeof(BatchGraph), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(st.d_maxabs, st.h_maxabs, g * sizeof(int), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(st.d_changed, st.h_changed, g * sizeof(int), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(st.d_items, st.h_items, nitems * sizeof(BatchItem), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess)
-            e = launch_grouped_step(dt, st.d_graphs, st.d_items, nitems,
-                                    dt == BTAS_INT32 ? st.d_maxabs : nullptr, st.d_changed, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(st.h_changed, st.d_changed, g * sizeof(int), hipMemcpyDeviceToHost, stream);
-        launches++;
         return e;
     }
 
@@ -491,6 +528,14 @@ btas_status_t btas_server_create(btas_server_t* out, int device, btas_dtype_t dt
     if (quantum_terms > 0) s.quantum = quantum_terms;
     if (!s.pool.init(budget_bytes)) return BTAS_ERR_OOM;
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return BTAS_ERR_DEVICE;
+    // Split-K workspace for the single-GEMM path (only products with fewer than
+    // 256 output tiles split, i.e. n < 512: at most a few MiB).
+    s.splitk_bytes = 16u << 20;
+    if (hipMalloc(&s.splitk_ws, s.splitk_bytes) != hipSuccess || hipMalloc((void**)&s.d_zero, 4) != hipSuccess ||
+        hipMemset(s.d_zero, 0, 4) != hipSuccess) {
+        s.free_staging();
+        return BTAS_ERR_OOM;
+    }
     s.engine = std::thread([p = &s] { p->run(); });
     *out = srv.release();
     return BTAS_OK;
