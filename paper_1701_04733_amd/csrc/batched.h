@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "btas.h"
@@ -21,13 +22,14 @@ struct BatchGraph {
     int parity;
 };
 
-enum { BATCH_TILE_128 = 0, BATCH_TILE_64 = 1 };
+enum { BATCH_TILE_128 = 0, BATCH_TILE_64 = 1, BATCH_TILE_NONE = -1 };
 
 // One output tile of one squaring of one graph.
 struct BatchItem {
     int graph;
     int m0, n0;  // first output row / column of the tile
-    int kind;    // BATCH_TILE_128 (128x128 outputs) or BATCH_TILE_64 (64x64)
+    int kind;    // BATCH_TILE_128 (128x128 outputs), BATCH_TILE_64 (64x64), or
+                 // BATCH_TILE_NONE (placeholder: the workgroup exits at once)
     int step;    // squaring index s >= 1
     int pad;
 };
@@ -68,6 +70,51 @@ inline double tile_plan_cost(int n, int shape, double w64 = 1.15) {
     double c = 0;
     for (const TileRef& t : tile_plan(n, shape)) c += t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0 * w64;
     return c;
+}
+
+// Reorder one launch's items so that workgroup i, which the hardware places
+// on XCD i % 8 (each XCD has its own L2), works on tiles whose graph lives on
+// that XCD: graphs with fewer than 64 tiles go whole to the XCD with the least
+// work so far (largest first), larger graphs are cut into 8 bands of
+// consecutive tiles, one per XCD.  Queues of unequal length are padded with
+// placeholder items.  `items` must be grouped by graph.
+inline std::vector<BatchItem> order_for_xcds(const std::vector<BatchItem>& items,
+                                             const std::vector<int>& graph_n) {
+    constexpr int X = 8;
+    std::vector<std::vector<BatchItem>> q(X);
+    double load[X] = {0};
+    size_t i = 0;
+    while (i < items.size()) {
+        size_t j = i;
+        while (j < items.size() && items[j].graph == items[i].graph) ++j;
+        const size_t cnt = j - i;
+        const double n = graph_n[items[i].graph];
+        auto work = [&](const BatchItem& it) { return (it.kind == BATCH_TILE_128 ? 16384.0 : 4096.0) * n; };
+        if (cnt >= 64) {
+            for (int x = 0; x < X; ++x)
+                for (size_t t = i + cnt * x / X; t < i + cnt * (x + 1) / X; ++t) {
+                    q[x].push_back(items[t]);
+                    load[x] += work(items[t]);
+                }
+        } else {
+            int best = 0;
+            for (int x = 1; x < X; ++x)
+                if (load[x] < load[best]) best = x;
+            for (size_t t = i; t < j; ++t) {
+                q[best].push_back(items[t]);
+                load[best] += work(items[t]);
+            }
+        }
+        i = j;
+    }
+    size_t len = 0;
+    for (auto& v : q) len = std::max(len, v.size());
+    std::vector<BatchItem> out;
+    out.reserve(len * X);
+    const BatchItem none{0, 0, 0, BATCH_TILE_NONE, 1, 0};
+    for (size_t r = 0; r < len; ++r)
+        for (int x = 0; x < X; ++x) out.push_back(r < q[x].size() ? q[x][r] : none);
+    return out;
 }
 
 inline int model_shape(int n) {

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
                                                             int* __restrict__ changed) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchItem it = items[blockIdx.x];
+    if (it.kind == BATCH_TILE_NONE) return;
     const BatchGraph g = graphs[it.graph];
     const int s = it.step;                      // squaring index, 1-based
     const T* src = (const T*)g.buf[(g.parity + s - 1) & 1];

@@ -212,9 +212,12 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                     // taken for in-range int32 data.
                     (void)launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
                     float ms_of[NUM_SHAPES] = {1e30f, 1e30f, 1e30f};
+                    std::vector<int> all_n(ng);
+                    for (int g = 0; g < ng; ++g) all_n[g] = hg[g].n;
                     for (int cand : {SHAPE_128, SHAPE_64, SHAPE_MIXED}) {
                         std::vector<BatchItem> its;
                         for (int g : kv.second) append_items(its, g, hg[g].n, cand, 1);
+                        its = order_for_xcds(its, all_n);
                         BatchItem* d_its = nullptr;
                         st = upload(h, fn, (void**)&d_its, its.data(), sizeof(BatchItem) * its.size());
                         if (st != BTAS_OK) return st;
@@ -255,12 +258,19 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
 
         // Work lists: launch t holds the tiles of every graph with T >= t.
         std::vector<BatchItem> items;
+        std::vector<int> graph_n(ng);
+        for (int g = 0; g < ng; ++g) graph_n[g] = hg[g].n;
+        const char* xo = getenv("BTAS_XCD_ORDER");
+        const bool xcd_order = !(xo && xo[0] == '0');
         const int Tmax = ng > 0 ? hg[0].T : 0;
         for (int t = 1; t <= Tmax; ++t) {
-            p->step_off.push_back((int)items.size());
+            std::vector<BatchItem> step;
             for (int g = 0; g < ng && hg[g].T >= t; ++g)
-                append_items(items, g, hg[g].n, kind_of_bucket[size_bucket(hg[g].n)], t);
-            p->step_cnt.push_back((int)items.size() - p->step_off.back());
+                append_items(step, g, hg[g].n, kind_of_bucket[size_bucket(hg[g].n)], t);
+            if (xcd_order) step = order_for_xcds(step, graph_n);
+            p->step_off.push_back((int)items.size());
+            items.insert(items.end(), step.begin(), step.end());
+            p->step_cnt.push_back((int)step.size());
         }
         st = upload(h, fn, (void**)&p->d_items, items.data(), sizeof(BatchItem) * items.size());
         if (st != BTAS_OK) return st;

@@ -121,24 +121,47 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int m, int n, int S,
     if (wide_out != nullptr && __any(wide) && (threadIdx.x & 63) == 0) *wide_out = 1;
 }
 
-// Chunks for a split-K launch of Cfg (0 or 1: no split).  Aim at about 512
-// workgroups with at least 32 k per chunk.
 template <typename Cfg>
-static int splitk_chunks(int m, int n, int k) {
-    const long tiles = (long)((m + Cfg::BM - 1) / Cfg::BM) * ((n + Cfg::BN - 1) / Cfg::BN);
-    if (tiles >= 256 || k < 128) return 1;
-    long S = (512 + tiles - 1) / tiles;
+static long tiles_for(int m, int n) {
+    return (long)((m + Cfg::BM - 1) / Cfg::BM) * ((n + Cfg::BN - 1) / Cfg::BN);
+}
+
+// Tile configuration and split-K factor for an m x n x k product.  The aim
+// is enough work to occupy the GPU: at least ~512 workgroups of 256 threads
+// (two per CU).  Large outputs use 128x128 tiles; mid-size outputs 64x64
+// tiles, with k split into chunks of at least 32 when there are fewer than
+// 512 of them; tiny outputs (m or n <= 48) 32x32 tiles of 64 threads with
+// k split the same way.
+GemmPlan plan_gemm(int m, int n, int k) {
+    GemmPlan p{GEMM_CFG_L, 1};
+    if (tiles_for<CfgL>(m, n) >= 512) return p;
+    const long tm = tiles_for<CfgM>(m, n);
+    if (tm >= 512) {
+        p.cfg = GEMM_CFG_M;
+        return p;
+    }
+    if (m > 48 && n > 48) {
+        p.cfg = GEMM_CFG_M;
+        long S = (512 + tm - 1) / tm;
+        S = std::min<long>(S, k / 32);
+        p.splits = (int)std::max<long>(1, std::min<long>(S, 64));
+        return p;
+    }
+    p.cfg = GEMM_CFG_S;
+    const long ts = tiles_for<CfgS>(m, n);
+    long S = (2048 + ts - 1) / ts;  // 64-thread workgroups: aim at 2048 of them
     S = std::min<long>(S, k / 32);
-    return (int)std::max<long>(1, std::min<long>(S, 64));
+    p.splits = (int)std::max<long>(1, std::min<long>(S, 64));
+    return p;
 }
 
 size_t gemm_splitk_bytes(int m, int n, int k) {
-    const int S = splitk_chunks<CfgS>(m, n, k);
-    return S > 1 ? (size_t)S * m * n * 4 : 0;
+    const GemmPlan p = plan_gemm(m, n, k);
+    return p.splits > 1 ? (size_t)p.splits * m * n * 4 : 0;
 }
 
 template <typename Cfg, typename T, int SR>
-static hipError_t launch_cfg(const GemmArgs& g, hipStream_t s) {
+static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
     const int nbm = (g.m + Cfg::BM - 1) / Cfg::BM;
     const int nbn = (g.n + Cfg::BN - 1) / Cfg::BN;
     const long nb = (long)nbm * nbn;
@@ -149,7 +172,6 @@ static hipError_t launch_cfg(const GemmArgs& g, hipStream_t s) {
                                             (uintptr_t)g.Cin | (uintptr_t)g.Cout) % 16 == 0);
     TileArgs<T> a{g.m, g.n, g.k, (const T*)g.A, g.lda, (const T*)g.B, g.ldb, (const T*)g.Cin,
                   g.ldci, (T*)g.Cout, g.ldco, g.changed, g.wide_out};
-    int S = splitk_chunks<Cfg>(g.m, g.n, g.k);
     if (S > 1 && (g.ws == nullptr || (size_t)S * g.m * g.n * 4 > g.ws_bytes)) S = 1;
     if (S > 1) {
         // chunk length: a multiple of BK, so every chunk but the last is full
@@ -183,23 +205,14 @@ static hipError_t launch_cfg(const GemmArgs& g, hipStream_t s) {
 
 template <typename T, int SR>
 static hipError_t launch_typed(const GemmArgs& a, int cfg, hipStream_t s) {
-    if (cfg < 0) cfg = pick_gemm_cfg(a.m, a.n, a.k);
-    switch (cfg) {
-        case GEMM_CFG_L: return launch_cfg<CfgL, T, SR>(a, s);
-        case GEMM_CFG_M: return launch_cfg<CfgM, T, SR>(a, s);
-        case GEMM_CFG_S: return launch_cfg<CfgS, T, SR>(a, s);
+    GemmPlan p = plan_gemm(a.m, a.n, a.k);
+    if (cfg >= 0 && cfg != p.cfg) p = GemmPlan{cfg, 1};  // a forced configuration does not split
+    switch (p.cfg) {
+        case GEMM_CFG_L: return launch_cfg<CfgL, T, SR>(a, p.splits, s);
+        case GEMM_CFG_M: return launch_cfg<CfgM, T, SR>(a, p.splits, s);
+        case GEMM_CFG_S: return launch_cfg<CfgS, T, SR>(a, p.splits, s);
         default: return hipErrorInvalidValue;
     }
-}
-
-int pick_gemm_cfg(int m, int n, int /*k*/) {
-    // Enough 128x128 tiles to give every CU two workgroups -> large tiles
-    // (best arithmetic intensity); otherwise trade intensity for parallelism.
-    const long tl = (long)((m + 127) / 128) * ((n + 127) / 128);
-    if (tl >= 512) return GEMM_CFG_L;
-    const long tmid = (long)((m + 63) / 64) * ((n + 63) / 64);
-    if (tmid >= 256) return GEMM_CFG_M;
-    return GEMM_CFG_S;
 }
 
 hipError_t launch_gemm(int sr, int dt, const GemmArgs& a, int cfg, hipStream_t s) {

@@ -40,7 +40,12 @@ size_t gemm_splitk_bytes(int m, int n, int k);
 
 enum { GEMM_CFG_L = 0, GEMM_CFG_M = 1, GEMM_CFG_S = 2, GEMM_NUM_CFGS = 3 };
 
-int pick_gemm_cfg(int m, int n, int k);
+struct GemmPlan {
+    int cfg;     // GEMM_CFG_*
+    int splits;  // split-K chunks (1: none)
+};
+// Configuration launch_gemm uses for an m x n x k product (cfg < 0).
+GemmPlan plan_gemm(int m, int n, int k);
 hipError_t launch_gemm(int sr, int dt, const GemmArgs& a, int cfg, hipStream_t s);
 
 // y <- y (+) A (.) x

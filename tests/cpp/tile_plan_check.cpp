@@ -26,6 +26,40 @@ int main() {
                     break;
                 }
         }
+    // XCD ordering: a permutation of the items plus placeholders, and every
+    // graph with fewer than 64 tiles stays on one XCD (position mod 8).
+    {
+        std::vector<btas::BatchItem> items;
+        std::vector<int> graph_n;
+        for (int g = 0; g < 300; ++g) {
+            const int n = 16 + (g * 37) % 1500;
+            graph_n.push_back(n);
+            for (const btas::TileRef& t : btas::tile_plan(n, g % btas::NUM_SHAPES))
+                items.push_back({g, t.m0, t.n0, t.kind, 1, 0});
+        }
+        const auto out = btas::order_for_xcds(items, graph_n);
+        if (out.size() % 8) ++bad;
+        std::vector<int> seen(items.size(), 0), xcd(graph_n.size(), -1);
+        std::vector<int> count(graph_n.size(), 0);
+        for (const auto& it : items) count[it.graph]++;
+        for (size_t p = 0; p < out.size(); ++p) {
+            const auto& it = out[p];
+            if (it.kind == btas::BATCH_TILE_NONE) continue;
+            size_t idx = 0;
+            for (; idx < items.size(); ++idx)
+                if (!seen[idx] && items[idx].graph == it.graph && items[idx].m0 == it.m0 &&
+                    items[idx].n0 == it.n0 && items[idx].kind == it.kind)
+                    break;
+            if (idx == items.size()) { ++bad; continue; }
+            seen[idx] = 1;
+            if (count[it.graph] < 64) {
+                if (xcd[it.graph] < 0) xcd[it.graph] = (int)(p % 8);
+                else if (xcd[it.graph] != (int)(p % 8)) ++bad;
+            }
+        }
+        for (int s : seen)
+            if (!s) ++bad;
+    }
     std::printf("tile plan failures: %d\n", bad);
     return bad != 0;
 }
