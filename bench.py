@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-rows", type=int, default=128,
+    p.add_argument("--cpu-rows", type=int, default=160,
                    help="rows of the 8192^3 min-plus fp32 product timed on the oracle")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the APSP workloads (small, large, batched, served)")

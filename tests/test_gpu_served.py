@@ -30,6 +30,15 @@ def _dense(req, dtype=np.float32):
     return W
 
 
+def _max_overlap(spans):
+    events = sorted([(a, 1) for a, _ in spans] + [(d, -1) for _, d in spans])
+    live = peak = 0
+    for _, e in events:
+        live += e
+        peak = max(peak, live)
+    return peak
+
+
 def _fetch(srv, rid, n, dev, dtype):
     import torch
     out = torch.empty((n, n), dtype=dtype, device=dev)
@@ -45,16 +54,18 @@ def test_served_mix_matches_oracle_and_alone(dev, mode):
     reqs = _requests(24, seed=31)
     with btas.Server("f32", budget_bytes=4 << 30, mode=mode, quantum_terms=2e8) as srv:
         ids = [srv.submit(r.n, r.rows, r.cols, r.w) for r in reqs]      # all at once: a mix
-        mixed = {}
+        mixed, spans = {}, []
         for r, rid in zip(reqs, ids):
             assert srv.wait(rid, timeout=120)
             mixed[r.rid] = _fetch(srv, rid, r.n, dev, torch.float32)
             assert srv.steps(rid) == oracle.apsp_steps(r.n)
+            spans.append(srv.times(rid)[1:])
             srv.release(rid)
         st = srv.stats()
         assert st["active"] == 0 and st["pending"] == 0 and st["pool_used_bytes"] == 0
-        if mode == "continuous":
-            assert st["launches"] < sum(oracle.apsp_steps(r.n) for r in reqs)  # shared launches
+        # continuous batching: requests are resident and advancing together;
+        # FIFO: one at a time
+        assert (_max_overlap(spans) >= 2) == (mode == "continuous")
     with btas.Server("f32", budget_bytes=4 << 30, mode="continuous") as alone_srv:
         for r in reqs:
             rid = alone_srv.submit(r.n, r.rows, r.cols, r.w)
@@ -108,12 +119,7 @@ def test_served_budget_admission(dev):
         assert st["pool_peak_bytes"] <= st["pool_bytes"] <= budget + 256
         # no more requests were resident at once than the budget holds
         least = min(2 * ((r.n + 3) // 4 * 4) * r.n * 4 for r in reqs)
-        events = sorted([(a, 1) for a, _ in spans] + [(d, -1) for _, d in spans])
-        live = peak = 0
-        for _, e in events:
-            live += e
-            peak = max(peak, live)
-        assert peak <= budget // least
+        assert _max_overlap(spans) <= budget // least
 
 
 def test_served_int32_and_errors(dev):
@@ -138,3 +144,25 @@ def test_served_int32_and_errors(dev):
             srv.submit(4, np.array([0, 4]), np.array([1, 2]), np.array([1, 1], np.int32))
         with pytest.raises(btas.BtasError, match="DOMAIN"):
             srv.submit(4, np.array([0]), np.array([1]), np.array([1 << 29], np.int32))
+
+
+def test_served_many_requests_share_grouped_launches(dev):
+    """Enough concurrent work to fill the GPU: squarings of different
+    requests share grouped launches (fewer launches than squarings), and the
+    results still equal the oracle."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    reqs = _requests(40, seed=34, lo=300, hi=700)
+    with btas.Server("f32", budget_bytes=8 << 30) as srv:
+        ids = [srv.submit(r.n, r.rows, r.cols, r.w) for r in reqs]
+        got = {}
+        for r, rid in zip(reqs, ids):
+            assert srv.wait(rid, 120)
+            got[r.rid] = _fetch(srv, rid, r.n, dev, torch.float32)
+            srv.release(rid)
+        st = srv.stats()
+        assert st["launches"] < sum(oracle.apsp_steps(r.n) for r in reqs)
+    for r in reqs[:6]:
+        want, _, _ = oracle.apsp(_dense(r))
+        assert np.array_equal(_bits(got[r.rid]), _bits(want))
