@@ -191,11 +191,11 @@ int btas_apsp_num_steps(int n);
  *   it would not change the result).
  * The first call with a given argument set builds a plan (device workspace of
  * two padded n_i x n_i buffers per graph, work lists, per-size-bucket tile
- * shapes chosen by timing both candidate shapes on this device, the captured
- * graph) and synchronises; later calls with identical arguments only launch
- * the graph (asynchronous).  The environment variable BTAS_BATCHED_TILE=128
- * or 64 forces one tile shape; BTAS_AUTOTUNE=0 uses a cost model instead of
- * timing.
+ * shapes chosen by timing every candidate shape of btas_tile_shape_t on this
+ * device, the captured graph) and synchronises; later calls with identical
+ * arguments only launch the graph (asynchronous).  The environment variable
+ * BTAS_BATCHED_TILE=128, 64, mixed, w64 or wmix forces one tile shape;
+ * BTAS_AUTOTUNE=0 uses a cost model instead of timing.
  */
 btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int count,
                                          const int *n, const void *const *W, const int *ldw,
@@ -206,8 +206,19 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
  * outputs, either may be NULL).  INVALID_ARG if no plan exists. */
 btas_status_t btas_batched_plan_info(btas_handle_t h, int *num_launches, double *total_terms);
 
-/* Output-tile edge (128 or 64) the handle uses for graphs of n vertices of
- * dtype dt, or -1 if that size bucket has not been planned yet. */
+/* How the batched path cuts a graph's n x n output into work items.  The
+ * block shapes give each tile a workgroup of four waves, the wave shapes a
+ * single wave; one plan uses shapes of one family only. */
+typedef enum {
+    BTAS_TILES_128 = 0,    /* 128x128 tiles, ragged edge padded to 128 */
+    BTAS_TILES_64 = 1,     /* 64x64 tiles (four waves, 4x4 outputs per thread) */
+    BTAS_TILES_MIXED = 2,  /* 128x128 on the multiple-of-128 core, 64x64 on the edge */
+    BTAS_TILES_W64 = 3,    /* 64x64 tiles, one wave, 8x8 outputs per thread */
+    BTAS_TILES_WMIX = 4    /* one-wave 64x64 on the multiple-of-64 core, 32x32 on the edge */
+} btas_tile_shape_t;
+
+/* The btas_tile_shape_t the handle's most recent batched plan used for graphs
+ * of n vertices of dtype dt, or -1 if that size bucket has not been planned. */
 int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n);
 
 /* ---------------------------------------------------------------------------

@@ -22,62 +22,90 @@ struct BatchGraph {
     int parity;
 };
 
-enum { BATCH_TILE_128 = 0, BATCH_TILE_64 = 1, BATCH_TILE_NONE = -1 };
+// Tile kinds.  The block kinds run in the 256-thread grouped kernel, the wave
+// kinds in the 64-thread one (one wave per tile); a launch holds kinds of one
+// family only.
+enum {
+    BATCH_TILE_128 = 0,   // 128x128 outputs, 4 waves, 8x8 per thread
+    BATCH_TILE_64 = 1,    // 64x64 outputs, 4 waves, 4x4 per thread
+    BATCH_TILE_W64 = 2,   // 64x64 outputs, 1 wave, 8x8 per thread
+    BATCH_TILE_W32 = 3,   // 32x32 outputs, 1 wave, 4x4 per thread
+    BATCH_TILE_NONE = -1  // placeholder: the workgroup exits at once
+};
+
+inline int tile_edge(int kind) {
+    return kind == BATCH_TILE_128 ? 128 : kind == BATCH_TILE_W32 ? 32 : 64;
+}
+inline bool tile_is_wave(int kind) { return kind == BATCH_TILE_W64 || kind == BATCH_TILE_W32; }
 
 // One output tile of one squaring of one graph.
 struct BatchItem {
     int graph;
     int m0, n0;  // first output row / column of the tile
-    int kind;    // BATCH_TILE_128 (128x128 outputs), BATCH_TILE_64 (64x64), or
-                 // BATCH_TILE_NONE (placeholder: the workgroup exits at once)
+    int kind;    // BATCH_TILE_*
     int step;    // squaring index s >= 1
     int pad;
 };
 
-// How a graph's n x n output is cut into tiles.
-enum { SHAPE_128 = 0, SHAPE_64 = 1, SHAPE_MIXED = 2, NUM_SHAPES = 3 };
+// How a graph's n x n output is cut into tiles.  SHAPE_128/64/MIXED use the
+// block kinds, SHAPE_W64/WMIX the wave kinds.
+enum { SHAPE_128 = 0, SHAPE_64 = 1, SHAPE_MIXED = 2, SHAPE_W64 = 3, SHAPE_WMIX = 4, NUM_SHAPES = 5 };
+inline bool shape_is_wave(int shape) { return shape == SHAPE_W64 || shape == SHAPE_WMIX; }
 
 struct TileRef {
     int m0, n0, kind;
 };
 
-// Tiles covering [0,n)^2.  SHAPE_MIXED uses 128x128 tiles on the
-// floor(n/128)*128 core and 64x64 tiles on the remainder strips, which keeps
-// most work on the larger tile while padding the ragged edge only to 64.
+// Tiles covering [0,n)^2.  The mixed shapes use the large tile on the
+// floor(n/big)*big core and the small one on the remainder strips, which keeps
+// most work on the larger tile while padding the ragged edge only to the
+// small edge (SHAPE_MIXED: 128 + 64, SHAPE_WMIX: 64 + 32).
 inline std::vector<TileRef> tile_plan(int n, int shape) {
     std::vector<TileRef> out;
     if (n <= 0) return out;
-    if (shape == SHAPE_128 || shape == SHAPE_64) {
-        const int t = shape == SHAPE_128 ? 128 : 64;
-        const int kind = shape == SHAPE_128 ? BATCH_TILE_128 : BATCH_TILE_64;
+    if (shape == SHAPE_128 || shape == SHAPE_64 || shape == SHAPE_W64) {
+        const int kind = shape == SHAPE_128 ? BATCH_TILE_128
+                         : shape == SHAPE_64 ? BATCH_TILE_64 : BATCH_TILE_W64;
+        const int t = tile_edge(kind);
         for (int i = 0; i < n; i += t)
             for (int j = 0; j < n; j += t) out.push_back({i, j, kind});
         return out;
     }
-    const int core = n / 128 * 128;
-    // 64-wide segments: the core split in halves plus the remainder
-    for (int i = 0; i < core; i += 128)
-        for (int j = 0; j < core; j += 128) out.push_back({i, j, BATCH_TILE_128});
-    for (int i = 0; i < n; i += 64)
-        for (int j = 0; j < n; j += 64)
-            if (i >= core || j >= core) out.push_back({i, j, BATCH_TILE_64});
+    const bool wave = shape == SHAPE_WMIX;
+    const int big = wave ? 64 : 128, small = big / 2;
+    const int kbig = wave ? BATCH_TILE_W64 : BATCH_TILE_128;
+    const int ksmall = wave ? BATCH_TILE_W32 : BATCH_TILE_64;
+    const int core = n / big * big;
+    for (int i = 0; i < core; i += big)
+        for (int j = 0; j < core; j += big) out.push_back({i, j, kbig});
+    for (int i = 0; i < n; i += small)
+        for (int j = 0; j < n; j += small)
+            if (i >= core || j >= core) out.push_back({i, j, ksmall});
     return out;
 }
 
-// Padded output area of a plan, 64x64 tiles weighted by `w64` (their lower
-// efficiency per element); the model used when tiles are not timed.
-inline double tile_plan_cost(int n, int shape, double w64 = 1.15) {
+// Output elements a tile covers (padding included).
+inline double tile_area(int kind) {
+    const double e = tile_edge(kind);
+    return e * e;
+}
+
+// Padded output area of a plan, small tiles weighted by `w_small` (their
+// lower efficiency per element); the model used when tiles are not timed.
+inline double tile_plan_cost(int n, int shape, double w_small = 1.15) {
     double c = 0;
-    for (const TileRef& t : tile_plan(n, shape)) c += t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0 * w64;
+    for (const TileRef& t : tile_plan(n, shape))
+        c += tile_area(t.kind) * (t.kind == BATCH_TILE_64 || t.kind == BATCH_TILE_W32 ? w_small : 1.0);
     return c;
 }
 
 // Reorder one launch's items so that workgroup i, which the hardware places
 // on XCD i % 8 (each XCD has its own L2), works on tiles whose graph lives on
-// that XCD: graphs with fewer than 64 tiles go whole to the XCD with the least
-// work so far (largest first), larger graphs are cut into 8 bands of
-// consecutive tiles, one per XCD.  Queues of unequal length are padded with
-// placeholder items.  `items` must be grouped by graph.
+// that XCD: a graph goes whole to the XCD with the least work so far (largest
+// first), unless it holds more than half of one XCD's share of the launch's
+// items; such a graph is cut into 8 bands of consecutive tiles, one per XCD.
+// Queues of unequal length are padded with placeholder items.  `items` must
+// be grouped by graph.
 inline std::vector<BatchItem> order_for_xcds(const std::vector<BatchItem>& items,
                                              const std::vector<int>& graph_n) {
     constexpr int X = 8;
@@ -89,8 +117,8 @@ inline std::vector<BatchItem> order_for_xcds(const std::vector<BatchItem>& items
         while (j < items.size() && items[j].graph == items[i].graph) ++j;
         const size_t cnt = j - i;
         const double n = graph_n[items[i].graph];
-        auto work = [&](const BatchItem& it) { return (it.kind == BATCH_TILE_128 ? 16384.0 : 4096.0) * n; };
-        if (cnt >= 64) {
+        auto work = [&](const BatchItem& it) { return tile_area(it.kind) * n; };
+        if (cnt * 2 * X > items.size()) {
             for (int x = 0; x < X; ++x)
                 for (size_t t = i + cnt * x / X; t < i + cnt * (x + 1) / X; ++t) {
                     q[x].push_back(items[t]);
@@ -117,11 +145,23 @@ inline std::vector<BatchItem> order_for_xcds(const std::vector<BatchItem>& items
     return out;
 }
 
+static_assert(SHAPE_128 == BTAS_TILES_128 && SHAPE_64 == BTAS_TILES_64 &&
+                  SHAPE_MIXED == BTAS_TILES_MIXED && SHAPE_W64 == BTAS_TILES_W64 &&
+                  SHAPE_WMIX == BTAS_TILES_WMIX,
+              "internal shape codes are the ABI's");
+
+// Cheapest block-family shape by the padded-area model.
 inline int model_shape(int n) {
     int best = SHAPE_128;
     for (int s : {SHAPE_64, SHAPE_MIXED})
         if (tile_plan_cost(n, s) < tile_plan_cost(n, best)) best = s;
     return best;
+}
+
+// Cheapest wave-family shape by the padded-area model (a 32x32 wave tile
+// costs about 1.3x a 64x64 one per element: half the register tile).
+inline int model_wave_shape(int n) {
+    return tile_plan_cost(n, SHAPE_WMIX, 1.3) < tile_plan_cost(n, SHAPE_W64) ? SHAPE_WMIX : SHAPE_W64;
 }
 
 // An external matrix (the caller's W or D) paired with a graph.  Jobs of one
@@ -135,12 +175,14 @@ struct BatchCopy {
     const void* ext;
 };
 
-// Squarings for items[0, nitems): one workgroup of 256 threads per item.
-// maxabs (int32 only, may be null): per-graph max |finite weight| recorded by
+// Squarings for items[0, nitems): one workgroup per item, 256 threads for the
+// block kinds, 64 for the wave kinds (`wave` selects the family; every item of
+// the launch must belong to it, placeholders aside).  maxabs (int32 only, may be null): per-graph max |finite weight| recorded by
 // launch_grouped_init.  changed (may be null): per-graph flag set to 1 when a
 // squaring changed some entry.
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
-                               int nitems, const int* maxabs, int* changed, hipStream_t s);
+                               int nitems, const int* maxabs, int* changed, hipStream_t s,
+                               bool wave = false);
 // buf[parity] <- I (+) W for each job; int32: maxabs[graph] <- max |finite W|
 // (maxabs must be zeroed first).
 // total_blocks = sum of the jobs' nblocks.

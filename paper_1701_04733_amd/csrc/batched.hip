@@ -42,9 +42,9 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
     const BatchItem it = items[blockIdx.x];
     if (it.kind == BATCH_TILE_NONE) return;
     const BatchGraph g = graphs[it.graph];
-    const int s = it.step;                      // squaring index, 1-based
-    const T* src = (const T*)g.buf[(g.parity + s - 1) & 1];
-    T* dst = (T*)g.buf[(g.parity + s) & 1];
+    const bool odd = ((g.parity + it.step) & 1) != 0;  // squaring it.step writes buf[odd]
+    const T* src = (const T*)(odd ? g.buf[0] : g.buf[1]);
+    T* dst = (T*)(odd ? g.buf[1] : g.buf[0]);
     int* chg = changed != nullptr ? changed + it.graph : nullptr;
     TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
     const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
@@ -71,9 +71,57 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
 
 static_assert(CfgL::NT == 256 && CfgM::NT == 256, "grouped kernel mixes both tile shapes");
 
+// The same squaring step for the wave kinds: one 64-thread workgroup per tile.
+template <typename T, int SR>
+__global__ __launch_bounds__(64) void grouped_wave_step_kernel(const BatchGraph* __restrict__ graphs,
+                                                                const BatchItem* __restrict__ items,
+                                                                const int* __restrict__ maxabs,
+                                                                int* __restrict__ changed) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const BatchItem it = items[blockIdx.x];
+    if (it.kind == BATCH_TILE_NONE) return;
+    const BatchGraph g = graphs[it.graph];
+    const bool odd = ((g.parity + it.step) & 1) != 0;  // squaring it.step writes buf[odd]
+    const T* src = (const T*)(odd ? g.buf[0] : g.buf[1]);
+    T* dst = (T*)(odd ? g.buf[1] : g.buf[0]);
+    int* chg = changed != nullptr ? changed + it.graph : nullptr;
+    TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
+    const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
+    if (it.kind == BATCH_TILE_W64) {
+        if constexpr (std::is_same_v<T, int32_t>) {
+            if (narrow) {
+                GemmTile<CfgW, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
+                return;
+            }
+        }
+        GemmTile<CfgW, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
+    } else {
+        if constexpr (std::is_same_v<T, int32_t>) {
+            if (narrow) {
+                GemmTile<CfgS, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
+                return;
+            }
+        }
+        GemmTile<CfgS, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
+    }
+}
+
+static_assert(CfgW::NT == 64 && CfgS::NT == 64, "wave kernel mixes both wave tile shapes");
+
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
-                               int nitems, const int* maxabs, int* changed, hipStream_t s) {
+                               int nitems, const int* maxabs, int* changed, hipStream_t s,
+                               bool wave) {
     if (nitems <= 0) return hipSuccess;
+    if (wave) {
+        const size_t lds = CfgW::lds_bytes > CfgS::lds_bytes ? CfgW::lds_bytes : CfgS::lds_bytes;
+        if (dt == BTAS_FLOAT32)
+            hipLaunchKernelGGL((grouped_wave_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems),
+                               dim3(64), lds, s, graphs, items, nullptr, changed);
+        else
+            hipLaunchKernelGGL((grouped_wave_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems),
+                               dim3(64), lds, s, graphs, items, maxabs, changed);
+        return hipGetLastError();
+    }
     const size_t lds = CfgL::lds_bytes > CfgM::lds_bytes ? CfgL::lds_bytes : CfgM::lds_bytes;
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL((grouped_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems), dim3(256), lds,

@@ -44,6 +44,7 @@ struct BatchPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double terms = 0;                     // sum over graphs of T(n) * n^3
+    bool wave = false;                    // squaring launches use the one-wave tile kernel
 };
 
 void destroy_batch_plan(BatchPlan* p) {
@@ -89,6 +90,88 @@ btas_status_t upload(btas_handle_t h, const char* fn, void** dst, const void* sr
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate %zu bytes of descriptors", fn, bytes);
     hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+// BTAS_BATCHED_TILE=128|64|mixed|w64|wmix forces a shape; -1 if unset.
+int forced_shape() {
+    const char* f = getenv("BTAS_BATCHED_TILE");
+    if (!f || !*f) return -1;
+    const char* names[NUM_SHAPES] = {"128", "64", "mixed", "w64", "wmix"};
+    for (int s = 0; s < NUM_SHAPES; ++s)
+        if (std::strcmp(f, names[s]) == 0) return s;
+    return -1;
+}
+
+// Time one squaring of a size bucket with every candidate shape, on the
+// plan's (not yet initialised) buffers: the kernels' speed does not depend on
+// the values, and the binary32 path is the one taken for in-range int32 data.
+// The bucket's work list is repeated until a launch holds enough work to keep
+// every compute unit busy for several rounds, so the measurement is the
+// shape's throughput inside a full launch (where the plan will run it), not
+// the latency of a launch too small to fill the device.  Repeated items write
+// identical values.
+btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
+                          const std::vector<HostGraph>& hg, const std::vector<int>& slots,
+                          BucketTiming* out) {
+    hipError_t e = launch_clear_ints(p->d_maxabs, std::max((int)hg.size(), 1), h->aux_stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    double useful = 0;
+    for (int g : slots) useful += (double)hg[g].n * hg[g].n * hg[g].n;
+    std::vector<int> all_n(hg.size());
+    for (size_t g = 0; g < hg.size(); ++g) all_n[g] = hg[g].n;
+    double spt[NUM_SHAPES];
+    for (int cand = 0; cand < NUM_SHAPES; ++cand) {
+        std::vector<BatchItem> one;
+        double padded = 0;
+        for (int g : slots) {
+            const size_t before = one.size();
+            append_items(one, g, hg[g].n, cand, 1);
+            for (size_t i = before; i < one.size(); ++i) padded += tile_area(one[i].kind) * hg[g].n;
+        }
+        // at least ~2e10 padded terms (a millisecond of work) and 8 items per CU
+        int reps = 1;
+        while (reps < 256 && (padded * reps < 2e10 || one.size() * reps < 2048)) reps *= 2;
+        std::vector<BatchItem> its;
+        its.reserve(one.size() * reps);
+        for (int r = 0; r < reps; ++r) its.insert(its.end(), one.begin(), one.end());
+        its = order_for_xcds(its, all_n);
+        BatchItem* d_its = nullptr;
+        btas_status_t st = upload(h, fn, (void**)&d_its, its.data(), sizeof(BatchItem) * its.size());
+        if (st != BTAS_OK) return st;
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        float best = 1e30f;
+        for (int rep_i = 0; rep_i < 3 && e == hipSuccess; ++rep_i) {
+            (void)hipEventRecord(e0, h->aux_stream);
+            e = launch_grouped_step(dt, p->d_graphs, d_its, (int)its.size(), p->d_maxabs, nullptr,
+                                    h->aux_stream, shape_is_wave(cand));
+            (void)hipEventRecord(e1, h->aux_stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (rep_i > 0) best = std::min(best, t);  // the first run warms up
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipFree(d_its);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        spt[cand] = best * 1e-3 / (useful * reps);
+    }
+    out->best[0] = SHAPE_128;
+    out->best[1] = SHAPE_W64;
+    for (int cand = 0; cand < NUM_SHAPES; ++cand) {
+        const int f = shape_is_wave(cand) ? 1 : 0;
+        if (spt[cand] < spt[out->best[f]]) out->best[f] = cand;
+    }
+    out->spt[0] = spt[out->best[0]];
+    out->spt[1] = spt[out->best[1]];
+    if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1')
+        fprintf(stderr, "[btas] autotune dt=%d n<=%d graphs=%zu Tterm/s: 128 %.1f, 64 %.1f, mixed %.1f, "
+                "w64 %.1f, wmix %.1f -> block %d, wave %d\n", dt, hg[slots.front()].n, slots.size(),
+                1e-12 / spt[0], 1e-12 / spt[1], 1e-12 / spt[2], 1e-12 / spt[3], 1e-12 / spt[4],
+                out->best[0], out->best[1]);
+    return BTAS_OK;
 }
 
 }  // namespace
@@ -187,74 +270,44 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
             return fail(h, BTAS_ERR_OOM, "%s: cannot allocate flags", fn);
 
         // Tile shape per size bucket: forced, modelled, or measured.
-        const char* force = getenv("BTAS_BATCHED_TILE");
-        const char* tune_env = getenv("BTAS_AUTOTUNE");
-        const bool tune = !(tune_env && tune_env[0] == '0');
         std::map<int, std::vector<int>> buckets;  // bucket -> graph slots
         for (int g = 0; g < ng; ++g)
             if (hg[g].T > 0) buckets[size_bucket(hg[g].n)].push_back(g);
         std::map<int, int> kind_of_bucket;
-        for (auto& kv : buckets) {
-            int kind;
-            const int rep = hg[kv.second.front()].n;  // largest n of the bucket
-            if (force && std::strcmp(force, "128") == 0) kind = SHAPE_128;
-            else if (force && std::strcmp(force, "64") == 0) kind = SHAPE_64;
-            else if (force && std::strcmp(force, "mixed") == 0) kind = SHAPE_MIXED;
-            else if (!tune) kind = model_shape(rep);
-            else {
-                auto it = h->tile_choice.find({(int)dt, kv.first});
-                if (it != h->tile_choice.end()) {
-                    kind = it->second;
-                } else {
-                    // Time one squaring of the whole bucket with each shape on the
-                    // plan's (not yet initialised) buffers: the kernels' speed does
-                    // not depend on the values, and the binary32 path is the one
-                    // taken for in-range int32 data.
-                    (void)launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
-                    float ms_of[NUM_SHAPES] = {1e30f, 1e30f, 1e30f};
-                    std::vector<int> all_n(ng);
-                    for (int g = 0; g < ng; ++g) all_n[g] = hg[g].n;
-                    for (int cand : {SHAPE_128, SHAPE_64, SHAPE_MIXED}) {
-                        std::vector<BatchItem> its;
-                        for (int g : kv.second) append_items(its, g, hg[g].n, cand, 1);
-                        its = order_for_xcds(its, all_n);
-                        BatchItem* d_its = nullptr;
-                        st = upload(h, fn, (void**)&d_its, its.data(), sizeof(BatchItem) * its.size());
-                        if (st != BTAS_OK) return st;
-                        hipEvent_t e0, e1;
-                        (void)hipEventCreate(&e0);
-                        (void)hipEventCreate(&e1);
-                        for (int rep_i = 0; rep_i < 3 && e == hipSuccess; ++rep_i) {
-                            (void)hipEventRecord(e0, h->aux_stream);
-                            e = launch_grouped_step(dt, p->d_graphs, d_its, (int)its.size(),
-                                                    p->d_maxabs, nullptr, h->aux_stream);
-                            (void)hipEventRecord(e1, h->aux_stream);
-                            if (e == hipSuccess) e = hipEventSynchronize(e1);
-                            float t = 0;
-                            (void)hipEventElapsedTime(&t, e0, e1);
-                            if (rep_i > 0) ms_of[cand] = std::min(ms_of[cand], t);  // first run warms up
-                        }
-                        (void)hipEventDestroy(e0);
-                        (void)hipEventDestroy(e1);
-                        (void)hipFree(d_its);
-                        if (e != hipSuccess) return device_fail(h, fn, e);
-                    }
-                    kind = SHAPE_128;
-                    for (int cand : {SHAPE_64, SHAPE_MIXED})
-                        if (ms_of[cand] < ms_of[kind]) kind = cand;
-                    if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1') {
-                        double terms = 0;
-                        for (int g : kv.second) terms += (double)hg[g].n * hg[g].n * hg[g].n;
-                        fprintf(stderr, "[btas] autotune dt=%d bucket=%d n<=%d graphs=%zu: 128: %.3f ms "
-                                "(%.1f Tterm/s), 64: %.3f ms (%.1f), mixed: %.3f ms (%.1f) -> shape %d\n",
-                                (int)dt, kv.first, rep, kv.second.size(), ms_of[0], terms / ms_of[0] / 1e9,
-                                ms_of[1], terms / ms_of[1] / 1e9, ms_of[2], terms / ms_of[2] / 1e9, kind);
-                    }
-                    h->tile_choice[{(int)dt, kv.first}] = kind;
+        bool wave = true;
+        const int forced = forced_shape();
+        const char* tune_env = getenv("BTAS_AUTOTUNE");
+        const bool tune = !(tune_env && tune_env[0] == '0');
+        if (forced >= 0) {
+            wave = shape_is_wave(forced);
+            for (auto& kv : buckets) kind_of_bucket[kv.first] = forced;
+        } else if (!tune) {
+            for (auto& kv : buckets) kind_of_bucket[kv.first] = model_wave_shape(hg[kv.second.front()].n);
+        } else {
+            // Measure the buckets this handle has not timed yet, then take the
+            // family with the smaller predicted time for the whole plan.
+            double cost[2] = {0, 0};
+            for (auto& kv : buckets) {
+                auto it = h->tile_timing.find({(int)dt, kv.first});
+                if (it == h->tile_timing.end()) {
+                    BucketTiming bt;
+                    st = time_bucket(h, fn, dt, p.get(), hg, kv.second, &bt);
+                    if (st != BTAS_OK) return st;
+                    it = h->tile_timing.emplace(std::make_pair((int)dt, kv.first), bt).first;
                 }
+                double terms = 0;
+                for (int g : kv.second) terms += (double)hg[g].T * hg[g].n * (double)hg[g].n * hg[g].n;
+                for (int f = 0; f < 2; ++f) cost[f] += terms * it->second.spt[f];
             }
-            kind_of_bucket[kv.first] = kind;
+            wave = cost[1] <= cost[0];
+            for (auto& kv : buckets)
+                kind_of_bucket[kv.first] = h->tile_timing[{(int)dt, kv.first}].best[wave ? 1 : 0];
+            if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1')
+                fprintf(stderr, "[btas] batched plan: predicted %.3f ms with block tiles, %.3f ms with "
+                        "wave tiles -> %s\n", cost[0] * 1e3, cost[1] * 1e3, wave ? "wave" : "block");
         }
+        p->wave = wave;
+        for (auto& kv : kind_of_bucket) h->tile_choice[{(int)dt, kv.first}] = kv.second;
 
         // Work lists: launch t holds the tiles of every graph with T >= t.
         std::vector<BatchItem> items;
@@ -298,7 +351,8 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                                     dt == BTAS_INT32 ? p->d_maxabs : nullptr, h->aux_stream);
         for (int t = 0; t < Tmax && e == hipSuccess; ++t)
             e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
-                                    dt == BTAS_INT32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream);
+                                    dt == BTAS_INT32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream,
+                                    p->wave);
         if (e == hipSuccess) e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
@@ -329,6 +383,5 @@ extern "C" btas_status_t btas_batched_plan_info(btas_handle_t h, int* num_launch
 extern "C" int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n) {
     if (!h) return -1;
     auto it = h->tile_choice.find({(int)dt, size_bucket(n)});
-    if (it == h->tile_choice.end()) return -1;
-    return it->second == SHAPE_128 ? 128 : it->second == SHAPE_64 ? 64 : 0;
+    return it == h->tile_choice.end() ? -1 : it->second;
 }

@@ -19,6 +19,13 @@ void destroy_batch_plan(BatchPlan* p);
 struct BatchPlanDeleter {
     void operator()(BatchPlan* p) const { destroy_batch_plan(p); }
 };
+// Measured speed of one size bucket's squaring: for each tile family (0 =
+// four-wave blocks, 1 = single waves) the fastest shape and its seconds per
+// useful term.
+struct BucketTiming {
+    int best[2];
+    double spt[2];
+};
 }  // namespace btas
 
 struct btas_ctx {
@@ -35,7 +42,8 @@ struct btas_ctx {
     int* dflags = nullptr;               // device flags [kNumFlags], see the FLAG_* slots
     int* hflags = nullptr;               // pinned host mirror
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
-    std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> tile shape
+    std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan
+    std::map<std::pair<int, int>, btas::BucketTiming> tile_timing;  // (dtype, size bucket) -> autotune
     hipGraph_t apsp_graph = nullptr;     // last captured single-solve graph (BTAS_APSP_GRAPH)
     hipGraphExec_t apsp_exec = nullptr;
     uint64_t apsp_key = 0;

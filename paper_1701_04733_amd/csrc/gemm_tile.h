@@ -31,13 +31,13 @@ using v4 = T __attribute__((ext_vector_type(4)));
 // Largest magnitude of a finite int32 element that the binary32 path accepts.
 constexpr int32_t FP32_EXACT_MAX = (1 << 23) - 1;
 
-template <int BM_, int BN_, int BK_, int TM_, int TN_>
+template <int BM_, int BN_, int BK_, int TM_, int TN_, int NBUF_ = 2>
 struct GemmCfg {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, TM = TM_, TN = TN_;
+    static constexpr int NBUF = NBUF_;           // LDS buffers: 2 = double-buffered, 1 = single
     static constexpr int TXN = BN / TN;          // threads along n
     static constexpr int TYN = BM / TM;          // threads along m
     static constexpr int NT = TXN * TYN;         // threads per workgroup
-    static constexpr int RG = TM / 4;            // 4-row groups per thread
     static constexpr int CG = TN / 4;            // 4-col groups per thread
     static constexpr int APAD = 4, BPAD = 4;
     static constexpr int LDA_S = BK + APAD;      // LDS row stride of the A tile
@@ -49,12 +49,22 @@ struct GemmCfg {
     static_assert(TM % 4 == 0 && TN % 4 == 0, "register tile is built from 4-wide groups");
     static_assert(BK % 4 == 0, "k-block is consumed in quads");
     static_assert(A_VECS % NT == 0 && B_VECS % NT == 0, "tile loads must split evenly");
-    static constexpr size_t lds_bytes = 2 * (BM * LDA_S + BK * LDB_S) * 4;
+    static_assert(NBUF == 1 || NBUF == 2, "one or two LDS buffers");
+    static constexpr size_t lds_bytes = NBUF * (BM * LDA_S + BK * LDB_S) * 4;
+    // Tile row of a thread's r-th register row: rows are strided by TYN, so
+    // the lanes of a wave read consecutive A rows, whose padded LDS rows
+    // start in distinct banks (no conflicts for up to 8 distinct rows).
+    __device__ __forceinline__ static int row_of(int r, int ty) { return r * TYN + ty; }
 };
 
 using CfgL = GemmCfg<128, 128, 16, 8, 8>;  // large problems: 256 threads, 8x8 per thread
 using CfgM = GemmCfg<64, 64, 16, 4, 4>;    // mid-size: 256 threads, 4x4 per thread
 using CfgS = GemmCfg<32, 32, 16, 4, 4>;    // small / latency-bound: 64 threads
+// One wave computes a 64x64 tile with the 8x8 register tile of CfgL.  The
+// 8-deep k-block keeps the prefetch registers at CfgL's count (about 160 VGPRs,
+// three waves per SIMD); its double-buffered LDS (10.5 KB) lets LDS hold as
+// many of these workgroups as the register file does.
+using CfgW = GemmCfg<64, 64, 8, 8, 8>;
 
 // Element conversion between storage and compute types.
 template <typename T, typename CT, int SR>
@@ -164,7 +174,7 @@ struct GemmTile {
             v4<CT> av[Cfg::TM];
 #pragma unroll
             for (int r = 0; r < Cfg::TM; ++r) {
-                const int row = (r / 4) * (Cfg::BM / Cfg::RG) + ty * 4 + (r % 4);
+                const int row = Cfg::row_of(r, ty);
                 av[r] = *reinterpret_cast<const v4<CT>*>(As + row * Cfg::LDA_S + q * 4);
             }
 #pragma unroll
@@ -199,8 +209,8 @@ struct GemmTile {
         using RT = Ring<SR, T>;
         CT* As0 = reinterpret_cast<CT*>(smem);
         CT* Bs0 = As0 + Cfg::BM * Cfg::LDA_S;
-        CT* As1 = Bs0 + Cfg::BK * Cfg::LDB_S;
-        CT* Bs1 = As1 + Cfg::BM * Cfg::LDA_S;
+        CT* As1 = Cfg::NBUF == 2 ? Bs0 + Cfg::BK * Cfg::LDB_S : As0;
+        CT* Bs1 = Cfg::NBUF == 2 ? As1 + Cfg::BM * Cfg::LDA_S : Bs0;
         const int tid = threadIdx.x;
         const int tx = tid % Cfg::TXN, ty = tid / Cfg::TXN;
         const bool mn_interior = (m0 + Cfg::BM <= a.m) && (n0 + Cfg::BN <= a.n);
@@ -219,14 +229,22 @@ struct GemmTile {
         }
         __syncthreads();
         for (int kb = 0; kb < nkb; ++kb) {
-            const bool even = (kb & 1) == 0;
+            const bool even = Cfg::NBUF == 1 || (kb & 1) == 0;
             const bool more = kb + 1 < nkb;
             if (more) {
                 const int k0 = (kb + 1) * Cfg::BK;
                 load_global(ra, rb, a, m0, n0, k0, mn_interior && k0 + Cfg::BK <= a.k, tid);
             }
             compute(acc, even ? As0 : As1, even ? Bs0 : Bs1, tx, ty);
-            if (more) store_lds(ra, rb, even ? As1 : As0, even ? Bs1 : Bs0, tid);
+            if constexpr (Cfg::NBUF == 1) {
+                // every thread has read the block before it is overwritten
+                if (more) {
+                    __syncthreads();
+                    store_lds(ra, rb, As0, Bs0, tid);
+                }
+            } else {
+                if (more) store_lds(ra, rb, even ? As1 : As0, even ? Bs1 : Bs0, tid);
+            }
             __syncthreads();
         }
 
@@ -234,7 +252,7 @@ struct GemmTile {
         bool diff = false, wide = false;
 #pragma unroll
         for (int r = 0; r < Cfg::TM; ++r) {
-            const int row = m0 + (r / 4) * (Cfg::BM / Cfg::RG) + ty * 4 + (r % 4);
+            const int row = m0 + Cfg::row_of(r, ty);
             if (row >= a.m) continue;
 #pragma unroll
             for (int g = 0; g < Cfg::CG; ++g) {

@@ -1,5 +1,6 @@
 // Host-logic check: every tile plan of the grouped APSP kernels covers each
-// output element of an n x n matrix exactly once, with tile origins in range.
+// output element of an n x n matrix exactly once, with tile origins in range
+// and tile kinds of the shape's family only (one kernel per launch).
 #include <cstdio>
 #include <vector>
 
@@ -11,7 +12,8 @@ int main() {
         for (int s = 0; s < btas::NUM_SHAPES; ++s) {
             std::vector<int> cov((size_t)n * n, 0);
             for (const btas::TileRef& t : btas::tile_plan(n, s)) {
-                const int sz = t.kind == btas::BATCH_TILE_128 ? 128 : 64;
+                const int sz = btas::tile_edge(t.kind);
+                if (btas::tile_is_wave(t.kind) != btas::shape_is_wave(s)) ++bad;
                 if (t.m0 < 0 || t.n0 < 0 || t.m0 >= n || t.n0 >= n) {
                     ++bad;
                     continue;
@@ -27,12 +29,12 @@ int main() {
                 }
         }
     // XCD ordering: a permutation of the items plus placeholders, and every
-    // graph with fewer than 64 tiles stays on one XCD (position mod 8).
+    // graph with at most 1/16 of the items stays on one XCD (position mod 8).
     {
         std::vector<btas::BatchItem> items;
         std::vector<int> graph_n;
         for (int g = 0; g < 300; ++g) {
-            const int n = 16 + (g * 37) % 1500;
+            const int n = g == 3 ? 12000 : 16 + (g * 37) % 1500;  // one graph large enough to band
             graph_n.push_back(n);
             for (const btas::TileRef& t : btas::tile_plan(n, g % btas::NUM_SHAPES))
                 items.push_back({g, t.m0, t.n0, t.kind, 1, 0});
@@ -52,13 +54,20 @@ int main() {
                     break;
             if (idx == items.size()) { ++bad; continue; }
             seen[idx] = 1;
-            if (count[it.graph] < 64) {
+            if (count[it.graph] * 16 <= (int)items.size()) {
                 if (xcd[it.graph] < 0) xcd[it.graph] = (int)(p % 8);
                 else if (xcd[it.graph] != (int)(p % 8)) ++bad;
             }
         }
         for (int s : seen)
             if (!s) ++bad;
+        // both placements occur in this mix: some graphs whole, some banded
+        int whole = 0, banded = 0;
+        for (size_t g = 0; g < graph_n.size(); ++g) (count[g] * 16 <= (int)items.size() ? whole : banded)++;
+        if (whole == 0 || banded == 0) {
+            std::printf("xcd order mix not exercised: whole=%d banded=%d\n", whole, banded);
+            ++bad;
+        }
     }
     std::printf("tile plan failures: %d\n", bad);
     return bad != 0;

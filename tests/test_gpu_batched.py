@@ -59,7 +59,7 @@ def test_batched_matches_oracle(dev, dt):
     assert info["launches"] >= 2
 
 
-@pytest.mark.parametrize("tile", ["128", "64", "mixed"])
+@pytest.mark.parametrize("tile", ["128", "64", "mixed", "w64", "wmix"])
 def test_batched_tile_shapes_same_bits(dev, tile, monkeypatch):
     """Every tile shape the autotuner may pick gives the same bits."""
     import torch
