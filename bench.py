@@ -110,8 +110,9 @@ def _events():
 def bench_apsp_small(dev, reps=200):
     """One APSP on an ER digraph, n=256, p=0.05, int32 weights U{1..100}, T=8:
     per-solve latency of the plain path (init + 8 split-K squarings), of the
-    same sequence captured as one hipGraph launch, and of the batched path
-    with a single graph."""
+    same sequence captured as one hipGraph launch, of the whole solve as one
+    cooperative kernel (fixed T, and with the early-exit test on the device),
+    and of the batched path with a single graph."""
     import numpy as np
     import torch
 
@@ -123,6 +124,9 @@ def bench_apsp_small(dev, reps=200):
     out = {"workload": "APSP n=256 ER p=0.05 int32 U{1..100}, T=8 squarings"}
     for name, fn in (("plain", lambda: btas.apsp(W, out=D, return_steps=False)),
                      ("graph", lambda: btas.apsp(W, out=D, return_steps=False, graph=True)),
+                     ("single_launch", lambda: btas.apsp(W, out=D, return_steps=False, single_launch=True)),
+                     ("single_launch_early_exit",
+                      lambda: btas.apsp(W, out=D, return_steps=False, single_launch=True, early_exit=True)),
                      ("batched_one_graph", g.run)):
         for _ in range(10):
             fn()

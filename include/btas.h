@@ -161,6 +161,14 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     first call with a given (dtype, n, W, ldw, D, ldd) and replay it on later
  *     calls (one launch per solve; for latency-bound small n).  The handle
  *     keeps one such graph.  Not combinable with EARLY_EXIT.
+ *   BTAS_APSP_SINGLE_LAUNCH: for n <= 500, run the whole solve (init, every
+ *     squaring, and with EARLY_EXIT the stop test) as one cooperative kernel
+ *     launch with a device-wide barrier between squarings: no per-step
+ *     launches and no host round trip, also with EARLY_EXIT (the host then
+ *     synchronises only if steps_out is not NULL).  Larger n ignore the flag.
+ *     Not combinable with GRAPH.  BTAS_ERR_DEVICE if the device cannot launch
+ *     it cooperatively, or (reported when steps_out is read) if a barrier
+ *     wait timed out.
  * steps_out: host int receiving the number of squarings executed (may be
  * NULL; when non-NULL the call synchronises).  Integer contract: all finite
  * path lengths must stay within +-BTAS_I32_FINITE_MAX.  The handle keeps an
@@ -169,6 +177,7 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
 #define BTAS_APSP_EARLY_EXIT 1u
 #define BTAS_APSP_CHECK_NEG_CYCLE 2u
 #define BTAS_APSP_GRAPH 4u
+#define BTAS_APSP_SINGLE_LAUNCH 8u
 btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n,
                                  const void *W, int ldw, void *D, int ldd,
                                  unsigned flags, int *steps_out);

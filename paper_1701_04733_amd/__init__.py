@@ -28,7 +28,7 @@ I32_FINITE_MAX = (1 << 29) - 1
 
 MIN_PLUS, MAX_PLUS = 0, 1
 INT32, FLOAT32 = 0, 1
-APSP_EARLY_EXIT, APSP_CHECK_NEG_CYCLE, APSP_GRAPH = 1, 2, 4
+APSP_EARLY_EXIT, APSP_CHECK_NEG_CYCLE, APSP_GRAPH, APSP_SINGLE_LAUNCH = 1, 2, 4, 8
 
 STATUS = {0: "BTAS_OK", 1: "BTAS_ERR_INVALID_ARG", 2: "BTAS_ERR_ALIAS", 3: "BTAS_ERR_DOMAIN",
           4: "BTAS_ERR_OOM", 5: "BTAS_ERR_DEVICE", 6: "BTAS_ERR_UNSUPPORTED",
@@ -307,12 +307,15 @@ def axpy(alpha, x, y, semiring="min", handle=None):
 
 
 def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True, graph=False,
-         handle=None):
+         single_launch=False, handle=None):
     """All-pairs shortest paths by repeated min-plus squaring of I (+) W.
 
     Returns (D, steps, status); status is OK or WARN_NEG_CYCLE.  With
-    ``return_steps=False`` and no flags the call stays asynchronous and steps
-    is None.  ``out`` may be W itself (in place).
+    ``return_steps=False`` steps is None and the call stays asynchronous unless
+    a flag needs the host (early exit on the per-squaring path, the
+    negative-cycle check).  ``graph`` replays a captured hipGraph of the
+    fixed-T solve; ``single_launch`` runs the whole solve as one cooperative
+    kernel (n <= 500).  ``out`` may be W itself (in place).
     """
     import torch
     n = W.size(0)
@@ -324,9 +327,9 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     pw, ldw = _mat(W, "W")
     pd, ldd = _mat(out, "D")
     flags = (APSP_EARLY_EXIT if early_exit else 0) | (APSP_CHECK_NEG_CYCLE if check_neg_cycle else 0) \
-        | (APSP_GRAPH if graph else 0)
+        | (APSP_GRAPH if graph else 0) | (APSP_SINGLE_LAUNCH if single_launch else 0)
     steps = ctypes.c_int(0)
-    sp = ctypes.byref(steps) if (return_steps or (flags & ~APSP_GRAPH)) else None
+    sp = ctypes.byref(steps) if return_steps else None
     st = h.check(lib().btas_apsp_squaring(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
                  allow=(OK, WARN_NEG_CYCLE))
     return out, (steps.value if sp is not None else None), st

@@ -126,6 +126,15 @@ btas_status_t btas_create(btas_handle_t* out, int device) {
         delete h;
         return BTAS_ERR_OOM;
     }
+    if (hipMemset(h->dflags, 0, kNumFlags * sizeof(int)) != hipSuccess ||
+        hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        h->num_cus < 1) {
+        (void)hipFree(h->dflags);
+        (void)hipHostFree(h->hflags);
+        (void)hipFree(h->partials);
+        delete h;
+        return BTAS_ERR_DEVICE;
+    }
     *out = h;
     return BTAS_OK;
 }
@@ -347,10 +356,13 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (ldw=%d) < max(1,n=%d)", fn, ldw, n);
     if (ldd < (n > 1 ? n : 1))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (ldd=%d) < max(1,n=%d)", fn, ldd, n);
-    if (flags & ~(BTAS_APSP_EARLY_EXIT | BTAS_APSP_CHECK_NEG_CYCLE | BTAS_APSP_GRAPH))
+    if (flags & ~(BTAS_APSP_EARLY_EXIT | BTAS_APSP_CHECK_NEG_CYCLE | BTAS_APSP_GRAPH |
+                  BTAS_APSP_SINGLE_LAUNCH))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (flags=0x%x) has unknown bits", fn, flags);
     if ((flags & BTAS_APSP_EARLY_EXIT) && (flags & BTAS_APSP_GRAPH))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: EARLY_EXIT and GRAPH cannot be combined", fn);
+    if ((flags & BTAS_APSP_SINGLE_LAUNCH) && (flags & BTAS_APSP_GRAPH))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: SINGLE_LAUNCH and GRAPH cannot be combined", fn);
     if (n > 0 && (!W || !D)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W or D is null", fn);
     const bool in_place = W == D && ldw == ldd;
     if (!in_place && overlap(mat_span(W, n, n, ldw), mat_span(D, n, n, ldd)))
@@ -376,12 +388,32 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
             return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
         h->ws_bytes = need;
     }
-    if (T > 0 && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
+    const bool resident = (flags & BTAS_APSP_SINGLE_LAUNCH) && n <= btas::RESIDENT_MAX_N;
+    if (T > 0 && !resident && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
     const bool early = flags & BTAS_APSP_EARLY_EXIT;
     hipError_t e = hipSuccess;
     int steps = 0;
-    if (!early && (flags & BTAS_APSP_GRAPH)) {
+    if (resident) {
+        // One cooperative launch: init, every squaring and (early exit) the
+        // stop decision on the device; the host reads the step count only if
+        // asked for it.
+        int* rf = h->dflags + FLAG_RESIDENT;
+        unsigned* bar = reinterpret_cast<unsigned*>(h->dflags + FLAG_BARRIER);
+        e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
+        if (e == hipSuccess)
+            e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, bar, rf,
+                                           h->num_cus, 1 << 20, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        steps = T;
+        if (steps_out) {
+            btas_status_t st = sync_flags(h, fn, FLAG_RESIDENT + 2);
+            if (st != BTAS_OK) return st;
+            if (h->hflags[FLAG_RESIDENT] != 0)  // a barrier wait timed out: D is not valid
+                return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
+            steps = h->hflags[FLAG_RESIDENT + 1];
+        }
+    } else if (!early && (flags & BTAS_APSP_GRAPH)) {
         // One hipGraph per argument set: capture once on the auxiliary stream,
         // replay on the handle's stream.
         uint64_t key = 0x9E37ull;

@@ -105,14 +105,14 @@ int forced_shape() {
 // Time one squaring of a size bucket with every candidate shape, on the
 // plan's (not yet initialised) buffers: the kernels' speed does not depend on
 // the values, and the binary32 path is the one taken for in-range int32 data.
-// The bucket's work list is repeated until a launch holds enough work to keep
-// every compute unit busy for several rounds, so the measurement is the
-// shape's throughput inside a full launch (where the plan will run it), not
-// the latency of a launch too small to fill the device.  Repeated items write
-// identical values.
+// The bucket's work list is repeated until the launch holds about as much
+// work as the plan's own squaring launches (`target_terms`, capped at a
+// millisecond of work), so a bucket that shares big launches is measured at
+// the throughput it gets there, and a plan too small to fill the device is
+// measured at its latency.  Repeated items write identical values.
 btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
                           const std::vector<HostGraph>& hg, const std::vector<int>& slots,
-                          BucketTiming* out) {
+                          double target_terms, BucketTiming* out) {
     hipError_t e = launch_clear_ints(p->d_maxabs, std::max((int)hg.size(), 1), h->aux_stream);
     if (e != hipSuccess) return device_fail(h, fn, e);
     double useful = 0;
@@ -128,9 +128,8 @@ btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
             append_items(one, g, hg[g].n, cand, 1);
             for (size_t i = before; i < one.size(); ++i) padded += tile_area(one[i].kind) * hg[g].n;
         }
-        // at least ~2e10 padded terms (a millisecond of work) and 8 items per CU
         int reps = 1;
-        while (reps < 256 && (padded * reps < 2e10 || one.size() * reps < 2048)) reps *= 2;
+        while (reps < 256 && padded * 2 * reps <= target_terms) reps *= 2;
         std::vector<BatchItem> its;
         its.reserve(one.size() * reps);
         for (int r = 0; r < reps; ++r) its.insert(its.end(), one.begin(), one.end());
@@ -287,13 +286,19 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
             // Measure the buckets this handle has not timed yet, then take the
             // family with the smaller predicted time for the whole plan.
             double cost[2] = {0, 0};
+            double step1 = 0;  // useful terms of the first squaring launch
+            for (int g = 0; g < ng; ++g)
+                if (hg[g].T > 0) step1 += (double)hg[g].n * hg[g].n * hg[g].n;
+            const double target = std::min(step1, 2e10);
+            const int scale = (int)std::floor(std::log2(std::max(target, 1.0)));
             for (auto& kv : buckets) {
-                auto it = h->tile_timing.find({(int)dt, kv.first});
+                const auto key = std::make_tuple((int)dt, kv.first, scale);
+                auto it = h->tile_timing.find(key);
                 if (it == h->tile_timing.end()) {
                     BucketTiming bt;
-                    st = time_bucket(h, fn, dt, p.get(), hg, kv.second, &bt);
+                    st = time_bucket(h, fn, dt, p.get(), hg, kv.second, target, &bt);
                     if (st != BTAS_OK) return st;
-                    it = h->tile_timing.emplace(std::make_pair((int)dt, kv.first), bt).first;
+                    it = h->tile_timing.emplace(key, bt).first;
                 }
                 double terms = 0;
                 for (int g : kv.second) terms += (double)hg[g].T * hg[g].n * (double)hg[g].n * hg[g].n;
@@ -301,7 +306,8 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
             }
             wave = cost[1] <= cost[0];
             for (auto& kv : buckets)
-                kind_of_bucket[kv.first] = h->tile_timing[{(int)dt, kv.first}].best[wave ? 1 : 0];
+                kind_of_bucket[kv.first] =
+                    h->tile_timing[std::make_tuple((int)dt, kv.first, scale)].best[wave ? 1 : 0];
             if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1')
                 fprintf(stderr, "[btas] batched plan: predicted %.3f ms with block tiles, %.3f ms with "
                         "wave tiles -> %s\n", cost[0] * 1e3, cost[1] * 1e3, wave ? "wave" : "block");

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <utility>
 
 #include "btas.h"
@@ -34,6 +35,7 @@ struct btas_ctx {
     hipStream_t aux_stream = nullptr;    // owned: graph capture and autotuning
     std::string last_error;
     bool validate = false;
+    int num_cus = 0;                     // compute units of the device
     void* ws = nullptr;                  // APSP ping-pong partner matrix
     size_t ws_bytes = 0;
     void* partials = nullptr;            // dot reduction partials
@@ -43,7 +45,8 @@ struct btas_ctx {
     int* hflags = nullptr;               // pinned host mirror
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan
-    std::map<std::pair<int, int>, btas::BucketTiming> tile_timing;  // (dtype, size bucket) -> autotune
+    // (dtype, size bucket, log2 of the plan's launch size) -> autotune result
+    std::map<std::tuple<int, int, int>, btas::BucketTiming> tile_timing;
     hipGraph_t apsp_graph = nullptr;     // last captured single-solve graph (BTAS_APSP_GRAPH)
     hipGraphExec_t apsp_exec = nullptr;
     uint64_t apsp_key = 0;
@@ -55,8 +58,12 @@ namespace btas {
 constexpr int FLAG_CHANGED = 0;    // early exit: some output changed this step
 constexpr int FLAG_CHECK = 1;      // domain scan / negative-cycle check
 constexpr int FLAG_GEMM_WIDE = 2;  // int32 gemm operands exceed the binary32-exact range
-constexpr int FLAG_STEP_WIDE = 8;  // APSP: slot 8 + t describes D_t (t = 0..T <= 32)
-constexpr int kNumFlags = 64;
+constexpr int FLAG_STEP_WIDE = 8;  // APSP: slot 8 + t describes D_t (t = 0..T <= 31)
+constexpr int FLAG_RESIDENT = 44;  // single-launch solve: +0 error, +1 steps, +1+t squaring t changed D
+constexpr int FLAG_BARRIER = 64;   // its device-wide barrier: 2 + (up to 64 groups) counters
+constexpr int FLAG_RESIDENT_END = FLAG_BARRIER + 2 + 64;
+constexpr int kNumFlags = 192;
+static_assert(FLAG_RESIDENT + 2 + 9 <= FLAG_BARRIER, "slots for T(500) = 9 squarings");
 
 struct DeviceGuard {
     int prev = -1;

@@ -82,6 +82,19 @@ hipError_t launch_neg_diag_check(int dt, int n, const void* D, long ldd, int* fl
 // Copy an n-column, m-row matrix between leading dimensions (4-byte elements).
 hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst, long ldd,
                               hipStream_t s);
+// Whole APSP solve in one cooperative launch (n <= RESIDENT_MAX_N): D_0 =
+// I (+) W, then T squarings (or fewer with early exit) separated by a
+// device-wide barrier, ping-ponging between D and ws (n x n, leading
+// dimension n); the result ends in D.  bar: 66 device words, zero at launch.
+// flags (device): [0] set on a barrier timeout, [1] <- the number of
+// squarings run, [1 + t] set if squaring t changed D; zero at launch.
+// num_cus: compute units of the device; spin_limit: polls per barrier wait
+// before giving up.
+constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
+size_t resident_lds_bytes(int n);
+hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
+                                void* ws, int T, bool early, unsigned* bar, int* flags,
+                                int num_cus, int spin_limit, hipStream_t s);
 // Domain scan (BTAS_VALIDATE=1): flag <- 1 if some element of the m x n matrix
 // is not a legal (.) operand of the semiring.
 hipError_t launch_domain_scan(int sr, int dt, int m, int n, const void* X, long ld, int* flag,

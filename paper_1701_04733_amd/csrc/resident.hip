@@ -1,0 +1,274 @@
+// Whole-solve APSP in one cooperative launch, for small graphs.
+//
+// Repeated squaring (Sec. III) needs every entry of D_{t-1} before any entry
+// of D_t can be finished, so the ordinary path issues one product launch (and
+// for small n a split-K reduction) per squaring; for n of a few hundred the
+// launches, not the O(n^3) work, set the latency.  Here one launch of at most
+// one resident workgroup set does the whole solve:
+//
+//   D_0 = I (+) W;  for t = 1..T:  D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1}
+//
+// with a device-wide barrier between squarings.  Each workgroup owns 16x16
+// output tiles (one output per thread, full k): it stages the tile's 16 rows
+// of D_{t-1} and its 16 columns (transposed) in LDS, folds four k per pair of
+// three-input min/max, and writes D_t to the other buffer of the ping-pong
+// pair.  Early exit reads a per-step "changed" flag after the barrier, so
+// every workgroup takes the same decision.
+//
+// Coherence across the XCDs (each has its own L2) is obtained without cache
+// maintenance: every access to the matrices that another workgroup may touch
+// in the same launch is a device-scope (relaxed atomic) load or store, which
+// the hardware performs at the device's coherence point, and every wave waits
+// for its stores to complete before its workgroup arrives at the barrier.
+// The barrier counts arrivals per group of 16 workgroups and then per group,
+// so no single word takes more than 16 atomic increments per barrier; the
+// counters only grow within a launch (a group's last arrival is the one that
+// makes its count a multiple of the group size) and the caller zeroes them
+// before each launch.  The launch is cooperative, so every workgroup is
+// resident and the barrier cannot wait on one that has not started; each wait
+// is still bounded and, when the bound is hit, the kernel records an error
+// and runs to its end so that no wave is left spinning.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "gemm_tile.h"
+#include "kernels.h"
+#include "semiring.h"
+
+namespace btas {
+
+namespace {
+
+constexpr int RT = 16;        // output tile edge
+constexpr int RNT = RT * RT;  // threads per workgroup, one output each
+constexpr int PB = 8;         // panel loads in flight per thread
+
+template <typename T>
+struct ResidentArgs {
+    int n;
+    int nsq;          // squarings to run (the fixed count T)
+    int early;        // stop after the first squaring that changes nothing
+    int cur0;         // buffer index that receives D_0
+    int ls;           // LDS row stride in elements (>= n rounded to 4, plus padding)
+    int spin_limit;   // bound on each barrier wait, in polls
+    const T* W;
+    long ldw;
+    T* buf0;          // the caller's D
+    long ld0;
+    T* buf1;          // the handle's workspace, leading dimension n
+    long ld1;
+    unsigned* bar;    // [0] barriers completed, [1] groups arrived, [2 + g] arrivals in group g
+    int* flags;       // [0] error, [1] steps executed, [1 + t] squaring t changed D
+};
+
+constexpr unsigned BAR_GROUP = 16;  // workgroups per first-level barrier counter
+
+// Device-scope loads and stores (coherent across XCDs without cache flushes).
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-wide barrier number `b` (1, 2, ... within a launch); returns false
+// if the wait bound was hit (then flags[0] is set).  Every thread of every
+// workgroup must call it with the same b.
+__device__ bool grid_barrier(unsigned* bar, unsigned b, int* err, int spin_limit) {
+    __shared__ int ok_s;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are performed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = blockIdx.x / BAR_GROUP;
+        const unsigned rest = gridDim.x - g * BAR_GROUP;
+        const unsigned gsize = rest < BAR_GROUP ? rest : BAR_GROUP;
+        const unsigned ngroups = (gridDim.x + BAR_GROUP - 1) / BAR_GROUP;
+        const unsigned a1 =
+            __hip_atomic_fetch_add(bar + 2 + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (a1 % gsize == 0) {
+            const unsigned a2 =
+                __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (a2 % ngroups == 0) st_dev(bar, a2 / ngroups);
+        }
+        int polls = 0;
+        while (ld_dev(bar) < b) {
+            if (++polls > spin_limit) {
+                st_dev(err, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* As = reinterpret_cast<T*>(smem_raw);  // [RT][ls]: rows m0.. of D_{t-1}
+    T* Bt = As + RT * a.ls;                  // [RT][ls]: columns n0.. of D_{t-1}, transposed
+    __shared__ int flag_s;
+    const int n = a.n, tid = threadIdx.x;
+    const long total = (long)n * n;
+    const long gthreads = (long)gridDim.x * RNT;
+    int cur = a.cur0;
+
+    // D_0 = I (+) W (the diagonal gets min(W_ii, 0)); in place when W is D.
+    {
+        T* D0 = cur ? a.buf1 : a.buf0;
+        const long ld0 = cur ? a.ld1 : a.ld0;
+        for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
+            const long i = e / n, j = e - i * n;
+            T w = a.W[i * a.ldw + j];
+            if (i == j && w > (T)0) w = (T)0;
+            st_dev(D0 + i * ld0 + j, w);
+        }
+    }
+    unsigned bno = 1;
+    grid_barrier(a.bar, bno++, a.flags, a.spin_limit);
+
+    const int nt = (n + RT - 1) / RT;
+    const int kpad = (n + 7) & ~7;
+    const int r = tid / RT, c = tid % RT;
+    int steps = 0;
+    for (int t = 1; t <= a.nsq; ++t) {
+        const T* src = cur ? a.buf1 : a.buf0;
+        const long lds = cur ? a.ld1 : a.ld0;
+        T* dst = cur ? a.buf0 : a.buf1;
+        const long ldd = cur ? a.ld0 : a.ld1;
+        bool changed = false;
+        for (int tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
+            const int m0 = (tile / nt) * RT, n0 = (tile % nt) * RT;
+            // Rows m0..m0+15 of src (k along the row) and columns n0..n0+15
+            // (stored transposed, Bt[col][k]), in batches of PB loads per
+            // thread so that the device-scope loads overlap their latency.
+            for (int e0 = 0; e0 < RT * kpad; e0 += RNT * PB) {
+                T va[PB], vb[PB];
+#pragma unroll
+                for (int u = 0; u < PB; ++u) {
+                    const int e = e0 + u * RNT + tid;
+                    const int rr = e / kpad, ka = e - rr * kpad;
+                    const int kb = e / RT, cc = e - kb * RT;
+                    va[u] = (e < RT * kpad && m0 + rr < n && ka < n)
+                                ? ld_dev(src + (long)(m0 + rr) * lds + ka) : R::absent();
+                    vb[u] = (e < RT * kpad && n0 + cc < n && kb < n)
+                                ? ld_dev(src + (long)kb * lds + n0 + cc) : R::absent();
+                }
+#pragma unroll
+                for (int u = 0; u < PB; ++u) {
+                    const int e = e0 + u * RNT + tid;
+                    if (e < RT * kpad) {
+                        const int rr = e / kpad, ka = e - rr * kpad;
+                        const int kb = e / RT, cc = e - kb * RT;
+                        As[rr * a.ls + ka] = va[u];
+                        Bt[cc * a.ls + kb] = vb[u];
+                    }
+                }
+            }
+            __syncthreads();
+            // Two accumulators and an unrolled loop keep several LDS reads in
+            // flight and break the serial min chain; the order of the (+)
+            // does not matter (associative, commutative, one rounding per term).
+            T acc0 = R::absent(), acc1 = R::absent();
+            const T* ar = As + r * a.ls;
+            const T* bc = Bt + c * a.ls;
+#pragma unroll 4
+            for (int k = 0; k < kpad; k += 8) {
+                const v4<T> x0 = *reinterpret_cast<const v4<T>*>(ar + k);
+                const v4<T> y0 = *reinterpret_cast<const v4<T>*>(bc + k);
+                const v4<T> x1 = *reinterpret_cast<const v4<T>*>(ar + k + 4);
+                const v4<T> y1 = *reinterpret_cast<const v4<T>*>(bc + k + 4);
+                acc0 = R::add3(acc0, R::mul(x0[0], y0[0]), R::mul(x0[1], y0[1]));
+                acc1 = R::add3(acc1, R::mul(x1[0], y1[0]), R::mul(x1[1], y1[1]));
+                acc0 = R::add3(acc0, R::mul(x0[2], y0[2]), R::mul(x0[3], y0[3]));
+                acc1 = R::add3(acc1, R::mul(x1[2], y1[2]), R::mul(x1[3], y1[3]));
+            }
+            const T acc = R::add(acc0, acc1);
+            const int row = m0 + r, col = n0 + c;
+            if (row < n && col < n) {
+                const T old = ld_dev(src + (long)row * lds + col);
+                const T nv = R::add(old, R::finish(acc));
+                changed |= bits_of(nv) != bits_of(old);
+                st_dev(dst + (long)row * ldd + col, nv);
+            }
+            __syncthreads();  // LDS is reloaded for the next tile
+        }
+        if (__syncthreads_or(changed) && tid == 0) st_dev(a.flags + 1 + t, 1);
+        grid_barrier(a.bar, bno++, a.flags, a.spin_limit);
+        cur ^= 1;
+        steps = t;
+        if (a.early) {
+            if (tid == 0) flag_s = ld_dev(a.flags + 1 + t);
+            __syncthreads();
+            if (flag_s == 0) break;
+        }
+    }
+
+    // After an early exit the result may sit in the workspace: copy it to D.
+    if (cur != 0) {
+        for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
+            const long i = e / n, j = e - i * n;
+            a.buf0[i * a.ld0 + j] = ld_dev(a.buf1 + i * a.ld1 + j);
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0) a.flags[1] = steps;
+}
+
+template <typename T>
+hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void* ws, int T_,
+                        bool early, unsigned* bar, int* flags, int num_cus, int spin_limit,
+                        hipStream_t s) {
+    ResidentArgs<T> a;
+    a.n = n;
+    a.nsq = T_;
+    a.early = early ? 1 : 0;
+    // The fixed-T solve ends in buf[0] when D_0 goes to buf[T & 1].
+    a.cur0 = T_ & 1;
+    a.ls = ((n + 7) & ~7) + 4;  // k padded to 8; rows start in distinct LDS banks
+    a.spin_limit = spin_limit;
+    a.W = (const T*)W;
+    a.ldw = ldw;
+    a.buf0 = (T*)D;
+    a.ld0 = ldd;
+    a.buf1 = (T*)ws;
+    a.ld1 = n;
+    a.bar = bar;
+    a.flags = flags;
+    const size_t lds = resident_lds_bytes(n);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(apsp_resident_kernel<T>), RNT, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int nt = (n + RT - 1) / RT;
+    long grid = (long)per_cu * num_cus;
+    if (grid > (long)nt * nt) grid = (long)nt * nt;
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apsp_resident_kernel<T>),
+                                      dim3((unsigned)grid), dim3(RNT), args, (unsigned)lds, s);
+}
+
+}  // namespace
+
+size_t resident_lds_bytes(int n) { return (size_t)2 * RT * (((n + 7) & ~7) + 4) * 4; }
+
+hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
+                                void* ws, int T, bool early, unsigned* bar, int* flags,
+                                int num_cus, int spin_limit, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (dt == BTAS_FLOAT32)
+        return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, bar, flags, num_cus,
+                                   spin_limit, s);
+    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, bar, flags, num_cus, spin_limit,
+                                 s);
+}
+
+}  // namespace btas

@@ -1,0 +1,122 @@
+"""APSP as one cooperative launch (BTAS_APSP_SINGLE_LAUNCH): bit-identical to
+the oracle and to the per-squaring path, with early exit decided on the
+device, in place and with padded leading dimensions, and stable over many
+launches in a row (the device-wide barrier's words return to zero)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DT = ["i32", "f32"]
+
+
+def _bits(x):
+    x = np.ascontiguousarray(x).copy()
+    if x.dtype == np.float32:
+        x[x == 0] = 0.0
+    return x.view(np.uint32)
+
+
+def _graph(dt, n, seed, deg=3.0):
+    Wi = wl.er_digraph_i32(n, min(1.0, deg / max(n, 1)), 1, 1000, seed=seed)
+    if dt == "i32":
+        return Wi
+    g = wl.rng(seed + 1)
+    W = np.where(Wi == wl.I32_INF, np.inf, g.exponential(1.0, (n, n))).astype(np.float32)
+    np.fill_diagonal(W, 0)
+    return W
+
+
+def _dev(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 100, 255, 256, 300, 500])
+def test_single_launch_matches_oracle(dev, dt, n):
+    import paper_1701_04733_amd as btas
+    W = _graph(dt, n, seed=1000 + n)
+    want, wsteps, _ = oracle.apsp(W)
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True)
+    assert steps == wsteps
+    assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"{dt} n={n}"
+    want_e, wsteps_e, _ = oracle.apsp(W, early_exit=True)
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True, early_exit=True)
+    assert steps == wsteps_e
+    assert np.array_equal(_bits(D.cpu().numpy()), _bits(want_e)), f"{dt} n={n} early exit"
+
+
+def test_single_launch_small_config_golden(dev):
+    """n=256 ER digraph (p=0.05, weights U{1..100}, seed 1), T=8 squarings."""
+    import paper_1701_04733_amd as btas
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "apsp_er256.json")))
+    W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True)
+    assert steps == 8
+    assert hashlib.sha256(D.cpu().numpy().tobytes()).hexdigest() == gold["apsp_er256_i32_seed1"]["D_sha256"]
+    D2, steps2, _ = btas.apsp(_dev(W, dev), single_launch=True, early_exit=True)
+    assert steps2 == gold["apsp_er256_i32_seed1_early_exit"]["steps"]
+    assert hashlib.sha256(D2.cpu().numpy().tobytes()).hexdigest() == gold["apsp_er256_i32_seed1"]["D_sha256"]
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_single_launch_in_place_padded_and_plain_path(dev, dt):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    for n in (133, 100):                                     # T = 8 (even), 7 (odd)
+        W = _graph(dt, n, seed=77 + n, deg=5.0)
+        want, _, _ = oracle.apsp(W)
+        t = _dev(W, dev)
+        plain, _, _ = btas.apsp(t)
+        btas.apsp(t, out=t, single_launch=True)              # in place
+        assert np.array_equal(_bits(t.cpu().numpy()), _bits(want)), f"in place n={n}"
+        assert torch.equal(t, plain)
+        big = torch.full((n, n + 5), 7, dtype=t.dtype, device=dev)
+        big[:, :n] = _dev(W, dev)
+        out = torch.zeros((n + 1, n + 3), dtype=t.dtype, device=dev)
+        btas.apsp(big[:, :n], out=out[:n, :n], single_launch=True, early_exit=True)
+        assert np.array_equal(_bits(out.cpu().numpy()[:n, :n]), _bits(want)), f"padded n={n}"
+        assert (out[n, :] == 0).all() and (out[:, n:] == 0).all()   # nothing outside D written
+        assert (big[:, n:] == 7).all()
+
+
+def test_single_launch_many_in_a_row_and_async(dev):
+    """Launches back to back without host synchronisation: every result is
+    right, so the barrier state carries over correctly between launches."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = [_graph("f32", 64 + 37 * i, seed=500 + i, deg=4.0) for i in range(12)]
+    ts = [_dev(W, dev) for W in Ws]
+    outs = [torch.empty_like(t) for t in ts]
+    for _ in range(3):
+        for t, o in zip(ts, outs):
+            btas.apsp(t, out=o, single_launch=True, early_exit=True, return_steps=False)
+    torch.cuda.synchronize()
+    for W, o in zip(Ws, outs):
+        want, _, _ = oracle.apsp(W)
+        assert np.array_equal(_bits(o.cpu().numpy()), _bits(want)), f"n={W.shape[0]}"
+
+
+def test_single_launch_neg_cycle_large_n_and_errors(dev):
+    import paper_1701_04733_amd as btas
+    INF = wl.I32_INF
+    W = np.array([[0, 1, INF], [-3, 0, INF], [INF, 2, 0]], np.int32)
+    _, _, st = btas.apsp(_dev(W, dev), single_launch=True, check_neg_cycle=True)
+    assert st == btas.WARN_NEG_CYCLE
+    # n above the single-launch limit takes the per-squaring path, same bits
+    W = _graph("i32", 600, seed=9)
+    want, wsteps, _ = oracle.apsp(W)
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True)
+    assert steps == wsteps and np.array_equal(D.cpu().numpy(), want)
+    with pytest.raises(btas.BtasError, match="INVALID_ARG"):
+        btas.apsp(_dev(W[:10, :10], dev), single_launch=True, graph=True)
