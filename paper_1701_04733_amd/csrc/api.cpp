@@ -388,7 +388,14 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
             return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
         h->ws_bytes = need;
     }
-    const bool resident = (flags & BTAS_APSP_SINGLE_LAUNCH) && n <= btas::RESIDENT_MAX_N;
+    // Graphs of 24..192 vertices take the single-launch solve also without
+    // the flag (it is faster there: one launch instead of one or two per
+    // squaring) unless a captured graph was asked for or BTAS_SINGLE_LAUNCH=0.
+    const char* sl_env = getenv("BTAS_SINGLE_LAUNCH");
+    const bool auto_single = !(sl_env && sl_env[0] == '0') && n >= btas::AUTO_SINGLE_LAUNCH_MIN_N &&
+                             n <= btas::AUTO_SINGLE_LAUNCH_N && !(flags & BTAS_APSP_GRAPH);
+    const bool resident =
+        n <= btas::RESIDENT_MAX_N && ((flags & BTAS_APSP_SINGLE_LAUNCH) || auto_single);
     if (T > 0 && !resident && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
     const bool early = flags & BTAS_APSP_EARLY_EXIT;

@@ -8,6 +8,7 @@
 #include "gemm_tile.h"
 #include "kernels.h"
 #include "semiring.h"
+#include "flat_index.h"
 
 namespace btas {
 
@@ -20,7 +21,8 @@ __global__ __launch_bounds__(256) void apsp_init_kernel(int n, const T* W, long 
     bool w_wide = false;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const long i = e / n, j = e - i * n;
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
         T w = W[i * ldw + j];
         if (i == j && w > (T)0) w = (T)0;
         D[i * ldd + j] = w;
@@ -57,7 +59,8 @@ __global__ __launch_bounds__(256) void range_scan_kernel(int m, int n, const int
     bool wide = false;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const long i = e / n, j = e - i * n;
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
         const int32_t x = X[i * ld + j];
         wide |= x != Ring<SR, int32_t>::absent() && (x > FP32_EXACT_MAX || x < -FP32_EXACT_MAX);
     }
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(256) void copy_matrix_kernel(int m, int n, const ui
     const long total = (long)m * n;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const long i = e / n, j = e - i * n;
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
         dst[i * ldd + j] = src[i * lds + j];
     }
 }
@@ -153,7 +157,8 @@ __global__ __launch_bounds__(256) void domain_scan_kernel(int m, int n, const T*
     bool bad = false;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const long i = e / n, j = e - i * n;
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
         bad |= !operand_ok<T, SR>(X[i * ld + j]);
     }
     if (bad) *flag = 1;

@@ -177,20 +177,32 @@ struct BatchCopy {
 
 // Squarings for items[0, nitems): one workgroup per item, 256 threads for the
 // block kinds, 64 for the wave kinds (`wave` selects the family; every item of
-// the launch must belong to it, placeholders aside).  maxabs (int32 only, may be null): per-graph max |finite weight| recorded by
-// launch_grouped_init.  changed (may be null): per-graph flag set to 1 when a
-// squaring changed some entry.
+// the launch must belong to it, placeholders aside).  maxabs (int32 only, may
+// be null): per-graph max |finite element of D_0|; an int32 graph with
+// 2^T * maxabs <= 2^23-1 is computed on the binary32 pipeline, reading int32
+// storage with conversions, or (float_storage) buffers that
+// launch_grouped_init filled with binary32 values.  changed (may be null):
+// per-graph flag set to 1 when a squaring changed some entry.
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
                                int nitems, const int* maxabs, int* changed, hipStream_t s,
-                               bool wave = false);
-// buf[parity] <- I (+) W for each job; int32: maxabs[graph] <- max |finite W|
-// (maxabs must be zeroed first).
-// total_blocks = sum of the jobs' nblocks.
+                               bool wave = false, bool float_storage = false);
+// int32: maxabs[graph] <- max |finite element of I (+) W| (maxabs zeroed
+// first); the first pass of the float-storage mode.
+hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
+                                 int total_blocks, int* maxabs, hipStream_t s);
+// buf[parity] <- I (+) W for each job.  int32 without float_storage:
+// maxabs[graph] <- max |finite element| (maxabs zeroed first).  int32 with
+// float_storage: maxabs is complete (launch_grouped_maxabs) and graphs in the
+// binary32-exact range are stored as binary32.  total_blocks = sum of the
+// jobs' nblocks.
 hipError_t launch_grouped_init(int dt, const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                               int total_blocks, int* maxabs, hipStream_t s);
-// D_ext <- buf[(parity + T) & 1] for each job.
+                               int total_blocks, int* maxabs, hipStream_t s,
+                               bool float_storage = false);
+// D_ext <- buf[(parity + T) & 1] for each job; float_maxabs (int32
+// float-storage mode, else null) converts the graphs stored as binary32 back.
 hipError_t launch_grouped_copy_out(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                                   int total_blocks, hipStream_t s);
+                                   int total_blocks, hipStream_t s,
+                                   const int* float_maxabs = nullptr);
 // Workgroups an n x n copy job should get (about 4096 elements each, <= 256).
 inline int copy_blocks_for(int n) {
     long b = ((long)n * n + 4095) / 4096;

@@ -15,6 +15,7 @@
 
 #include "batched.h"
 #include "gemm_tile.h"
+#include "flat_index.h"
 
 namespace btas {
 
@@ -33,11 +34,18 @@ __device__ __forceinline__ bool graph_is_narrow(const BatchGraph& g, const int* 
     }
 }
 
+// Float view of an int32 graph's buffers when they hold binary32 values.
+struct FloatView {
+    const float* src;
+    float* dst;
+};
+
 template <typename T, int SR>
 __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __restrict__ graphs,
                                                             const BatchItem* __restrict__ items,
                                                             const int* __restrict__ maxabs,
-                                                            int* __restrict__ changed) {
+                                                            int* __restrict__ changed,
+                                                            int float_storage) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchItem it = items[blockIdx.x];
     if (it.kind == BATCH_TILE_NONE) return;
@@ -48,25 +56,23 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
     int* chg = changed != nullptr ? changed + it.graph : nullptr;
     TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
     const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
-    if (it.kind == BATCH_TILE_128) {
-        const int m0 = it.m0, n0 = it.n0;
-        if constexpr (std::is_same_v<T, int32_t>) {
-            if (narrow) {
-                GemmTile<CfgL, T, float, SR, true>::run(a, m0, n0, smem_raw);
-                return;
-            }
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (narrow && float_storage) {
+            // the buffers hold binary32 values: the plain fp32 kernel, no conversions
+            TileArgs<float> f{g.n, g.n, g.n, (const float*)src, g.ld, (const float*)src, g.ld,
+                              (const float*)src, g.ld, (float*)dst, g.ld, chg, nullptr};
+            if (it.kind == BATCH_TILE_128) GemmTile<CfgL, float, float, SR, true>::run(f, it.m0, it.n0, smem_raw);
+            else GemmTile<CfgM, float, float, SR, true>::run(f, it.m0, it.n0, smem_raw);
+            return;
         }
-        GemmTile<CfgL, T, T, SR, true>::run(a, m0, n0, smem_raw);
-    } else {
-        const int m0 = it.m0, n0 = it.n0;
-        if constexpr (std::is_same_v<T, int32_t>) {
-            if (narrow) {
-                GemmTile<CfgM, T, float, SR, true>::run(a, m0, n0, smem_raw);
-                return;
-            }
+        if (narrow) {
+            if (it.kind == BATCH_TILE_128) GemmTile<CfgL, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
+            else GemmTile<CfgM, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
+            return;
         }
-        GemmTile<CfgM, T, T, SR, true>::run(a, m0, n0, smem_raw);
     }
+    if (it.kind == BATCH_TILE_128) GemmTile<CfgL, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
+    else GemmTile<CfgM, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
 }
 
 static_assert(CfgL::NT == 256 && CfgM::NT == 256, "grouped kernel mixes both tile shapes");
@@ -76,7 +82,8 @@ template <typename T, int SR>
 __global__ __launch_bounds__(64) void grouped_wave_step_kernel(const BatchGraph* __restrict__ graphs,
                                                                 const BatchItem* __restrict__ items,
                                                                 const int* __restrict__ maxabs,
-                                                                int* __restrict__ changed) {
+                                                                int* __restrict__ changed,
+                                                                int float_storage) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchItem it = items[blockIdx.x];
     if (it.kind == BATCH_TILE_NONE) return;
@@ -87,48 +94,48 @@ __global__ __launch_bounds__(64) void grouped_wave_step_kernel(const BatchGraph*
     int* chg = changed != nullptr ? changed + it.graph : nullptr;
     TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
     const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
-    if (it.kind == BATCH_TILE_W64) {
-        if constexpr (std::is_same_v<T, int32_t>) {
-            if (narrow) {
-                GemmTile<CfgW, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
-                return;
-            }
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (narrow && float_storage) {
+            TileArgs<float> f{g.n, g.n, g.n, (const float*)src, g.ld, (const float*)src, g.ld,
+                              (const float*)src, g.ld, (float*)dst, g.ld, chg, nullptr};
+            if (it.kind == BATCH_TILE_W64) GemmTile<CfgW, float, float, SR, true>::run(f, it.m0, it.n0, smem_raw);
+            else GemmTile<CfgS, float, float, SR, true>::run(f, it.m0, it.n0, smem_raw);
+            return;
         }
-        GemmTile<CfgW, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
-    } else {
-        if constexpr (std::is_same_v<T, int32_t>) {
-            if (narrow) {
-                GemmTile<CfgS, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
-                return;
-            }
+        if (narrow) {
+            if (it.kind == BATCH_TILE_W64) GemmTile<CfgW, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
+            else GemmTile<CfgS, T, float, SR, true>::run(a, it.m0, it.n0, smem_raw);
+            return;
         }
-        GemmTile<CfgS, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
     }
+    if (it.kind == BATCH_TILE_W64) GemmTile<CfgW, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
+    else GemmTile<CfgS, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
 }
 
 static_assert(CfgW::NT == 64 && CfgS::NT == 64, "wave kernel mixes both wave tile shapes");
 
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
                                int nitems, const int* maxabs, int* changed, hipStream_t s,
-                               bool wave) {
+                               bool wave, bool float_storage) {
     if (nitems <= 0) return hipSuccess;
+    const int fs = float_storage ? 1 : 0;
     if (wave) {
         const size_t lds = CfgW::lds_bytes > CfgS::lds_bytes ? CfgW::lds_bytes : CfgS::lds_bytes;
         if (dt == BTAS_FLOAT32)
             hipLaunchKernelGGL((grouped_wave_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems),
-                               dim3(64), lds, s, graphs, items, nullptr, changed);
+                               dim3(64), lds, s, graphs, items, nullptr, changed, 0);
         else
             hipLaunchKernelGGL((grouped_wave_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems),
-                               dim3(64), lds, s, graphs, items, maxabs, changed);
+                               dim3(64), lds, s, graphs, items, maxabs, changed, fs);
         return hipGetLastError();
     }
     const size_t lds = CfgL::lds_bytes > CfgM::lds_bytes ? CfgL::lds_bytes : CfgM::lds_bytes;
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL((grouped_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems), dim3(256), lds,
-                           s, graphs, items, nullptr, changed);
+                           s, graphs, items, nullptr, changed, 0);
     else
         hipLaunchKernelGGL((grouped_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems), dim3(256),
-                           lds, s, graphs, items, maxabs, changed);
+                           lds, s, graphs, items, maxabs, changed, fs);
     return hipGetLastError();
 }
 
@@ -144,10 +151,53 @@ __device__ __forceinline__ int find_job(const BatchCopy* jobs, int njobs, int b)
 }
 
 // ---- init: buf[parity] <- I (+) W, and max |finite w| per graph (int32) ----
+// |x| of a finite int32 element (the absent value excluded), saturating.
+__device__ __forceinline__ int abs_finite(int32_t w) {
+    if (w == BTAS_I32_INF) return 0;
+    return w < 0 ? (w == INT32_MIN ? INT32_MAX : -w) : w;
+}
+
+__device__ __forceinline__ void block_max_to(int* dst, int mx) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(dst, mx);
+}
+
+// int32, first pass of the float-storage mode: maxabs[graph] <- max |finite
+// element of I (+) W|.
+__global__ __launch_bounds__(256) void grouped_maxabs_kernel(const BatchGraph* __restrict__ graphs,
+                                                              const BatchCopy* __restrict__ jobs,
+                                                              int njobs, int* __restrict__ maxabs) {
+    const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
+    const int n = graphs[jb.graph].n;
+    const int32_t* W = (const int32_t*)jb.ext;
+    const long total = (long)n * n;
+    const long stride = (long)jb.nblocks * blockDim.x;
+    int mx = 0;
+    for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
+         e += stride) {
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
+        int32_t w = W[i * jb.ld_ext + j];
+        if (i == j && w > 0) w = 0;
+        const int aw = abs_finite(w);
+        mx = aw > mx ? aw : mx;
+    }
+    block_max_to(maxabs + jb.graph, mx);
+}
+
+// float_storage (int32 only; maxabs already complete): graphs whose squarings
+// stay in the binary32-exact range are written as binary32 values (absent ->
+// +inf), so the squaring kernels read and write them without conversions.
+// Otherwise (int32) maxabs[graph] is accumulated here.
 template <typename T>
 __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __restrict__ graphs,
                                                             const BatchCopy* __restrict__ jobs,
-                                                            int njobs, int* __restrict__ maxabs) {
+                                                            int njobs, int* __restrict__ maxabs,
+                                                            int float_storage) {
     const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
     const BatchGraph g = graphs[jb.graph];
     const int n = g.n;
@@ -155,36 +205,37 @@ __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __r
     T* D = (T*)g.buf[g.parity & 1];
     const long total = (long)n * n;
     const long stride = (long)jb.nblocks * blockDim.x;
+    bool as_float = false;
+    if constexpr (std::is_same_v<T, int32_t>) as_float = float_storage && graph_is_narrow<T>(g, maxabs, jb.graph);
     int mx = 0;
     for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
          e += stride) {
-        const long i = e / n, j = e - i * n;
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
         T w = W[i * jb.ld_ext + j];
         if (i == j && w > (T)0) w = (T)0;
-        D[i * g.ld + j] = w;
         if constexpr (std::is_same_v<T, int32_t>) {
-            if (w != BTAS_I32_INF) {
-                const int aw = w < 0 ? (w == INT32_MIN ? INT32_MAX : -w) : w;
-                mx = aw > mx ? aw : mx;
+            if (as_float) {
+                reinterpret_cast<float*>(D)[i * g.ld + j] = Conv<int32_t, float, BTAS_MIN_PLUS>::in(w);
+                continue;
             }
+            const int aw = abs_finite(w);
+            mx = aw > mx ? aw : mx;
         }
+        D[i * g.ld + j] = w;
     }
     if constexpr (std::is_same_v<T, int32_t>) {
-        if (maxabs != nullptr) {
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const int o = __shfl_xor(mx, off, 64);
-                mx = o > mx ? o : mx;
-            }
-            if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(maxabs + jb.graph, mx);
-        }
+        if (maxabs != nullptr && !float_storage) block_max_to(maxabs + jb.graph, mx);
     }
 }
 
 // ---- final copy: D_ext <- buf[(parity + T) & 1] ----
+// float_maxabs (int32 float-storage mode, else null): graphs stored as
+// binary32 are converted back to int32 (exact integers, +inf -> INF).
 __global__ __launch_bounds__(256) void grouped_copy_out_kernel(const BatchGraph* __restrict__ graphs,
                                                                 const BatchCopy* __restrict__ jobs,
-                                                                int njobs) {
+                                                                int njobs,
+                                                                const int* __restrict__ float_maxabs) {
     const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
     const BatchGraph g = graphs[jb.graph];
     const int n = g.n;
@@ -192,10 +243,15 @@ __global__ __launch_bounds__(256) void grouped_copy_out_kernel(const BatchGraph*
     uint32_t* D = (uint32_t*)const_cast<void*>(jb.ext);
     const long total = (long)n * n;
     const long stride = (long)jb.nblocks * blockDim.x;
+    const bool from_float =
+        float_maxabs != nullptr && graph_is_narrow<int32_t>(g, float_maxabs, jb.graph);
     for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
          e += stride) {
-        const long i = e / n, j = e - i * n;
-        D[i * jb.ld_ext + j] = S[i * g.ld + j];
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
+        const uint32_t x = S[i * g.ld + j];
+        D[i * jb.ld_ext + j] =
+            from_float ? (uint32_t)Conv<int32_t, float, BTAS_MIN_PLUS>::out(__uint_as_float(x)) : x;
     }
 }
 
@@ -205,7 +261,8 @@ __global__ __launch_bounds__(256) void fill_identity_kernel(T* D, int n, int ld)
     const long total = (long)n * n;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const long i = e / n, j = e - i * n;
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
         D[i * ld + j] = i == j ? (T)0 : Ring<BTAS_MIN_PLUS, T>::absent();
     }
 }
@@ -269,23 +326,31 @@ hipError_t launch_clear_ints(int* p, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
+                                 int total_blocks, int* maxabs, hipStream_t s) {
+    if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grouped_maxabs_kernel, dim3(total_blocks), dim3(256), 0, s, graphs, jobs,
+                       njobs, maxabs);
+    return hipGetLastError();
+}
+
 hipError_t launch_grouped_init(int dt, const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                               int total_blocks, int* maxabs, hipStream_t s) {
+                               int total_blocks, int* maxabs, hipStream_t s, bool float_storage) {
     if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL(grouped_init_kernel<float>, dim3(total_blocks), dim3(256), 0, s, graphs,
-                           jobs, njobs, nullptr);
+                           jobs, njobs, nullptr, 0);
     else
         hipLaunchKernelGGL(grouped_init_kernel<int32_t>, dim3(total_blocks), dim3(256), 0, s,
-                           graphs, jobs, njobs, maxabs);
+                           graphs, jobs, njobs, maxabs, float_storage ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_grouped_copy_out(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                                   int total_blocks, hipStream_t s) {
+                                   int total_blocks, hipStream_t s, const int* float_maxabs) {
     if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(grouped_copy_out_kernel, dim3(total_blocks), dim3(256), 0, s, graphs, jobs,
-                       njobs);
+                       njobs, float_maxabs);
     return hipGetLastError();
 }
 

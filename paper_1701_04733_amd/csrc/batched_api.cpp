@@ -144,7 +144,7 @@ btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
         for (int rep_i = 0; rep_i < 3 && e == hipSuccess; ++rep_i) {
             (void)hipEventRecord(e0, h->aux_stream);
             e = launch_grouped_step(dt, p->d_graphs, d_its, (int)its.size(), p->d_maxabs, nullptr,
-                                    h->aux_stream, shape_is_wave(cand));
+                                    h->aux_stream, shape_is_wave(cand), dt == BTAS_INT32);
             (void)hipEventRecord(e1, h->aux_stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0;
@@ -351,15 +351,22 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         // Capture the whole solve.
         e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return device_fail(h, fn, e);
-        if (dt == BTAS_INT32) e = launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
+        // int32: max |w| per graph first, so that graphs in the binary32-exact
+        // range are stored (and squared) as binary32 with no per-element
+        // conversions in the squarings.
+        const bool i32 = dt == BTAS_INT32;
+        if (i32) e = launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
+        if (e == hipSuccess && i32)
+            e = launch_grouped_maxabs(p->d_graphs, p->d_init, ng, blocks, p->d_maxabs, h->aux_stream);
         if (e == hipSuccess)
-            e = launch_grouped_init(dt, p->d_graphs, p->d_init, ng, blocks,
-                                    dt == BTAS_INT32 ? p->d_maxabs : nullptr, h->aux_stream);
+            e = launch_grouped_init(dt, p->d_graphs, p->d_init, ng, blocks, i32 ? p->d_maxabs : nullptr,
+                                    h->aux_stream, i32);
         for (int t = 0; t < Tmax && e == hipSuccess; ++t)
             e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
-                                    dt == BTAS_INT32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream,
-                                    p->wave);
-        if (e == hipSuccess) e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream);
+                                    i32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream, p->wave, i32);
+        if (e == hipSuccess)
+            e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream,
+                                        i32 ? p->d_maxabs : nullptr);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -381,7 +388,7 @@ extern "C" btas_status_t btas_batched_plan_info(btas_handle_t h, int* num_launch
     if (!h) return BTAS_ERR_INVALID_ARG;
     const BatchPlan* p = h->batch_plan.get();
     if (!p) return fail(h, BTAS_ERR_INVALID_ARG, "btas_batched_plan_info: no batched plan yet");
-    if (num_launches) *num_launches = (int)p->step_cnt.size() + (p->dt == BTAS_INT32 ? 3 : 2);
+    if (num_launches) *num_launches = (int)p->step_cnt.size() + (p->dt == BTAS_INT32 ? 4 : 2);
     if (total_terms) *total_terms = p->terms;
     return BTAS_OK;
 }

@@ -91,6 +91,11 @@ hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst
 // num_cus: compute units of the device; spin_limit: polls per barrier wait
 // before giving up.
 constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
+// Between these sizes the single-launch solve beats one launch per squaring
+// on MI355X (measured latency: n=9 49 us vs 37 us, n=33 62 us vs 81 us,
+// n=129 115 us vs 153 us, n=256 187 us vs 169 us).
+constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 24;
+constexpr int AUTO_SINGLE_LAUNCH_N = 192;
 size_t resident_lds_bytes(int n);
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
                                 void* ws, int T, bool early, unsigned* bar, int* flags,

@@ -35,6 +35,7 @@
 #include "gemm_tile.h"
 #include "kernels.h"
 #include "semiring.h"
+#include "flat_index.h"
 
 namespace btas {
 
@@ -126,7 +127,8 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
         T* D0 = cur ? a.buf1 : a.buf0;
         const long ld0 = cur ? a.ld1 : a.ld0;
         for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
-            const long i = e / n, j = e - i * n;
+            long i, j;
+        flat_to_rc(e, n, total, i, j);
             T w = a.W[i * a.ldw + j];
             if (i == j && w > (T)0) w = (T)0;
             st_dev(D0 + i * ld0 + j, w);
@@ -215,7 +217,8 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
     // After an early exit the result may sit in the workspace: copy it to D.
     if (cur != 0) {
         for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
-            const long i = e / n, j = e - i * n;
+            long i, j;
+        flat_to_rc(e, n, total, i, j);
             a.buf0[i * a.ld0 + j] = ld_dev(a.buf1 + i * a.ld1 + j);
         }
     }

@@ -79,6 +79,29 @@ def test_batched_tile_shapes_same_bits(dev, tile, monkeypatch):
     h.close()
 
 
+def test_batched_int32_storage_modes(dev):
+    """int32 graphs whose squarings stay within +-(2^23-1) are stored and
+    squared as binary32, the others as int32; one batch mixes both (and a
+    graph that is wide only because of a negative diagonal entry)."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = []
+    for i in range(12):
+        n = [40, 130, 257, 300][i % 4]
+        hi = 1000 if i % 2 == 0 else (1 << 20)              # odd: 2^T * max|w| > 2^23 - 1
+        Ws.append(wl.er_digraph_i32(n, min(1.0, 5.0 / n), 1, hi, seed=700 + i))
+    W = wl.er_digraph_i32(90, 0.05, 1, 100, seed=799)
+    W[3, 3] = -(1 << 17)                                   # D_33 = W_33 < 0: wide, negative cycle
+    Ws.append(W)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    Ds = btas.apsp_batched(tW)
+    torch.cuda.synchronize()
+    for i, (W, D) in enumerate(zip(Ws, Ds)):
+        want, _, _ = oracle.apsp(W)
+        assert np.array_equal(D.cpu().numpy(), want), f"graph {i} n={W.shape[0]}"
+
+
 def test_batched_in_place_and_errors(dev):
     import torch
 

@@ -245,9 +245,14 @@ def test_apsp_small_config_golden(btas, dev):
     assert_same(to_np(D2), want, "apsp n=256 early exit")
 
 
+@pytest.mark.parametrize("path", ["default", "per_squaring"])
 @pytest.mark.parametrize("dt", DT)
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 16, 32, 64, 128, 200, 201, 512])
-def test_apsp_sizes(btas, dev, dt, n):
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 16, 32, 64, 128, 192, 193, 200, 201, 512])
+def test_apsp_sizes(btas, dev, dt, n, path, monkeypatch):
+    """Small n take the single-launch solve by default; BTAS_SINGLE_LAUNCH=0
+    keeps them on one launch per squaring.  Both equal the oracle."""
+    if path == "per_squaring":
+        monkeypatch.setenv("BTAS_SINGLE_LAUNCH", "0")
     Wi = wl.er_digraph_i32(n, min(1.0, 3.0 / n), 1, 1000, seed=n)
     if dt == "f32":
         g = wl.rng(n + 1)
