@@ -14,7 +14,9 @@
 //    register tile split into 4-wide groups so that LDS reads are 128-bit.
 //  * A (BM x BK) and B (BK x BN) are staged row-major in padded LDS,
 //    double-buffered: the next k-block is fetched from HBM into registers
-//    while the current one is consumed, one barrier per block.
+//    while the current one is consumed, one barrier per block.  fp32
+//    products whose tiles are all full load the next k-block straight into
+//    LDS instead (no staging registers).
 //  * Ragged m/n/k edges are filled with the absent value, which never wins
 //    the (+)-reduction, so tile boundaries need no special compute path.
 //  * Workgroup ids are remapped so that each XCD (own L2) receives a
@@ -64,6 +66,17 @@ __global__ __launch_bounds__(Cfg::NT) void tropical_gemm_kernel(TileArgs<T> a,
         }
     }
     GemmTile<Cfg, T, T, SR, VEC>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
+}
+
+// fp32, every tile full and 16-byte aligned: direct global -> LDS loads.
+template <typename Cfg, int SR>
+__global__ __launch_bounds__(Cfg::NT) __attribute__((amdgpu_waves_per_eu(4))) void tropical_gemm_direct_kernel(
+    TileArgs<float> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nbm = a.m / Cfg::BM, nbn = a.n / Cfg::BN;
+    int tm, tn;
+    tile_of(blockIdx.x, nbm * nbn, nbm, nbn, tm, tn);
+    GemmTileDirect<Cfg, SR>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
 }
 
 // Split-K: blockIdx.x = tile * S + chunk; the chunk's partial product goes to
@@ -194,6 +207,13 @@ static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
         return hipGetLastError();
     }
     dim3 grid((unsigned)nb), block(Cfg::NT);
+    if constexpr (std::is_same_v<T, float> && std::is_same_v<Cfg, CfgL>) {
+        if (vec && g.m % Cfg::BM == 0 && g.n % Cfg::BN == 0 && g.k % Cfg::BK == 0) {
+            hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR>), grid, block,
+                               (GemmTileDirect<Cfg, SR>::lds_bytes), s, a);
+            return hipGetLastError();
+        }
+    }
     if (vec)
         hipLaunchKernelGGL((tropical_gemm_kernel<Cfg, T, SR, true>), grid, block, Cfg::lds_bytes,
                            s, a, g.wide_in);

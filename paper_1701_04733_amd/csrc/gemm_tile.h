@@ -167,6 +167,7 @@ struct GemmTile {
     // rolled so that only one quad's operands are live (about 150 VGPRs for
     // the 8x8 tile, three waves per SIMD); each quad folds two k-steps per
     // three-input min/max.
+    template <int LDA = Cfg::LDA_S, int LDB = Cfg::LDB_S>
     __device__ __forceinline__ static void compute(CT (&acc)[Cfg::TM][Cfg::TN], const CT* As,
                                                    const CT* Bs, int tx, int ty) {
 #pragma unroll 1
@@ -175,7 +176,7 @@ struct GemmTile {
 #pragma unroll
             for (int r = 0; r < Cfg::TM; ++r) {
                 const int row = Cfg::row_of(r, ty);
-                av[r] = *reinterpret_cast<const v4<CT>*>(As + row * Cfg::LDA_S + q * 4);
+                av[r] = *reinterpret_cast<const v4<CT>*>(As + row * LDA + q * 4);
             }
 #pragma unroll
             for (int kk = 0; kk < 4; kk += 2) {
@@ -184,9 +185,9 @@ struct GemmTile {
                 for (int g = 0; g < Cfg::CG; ++g) {
                     const int col = g * (Cfg::BN / Cfg::CG) + tx * 4;
                     const v4<CT> x0 = *reinterpret_cast<const v4<CT>*>(
-                        Bs + (q * 4 + kk) * Cfg::LDB_S + col);
+                        Bs + (q * 4 + kk) * LDB + col);
                     const v4<CT> x1 = *reinterpret_cast<const v4<CT>*>(
-                        Bs + (q * 4 + kk + 1) * Cfg::LDB_S + col);
+                        Bs + (q * 4 + kk + 1) * LDB + col);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         b0[g * 4 + e] = x0[e];
@@ -296,6 +297,126 @@ struct GemmTile {
         } else {
             return false;
         }
+    }
+};
+
+// fp32 operands, every tile full (m % BM == n % BN == k % BK == 0, rows
+// 16-byte aligned): A and B k-blocks go from global memory straight into LDS
+// (gfx950 global_load_lds_dwordx4: each wave instruction fills 1 KB of LDS in
+// lane order), so no registers hold the next block while the current one is
+// consumed.  The LDS rows are therefore unpadded; with the register-row
+// mapping of GemmCfg::row_of the lanes of a wave still read A rows that start
+// in distinct banks, and B rows are read as contiguous 16-byte chunks.
+template <typename Cfg, int SR>
+struct GemmTileDirect {
+    using R = Ring<SR, float>;
+    static constexpr int LDA = Cfg::BK, LDB = Cfg::BN;  // unpadded LDS rows
+    static constexpr int NW = Cfg::NT / 64;              // waves per workgroup
+    static constexpr int A_ROWS = 1024 / (Cfg::BK * 4);  // A rows per wave instruction
+    static constexpr int B_ROWS = 1024 / (Cfg::BN * 4);  // B rows per wave instruction
+    static constexpr int AI = Cfg::BM / A_ROWS / NW;     // instructions per wave per k-block
+    static constexpr int BI = Cfg::BK / B_ROWS / NW;
+    static_assert(AI >= 1 && BI >= 1 && Cfg::BM % (A_ROWS * NW) == 0 && Cfg::BK % (B_ROWS * NW) == 0,
+                  "each wave moves whole 1 KB pieces of both k-block tiles");
+    static constexpr size_t lds_bytes = 2 * (Cfg::BM * LDA + Cfg::BK * LDB) * 4;
+
+    using lds_ptr = __attribute__((address_space(3))) void*;
+    using gbl_ptr = __attribute__((address_space(1))) void*;
+
+    __device__ __forceinline__ static void issue(const TileArgs<float>& a, int m0, int n0, int k0,
+                                                 float* As, float* Bs) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int i = 0; i < AI; ++i) {
+            const int rb = (w * AI + i) * A_ROWS;
+            const int row = rb + lane / (Cfg::BK / 4), kq = lane % (Cfg::BK / 4);
+            const float* src = a.A + (long)(m0 + row) * a.lda + k0 + kq * 4;
+            __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(As + rb * LDA), 16, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < BI; ++i) {
+            const int rb = (w * BI + i) * B_ROWS;
+            const int row = rb + lane / (Cfg::BN / 4), cq = lane % (Cfg::BN / 4);
+            const float* src = a.B + (long)(k0 + row) * a.ldb + n0 + cq * 4;
+            __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(Bs + rb * LDB), 16, 0, 0);
+        }
+    }
+
+    // One LDS k-block into the register tile, two k-steps per iteration: the
+    // A operands are read as k-pairs (8-byte LDS reads), which keeps the live
+    // registers under the 128 that four waves per SIMD allow.
+    __device__ __forceinline__ static void compute(float (&acc)[Cfg::TM][Cfg::TN], const float* As,
+                                                   const float* Bs, int tx, int ty) {
+        using v2 = float __attribute__((ext_vector_type(2)));
+#pragma unroll 1
+        for (int kp = 0; kp < Cfg::BK / 2; ++kp) {
+            v2 av[Cfg::TM];
+#pragma unroll
+            for (int r = 0; r < Cfg::TM; ++r)
+                av[r] = *reinterpret_cast<const v2*>(As + Cfg::row_of(r, ty) * LDA + kp * 2);
+            float b0[Cfg::TN], b1[Cfg::TN];
+#pragma unroll
+            for (int g = 0; g < Cfg::CG; ++g) {
+                const int col = g * (Cfg::BN / Cfg::CG) + tx * 4;
+                const v4<float> x0 = *reinterpret_cast<const v4<float>*>(Bs + (kp * 2) * LDB + col);
+                const v4<float> x1 = *reinterpret_cast<const v4<float>*>(Bs + (kp * 2 + 1) * LDB + col);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    b0[g * 4 + e] = x0[e];
+                    b1[g * 4 + e] = x1[e];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < Cfg::TM; ++r)
+#pragma unroll
+                for (int c = 0; c < Cfg::TN; ++c)
+                    acc[r][c] = R::add3(acc[r][c], R::mul(av[r][0], b0[c]), R::mul(av[r][1], b1[c]));
+        }
+    }
+
+    __device__ __forceinline__ static void run(const TileArgs<float>& a, int m0, int n0,
+                                               unsigned char* smem) {
+        float* As0 = reinterpret_cast<float*>(smem);
+        float* Bs0 = As0 + Cfg::BM * LDA;
+        float* As1 = Bs0 + Cfg::BK * LDB;
+        float* Bs1 = As1 + Cfg::BM * LDA;
+        const int tid = threadIdx.x;
+        const int tx = tid % Cfg::TXN, ty = tid / Cfg::TXN;
+        float acc[Cfg::TM][Cfg::TN];
+#pragma unroll
+        for (int r = 0; r < Cfg::TM; ++r)
+#pragma unroll
+            for (int c = 0; c < Cfg::TN; ++c) acc[r][c] = R::absent();
+        const int nkb = a.k / Cfg::BK;
+        if (nkb > 0) issue(a, m0, n0, 0, As0, Bs0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's pieces are in LDS
+        __syncthreads();                                   // and everyone else's
+        for (int kb = 0; kb < nkb; ++kb) {
+            const bool even = (kb & 1) == 0;
+            if (kb + 1 < nkb) issue(a, m0, n0, (kb + 1) * Cfg::BK, even ? As1 : As0, even ? Bs1 : Bs0);
+            compute(acc, even ? As0 : As1, even ? Bs0 : Bs1, tx, ty);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+        }
+        // Epilogue (every tile is interior): Cout = Cin (+) acc, changed flag.
+        bool diff = false;
+#pragma unroll
+        for (int r = 0; r < Cfg::TM; ++r) {
+            const int row = m0 + Cfg::row_of(r, ty);
+#pragma unroll
+            for (int g = 0; g < Cfg::CG; ++g) {
+                const int col = n0 + g * (Cfg::BN / Cfg::CG) + tx * 4;
+                const v4<float> old = *reinterpret_cast<const v4<float>*>(a.Cin + (long)row * a.ldci + col);
+                v4<float> nv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    nv[e] = R::add(old[e], acc[r][g * 4 + e]);
+                    diff |= bits_of(nv[e]) != bits_of(old[e]);
+                }
+                *reinterpret_cast<v4<float>*>(a.Cout + (long)row * a.ldco + col) = nv;
+            }
+        }
+        if (a.changed != nullptr && __any(diff) && (threadIdx.x & 63) == 0) *a.changed = 1;
     }
 };
 

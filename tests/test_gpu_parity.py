@@ -101,6 +101,34 @@ def test_gemm_large_tiles_ragged(btas, dev, sr, dt, frac):
 
 
 @pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("frac", [0.0, 0.1, 1.0])
+def test_gemm_full_tiles_direct_lds_path(btas, dev, sr, frac):
+    """fp32 shapes whose 128x128 tiles are all full (the direct global->LDS
+    path), signed values, a C that is partly absent, padded leading
+    dimensions, and the same product through a ragged shape (the staged
+    path) for comparison."""
+    torch = torch_mod()
+    m, n, k = 3200, 2688, 96                       # 25 x 21 = 525 >= 512 tiles of 128 x 128
+    A, B = operands(m, n, k, "f32", sr, seed=91, frac=frac, signed=True)
+    C = wl.signed_operand((m, n), "f32", sr, seed=92, inf_frac=0.3)
+    want = oracle.gemm(sr, A, B, C)
+    Ap = torch.zeros((m, k + 4), dtype=torch.float32, device=dev)
+    Ap[:, :k] = to_dev(A, dev)
+    Bp = torch.zeros((k, n + 8), dtype=torch.float32, device=dev)
+    Bp[:, :n] = to_dev(B, dev)
+    Cp = torch.zeros((m, n + 4), dtype=torch.float32, device=dev)
+    Cp[:, :n] = to_dev(C, dev)
+    btas.tropical_gemm(Ap[:, :k], Bp[:, :n], Cp[:, :n], semiring=sr)
+    assert_same(to_np(Cp[:, :n]), want, f"{sr}/frac={frac} full tiles")
+    assert (Cp[:, n:] == 0).all()
+    # a ragged sub-shape of the same operands goes through the staged kernel
+    mr, nr = m - 1, n - 3
+    Cr = to_dev(C[:mr, :nr], dev)
+    btas.tropical_gemm(to_dev(A[:mr], dev), to_dev(B[:, :nr], dev), Cr, semiring=sr)
+    assert_same(to_np(Cr), want[:mr, :nr], f"{sr}/frac={frac} ragged")
+
+
+@pytest.mark.parametrize("sr", SR)
 @pytest.mark.parametrize("dt", DT)
 def test_gemm_leading_dimensions_and_alignment(btas, dev, sr, dt):
     """Sub-views with padded rows, including leading dimensions that are not a
