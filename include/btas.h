@@ -205,7 +205,7 @@ int btas_apsp_num_steps(int n);
  * shapes chosen by timing every candidate shape of btas_tile_shape_t on this
  * device, the captured graph) and synchronises; later calls with identical
  * arguments only launch the graph (asynchronous).  The environment variable
- * BTAS_BATCHED_TILE=128, 64, mixed, w64 or wmix forces one tile shape;
+ * BTAS_BATCHED_TILE=128, 64, mixed, w64, wmix or w64d forces one tile shape;
  * BTAS_AUTOTUNE=0 uses a cost model instead of timing.
  */
 btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int count,
@@ -225,7 +225,9 @@ typedef enum {
     BTAS_TILES_64 = 1,     /* 64x64 tiles (four waves, 4x4 outputs per thread) */
     BTAS_TILES_MIXED = 2,  /* 128x128 on the multiple-of-128 core, 64x64 on the edge */
     BTAS_TILES_W64 = 3,    /* 64x64 tiles, one wave, 8x8 outputs per thread */
-    BTAS_TILES_WMIX = 4    /* one-wave 64x64 on the multiple-of-64 core, 32x32 on the edge */
+    BTAS_TILES_WMIX = 4,   /* one-wave 64x64 on the multiple-of-64 core, 32x32 on the edge */
+    BTAS_TILES_W64_DIRECT = 5  /* one-wave 64x64 tiles over the matrix padded to a multiple of
+                                  64 with the absent value, operands loaded straight into LDS */
 } btas_tile_shape_t;
 
 /* The btas_tile_shape_t the handle's most recent batched plan used for graphs

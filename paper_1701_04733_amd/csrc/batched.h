@@ -20,6 +20,8 @@ struct BatchGraph {
     int ld;
     int T;
     int parity;
+    int np;  // > 0: the buffers are np x np (np = ld, a multiple of 64) and rows /
+             // columns n..np-1 hold the absent value (BATCH_TILE_W64D items)
 };
 
 // Tile kinds.  The block kinds run in the 256-thread grouped kernel, the wave
@@ -30,13 +32,21 @@ enum {
     BATCH_TILE_64 = 1,    // 64x64 outputs, 4 waves, 4x4 per thread
     BATCH_TILE_W64 = 2,   // 64x64 outputs, 1 wave, 8x8 per thread
     BATCH_TILE_W32 = 3,   // 32x32 outputs, 1 wave, 4x4 per thread
+    BATCH_TILE_W64D = 4,  // 64x64 outputs of the padded matrix, 1 wave, direct LDS loads
     BATCH_TILE_NONE = -1  // placeholder: the workgroup exits at once
 };
 
 inline int tile_edge(int kind) {
     return kind == BATCH_TILE_128 ? 128 : kind == BATCH_TILE_W32 ? 32 : 64;
 }
-inline bool tile_is_wave(int kind) { return kind == BATCH_TILE_W64 || kind == BATCH_TILE_W32; }
+// Kernel family of a tile kind: 0 = four-wave blocks, 1 = one-wave tiles,
+// 2 = one-wave direct-load tiles of padded matrices.
+inline int tile_family(int kind) {
+    return kind == BATCH_TILE_W64D ? 2 : (kind == BATCH_TILE_W64 || kind == BATCH_TILE_W32) ? 1 : 0;
+}
+inline bool tile_is_wave(int kind) { return tile_family(kind) == 1; }
+// Storage edge of a graph's padded buffers.
+inline int padded_edge(int n) { return (n + 63) / 64 * 64; }
 
 // One output tile of one squaring of one graph.
 struct BatchItem {
@@ -48,9 +58,16 @@ struct BatchItem {
 };
 
 // How a graph's n x n output is cut into tiles.  SHAPE_128/64/MIXED use the
-// block kinds, SHAPE_W64/WMIX the wave kinds.
-enum { SHAPE_128 = 0, SHAPE_64 = 1, SHAPE_MIXED = 2, SHAPE_W64 = 3, SHAPE_WMIX = 4, NUM_SHAPES = 5 };
-inline bool shape_is_wave(int shape) { return shape == SHAPE_W64 || shape == SHAPE_WMIX; }
+// block kinds, SHAPE_W64/WMIX the wave kinds, SHAPE_W64D the direct kind.
+enum {
+    SHAPE_128 = 0, SHAPE_64 = 1, SHAPE_MIXED = 2, SHAPE_W64 = 3, SHAPE_WMIX = 4, SHAPE_W64D = 5,
+    NUM_SHAPES = 6
+};
+constexpr int NUM_FAMILIES = 3;
+inline int shape_family(int shape) {
+    return shape == SHAPE_W64D ? 2 : (shape == SHAPE_W64 || shape == SHAPE_WMIX) ? 1 : 0;
+}
+inline bool shape_is_wave(int shape) { return shape_family(shape) == 1; }
 
 struct TileRef {
     int m0, n0, kind;
@@ -63,9 +80,10 @@ struct TileRef {
 inline std::vector<TileRef> tile_plan(int n, int shape) {
     std::vector<TileRef> out;
     if (n <= 0) return out;
-    if (shape == SHAPE_128 || shape == SHAPE_64 || shape == SHAPE_W64) {
+    if (shape == SHAPE_128 || shape == SHAPE_64 || shape == SHAPE_W64 || shape == SHAPE_W64D) {
         const int kind = shape == SHAPE_128 ? BATCH_TILE_128
-                         : shape == SHAPE_64 ? BATCH_TILE_64 : BATCH_TILE_W64;
+                         : shape == SHAPE_64 ? BATCH_TILE_64
+                         : shape == SHAPE_W64 ? BATCH_TILE_W64 : BATCH_TILE_W64D;
         const int t = tile_edge(kind);
         for (int i = 0; i < n; i += t)
             for (int j = 0; j < n; j += t) out.push_back({i, j, kind});
@@ -147,7 +165,7 @@ inline std::vector<BatchItem> order_for_xcds(const std::vector<BatchItem>& items
 
 static_assert(SHAPE_128 == BTAS_TILES_128 && SHAPE_64 == BTAS_TILES_64 &&
                   SHAPE_MIXED == BTAS_TILES_MIXED && SHAPE_W64 == BTAS_TILES_W64 &&
-                  SHAPE_WMIX == BTAS_TILES_WMIX,
+                  SHAPE_WMIX == BTAS_TILES_WMIX && SHAPE_W64D == BTAS_TILES_W64_DIRECT,
               "internal shape codes are the ABI's");
 
 // Cheapest block-family shape by the padded-area model.
@@ -176,8 +194,9 @@ struct BatchCopy {
 };
 
 // Squarings for items[0, nitems): one workgroup per item, 256 threads for the
-// block kinds, 64 for the wave kinds (`wave` selects the family; every item of
-// the launch must belong to it, placeholders aside).  maxabs (int32 only, may
+// block kinds, 64 for the wave and direct kinds (`family` selects the kernel:
+// 0 block, 1 wave, 2 direct; every item of the launch must belong to it,
+// placeholders aside; direct items need graphs with padded buffers, np > 0).  maxabs (int32 only, may
 // be null): per-graph max |finite element of D_0|; an int32 graph with
 // 2^T * maxabs <= 2^23-1 is computed on the binary32 pipeline, reading int32
 // storage with conversions, or (float_storage) buffers that
@@ -185,12 +204,13 @@ struct BatchCopy {
 // per-graph flag set to 1 when a squaring changed some entry.
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
                                int nitems, const int* maxabs, int* changed, hipStream_t s,
-                               bool wave = false, bool float_storage = false);
+                               int family = 0, bool float_storage = false);
 // int32: maxabs[graph] <- max |finite element of I (+) W| (maxabs zeroed
 // first); the first pass of the float-storage mode.
 hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
                                  int total_blocks, int* maxabs, hipStream_t s);
-// buf[parity] <- I (+) W for each job.  int32 without float_storage:
+// buf[parity] <- I (+) W for each job (graphs with np > 0: rows and columns
+// n..np-1 of that buffer <- the absent value).  int32 without float_storage:
 // maxabs[graph] <- max |finite element| (maxabs zeroed first).  int32 with
 // float_storage: maxabs is complete (launch_grouped_maxabs) and graphs in the
 // binary32-exact range are stored as binary32.  total_blocks = sum of the

@@ -114,12 +114,55 @@ __global__ __launch_bounds__(64) void grouped_wave_step_kernel(const BatchGraph*
 
 static_assert(CfgW::NT == 64 && CfgS::NT == 64, "wave kernel mixes both wave tile shapes");
 
+// Direct-load step for graphs stored padded (np x np, absent beyond n): every
+// 64x64 tile of the padded matrix is full, so the operands go from global
+// memory straight into LDS (no staging registers, four waves per SIMD); the
+// padding stays absent (a padded row or column only meets absent values).
+// int32 graphs outside the binary32-exact range (rare) take the staged
+// integer tile on the same padded matrix.
+template <typename T, int SR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+grouped_direct_step_kernel(const BatchGraph* __restrict__ graphs, const BatchItem* __restrict__ items,
+                           const int* __restrict__ maxabs, int* __restrict__ changed,
+                           int float_storage) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const BatchItem it = items[blockIdx.x];
+    if (it.kind == BATCH_TILE_NONE) return;
+    const BatchGraph g = graphs[it.graph];
+    const bool odd = ((g.parity + it.step) & 1) != 0;
+    const T* src = (const T*)(odd ? g.buf[0] : g.buf[1]);
+    T* dst = (T*)(odd ? g.buf[1] : g.buf[0]);
+    int* chg = changed != nullptr ? changed + it.graph : nullptr;
+    const int np = g.np;
+    if (std::is_same_v<T, float> || (float_storage && graph_is_narrow<T>(g, maxabs, it.graph))) {
+        TileArgs<float> f{np, np, np, (const float*)src, np, (const float*)src, np,
+                          (const float*)src, np, (float*)dst, np, chg, nullptr};
+        GemmTileDirect<CfgWD, SR>::run(f, it.m0, it.n0, smem_raw);
+        return;
+    }
+    if constexpr (std::is_same_v<T, int32_t>) {
+        TileArgs<T> a{np, np, np, src, np, src, np, src, np, dst, np, chg, nullptr};
+        GemmTile<CfgW, T, T, SR, true>::run(a, it.m0, it.n0, smem_raw);
+    }
+}
+
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
                                int nitems, const int* maxabs, int* changed, hipStream_t s,
-                               bool wave, bool float_storage) {
+                               int family, bool float_storage) {
     if (nitems <= 0) return hipSuccess;
     const int fs = float_storage ? 1 : 0;
-    if (wave) {
+    if (family == 2) {
+        const size_t lds = GemmTileDirect<CfgWD, BTAS_MIN_PLUS>::lds_bytes > CfgW::lds_bytes
+                               ? GemmTileDirect<CfgWD, BTAS_MIN_PLUS>::lds_bytes : CfgW::lds_bytes;
+        if (dt == BTAS_FLOAT32)
+            hipLaunchKernelGGL((grouped_direct_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems),
+                               dim3(64), lds, s, graphs, items, nullptr, changed, 0);
+        else
+            hipLaunchKernelGGL((grouped_direct_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems),
+                               dim3(64), lds, s, graphs, items, maxabs, changed, fs);
+        return hipGetLastError();
+    }
+    if (family == 1) {
         const size_t lds = CfgW::lds_bytes > CfgS::lds_bytes ? CfgW::lds_bytes : CfgS::lds_bytes;
         if (dt == BTAS_FLOAT32)
             hipLaunchKernelGGL((grouped_wave_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems),
@@ -207,6 +250,19 @@ __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __r
     const long stride = (long)jb.nblocks * blockDim.x;
     bool as_float = false;
     if constexpr (std::is_same_v<T, int32_t>) as_float = float_storage && graph_is_narrow<T>(g, maxabs, jb.graph);
+    if (g.np > n) {
+        // padded storage: rows and columns n..np-1 get the absent value
+        const long np = g.np, ptotal = np * np;
+        const uint32_t absent = as_float || std::is_same_v<T, float>
+                                    ? __float_as_uint(Ring<BTAS_MIN_PLUS, float>::absent())
+                                    : (uint32_t)BTAS_I32_INF;
+        for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < ptotal;
+             e += stride) {
+            long i, j;
+            flat_to_rc(e, (int)np, ptotal, i, j);
+            if (i >= n || j >= n) reinterpret_cast<uint32_t*>(D)[i * np + j] = absent;
+        }
+    }
     int mx = 0;
     for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
          e += stride) {

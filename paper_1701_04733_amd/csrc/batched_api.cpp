@@ -44,7 +44,7 @@ struct BatchPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double terms = 0;                     // sum over graphs of T(n) * n^3
-    bool wave = false;                    // squaring launches use the one-wave tile kernel
+    int family = 0;                       // squaring kernel: 0 block, 1 wave, 2 direct
 };
 
 void destroy_batch_plan(BatchPlan* p) {
@@ -96,7 +96,7 @@ btas_status_t upload(btas_handle_t h, const char* fn, void** dst, const void* sr
 int forced_shape() {
     const char* f = getenv("BTAS_BATCHED_TILE");
     if (!f || !*f) return -1;
-    const char* names[NUM_SHAPES] = {"128", "64", "mixed", "w64", "wmix"};
+    const char* names[NUM_SHAPES] = {"128", "64", "mixed", "w64", "wmix", "w64d"};
     for (int s = 0; s < NUM_SHAPES; ++s)
         if (std::strcmp(f, names[s]) == 0) return s;
     return -1;
@@ -144,7 +144,7 @@ btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
         for (int rep_i = 0; rep_i < 3 && e == hipSuccess; ++rep_i) {
             (void)hipEventRecord(e0, h->aux_stream);
             e = launch_grouped_step(dt, p->d_graphs, d_its, (int)its.size(), p->d_maxabs, nullptr,
-                                    h->aux_stream, shape_is_wave(cand), dt == BTAS_INT32);
+                                    h->aux_stream, shape_family(cand), dt == BTAS_INT32);
             (void)hipEventRecord(e1, h->aux_stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0;
@@ -159,17 +159,17 @@ btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
     }
     out->best[0] = SHAPE_128;
     out->best[1] = SHAPE_W64;
+    out->best[2] = SHAPE_W64D;
     for (int cand = 0; cand < NUM_SHAPES; ++cand) {
-        const int f = shape_is_wave(cand) ? 1 : 0;
+        const int f = shape_family(cand);
         if (spt[cand] < spt[out->best[f]]) out->best[f] = cand;
     }
-    out->spt[0] = spt[out->best[0]];
-    out->spt[1] = spt[out->best[1]];
+    for (int f = 0; f < NUM_FAMILIES; ++f) out->spt[f] = spt[out->best[f]];
     if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1')
         fprintf(stderr, "[btas] autotune dt=%d n<=%d graphs=%zu Tterm/s: 128 %.1f, 64 %.1f, mixed %.1f, "
-                "w64 %.1f, wmix %.1f -> block %d, wave %d\n", dt, hg[slots.front()].n, slots.size(),
-                1e-12 / spt[0], 1e-12 / spt[1], 1e-12 / spt[2], 1e-12 / spt[3], 1e-12 / spt[4],
-                out->best[0], out->best[1]);
+                "w64 %.1f, wmix %.1f, w64d %.1f -> block %d, wave %d\n", dt, hg[slots.front()].n,
+                slots.size(), 1e-12 / spt[0], 1e-12 / spt[1], 1e-12 / spt[2], 1e-12 / spt[3],
+                1e-12 / spt[4], 1e-12 / spt[5], out->best[0], out->best[1]);
     return BTAS_OK;
 }
 
@@ -242,25 +242,27 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         // Order graphs: decreasing T, then decreasing n; drop n == 0.
         std::vector<HostGraph> hg;
         for (int i = 0; i < count; ++i)
-            if (n[i] > 0) hg.push_back({i, n[i], apsp_steps(n[i]), (int)round_up(n[i], 4)});
+            if (n[i] > 0) hg.push_back({i, n[i], apsp_steps(n[i]), padded_edge(n[i])});
         std::stable_sort(hg.begin(), hg.end(), [](const HostGraph& a, const HostGraph& b) {
             return a.T != b.T ? a.T > b.T : a.n > b.n;
         });
         const int ng = (int)hg.size();
-        // Workspace: two 256-byte aligned buffers per graph.
+        // Workspace: two 256-byte aligned np x np buffers per graph (np = n
+        // rounded up to 64, the padding filled with the absent value at init),
+        // so that every shape, including the direct one, can run on them.
         std::vector<size_t> off(ng);
         size_t total = 0;
         for (int g = 0; g < ng; ++g) {
             off[g] = total;
-            total += 2 * round_up((size_t)hg[g].n * hg[g].ld * 4, 256);
+            total += 2 * round_up((size_t)hg[g].ld * hg[g].ld * 4, 256);
         }
         if (total > 0 && hipMalloc(&p->ws, total) != hipSuccess)
             return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte batch workspace", fn, total);
         std::vector<BatchGraph> graphs(ng);
         for (int g = 0; g < ng; ++g) {
-            const size_t half = round_up((size_t)hg[g].n * hg[g].ld * 4, 256);
+            const size_t half = round_up((size_t)hg[g].ld * hg[g].ld * 4, 256);
             char* base = (char*)p->ws + off[g];
-            graphs[g] = {{base, base + half}, hg[g].n, hg[g].ld, hg[g].T, 0};
+            graphs[g] = {{base, base + half}, hg[g].n, hg[g].ld, hg[g].T, 0, hg[g].ld};
             p->terms += (double)hg[g].T * hg[g].n * (double)hg[g].n * hg[g].n;
         }
         btas_status_t st = upload(h, fn, (void**)&p->d_graphs, graphs.data(), sizeof(BatchGraph) * ng);
@@ -273,19 +275,19 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         for (int g = 0; g < ng; ++g)
             if (hg[g].T > 0) buckets[size_bucket(hg[g].n)].push_back(g);
         std::map<int, int> kind_of_bucket;
-        bool wave = true;
+        int family = 2;
         const int forced = forced_shape();
         const char* tune_env = getenv("BTAS_AUTOTUNE");
         const bool tune = !(tune_env && tune_env[0] == '0');
         if (forced >= 0) {
-            wave = shape_is_wave(forced);
+            family = shape_family(forced);
             for (auto& kv : buckets) kind_of_bucket[kv.first] = forced;
         } else if (!tune) {
-            for (auto& kv : buckets) kind_of_bucket[kv.first] = model_wave_shape(hg[kv.second.front()].n);
+            for (auto& kv : buckets) kind_of_bucket[kv.first] = SHAPE_W64D;
         } else {
             // Measure the buckets this handle has not timed yet, then take the
             // family with the smaller predicted time for the whole plan.
-            double cost[2] = {0, 0};
+            double cost[NUM_FAMILIES] = {0, 0, 0};
             double step1 = 0;  // useful terms of the first squaring launch
             for (int g = 0; g < ng; ++g)
                 if (hg[g].T > 0) step1 += (double)hg[g].n * hg[g].n * hg[g].n;
@@ -302,17 +304,20 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                 }
                 double terms = 0;
                 for (int g : kv.second) terms += (double)hg[g].T * hg[g].n * (double)hg[g].n * hg[g].n;
-                for (int f = 0; f < 2; ++f) cost[f] += terms * it->second.spt[f];
+                for (int f = 0; f < NUM_FAMILIES; ++f) cost[f] += terms * it->second.spt[f];
             }
-            wave = cost[1] <= cost[0];
+            family = 0;
+            for (int f = 1; f < NUM_FAMILIES; ++f)
+                if (cost[f] < cost[family]) family = f;
             for (auto& kv : buckets)
                 kind_of_bucket[kv.first] =
-                    h->tile_timing[std::make_tuple((int)dt, kv.first, scale)].best[wave ? 1 : 0];
+                    h->tile_timing[std::make_tuple((int)dt, kv.first, scale)].best[family];
             if (const char* lg = getenv("BTAS_LOG"); lg && lg[0] == '1')
                 fprintf(stderr, "[btas] batched plan: predicted %.3f ms with block tiles, %.3f ms with "
-                        "wave tiles -> %s\n", cost[0] * 1e3, cost[1] * 1e3, wave ? "wave" : "block");
+                        "wave tiles, %.3f ms with direct tiles -> family %d\n", cost[0] * 1e3,
+                        cost[1] * 1e3, cost[2] * 1e3, family);
         }
-        p->wave = wave;
+        p->family = family;
         for (auto& kv : kind_of_bucket) h->tile_choice[{(int)dt, kv.first}] = kv.second;
 
         // Work lists: launch t holds the tiles of every graph with T >= t.
@@ -363,7 +368,7 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                                     h->aux_stream, i32);
         for (int t = 0; t < Tmax && e == hipSuccess; ++t)
             e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
-                                    i32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream, p->wave, i32);
+                                    i32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream, p->family, i32);
         if (e == hipSuccess)
             e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream,
                                         i32 ? p->d_maxabs : nullptr);

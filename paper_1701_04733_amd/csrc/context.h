@@ -21,11 +21,11 @@ struct BatchPlanDeleter {
     void operator()(BatchPlan* p) const { destroy_batch_plan(p); }
 };
 // Measured speed of one size bucket's squaring: for each tile family (0 =
-// four-wave blocks, 1 = single waves) the fastest shape and its seconds per
-// useful term.
+// four-wave blocks, 1 = single waves, 2 = single-wave direct loads on padded
+// buffers) the fastest shape and its seconds per useful term.
 struct BucketTiming {
-    int best[2];
-    double spt[2];
+    int best[3];
+    double spt[3];
 };
 }  // namespace btas
 

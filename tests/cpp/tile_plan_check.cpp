@@ -13,7 +13,7 @@ int main() {
             std::vector<int> cov((size_t)n * n, 0);
             for (const btas::TileRef& t : btas::tile_plan(n, s)) {
                 const int sz = btas::tile_edge(t.kind);
-                if (btas::tile_is_wave(t.kind) != btas::shape_is_wave(s)) ++bad;
+                if (btas::tile_family(t.kind) != btas::shape_family(s)) ++bad;
                 if (t.m0 < 0 || t.n0 < 0 || t.m0 >= n || t.n0 >= n) {
                     ++bad;
                     continue;

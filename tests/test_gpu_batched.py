@@ -59,7 +59,7 @@ def test_batched_matches_oracle(dev, dt):
     assert info["launches"] >= 2
 
 
-@pytest.mark.parametrize("tile", ["128", "64", "mixed", "w64", "wmix"])
+@pytest.mark.parametrize("tile", ["128", "64", "mixed", "w64", "wmix", "w64d"])
 def test_batched_tile_shapes_same_bits(dev, tile, monkeypatch):
     """Every tile shape the autotuner may pick gives the same bits."""
     import torch
@@ -79,13 +79,17 @@ def test_batched_tile_shapes_same_bits(dev, tile, monkeypatch):
     h.close()
 
 
-def test_batched_int32_storage_modes(dev):
+@pytest.mark.parametrize("tile", [None, "w64d", "mixed"])
+def test_batched_int32_storage_modes(dev, tile, monkeypatch):
     """int32 graphs whose squarings stay within +-(2^23-1) are stored and
     squared as binary32, the others as int32; one batch mixes both (and a
-    graph that is wide only because of a negative diagonal entry)."""
+    graph that is wide only because of a negative diagonal entry), with the
+    autotuned shapes and forced ones (the direct kernel's integer path)."""
     import torch
 
     import paper_1701_04733_amd as btas
+    if tile is not None:
+        monkeypatch.setenv("BTAS_BATCHED_TILE", tile)
     Ws = []
     for i in range(12):
         n = [40, 130, 257, 300][i % 4]
@@ -95,11 +99,14 @@ def test_batched_int32_storage_modes(dev):
     W[3, 3] = -(1 << 17)                                   # D_33 = W_33 < 0: wide, negative cycle
     Ws.append(W)
     tW = [torch.from_numpy(w).to(dev) for w in Ws]
-    Ds = btas.apsp_batched(tW)
+    h = btas.Handle(0)
+    h.bind_stream()
+    Ds = btas.apsp_batched(tW, handle=h)
     torch.cuda.synchronize()
     for i, (W, D) in enumerate(zip(Ws, Ds)):
         want, _, _ = oracle.apsp(W)
         assert np.array_equal(D.cpu().numpy(), want), f"graph {i} n={W.shape[0]}"
+    h.close()
 
 
 def test_batched_in_place_and_errors(dev):
