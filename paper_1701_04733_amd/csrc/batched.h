@@ -184,6 +184,8 @@ inline int model_wave_shape(int n) {
 
 // An external matrix (the caller's W or D) paired with a graph.  Jobs of one
 // launch own consecutive ranges of workgroups: [first_block, first_block + nblocks).
+// The copy launchers take an optional table block_job[workgroup] -> job
+// (else each workgroup finds its job by binary search over first_block).
 struct BatchCopy {
     int graph;
     int first_block;
@@ -208,7 +210,8 @@ hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem
 // int32: maxabs[graph] <- max |finite element of I (+) W| (maxabs zeroed
 // first); the first pass of the float-storage mode.
 hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                                 int total_blocks, int* maxabs, hipStream_t s);
+                                 int total_blocks, int* maxabs, hipStream_t s,
+                                 const int* block_job = nullptr);
 // buf[parity] <- I (+) W for each job (graphs with np > 0: rows and columns
 // n..np-1 of that buffer <- the absent value).  int32 without float_storage:
 // maxabs[graph] <- max |finite element| (maxabs zeroed first).  int32 with
@@ -217,12 +220,13 @@ hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs
 // jobs' nblocks.
 hipError_t launch_grouped_init(int dt, const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
                                int total_blocks, int* maxabs, hipStream_t s,
-                               bool float_storage = false);
+                               bool float_storage = false, const int* block_job = nullptr);
 // D_ext <- buf[(parity + T) & 1] for each job; float_maxabs (int32
 // float-storage mode, else null) converts the graphs stored as binary32 back.
 hipError_t launch_grouped_copy_out(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
                                    int total_blocks, hipStream_t s,
-                                   const int* float_maxabs = nullptr);
+                                   const int* float_maxabs = nullptr,
+                                   const int* block_job = nullptr);
 // Workgroups an n x n copy job should get (about 4096 elements each, <= 256).
 inline int copy_blocks_for(int n) {
     long b = ((long)n * n + 4095) / 4096;

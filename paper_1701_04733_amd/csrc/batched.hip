@@ -209,25 +209,58 @@ __device__ __forceinline__ void block_max_to(int* dst, int mx) {
     if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(dst, mx);
 }
 
+// The three passes below work on quads: four consecutive columns of one row
+// (one index division per quad; 16-byte loads and stores on the padded
+// internal buffers, whose rows are multiples of 4), QB quads per thread per
+// round with every load issued before any is used, so that each thread keeps
+// several HBM reads in flight.
+constexpr int QB = 4;
+
 // int32, first pass of the float-storage mode: maxabs[graph] <- max |finite
 // element of I (+) W|.
 __global__ __launch_bounds__(256) void grouped_maxabs_kernel(const BatchGraph* __restrict__ graphs,
                                                               const BatchCopy* __restrict__ jobs,
-                                                              int njobs, int* __restrict__ maxabs) {
-    const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
+                                                              int njobs, const int* __restrict__ block_job,
+                                                              int* __restrict__ maxabs) {
+    const BatchCopy jb = jobs[block_job != nullptr ? block_job[blockIdx.x] : find_job(jobs, njobs, blockIdx.x)];
     const int n = graphs[jb.graph].n;
     const int32_t* W = (const int32_t*)jb.ext;
-    const long total = (long)n * n;
+    const int nq = (n + 3) / 4;
+    const long total = (long)n * nq;
     const long stride = (long)jb.nblocks * blockDim.x;
+    const bool vec = jb.ld_ext % 4 == 0 && (uintptr_t)W % 16 == 0;  // 16-byte row quads
     int mx = 0;
-    for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
-         e += stride) {
-        long i, j;
-        flat_to_rc(e, n, total, i, j);
-        int32_t w = W[i * jb.ld_ext + j];
-        if (i == j && w > 0) w = 0;
-        const int aw = abs_finite(w);
-        mx = aw > mx ? aw : mx;
+    // QB quads per thread per round, all loads issued before any is used
+    for (long e0 = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e0 < total;
+         e0 += QB * stride) {
+        int32_t w[QB][4];
+        long ii[QB], qq[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const long e = e0 + b * stride;
+            ii[b] = -1;
+            if (e < total) flat_to_rc(e, nq, total, ii[b], qq[b]);
+            if (vec && ii[b] >= 0 && qq[b] * 4 + 3 < n) {
+                const v4<int32_t> x = *reinterpret_cast<const v4<int32_t>*>(W + ii[b] * jb.ld_ext + qq[b] * 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) w[b][u] = x[u];
+                continue;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long j = qq[b] * 4 + u;
+                w[b][u] = (ii[b] >= 0 && j < n) ? W[ii[b] * jb.ld_ext + j] : BTAS_I32_INF;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int32_t x = w[b][u];
+                if (ii[b] == qq[b] * 4 + u && x > 0) x = 0;
+                const int aw = abs_finite(x);
+                mx = aw > mx ? aw : mx;
+            }
     }
     block_max_to(maxabs + jb.graph, mx);
 }
@@ -235,50 +268,80 @@ __global__ __launch_bounds__(256) void grouped_maxabs_kernel(const BatchGraph* _
 // float_storage (int32 only; maxabs already complete): graphs whose squarings
 // stay in the binary32-exact range are written as binary32 values (absent ->
 // +inf), so the squaring kernels read and write them without conversions.
-// Otherwise (int32) maxabs[graph] is accumulated here.
+// Otherwise (int32) maxabs[graph] is accumulated here.  Padded graphs (np > 0)
+// get the absent value in rows and columns n..np-1.
 template <typename T>
 __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __restrict__ graphs,
                                                             const BatchCopy* __restrict__ jobs,
-                                                            int njobs, int* __restrict__ maxabs,
-                                                            int float_storage) {
-    const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
+                                                            int njobs, const int* __restrict__ block_job,
+                                                            int* __restrict__ maxabs, int float_storage) {
+    const BatchCopy jb = jobs[block_job != nullptr ? block_job[blockIdx.x] : find_job(jobs, njobs, blockIdx.x)];
     const BatchGraph g = graphs[jb.graph];
     const int n = g.n;
     const T* W = (const T*)jb.ext;
-    T* D = (T*)g.buf[g.parity & 1];
-    const long total = (long)n * n;
-    const long stride = (long)jb.nblocks * blockDim.x;
+    uint32_t* D = (uint32_t*)g.buf[g.parity & 1];
     bool as_float = false;
     if constexpr (std::is_same_v<T, int32_t>) as_float = float_storage && graph_is_narrow<T>(g, maxabs, jb.graph);
-    if (g.np > n) {
-        // padded storage: rows and columns n..np-1 get the absent value
-        const long np = g.np, ptotal = np * np;
-        const uint32_t absent = as_float || std::is_same_v<T, float>
-                                    ? __float_as_uint(Ring<BTAS_MIN_PLUS, float>::absent())
-                                    : (uint32_t)BTAS_I32_INF;
-        for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < ptotal;
-             e += stride) {
-            long i, j;
-            flat_to_rc(e, (int)np, ptotal, i, j);
-            if (i >= n || j >= n) reinterpret_cast<uint32_t*>(D)[i * np + j] = absent;
-        }
-    }
+    const uint32_t absent = as_float || std::is_same_v<T, float>
+                                ? __float_as_uint(Ring<BTAS_MIN_PLUS, float>::absent())
+                                : (uint32_t)BTAS_I32_INF;
+    // quads over the stored rows x columns: np x np when padded, else n x n
+    // (the last quad of a row may reach into columns n..ld-1, which nothing reads)
+    const int rows = g.np > 0 ? g.np : n;
+    const int nq = ((g.np > 0 ? g.np : n) + 3) / 4;
+    const long total = (long)rows * nq;
+    const long stride = (long)jb.nblocks * blockDim.x;
+    const bool vec = jb.ld_ext % 4 == 0 && (uintptr_t)W % 16 == 0;
     int mx = 0;
-    for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
-         e += stride) {
-        long i, j;
-        flat_to_rc(e, n, total, i, j);
-        T w = W[i * jb.ld_ext + j];
-        if (i == j && w > (T)0) w = (T)0;
-        if constexpr (std::is_same_v<T, int32_t>) {
-            if (as_float) {
-                reinterpret_cast<float*>(D)[i * g.ld + j] = Conv<int32_t, float, BTAS_MIN_PLUS>::in(w);
+    for (long e0 = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e0 < total;
+         e0 += QB * stride) {
+        T w[QB][4];
+        long ii[QB], qq[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const long e = e0 + b * stride;
+            ii[b] = -1;
+            if (e < total) flat_to_rc(e, nq, total, ii[b], qq[b]);
+            if (vec && ii[b] >= 0 && ii[b] < n && qq[b] * 4 + 3 < n) {
+                const v4<T> x = *reinterpret_cast<const v4<T>*>(W + ii[b] * jb.ld_ext + qq[b] * 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) w[b][u] = x[u];
                 continue;
             }
-            const int aw = abs_finite(w);
-            mx = aw > mx ? aw : mx;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long j = qq[b] * 4 + u;
+                w[b][u] = (ii[b] >= 0 && ii[b] < n && j < n) ? W[ii[b] * jb.ld_ext + j] : (T)0;
+            }
         }
-        D[i * g.ld + j] = w;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            if (ii[b] < 0) continue;
+            const long i = ii[b];
+            v4<uint32_t> out;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long j = qq[b] * 4 + u;
+                uint32_t bits = absent;
+                if (i < n && j < n) {
+                    T x = w[b][u];
+                    if (i == j && x > (T)0) x = (T)0;
+                    if constexpr (std::is_same_v<T, int32_t>) {
+                        if (as_float) {
+                            bits = __float_as_uint(Conv<int32_t, float, BTAS_MIN_PLUS>::in(x));
+                        } else {
+                            bits = (uint32_t)x;
+                            const int aw = abs_finite(x);
+                            mx = aw > mx ? aw : mx;
+                        }
+                    } else {
+                        bits = __float_as_uint(x);
+                    }
+                }
+                out[u] = bits;
+            }
+            *reinterpret_cast<v4<uint32_t>*>(D + i * g.ld + qq[b] * 4) = out;
+        }
     }
     if constexpr (std::is_same_v<T, int32_t>) {
         if (maxabs != nullptr && !float_storage) block_max_to(maxabs + jb.graph, mx);
@@ -290,24 +353,51 @@ __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __r
 // binary32 are converted back to int32 (exact integers, +inf -> INF).
 __global__ __launch_bounds__(256) void grouped_copy_out_kernel(const BatchGraph* __restrict__ graphs,
                                                                 const BatchCopy* __restrict__ jobs,
-                                                                int njobs,
+                                                                int njobs, const int* __restrict__ block_job,
                                                                 const int* __restrict__ float_maxabs) {
-    const BatchCopy jb = jobs[find_job(jobs, njobs, blockIdx.x)];
+    const BatchCopy jb = jobs[block_job != nullptr ? block_job[blockIdx.x] : find_job(jobs, njobs, blockIdx.x)];
     const BatchGraph g = graphs[jb.graph];
     const int n = g.n;
     const uint32_t* S = (const uint32_t*)g.buf[(g.parity + g.T) & 1];
     uint32_t* D = (uint32_t*)const_cast<void*>(jb.ext);
-    const long total = (long)n * n;
+    const int nq = (n + 3) / 4;
+    const long total = (long)n * nq;
     const long stride = (long)jb.nblocks * blockDim.x;
     const bool from_float =
         float_maxabs != nullptr && graph_is_narrow<int32_t>(g, float_maxabs, jb.graph);
-    for (long e = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e < total;
-         e += stride) {
-        long i, j;
-        flat_to_rc(e, n, total, i, j);
-        const uint32_t x = S[i * g.ld + j];
-        D[i * jb.ld_ext + j] =
-            from_float ? (uint32_t)Conv<int32_t, float, BTAS_MIN_PLUS>::out(__uint_as_float(x)) : x;
+    const bool vec = jb.ld_ext % 4 == 0 && (uintptr_t)D % 16 == 0;
+    for (long e0 = (long)(blockIdx.x - jb.first_block) * blockDim.x + threadIdx.x; e0 < total;
+         e0 += QB * stride) {
+        v4<uint32_t> x[QB];
+        long ii[QB], qq[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const long e = e0 + b * stride;
+            ii[b] = -1;
+            if (e < total) {
+                flat_to_rc(e, nq, total, ii[b], qq[b]);
+                x[b] = *reinterpret_cast<const v4<uint32_t>*>(S + ii[b] * g.ld + qq[b] * 4);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            if (ii[b] < 0) continue;
+            uint32_t* row = D + ii[b] * jb.ld_ext;
+            v4<uint32_t> y;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                y[u] = from_float ? (uint32_t)Conv<int32_t, float, BTAS_MIN_PLUS>::out(__uint_as_float(x[b][u]))
+                                  : x[b][u];
+            if (vec && qq[b] * 4 + 3 < n) {
+                *reinterpret_cast<v4<uint32_t>*>(row + qq[b] * 4) = y;
+                continue;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long j = qq[b] * 4 + u;
+                if (j < n) row[j] = y[u];
+            }
+        }
     }
 }
 
@@ -383,30 +473,32 @@ hipError_t launch_clear_ints(int* p, int count, hipStream_t s) {
 }
 
 hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                                 int total_blocks, int* maxabs, hipStream_t s) {
+                                 int total_blocks, int* maxabs, hipStream_t s, const int* block_job) {
     if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(grouped_maxabs_kernel, dim3(total_blocks), dim3(256), 0, s, graphs, jobs,
-                       njobs, maxabs);
+                       njobs, block_job, maxabs);
     return hipGetLastError();
 }
 
 hipError_t launch_grouped_init(int dt, const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                               int total_blocks, int* maxabs, hipStream_t s, bool float_storage) {
+                               int total_blocks, int* maxabs, hipStream_t s, bool float_storage,
+                               const int* block_job) {
     if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL(grouped_init_kernel<float>, dim3(total_blocks), dim3(256), 0, s, graphs,
-                           jobs, njobs, nullptr, 0);
+                           jobs, njobs, block_job, nullptr, 0);
     else
         hipLaunchKernelGGL(grouped_init_kernel<int32_t>, dim3(total_blocks), dim3(256), 0, s,
-                           graphs, jobs, njobs, maxabs, float_storage ? 1 : 0);
+                           graphs, jobs, njobs, block_job, maxabs, float_storage ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_grouped_copy_out(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,
-                                   int total_blocks, hipStream_t s, const int* float_maxabs) {
+                                   int total_blocks, hipStream_t s, const int* float_maxabs,
+                                   const int* block_job) {
     if (njobs <= 0 || total_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(grouped_copy_out_kernel, dim3(total_blocks), dim3(256), 0, s, graphs, jobs,
-                       njobs, float_maxabs);
+                       njobs, block_job, float_maxabs);
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct BatchPlan {
     BatchCopy* d_init = nullptr;
     BatchCopy* d_out = nullptr;
     int* d_maxabs = nullptr;
+    int* d_block_job = nullptr;           // copy-pass workgroup -> graph job
     int init_blocks = 0, njobs = 0;
     std::vector<int> step_off, step_cnt;  // launch t (1-based) covers [off, off+cnt)
     hipGraph_t graph = nullptr;
@@ -52,7 +53,7 @@ void destroy_batch_plan(BatchPlan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     for (void* q : {(void*)p->d_graphs, (void*)p->d_items, (void*)p->d_init, (void*)p->d_out,
-                    (void*)p->d_maxabs, p->ws})
+                    (void*)p->d_maxabs, (void*)p->d_block_job, p->ws})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -349,6 +350,11 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         }
         p->init_blocks = blocks;
         p->njobs = ng;
+        std::vector<int> block_job(std::max(blocks, 1));
+        for (int g = 0; g < ng; ++g)
+            for (int b = 0; b < init[g].nblocks; ++b) block_job[init[g].first_block + b] = g;
+        st = upload(h, fn, (void**)&p->d_block_job, block_job.data(), sizeof(int) * block_job.size());
+        if (st != BTAS_OK) return st;
         st = upload(h, fn, (void**)&p->d_init, init.data(), sizeof(BatchCopy) * ng);
         if (st == BTAS_OK) st = upload(h, fn, (void**)&p->d_out, out.data(), sizeof(BatchCopy) * ng);
         if (st != BTAS_OK) return st;
@@ -362,16 +368,17 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         const bool i32 = dt == BTAS_INT32;
         if (i32) e = launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
         if (e == hipSuccess && i32)
-            e = launch_grouped_maxabs(p->d_graphs, p->d_init, ng, blocks, p->d_maxabs, h->aux_stream);
+            e = launch_grouped_maxabs(p->d_graphs, p->d_init, ng, blocks, p->d_maxabs, h->aux_stream,
+                                      p->d_block_job);
         if (e == hipSuccess)
             e = launch_grouped_init(dt, p->d_graphs, p->d_init, ng, blocks, i32 ? p->d_maxabs : nullptr,
-                                    h->aux_stream, i32);
+                                    h->aux_stream, i32, p->d_block_job);
         for (int t = 0; t < Tmax && e == hipSuccess; ++t)
             e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
                                     i32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream, p->family, i32);
         if (e == hipSuccess)
             e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream,
-                                        i32 ? p->d_maxabs : nullptr);
+                                        i32 ? p->d_maxabs : nullptr, p->d_block_job);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {

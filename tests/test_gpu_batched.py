@@ -109,6 +109,34 @@ def test_batched_int32_storage_modes(dev, tile, monkeypatch):
     h.close()
 
 
+def test_batched_padded_views(dev):
+    """W and D given as views with padded leading dimensions (16-byte rows):
+    the copy passes take their vector path with ragged last quads, and
+    nothing outside the n x n views is written."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws, tW, tD, bigD = [], [], [], []
+    for i, n in enumerate((37, 64, 130, 255)):
+        W = wl.er_digraph_i32(n, min(1.0, 6.0 / n), 1, 500, seed=900 + i)
+        ld = (n + 3) // 4 * 4 + 4
+        bw = torch.full((n, ld), -7, dtype=torch.int32, device=dev)
+        bw[:, :n] = torch.from_numpy(W).to(dev)
+        bd = torch.full((n + 1, ld), -9, dtype=torch.int32, device=dev)
+        Ws.append(W)
+        tW.append(bw[:, :n])
+        tD.append(bd[:n, :n])
+        bigD.append(bd)
+    btas.apsp_batched(tW, tD)
+    torch.cuda.synchronize()
+    for W, bd in zip(Ws, bigD):
+        n = W.shape[0]
+        want, _, _ = oracle.apsp(W)
+        got = bd.cpu().numpy()
+        assert np.array_equal(got[:n, :n], want), f"n={n}"
+        assert (got[:, n:] == -9).all() and (got[n, :] == -9).all(), f"n={n}: wrote outside D"
+
+
 def test_batched_in_place_and_errors(dev):
     import torch
 
