@@ -19,6 +19,11 @@
 
 namespace btas {
 
+// One-wave 64x64 tile (8x8 per lane, 8-deep k-blocks) of the direct-load step
+// kernel: operands go straight into LDS, so no staging registers; 8 KB of LDS
+// per workgroup.
+using CfgWD = GemmCfg<64, 64, 8, 8, 8>;
+
 // int32 graphs whose finite weights satisfy 2^T * max|w| <= FP32_EXACT_MAX
 // keep every finite distance of every step inside the binary32-exact range
 // (a step's entries are sums of at most 2^t weights), so their squarings run

@@ -65,9 +65,6 @@ using CfgS = GemmCfg<32, 32, 16, 4, 4>;    // small / latency-bound: 64 threads
 // three waves per SIMD); its double-buffered LDS (10.5 KB) lets LDS hold as
 // many of these workgroups as the register file does.
 using CfgW = GemmCfg<64, 64, 8, 8, 8>;
-// The same one-wave 64x64 tile for GemmTileDirect (operands loaded straight
-// into LDS, so no staging registers; 8 KB of LDS per workgroup).
-using CfgWD = GemmCfg<64, 64, 8, 8, 8>;
 
 // Element conversion between storage and compute types.
 template <typename T, typename CT, int SR>

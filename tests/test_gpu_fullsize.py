@@ -76,3 +76,34 @@ def test_apsp_16384_f32_properties(dev):
         Dn = D.cpu().numpy()
         again = oracle.gemm("min", Dn[sources], Dn, Dn[sources])
         assert np.array_equal(_bits(again), _bits(Dn[sources]))
+
+
+@pytest.mark.parametrize("dt", ["f32", "i32"])
+def test_gemm_output_beyond_2_31_elements(dev, dt):
+    """An output of 46 341 x 46 341 > 2^31 elements (8.6 GB): element offsets
+    and tile indices need 64-bit arithmetic.  k = 16 keeps the product short;
+    sampled rows at both ends and columns near the last tile are checked
+    against the oracle."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    n, k = 46341, 16
+    A = wl.gemm_operand((n, k), dt, "min", seed=11)
+    B = wl.gemm_operand((k, n), dt, "min", seed=12)
+    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    absent = float("inf") if dt == "f32" else wl.I32_INF
+    tC = torch.full((n, n), absent, dtype=tA.dtype, device=dev)
+    btas.tropical_gemm(tA, tB, tC, semiring="min")
+    rows = [0, 1, 23170, n - 2, n - 1]
+    got = tC[rows].cpu().numpy()
+    C0 = wl.semiring_identity_matrix((len(rows), n), dt, "min")
+    want = oracle.gemm("min", A[rows], B, C0)
+    for i, r in enumerate(rows):
+        assert np.array_equal(_bits(got[i]), _bits(want[i])), f"row {r}"
+    cols = [0, n - 1]
+    gotc = tC[:, cols].cpu().numpy()
+    Cc = wl.semiring_identity_matrix((n, len(cols)), dt, "min")
+    wantc = oracle.gemm("min", A, np.ascontiguousarray(B[:, cols]), Cc)
+    assert np.array_equal(_bits(gotc), _bits(wantc))
+    del tC
+    torch.cuda.empty_cache()
