@@ -160,32 +160,67 @@ __global__ __launch_bounds__(256) void tropical_axpy_kernel(long n, T alpha, con
         y[i * incy] = R::add(y[i * incy], R::finish(R::mul(alpha, x[i * incx])));
 }
 
+// Unit strides, 16-byte aligned: 128-bit accesses, two vectors per thread and
+// iteration; the n % 4 tail elements go to workgroup 0.
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void tropical_axpy_v4_kernel(long n, T alpha, const T* x, T* y) {
+    using R = Ring<SR, T>;
+    const long nv = n / 4, stride = (long)gridDim.x * blockDim.x;
+    const v4<T>* x4 = reinterpret_cast<const v4<T>*>(x);
+    v4<T>* y4 = reinterpret_cast<v4<T>*>(y);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += 2 * stride) {
+        const bool two = i + stride < nv;
+        const v4<T> a = __builtin_nontemporal_load(x4 + i), b = y4[i];
+        v4<T> c, d;
+        if (two) {
+            c = __builtin_nontemporal_load(x4 + i + stride);
+            d = y4[i + stride];
+        }
+        v4<T> r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = R::add(b[e], R::finish(R::mul(alpha, a[e])));
+        __builtin_nontemporal_store(r, y4 + i);
+        if (two) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) r[e] = R::add(d[e], R::finish(R::mul(alpha, c[e])));
+            __builtin_nontemporal_store(r, y4 + i + stride);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * 4) {
+        const long i = nv * 4 + threadIdx.x;
+        y[i] = R::add(y[i], R::finish(R::mul(alpha, x[i])));
+    }
+}
+
+template <typename T, int SR>
+static void axpy_typed(long n, T alpha, const void* x, long incx, void* y, long incy,
+                       hipStream_t s) {
+    const bool vec = incx == 1 && incy == 1 && (((uintptr_t)x | (uintptr_t)y) % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL((tropical_axpy_v4_kernel<T, SR>), dim3(grid_for((n + 3) / 4, 8)),
+                           dim3(256), 0, s, n, alpha, (const T*)x, (T*)y);
+    else
+        hipLaunchKernelGGL((tropical_axpy_kernel<T, SR>), dim3(grid_for(n, 4)), dim3(256), 0, s, n,
+                           alpha, (const T*)x, incx, (T*)y, incy);
+}
+
 hipError_t launch_axpy(int sr, int dt, int n, uint32_t alpha_bits, const void* x, long incx,
                        void* y, long incy, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    dim3 g(grid_for(n, 4)), b(256);
     if (dt == BTAS_FLOAT32) {
         const float a = __builtin_bit_cast(float, alpha_bits);
-        if (sr == BTAS_MIN_PLUS)
-            hipLaunchKernelGGL((tropical_axpy_kernel<float, 0>), g, b, 0, s, (long)n, a,
-                               (const float*)x, incx, (float*)y, incy);
-        else
-            hipLaunchKernelGGL((tropical_axpy_kernel<float, 1>), g, b, 0, s, (long)n, a,
-                               (const float*)x, incx, (float*)y, incy);
+        if (sr == BTAS_MIN_PLUS) axpy_typed<float, 0>(n, a, x, incx, y, incy, s);
+        else axpy_typed<float, 1>(n, a, x, incx, y, incy, s);
     } else {
         const int32_t a = (int32_t)alpha_bits;
-        if (sr == BTAS_MIN_PLUS)
-            hipLaunchKernelGGL((tropical_axpy_kernel<int32_t, 0>), g, b, 0, s, (long)n, a,
-                               (const int32_t*)x, incx, (int32_t*)y, incy);
-        else
-            hipLaunchKernelGGL((tropical_axpy_kernel<int32_t, 1>), g, b, 0, s, (long)n, a,
-                               (const int32_t*)x, incx, (int32_t*)y, incy);
+        if (sr == BTAS_MIN_PLUS) axpy_typed<int32_t, 0>(n, a, x, incx, y, incy, s);
+        else axpy_typed<int32_t, 1>(n, a, x, incx, y, incy, s);
     }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- dot ---
-static constexpr int DOT_MAX_BLOCKS = 1024;
+static constexpr int DOT_MAX_BLOCKS = 2048;
 
 int dot_partials_needed(int /*n*/) { return DOT_MAX_BLOCKS; }
 
@@ -200,6 +235,39 @@ __global__ __launch_bounds__(256) void tropical_dot_partial_kernel(long n, const
          i += (long)gridDim.x * blockDim.x)
         acc = R::add(acc, R::mul(x[i * incx], y[i * incy]));
     acc = wave_reduce<T, SR>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = R::add(R::add(red[0], red[1]), R::add(red[2], red[3]));
+}
+
+// Unit strides, 16-byte aligned: 128-bit non-temporal loads, two per vector
+// and iteration in flight (two independent accumulators); the n % 4 tail
+// elements go to workgroup 0.
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void tropical_dot_partial_v4_kernel(long n, const T* x,
+                                                                       const T* y, T* partials) {
+    using R = Ring<SR, T>;
+    __shared__ T red[4];
+    const long nv = n / 4;
+    const v4<T>* x4 = reinterpret_cast<const v4<T>*>(x);
+    const v4<T>* y4 = reinterpret_cast<const v4<T>*>(y);
+    const long stride = (long)gridDim.x * blockDim.x;
+    T acc0 = R::absent(), acc1 = R::absent();
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += 2 * stride) {
+        const v4<T> a = __builtin_nontemporal_load(x4 + i), b = __builtin_nontemporal_load(y4 + i);
+        if (i + stride < nv) {
+            const v4<T> c = __builtin_nontemporal_load(x4 + i + stride);
+            const v4<T> d = __builtin_nontemporal_load(y4 + i + stride);
+            acc1 = R::add3(acc1, R::mul(c[0], d[0]), R::mul(c[1], d[1]));
+            acc1 = R::add3(acc1, R::mul(c[2], d[2]), R::mul(c[3], d[3]));
+        }
+        acc0 = R::add3(acc0, R::mul(a[0], b[0]), R::mul(a[1], b[1]));
+        acc0 = R::add3(acc0, R::mul(a[2], b[2]), R::mul(a[3], b[3]));
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - nv * 4)
+        acc0 = R::add(acc0, R::mul(x[nv * 4 + threadIdx.x], y[nv * 4 + threadIdx.x]));
+    T acc = wave_reduce<T, SR>(R::add(acc0, acc1));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0)
@@ -225,10 +293,15 @@ static hipError_t dot_typed(int n, const void* x, long incx, const void* y, long
                             void* partials, void* result, hipStream_t s) {
     int blocks = 0;
     if (n > 0) {
-        blocks = (int)grid_for(n, 8);
+        const bool vec = incx == 1 && incy == 1 && (((uintptr_t)x | (uintptr_t)y) % 16 == 0);
+        blocks = (int)grid_for(vec ? (n + 3) / 4 : n, 8);
         if (blocks > DOT_MAX_BLOCKS) blocks = DOT_MAX_BLOCKS;
-        hipLaunchKernelGGL((tropical_dot_partial_kernel<T, SR>), dim3(blocks), dim3(256), 0, s,
-                           (long)n, (const T*)x, incx, (const T*)y, incy, (T*)partials);
+        if (vec)
+            hipLaunchKernelGGL((tropical_dot_partial_v4_kernel<T, SR>), dim3(blocks), dim3(256), 0, s,
+                               (long)n, (const T*)x, (const T*)y, (T*)partials);
+        else
+            hipLaunchKernelGGL((tropical_dot_partial_kernel<T, SR>), dim3(blocks), dim3(256), 0, s,
+                               (long)n, (const T*)x, incx, (const T*)y, incy, (T*)partials);
     }
     hipLaunchKernelGGL((tropical_dot_final_kernel<T, SR>), dim3(1), dim3(256), 0, s, blocks,
                        (const T*)partials, (T*)result);

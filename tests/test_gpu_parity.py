@@ -253,6 +253,22 @@ def test_level1(btas, dev, sr, dt, n):
         z = torch.empty(n // 2, dtype=tx.dtype, device=dev)
         btas.vmul(tx[::2][: n // 2], ty[1::2][: n // 2], z, semiring=sr)
         assert_same(to_np(z), oracle.vmul(sr, x[::2][: n // 2].copy(), y[1::2][: n // 2].copy()), "vmul strided")
+        ty3 = to_dev(y, dev)
+        m3 = n // 2
+        btas.axpy(alpha, tx[::2][:m3], ty3[1::2][:m3], semiring=sr)
+        want3 = y.copy()
+        want3[1::2][:m3] = oracle.axpy(sr, alpha, x[::2][:m3].copy(), y[1::2][:m3].copy())
+        assert_same(to_np(ty3), want3, "axpy strided")
+        ds = to_np(btas.dot(tx[::2], ty[::2], semiring=sr))[0]
+        assert_same(np.array([ds]), np.array([oracle.dot(sr, x[::2].copy(), y[::2].copy())], dtype=x.dtype),
+                    "dot strided")
+        # the winning term in the tail (n % 4 elements) and in the second vector
+        # of an unrolled iteration
+        for pos in (n - 1, n // 2 + 1):
+            xp = x.copy()
+            xp[pos] = (-1 if sr == "min" else 1) * (2**28 if dt == "i32" else 1e30)
+            dp = to_np(btas.dot(to_dev(xp, dev), ty, semiring=sr))[0]
+            assert_same(np.array([dp]), np.array([oracle.dot(sr, xp, y)], dtype=x.dtype), f"dot pos={pos}")
 
 
 # ----------------------------------------------------------------- APSP ---
