@@ -471,3 +471,105 @@ int or_fw_f64(long n, const double *W, long ldw, double *D, long ldd) {
         }
     return OR_OK;
 }
+
+/* ============ Blocked (three-phase) Floyd-Warshall ======================
+ * The same relaxations as Algorithm 2 -- d(x,y) <- d(x,y) (+) d(x,z) (.) d(z,y)
+ * for every pivot z -- grouped by pivot blocks of B consecutive vertices, the
+ * order a tiled GPU implementation follows.  For pivot block K:
+ *   1. the diagonal block (K,K), pivots of K in ascending order;
+ *   2. every other block of block-row K and of block-column K, pivots of K in
+ *      ascending order, reading the finished diagonal block;
+ *   3. every block (I,J) with I != K and J != K:
+ *        d(x,y) <- d(x,y) (+) (+)_{z in K} d(x,z) (.) d(z,y),
+ *      reading blocks (I,K) and (K,J), which this phase does not change.
+ * In exact arithmetic every order gives the shortest distances.  In binary32
+ * the operands of a relaxation depend on the order, so the result is defined
+ * by this order and by B (B >= n is sequential Floyd-Warshall; B = 1 as well).
+ * int32: exact integers carried in int64, absent = +INF absorbing.  fp32: each
+ * relaxation rounds the sum of two binary32 values to binary32 (computed in
+ * binary64 and rounded once, which is the same number) and keeps the smaller.
+ */
+static void fwb_relax_i64(int64_t *d, long n, long x, long y, long z) {
+    int64_t a = d[x * n + z], b = d[z * n + y];
+    if (a == OR_INF64 || b == OR_INF64) return;
+    if (a + b < d[x * n + y]) d[x * n + y] = a + b;
+}
+
+static void fwb_relax_f32(float *d, long n, long x, long y, long z) {
+    float s = (float)((double)d[x * n + z] + (double)d[z * n + y]);
+    if (s < d[x * n + y]) d[x * n + y] = s;
+}
+
+/* Runs the three phases with relax(d, n, x, y, z) over an n x n matrix. */
+#define OR_FW_BLOCKED(RELAX)                                                     \
+    do {                                                                         \
+        long nb = (n + B - 1) / B;                                               \
+        for (long K = 0; K < nb; ++K) {                                          \
+            long k0 = K * B, k1 = k0 + B < n ? k0 + B : n;                       \
+            for (long z = k0; z < k1; ++z) /* phase 1 */                         \
+                for (long x = k0; x < k1; ++x)                                   \
+                    for (long y = k0; y < k1; ++y) RELAX(d, n, x, y, z);         \
+            for (long J = 0; J < nb; ++J) { /* phase 2: block-row K */           \
+                if (J == K) continue;                                            \
+                long j0 = J * B, j1 = j0 + B < n ? j0 + B : n;                   \
+                for (long z = k0; z < k1; ++z)                                   \
+                    for (long x = k0; x < k1; ++x)                               \
+                        for (long y = j0; y < j1; ++y) RELAX(d, n, x, y, z);     \
+            }                                                                    \
+            for (long I = 0; I < nb; ++I) { /* phase 2: block-column K */        \
+                if (I == K) continue;                                            \
+                long i0 = I * B, i1 = i0 + B < n ? i0 + B : n;                   \
+                for (long z = k0; z < k1; ++z)                                   \
+                    for (long x = i0; x < i1; ++x)                               \
+                        for (long y = k0; y < k1; ++y) RELAX(d, n, x, y, z);     \
+            }                                                                    \
+            for (long I = 0; I < nb; ++I) { /* phase 3 */                        \
+                if (I == K) continue;                                            \
+                long i0 = I * B, i1 = i0 + B < n ? i0 + B : n;                   \
+                for (long J = 0; J < nb; ++J) {                                  \
+                    if (J == K) continue;                                        \
+                    long j0 = J * B, j1 = j0 + B < n ? j0 + B : n;               \
+                    for (long z = k0; z < k1; ++z)                               \
+                        for (long x = i0; x < i1; ++x)                           \
+                            for (long y = j0; y < j1; ++y) RELAX(d, n, x, y, z); \
+                }                                                                \
+            }                                                                    \
+        }                                                                        \
+    } while (0)
+
+int or_fw_blocked_i32(long n, const int32_t *W, long ldw, int32_t *D, long ldd, long B) {
+    if (n < 0 || B < 1 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (!scan_i32(OR_MIN_PLUS, n, n, W, ldw)) return OR_EDOMAIN;
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n * n : 1));
+    if (!d) return OR_EARG;
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) d[i * n + j] = i32_lift(OR_MIN_PLUS, W[i * ldw + j]);
+    for (long i = 0; i < n; ++i)
+        if (d[i * n + i] > 0) d[i * n + i] = 0;
+    OR_FW_BLOCKED(fwb_relax_i64);
+    int status = OR_OK;
+    for (long i = 0; i < n && status == OR_OK; ++i)
+        for (long j = 0; j < n; ++j)
+            if (i64_store(OR_MIN_PLUS, d[i * n + j], &D[i * ldd + j]) != OR_OK) {
+                status = OR_EDOMAIN;
+                break;
+            }
+    free(d);
+    return status;
+}
+
+int or_fw_blocked_f32(long n, const float *W, long ldw, float *D, long ldd, long B) {
+    if (n < 0 || B < 1 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (!scan_f32(OR_MIN_PLUS, n, n, W, ldw)) return OR_EDOMAIN;
+    float *d = (float *)malloc(sizeof(float) * (n > 0 ? n * n : 1));
+    if (!d) return OR_EARG;
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) d[i * n + j] = W[i * ldw + j];
+    for (long i = 0; i < n; ++i)
+        if (d[i * n + i] > 0.0f) d[i * n + i] = 0.0f;
+    OR_FW_BLOCKED(fwb_relax_f32);
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) D[i * ldd + j] = d[i * n + j];
+    free(d);
+    return OR_OK;
+}

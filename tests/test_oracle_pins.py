@@ -484,3 +484,81 @@ def test_hand_worked_example():
     Wf = np.where(W == INF32, np.inf, W).astype(np.float32)
     Df, _, _ = oracle.apsp(Wf)
     assert np.array_equal(Df, Dw.astype(np.float32))
+
+
+# ------------------------------------------------ blocked Floyd-Warshall ---
+
+def _fw_f32_numpy(W):
+    """Sequential Floyd-Warshall in binary32 with numpy: for each pivot z,
+    D <- min(D, D[:, z] + D[z, :]) with float32 adds (a vectorised statement,
+    independent of the oracle's loops)."""
+    D = W.astype(np.float32).copy()
+    np.fill_diagonal(D, np.minimum(np.diag(D), np.float32(0)))
+    for z in range(D.shape[0]):
+        S = D[:, z:z + 1] + D[z:z + 1, :]
+        assert S.dtype == np.float32
+        D = np.minimum(D, S)
+    return D
+
+
+@pytest.mark.parametrize("block", [1, 2, 3, 16, 64, 100, 500])
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 65, 130, 200])
+def test_fw_blocked_i32_equals_fw_and_squaring(n, block):
+    """Exact integers: every order of the relaxations gives the shortest
+    distances, so the blocked order equals sequential Floyd-Warshall and
+    repeated squaring, for every block size."""
+    W = wl.er_digraph_i32(n, min(1.0, 4.0 / n), 0, 100, seed=n + block)
+    Db = oracle.floyd_warshall_blocked(W, block)
+    assert np.array_equal(Db, oracle.floyd_warshall(W))
+    Dsq, _, _ = oracle.apsp(W)
+    assert np.array_equal(Db, Dsq)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fw_blocked_tiny_bruteforce(seed):
+    g = np.random.default_rng(50 + seed)
+    n = int(g.integers(1, 8))
+    W = wl.er_digraph_i32(n, 0.4, 0, 9, seed=300 + seed)
+    for block in (1, 2, 3, 8):
+        assert oracle.floyd_warshall_blocked(W, block).tolist() == oracle.brute_force_apsp(W.tolist(), INF32)
+
+
+@pytest.mark.parametrize("n", [5, 64, 97])
+def test_fw_blocked_f32_degenerate_blocks_are_sequential_fw(n):
+    """With one pivot per block (B = 1) or a single block (B >= n) the blocked
+    order is the sequential order, so the result equals a numpy binary32
+    Floyd-Warshall bit for bit, for general (non-integer) weights."""
+    r, c, w = wl.sparse_digraph_f32_exp(n, 5.0, seed=n)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    want = _fw_f32_numpy(W)
+    for block in (1, n, n + 7):
+        got = oracle.floyd_warshall_blocked(W, block)
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), f"block={block}"
+
+
+def test_fw_blocked_f32_integer_weights_exact():
+    n = 150
+    Wi = wl.er_digraph_i32(n, 0.05, 1, 1000, seed=21)
+    Wf = np.where(Wi == INF32, np.inf, Wi).astype(np.float32)
+    for block in (16, 64):
+        Db = oracle.floyd_warshall_blocked(Wf, block)
+        assert np.array_equal(Db.astype(np.float64), oracle.floyd_warshall(Wf))
+
+
+def test_fw_blocked_f32_rounding_bound_vs_dijkstra():
+    """Floyd-Warshall builds a path of h edges with at most h-1 rounded adds of
+    non-negative values, so (1-u)^(n-1) d* <= d32 <= (1+u)^(n-1) d*."""
+    n = 300
+    r, c, w = wl.sparse_digraph_f32_exp(n, 6.0, seed=8)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    D = oracle.floyd_warshall_blocked(W, 64).astype(np.float64)
+    exact = _dijkstra(W)
+    fin = np.isfinite(exact)
+    assert np.array_equal(fin, np.isfinite(D))
+    u = 2.0 ** -24
+    assert np.all(D[fin] <= exact[fin] * (1 + u) ** (n - 1) + 1e-300)
+    assert np.all(D[fin] >= exact[fin] * (1 - u) ** (n - 1) - 1e-300)
+    # and it is a different association from squaring in general: both are
+    # within the bound, and they agree on the reachability pattern
+    Dsq, _, _ = oracle.apsp(W)
+    assert np.array_equal(np.isfinite(Dsq), fin)
