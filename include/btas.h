@@ -212,6 +212,24 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
                                          const int *n, const void *const *W, const int *ldw,
                                          void *const *D, const int *ldd, unsigned flags);
 
+/* All-pairs shortest paths by blocked Floyd-Warshall: the relaxations of the
+ * paper's sequential algorithm (Sec. IV, Algorithm 2), d(x,y) <- d(x,y) (+)
+ * d(x,z) (.) d(z,y) for every pivot z, grouped into pivot blocks of 64
+ * vertices (diagonal block, then its block-row and block-column, then every
+ * other block as a tropical product with k = 64).  O(n^3) work instead of
+ * the O(n^3 log n) of repeated squaring.  D (leading dimension ldd) receives
+ * the result of I (+) W (the same reading of the diagonal as
+ * btas_apsp_squaring); W == D (same ld) runs in place, any other overlap is
+ * BTAS_ERR_ALIAS.  No workspace.  int32 results are the exact distances (equal
+ * to btas_apsp_squaring's); binary32 results are those of this relaxation
+ * order and block size (one rounding per relaxation), within the rounding
+ * bound of the exact distances, and may differ from squaring's in the last
+ * bits.  Graphs must have no negative cycle (checked with flags =
+ * BTAS_APSP_CHECK_NEG_CYCLE, which synchronises); flags may be 0 or that.
+ * Asynchronous otherwise. */
+btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, const void *W,
+                                       int ldw, void *D, int ldd, unsigned flags);
+
 /* Describe the handle's current batched plan: number of kernel launches in
  * its graph and the algorithmic work, sum_i T(n_i) * n_i^3 terms (host
  * outputs, either may be NULL).  INVALID_ARG if no plan exists. */

@@ -89,6 +89,7 @@ def lib():
         L.btas_apsp_squaring_batched.argtypes = [P, I, I, IP, PP, IP, PP, IP, U]
         L.btas_batched_plan_info.argtypes = [P, IP, ctypes.POINTER(ctypes.c_double)]
         L.btas_batched_tile_choice.argtypes = [P, I, I]
+        L.btas_apsp_floyd_warshall.argtypes = [P, I, I, P, I, P, I, U]
         L.btas_server_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.c_size_t, I, ctypes.c_double]
         L.btas_server_destroy.argtypes = [P]
         L.btas_server_now.argtypes = [P]
@@ -333,6 +334,24 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     st = h.check(lib().btas_apsp_squaring(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
                  allow=(OK, WARN_NEG_CYCLE))
     return out, (steps.value if sp is not None else None), st
+
+
+def floyd_warshall(W, out=None, check_neg_cycle=False, handle=None):
+    """All-pairs shortest paths of I (+) W by blocked Floyd-Warshall (pivot
+    blocks of 64 vertices).  Returns (D, status); ``out`` may be W itself."""
+    import torch
+    n = W.size(0)
+    if W.shape != (n, n):
+        raise ValueError("W must be square")
+    if out is None:
+        out = torch.empty_like(W)
+    h = _handle_for(W, handle)
+    pw, ldw = _mat(W, "W")
+    pd, ldd = _mat(out, "D")
+    st = h.check(lib().btas_apsp_floyd_warshall(h.ptr, _dt(W), n, pw, ldw, pd, ldd,
+                                                APSP_CHECK_NEG_CYCLE if check_neg_cycle else 0),
+                 allow=(OK, WARN_NEG_CYCLE))
+    return out, st
 
 
 class BatchedAPSP:

@@ -22,8 +22,8 @@ LIB = os.path.join(PKG, "libbtas.so")
 INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"
 
-SOURCES = ["gemm.hip", "level12.hip", "aux.hip", "batched.hip", "resident.hip", "api.cpp", "batched_api.cpp",
-           "server.cpp"]
+SOURCES = ["gemm.hip", "level12.hip", "aux.hip", "batched.hip", "resident.hip", "floyd.hip", "api.cpp",
+           "batched_api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -512,4 +512,45 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     return result;
 }
 
+// ------------------------------------------------------ Floyd-Warshall ---
+btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, const void* W,
+                                       int ldw, void* D, int ldd, unsigned flags) {
+    const char* fn = "btas_apsp_floyd_warshall";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
+    if (ldw < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (ldw=%d) < max(1,n=%d)", fn, ldw, n);
+    if (ldd < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (ldd=%d) < max(1,n=%d)", fn, ldd, n);
+    if (flags & ~BTAS_APSP_CHECK_NEG_CYCLE)
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (flags=0x%x): only CHECK_NEG_CYCLE", fn, flags);
+    if (n > 0 && (!W || !D)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W or D is null", fn);
+    const bool in_place = W == D && ldw == ldd;
+    if (!in_place && overlap(mat_span(W, n, n, ldw), mat_span(D, n, n, ldd)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: D partially overlaps W", fn);
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    {
+        const void* ps[1] = {W};
+        const long rows[1] = {n}, cols[1] = {n}, lds[1] = {ldw};
+        btas_status_t st = validate_operands(h, fn, BTAS_MIN_PLUS, dt, ps, rows, cols, lds, 1);
+        if (st != BTAS_OK) return st;
+    }
+    hipError_t e = btas::launch_apsp_init(dt, n, W, ldw, D, ldd, nullptr, h->stream);
+    if (e == hipSuccess) e = btas::launch_floyd_warshall(dt, n, D, ldd, h->stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    if (flags & BTAS_APSP_CHECK_NEG_CYCLE) {
+        int* flag = h->dflags + FLAG_CHECK;
+        e = btas::launch_clear_flags(flag, 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_neg_diag_check(dt, n, D, ldd, flag, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        btas_status_t st = sync_flags(h, fn, FLAG_CHECK + 1);
+        if (st != BTAS_OK) return st;
+        if (h->hflags[FLAG_CHECK]) return fail(h, BTAS_WARN_NEG_CYCLE, "%s: negative cycle (some D_ii < 0)", fn);
+    }
+    return BTAS_OK;
+}
+
 }  // extern "C"

@@ -100,6 +100,11 @@ size_t resident_lds_bytes(int n);
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
                                 void* ws, int T, bool early, unsigned* bar, int* flags,
                                 int num_cus, int spin_limit, hipStream_t s);
+// Blocked Floyd-Warshall in place on D (n x n, leading dimension ld), which
+// holds I (+) W: pivot blocks of fw_block_size() vertices, three launches per
+// block (diagonal block, its block-row and block-column, the rest).
+int fw_block_size();
+hipError_t launch_floyd_warshall(int dt, int n, void* D, long ld, hipStream_t s);
 // Domain scan (BTAS_VALIDATE=1): flag <- 1 if some element of the m x n matrix
 // is not a legal (.) operand of the semiring.
 hipError_t launch_domain_scan(int sr, int dt, int m, int n, const void* X, long ld, int* flag,

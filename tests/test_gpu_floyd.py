@@ -1,0 +1,127 @@
+"""Blocked Floyd-Warshall on the GPU: bit-exact against the oracle's blocked
+order (pivot blocks of 64), for int32 (then also equal to repeated squaring)
+and binary32, across ragged and full-block sizes, padded leading dimensions,
+in place, and the full n=16384 benchmark graph by sampled exact references."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+BLOCK = 64
+
+
+def _bits(x):
+    x = np.ascontiguousarray(x).copy()
+    if x.dtype == np.float32:
+        x[x == 0] = 0.0
+    return x.view(np.uint32)
+
+
+def _graph(dt, n, seed, deg=4.0):
+    if dt == "i32":
+        return wl.er_digraph_i32(n, min(1.0, deg / max(n, 1)), 1, 1000, seed=seed)
+    r, c, w = wl.sparse_digraph_f32_exp(n, deg, seed=seed)
+    return wl.coo_to_dense_f32(n, r, c, w)
+
+
+def _dev(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65, 127, 128, 200, 256, 257, 320, 513])
+def test_fw_matches_blocked_oracle(dev, dt, n):
+    import paper_1701_04733_amd as btas
+    W = _graph(dt, n, seed=4000 + n)
+    want = oracle.floyd_warshall_blocked(W, BLOCK)
+    D, st = btas.floyd_warshall(_dev(W, dev))
+    assert st == btas.OK
+    assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"{dt} n={n}"
+    if dt == "i32":
+        sq, _, _ = oracle.apsp(W)
+        assert np.array_equal(D.cpu().numpy(), sq)
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+def test_fw_in_place_padded_and_errors(dev, dt):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    for n in (100, 192):                                    # ragged, and full blocks
+        W = _graph(dt, n, seed=77 + n, deg=6.0)
+        want = oracle.floyd_warshall_blocked(W, BLOCK)
+        t = _dev(W, dev)
+        btas.floyd_warshall(t, out=t)
+        assert np.array_equal(_bits(t.cpu().numpy()), _bits(want)), f"in place n={n}"
+        big = torch.full((n, n + 4), 7, dtype=t.dtype, device=dev)
+        big[:, :n] = _dev(W, dev)
+        out = torch.zeros((n + 1, n + 8), dtype=t.dtype, device=dev)
+        btas.floyd_warshall(big[:, :n], out=out[:n, :n])
+        got = out.cpu().numpy()
+        assert np.array_equal(_bits(got[:n, :n]), _bits(want)), f"padded n={n}"
+        assert (got[n, :] == 0).all() and (got[:, n:] == 0).all()
+        assert (big[:, n:] == 7).all()
+    INF = wl.I32_INF
+    Wn = np.array([[0, 1, INF], [-3, 0, INF], [INF, 2, 0]], np.int32)
+    _, st = btas.floyd_warshall(_dev(Wn, dev), check_neg_cycle=True)
+    assert st == btas.WARN_NEG_CYCLE
+    M = torch.zeros((8, 9), dtype=torch.int32, device=dev)
+    with pytest.raises(btas.BtasError, match="ALIAS"):
+        btas.floyd_warshall(M[:, :8], out=M[:, 1:9])
+
+
+def test_fw_f32_larger_vs_oracle(dev):
+    """n = 1024 (16 pivot blocks, the direct-load phase 3) against the oracle."""
+    import paper_1701_04733_amd as btas
+    n = 1024
+    W = _graph("f32", n, seed=11, deg=12.0)
+    want = oracle.floyd_warshall_blocked(W, BLOCK)
+    D, _ = btas.floyd_warshall(_dev(W, dev))
+    assert np.array_equal(_bits(D.cpu().numpy()), _bits(want))
+
+
+def test_fw_16384_f32_sampled_sources(dev):
+    """The n=16384 benchmark graph (mean out-degree 16, exponential(1)
+    weights): the diagonal is 0 and rows from sampled sources equal fp64
+    Dijkstra within the rounding bounds of non-negative sums: at most
+    (1+u)^(h-1) above the exact distance for a shortest path of h edges, at
+    least (1-u)^(n-2) below."""
+    import torch
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra
+
+    import paper_1701_04733_amd as btas
+    n = 16384
+    r, c, w = wl.sparse_digraph_f32_exp(n, 16.0, seed=4)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    D, _ = btas.floyd_warshall(_dev(W, dev))
+    torch.cuda.synchronize()
+    assert torch.all(torch.diagonal(D) == 0)
+    src = list(range(0, n, n // 32))
+    got = D[src].cpu().numpy().astype(np.float64)
+    G = csr_matrix((w.astype(np.float64), (r, c)), shape=(n, n))
+    exact, pred = dijkstra(G, directed=True, indices=src, return_predecessors=True)
+    fin = np.isfinite(exact)
+    assert np.array_equal(fin, np.isfinite(got))
+    # hops h of each shortest path (from the predecessor trees): that path,
+    # summed in any association, is within (1+u)^(h-1) of its exact length,
+    # and the computed distance is at most that sum
+    hops = np.zeros_like(exact)
+    cur = np.tile(np.arange(n), (len(src), 1))
+    rows = np.arange(len(src))[:, None]
+    for _ in range(n):
+        step = pred[rows, cur]
+        live = step >= 0
+        if not live.any():
+            break
+        hops += live
+        cur = np.where(live, step, cur)
+    u = 2.0 ** -24
+    assert np.all(got[fin] <= exact[fin] * (1 + u) ** np.maximum(hops[fin] - 1, 0) + 1e-300)
+    assert np.all(got[fin] >= exact[fin] * (1 - u) ** (n - 1) - 1e-300)
+    del D
+    torch.cuda.empty_cache()
