@@ -62,6 +62,10 @@ def _lib():
         lib.or_fw_f64.argtypes = [L, P, L, P, L]
         lib.or_fw_blocked_i32.argtypes = [L, P, L, P, L, L]
         lib.or_fw_blocked_f32.argtypes = [L, P, L, P, L, L]
+        for name in ("or_gemm_witness_i32", "or_gemm_witness_f32"):
+            getattr(lib, name).argtypes = [I, L, L, L, P, L, P, L, P, L, P, L]
+        for name in ("or_successors_i32", "or_successors_f32"):
+            getattr(lib, name).argtypes = [L, P, L, P, L, P, L]
         lib.or_apsp_steps.argtypes = [L]
         lib.or_num_threads.restype = I
         lib.or_set_num_threads.argtypes = [I]
@@ -128,6 +132,40 @@ def gemm(semiring: str, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarr
     _check(fn(SEMIRINGS[semiring], m, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B),
               _ptr(out), max(1, n)), "gemm")
     return out
+
+
+def gemm_witness(semiring: str, A: np.ndarray, B: np.ndarray, C: np.ndarray,
+                 K: np.ndarray):
+    """Return (C', K') for C' = C (+) A (.) B: where C'_ij strictly improves on
+    C_ij, K'_ij is the smallest p with A_ip (.) B_pj = C'_ij; elsewhere C and K
+    are kept (neither input is modified)."""
+    A, B = _mat(A), _mat(B)
+    if A.dtype != B.dtype or A.dtype != C.dtype:
+        raise TypeError("dtype mismatch")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or C.shape != (m, n) or K.shape != (m, n):
+        raise ValueError("shape mismatch")
+    out = np.array(C, dtype=C.dtype, order="C", copy=True)
+    kout = np.array(K, dtype=np.int32, order="C", copy=True)
+    fn = getattr(_lib(), "or_gemm_witness_" + _sfx(A.dtype))
+    _check(fn(SEMIRINGS[semiring], m, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B),
+              _ptr(out), max(1, n), _ptr(kout), max(1, n)), "gemm_witness")
+    return out, kout
+
+
+def successors(W: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Successor matrix: S_ii = i; for i != j the smallest u != i minimising
+    W_iu (.) D_uj (min-plus), -1 if every such term is absent."""
+    W, D = _mat(W), _mat(D)
+    n = W.shape[0]
+    if W.shape != (n, n) or D.shape != (n, n) or W.dtype != D.dtype:
+        raise ValueError("W and D must be square, same shape and dtype")
+    S = np.empty((n, n), dtype=np.int32)
+    fn = getattr(_lib(), "or_successors_" + _sfx(W.dtype))
+    _check(fn(n, _ptr(W), max(1, _ld(W)), _ptr(D), max(1, _ld(D)), _ptr(S), max(1, n)),
+           "successors")
+    return S
 
 
 def gemv(semiring: str, A: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:

@@ -573,3 +573,127 @@ int or_fw_blocked_f32(long n, const float *W, long ldw, float *D, long ldd, long
     free(d);
     return OR_OK;
 }
+
+/* ============ Witnesses: which k attains each entry of a product ==========
+ * The product listing of Sec. IV takes a min over k; these functions also
+ * report the k.  For C <- C (+) A (.) B, an entry whose value strictly
+ * improves (smaller for min-plus, larger for max-plus) gets in K the
+ * smallest p whose term A_ip (.) B_pj equals the new value; an entry that
+ * does not strictly improve keeps both C and K as they were.  Ties between
+ * terms are decided on the terms' values in the data's own precision: exact
+ * integers for int32 (absent values absorb), one binary32 add for float32
+ * (the rounded value, Sec. I arithmetic as read for binary32).
+ */
+static int better_i64(int sr, int64_t x, int64_t y) { return sr == OR_MIN_PLUS ? x < y : x > y; }
+static int better_f32(int sr, float x, float y) { return sr == OR_MIN_PLUS ? x < y : x > y; }
+
+int or_gemm_witness_i32(int sr, long m, long n, long k, const int32_t *A, long lda,
+                        const int32_t *B, long ldb, int32_t *C, long ldc, int32_t *K, long ldk) {
+    if (!sr_ok(sr) || m < 0 || n < 0 || k < 0 || k > INT32_MAX) return OR_EARG;
+    if (!scan_i32(sr, m, k, A, lda) || !scan_i32(sr, k, n, B, ldb)) return OR_EDOMAIN;
+    int status = OR_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < m; ++i) {
+        for (long j = 0; j < n; ++j) {
+            int64_t best = i64_zero(sr);
+            long arg = -1;
+            for (long p = 0; p < k; ++p) {
+                int64_t term = i64_otimes(sr, i32_lift(sr, A[i * lda + p]),
+                                          i32_lift(sr, B[p * ldb + j]));
+                if (better_i64(sr, term, best)) {
+                    best = term;
+                    arg = p;
+                }
+            }
+            if (arg < 0 || !better_i64(sr, best, i32_lift(sr, C[i * ldc + j]))) continue;
+            int32_t out;
+            if (i64_store(sr, best, &out) != OR_OK) {
+#pragma omp atomic write
+                status = OR_EDOMAIN;
+                continue;
+            }
+            C[i * ldc + j] = out;
+            K[i * ldk + j] = (int32_t)arg;
+        }
+    }
+    return status;
+}
+
+int or_gemm_witness_f32(int sr, long m, long n, long k, const float *A, long lda,
+                        const float *B, long ldb, float *C, long ldc, int32_t *K, long ldk) {
+    if (!sr_ok(sr) || m < 0 || n < 0 || k < 0 || k > INT32_MAX) return OR_EARG;
+    if (!scan_f32(sr, m, k, A, lda) || !scan_f32(sr, k, n, B, ldb)) return OR_EDOMAIN;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < m; ++i) {
+        for (long j = 0; j < n; ++j) {
+            float best = (float)f64_zero(sr);
+            long arg = -1;
+            for (long p = 0; p < k; ++p) {
+                /* one binary32 add, evaluated exactly in binary64 and rounded */
+                float term = (float)((double)A[i * lda + p] + (double)B[p * ldb + j]);
+                if (better_f32(sr, term, best)) {
+                    best = term;
+                    arg = p;
+                }
+            }
+            if (arg < 0 || !better_f32(sr, best, C[i * ldc + j])) continue;
+            C[i * ldc + j] = best;
+            K[i * ldk + j] = (int32_t)arg;
+        }
+    }
+    return OR_OK;
+}
+
+/* Successor matrix of a distance matrix D (min-plus): S_ii = i, and for
+ * i != j, S_ij is the smallest u != i minimising W_iu (.) D_uj (the first
+ * hop of a shortest i -> j path when D holds the shortest distances and
+ * every weight is positive), or -1 when every such term is absent.  It is
+ * the witness of the product W' (.) D with W' = W off the diagonal. */
+int or_successors_i32(long n, const int32_t *W, long ldw, const int32_t *D, long ldd,
+                      int32_t *S, long lds) {
+    if (n < 0 || n > INT32_MAX || (n > 0 && (ldw < n || ldd < n || lds < n))) return OR_EARG;
+    if (!scan_i32(OR_MIN_PLUS, n, n, W, ldw) || !scan_i32(OR_MIN_PLUS, n, n, D, ldd))
+        return OR_EDOMAIN;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < n; ++i) {
+        for (long j = 0; j < n; ++j) {
+            int64_t best = OR_INF64;
+            long arg = -1;
+            for (long u = 0; u < n; ++u) {
+                if (u == i) continue;
+                int64_t term = i64_otimes(OR_MIN_PLUS, i32_lift(OR_MIN_PLUS, W[i * ldw + u]),
+                                          i32_lift(OR_MIN_PLUS, D[u * ldd + j]));
+                if (term < best) {
+                    best = term;
+                    arg = u;
+                }
+            }
+            S[i * lds + j] = (int32_t)(i == j ? i : arg);
+        }
+    }
+    return OR_OK;
+}
+
+int or_successors_f32(long n, const float *W, long ldw, const float *D, long ldd,
+                      int32_t *S, long lds) {
+    if (n < 0 || n > INT32_MAX || (n > 0 && (ldw < n || ldd < n || lds < n))) return OR_EARG;
+    if (!scan_f32(OR_MIN_PLUS, n, n, W, ldw) || !scan_f32(OR_MIN_PLUS, n, n, D, ldd))
+        return OR_EDOMAIN;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < n; ++i) {
+        for (long j = 0; j < n; ++j) {
+            float best = INFINITY;
+            long arg = -1;
+            for (long u = 0; u < n; ++u) {
+                if (u == i) continue;
+                float term = (float)((double)W[i * ldw + u] + (double)D[u * ldd + j]);
+                if (term < best) {
+                    best = term;
+                    arg = u;
+                }
+            }
+            S[i * lds + j] = (int32_t)(i == j ? i : arg);
+        }
+    }
+    return OR_OK;
+}

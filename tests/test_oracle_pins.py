@@ -562,3 +562,181 @@ def test_fw_blocked_f32_rounding_bound_vs_dijkstra():
     # within the bound, and they agree on the reachability pattern
     Dsq, _, _ = oracle.apsp(W)
     assert np.array_equal(np.isfinite(Dsq), fin)
+
+
+# ------------------------------------------------------------ witnesses ---
+
+def _witness_numpy(sr, A, B, C, K):
+    """Per-term values by numpy (binary32 adds for float32, masked int64 for
+    int32) and numpy's argmin/argmax, which returns the first (smallest)
+    index among equal extremes; strict improvement decides whether C and K
+    change."""
+    if A.dtype == np.float32:
+        S = A[:, :, None] + B[None, :, :]
+        assert S.dtype == np.float32
+    else:
+        absent = INF32 if sr == "min" else NINF32
+        big = np.int64(1) << 40
+        S = A.astype(np.int64)[:, :, None] + B.astype(np.int64)[None, :, :]
+        touch = (A == absent)[:, :, None] | (B == absent)[None, :, :]
+        S = np.where(touch, big if sr == "min" else -big, S)
+    arg = S.argmin(axis=1) if sr == "min" else S.argmax(axis=1)
+    red = np.take_along_axis(S, arg[:, None, :], axis=1)[:, 0, :]
+    if A.dtype == np.int32:
+        red = np.where(np.abs(red) >= (np.int64(1) << 40), absent, red)
+    Cw = C.astype(red.dtype)
+    imp = red < Cw if sr == "min" else red > Cw
+    return np.where(imp, red, Cw).astype(C.dtype), np.where(imp, arg, K).astype(np.int32)
+
+
+def _tie_heavy(dt, sr, shape, seed, absent_frac=0.15):
+    """Few distinct values, so many terms of one output tie."""
+    g = np.random.default_rng(seed)
+    if dt == "i32":
+        X = g.integers(-4, 5, shape).astype(np.int32)
+    else:
+        X = (g.integers(-8, 9, shape) * 0.25).astype(np.float32)
+    X[g.random(shape) < absent_frac] = _absent(dt, sr)
+    return X
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 7, 3), (17, 9, 33), (40, 31, 64)])
+def test_gemm_witness_equals_numpy_argmin(sr, dt, shape):
+    m, n, k = shape
+    A = _tie_heavy(dt, sr, (m, k), 1)
+    B = _tie_heavy(dt, sr, (k, n), 2)
+    C = _tie_heavy(dt, sr, (m, n), 3, absent_frac=0.5)
+    K = np.random.default_rng(4).integers(-1, 1000, (m, n)).astype(np.int32)
+    Cw, Kw = oracle.gemm_witness(sr, A, B, C, K)
+    Cn, Kn = _witness_numpy(sr, A, B, C, K)
+    assert np.array_equal(Cw, Cn) and np.array_equal(Kw, Kn)
+    # the values are the plain product's
+    assert np.array_equal(Cw, oracle.gemm(sr, A, B, C))
+    # every changed witness attains its value; untouched entries keep K
+    changed = Cw != C
+    assert np.array_equal(Kw[~changed], K[~changed])
+
+
+def test_gemm_witness_f32_ties_made_by_rounding():
+    """Terms that differ exactly but round to the same binary32 value tie, so
+    the smallest index wins; a term that rounds below the others wins."""
+    u = np.float32(2.0 ** -24)                  # half the spacing just above 1
+    A = np.array([[1.0, 1.0 + 4 * u, 1.0, 1.0]], np.float32)
+    C = np.full((1, 1), np.inf, np.float32)
+    K = np.full((1, 1), -1, np.int32)
+    # terms RN(1 + u/2) = 1, 1 + 4u, RN(1 + u/4) = 1, RN(1 - u/2) = 1 (a tie
+    # between 1 - u and 1, to even): four terms, three equal to 1 -> index 0
+    B = np.array([[u / 2], [0.0], [u / 4], [-u / 2]], np.float32)
+    Cw, Kw = oracle.gemm_witness("min", A, B, C, K)
+    assert Cw[0, 0] == 1.0 and Kw[0, 0] == 0
+    # 1 - u is representable and below 1: the last term wins
+    B[3, 0] = -u
+    Cw, Kw = oracle.gemm_witness("min", A, B, C, K)
+    assert Cw[0, 0] == np.float32(1.0) - u and Kw[0, 0] == 3
+    # max-plus: RN(1 + 4u) is the largest
+    Cm = np.full((1, 1), -np.inf, np.float32)
+    Cw, Kw = oracle.gemm_witness("max", A, B, Cm, K)
+    assert Cw[0, 0] == np.float32(1.0) + 4 * u and Kw[0, 0] == 1
+
+
+@pytest.mark.parametrize("sr", SR)
+def test_gemm_witness_no_change_keeps_k_and_absent_terms_never_win(sr):
+    dt = "i32"
+    A = np.full((3, 4), _absent(dt, sr), np.int32)
+    B = np.zeros((4, 2), np.int32)
+    C = np.array([[5, _absent(dt, sr)]] * 3, np.int32)
+    K = np.array([[7, 8]] * 3, np.int32)
+    Cw, Kw = oracle.gemm_witness(sr, A, B, C, K)
+    assert np.array_equal(Cw, C) and np.array_equal(Kw, K)
+    # k = 0: nothing changes
+    Cw, Kw = oracle.gemm_witness(sr, A[:, :0], B[:0], C, K)
+    assert np.array_equal(Cw, C) and np.array_equal(Kw, K)
+
+
+def _walk(S, i, j, limit):
+    path = [i]
+    while path[-1] != j and len(path) <= limit:
+        nxt = int(S[path[-1], j])
+        if nxt < 0:
+            return None
+        path.append(nxt)
+    return path if path[-1] == j else None
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_successors_tiny_bruteforce(seed):
+    """Positive weights: S_ij is the smallest neighbour u with
+    w(i,u) + d(u,j) = d(i,j), d by simple-path enumeration."""
+    g = np.random.default_rng(seed)
+    n = int(g.integers(1, 8))
+    W = wl.er_digraph_i32(n, 0.45, 1, 6, seed=300 + seed)
+    D, _, _ = oracle.apsp(W)
+    S = oracle.successors(W, D)
+    d = oracle.brute_force_apsp(W.tolist(), INF32)
+    for i in range(n):
+        assert S[i, i] == i
+        for j in range(n):
+            if i == j:
+                continue
+            cands = [u for u in range(n) if u != i and W[i, u] != INF32 and d[u][j] != INF32
+                     and W[i, u] + d[u][j] == d[i][j]]
+            assert S[i, j] == (min(cands) if d[i][j] != INF32 else -1), (i, j)
+
+
+@pytest.mark.parametrize("n,p", [(50, 0.1), (200, 0.03)])
+def test_successors_i32_paths_are_shortest(n, p):
+    """Following S from i reaches j in < n hops, the weights along the walk
+    sum exactly to d(i,j) (scipy Dijkstra), and S_ij = -1 exactly where j is
+    unreachable; S also equals numpy's first argmin of W' + D."""
+    W = wl.er_digraph_i32(n, p, 1, 1000, seed=n)
+    D, _, _ = oracle.apsp(W)
+    S = oracle.successors(W, D)
+    ref = _dijkstra(W)
+    for i in range(n):
+        for j in range(n):
+            if not np.isfinite(ref[i, j]):
+                assert S[i, j] == -1
+                continue
+            path = _walk(S, i, j, n)
+            assert path is not None, (i, j)
+            assert sum(int(W[a, b]) for a, b in zip(path, path[1:])) == ref[i, j]
+    Wp = W.copy()
+    np.fill_diagonal(Wp, INF32)
+    _, Kn = _witness_numpy("min", Wp, D, np.full((n, n), INF32, np.int32),
+                           np.full((n, n), -1, np.int32))
+    np.fill_diagonal(Kn, np.arange(n))
+    assert np.array_equal(S, Kn)
+
+
+def test_successors_f32_integer_weights_match_int32():
+    """Integer-valued binary32 weights: every sum is exact, so the float
+    successors equal the integer ones."""
+    n = 120
+    Wi = wl.er_digraph_i32(n, 0.05, 1, 100, seed=12)
+    Wf = np.where(Wi == INF32, np.inf, Wi).astype(np.float32)
+    Si = oracle.successors(Wi, oracle.apsp(Wi)[0])
+    Sf = oracle.successors(Wf, oracle.apsp(Wf)[0])
+    assert np.array_equal(Si, Sf)
+
+
+def test_successors_f32_general_weights_walks_reach_target():
+    """Exponential weights: every walk reaches its target, and its fp64 length
+    is within the rounding bound of the fp64 Dijkstra distance."""
+    n = 160
+    r, c, w = wl.sparse_digraph_f32_exp(n, 5.0, seed=21)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    D, steps, _ = oracle.apsp(W)
+    S = oracle.successors(W, D)
+    ref = _dijkstra(W)
+    u = 2.0 ** -24
+    for i in range(n):
+        for j in range(n):
+            if i == j or not np.isfinite(ref[i, j]):
+                assert S[i, j] == (i if i == j else -1)
+                continue
+            path = _walk(S, i, j, n)
+            assert path is not None, (i, j)
+            length = sum(float(W[a, b]) for a, b in zip(path, path[1:]))
+            assert ref[i, j] <= length <= ref[i, j] * (1 + u) ** (2 * steps + 2) * (1 + u) ** len(path)
