@@ -186,6 +186,55 @@ def bench_apsp_large(dev):
                                "max_rel_diff_vs_squaring": rel}}
 
 
+def bench_witness(dev, operands, reps=3):
+    """The argmin-carrying product on the 8192^3 min-plus fp32 operands (C
+    starts at the (+)-identity, K at -1) against the value-only product, and
+    the successor matrix of the n=16384 graph from its Floyd-Warshall
+    distances."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    A, B, C0 = operands
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = _events()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)) / 1e3
+
+    C = torch.empty_like(C0)
+    K = torch.empty(C0.shape, dtype=torch.int32, device=dev)
+
+    def witness():
+        C.copy_(C0)
+        K.fill_(-1)
+        btas.tropical_gemm_witness(A, B, C, K)
+
+    ops = 2.0 * N ** 3
+    sec = timed(witness)
+    out = {"workload": "witness product 8192^3 min-plus fp32 (C, K reset inside the timed region)",
+           "ms": round(sec * 1e3, 2), "Gop/s": round(ops / sec / 1e9, 1),
+           "frac_valu_peak": round(ops / sec / 1e12 / PEAK_TOPS, 4)}
+    del C, K
+    n = 16384
+    W = torch.from_numpy(wl.apsp_large_f32(n, 16.0, seed=4)).to(dev)
+    D, _ = btas.floyd_warshall(W)
+    S = torch.empty((n, n), dtype=torch.int32, device=dev)
+    sec = timed(lambda: btas.apsp_successors(W, D, out=S))
+    out["successors_16384"] = {"ms": round(sec * 1e3, 2),
+                               "Gop/s": round(2.0 * n ** 3 / sec / 1e9, 1)}
+    return out
+
+
 def bench_batched(dev, reps=5):
     """4096 independent graphs, n log-uniform in [16,512], p = 8/n, int32
     weights U{1..1000}: one hipGraph launch vs 4096 plain solves."""
@@ -419,6 +468,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host["A"], host["B"], host["C"], args.cpu_rows)
+    witness_operands = tensors[("min", "f32")]
     del host, tensors
     torch.cuda.empty_cache()
     if not args.no_extras:
@@ -426,6 +476,8 @@ def main():
         extras["level12"] = bench_level12(dev)
         extras["apsp_small"] = bench_apsp_small(dev)
         extras["apsp_large"] = bench_apsp_large(dev)
+        extras["witness"] = bench_witness(dev, witness_operands)
+        del witness_operands
         torch.cuda.empty_cache()
         extras["batched"] = bench_batched(dev)
         torch.cuda.empty_cache()

@@ -230,6 +230,43 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
 btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, const void *W,
                                        int ldw, void *D, int ldd, unsigned flags);
 
+/* Tropical product with witnesses: C <- C (+) A (.) B as btas_tropical_gemm
+ * (the Sec. IV product, whose inner step is a min (max) over k), and K
+ * records that step's argument: for every entry whose value strictly
+ * improves (smaller for min-plus, larger for max-plus), K[i*ldk+j] <- the
+ * smallest p whose term A_ip (.) B_pj equals the new value.  Entries that do
+ * not strictly improve keep C and K unchanged, so K needs no initialisation
+ * where C is the (+)-identity and callers may chain products over k-slices.
+ * Ties between terms are decided on the terms' values as the product
+ * computes them (one binary32 add per term; int32 terms exact inside the
+ * domain bound, absent values absorbing), so C equals btas_tropical_gemm's
+ * result bit for bit and K is unique.  A, B, C row-major as in
+ * btas_tropical_gemm; K is an m x n int32 device matrix (leading dimension
+ * ldk >= max(1,n)), caller-owned; C or K overlapping any other operand, or
+ * each other, is BTAS_ERR_ALIAS.  No workspace, no split-K, asynchronous.
+ * k must fit in int32 (it does). */
+btas_status_t btas_tropical_gemm_witness(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt,
+                                         int m, int n, int k, const void *A, int lda,
+                                         const void *B, int ldb, void *C, int ldc, int32_t *K,
+                                         int ldk);
+
+/* Successor (next-hop) matrix of an APSP result, min-plus: S[i*lds+i] = i,
+ * and for i != j, S[i*lds+j] = the smallest u != i minimising W_iu (.) D_uj,
+ * or -1 when every such term is absent.  It is the witness of the product
+ * W' (.) D, W' being W with its diagonal absent (the min over k of the
+ * Sec. IV product, taken once on the solved matrix).  With D the shortest
+ * distances of W (btas_apsp_squaring, btas_apsp_floyd_warshall) and every
+ * edge weight positive, S_ij is the first vertex after i on a shortest path
+ * to j and following S from i reaches j; int32 walks have exactly length
+ * D_ij.  Zero-weight cycles can make a walk loop.  W, D as in
+ * btas_apsp_squaring (n x n, leading dimensions ldw, ldd; W and D may be the
+ * same matrix only if the caller wants the successors of D itself); S is an
+ * n x n int32 device matrix, leading dimension lds >= max(1,n),
+ * caller-owned, and must not overlap W or D (BTAS_ERR_ALIAS).  One launch of
+ * n^3 terms, asynchronous. */
+btas_status_t btas_apsp_successors(btas_handle_t h, btas_dtype_t dt, int n, const void *W, int ldw,
+                                   const void *D, int ldd, int32_t *S, int lds);
+
 /* Describe the handle's current batched plan: number of kernel launches in
  * its graph and the algorithmic work, sum_i T(n_i) * n_i^3 terms (host
  * outputs, either may be NULL).  INVALID_ARG if no plan exists. */

@@ -90,6 +90,8 @@ def lib():
         L.btas_batched_plan_info.argtypes = [P, IP, ctypes.POINTER(ctypes.c_double)]
         L.btas_batched_tile_choice.argtypes = [P, I, I]
         L.btas_apsp_floyd_warshall.argtypes = [P, I, I, P, I, P, I, U]
+        L.btas_tropical_gemm_witness.argtypes = [P, I, I, I, I, I, P, I, P, I, P, I, P, I]
+        L.btas_apsp_successors.argtypes = [P, I, I, P, I, P, I, P, I]
         L.btas_server_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.c_size_t, I, ctypes.c_double]
         L.btas_server_destroy.argtypes = [P]
         L.btas_server_now.argtypes = [P]
@@ -236,6 +238,68 @@ def tropical_gemm(A, B, C=None, semiring="min", handle=None):
         raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
     h.check(lib().btas_tropical_gemm(h.ptr, sr, _dt(A), m, B.size(1), k, pa, lda, pb, ldb, pc, ldc))
     return C
+
+
+def tropical_gemm_witness(A, B, C=None, K=None, semiring="min", handle=None):
+    """C <- C (+) A (.) B and, where an entry strictly improves, K <- the
+    smallest p attaining it (C starts as the (+)-identity and K as -1 when
+    None).  Returns (C, K)."""
+    import torch
+    sr = _sr(semiring)
+    m, n = A.size(0), B.size(1)
+    if C is None:
+        fill = (I32_INF if sr == MIN_PLUS else I32_NEG_INF) if A.dtype == torch.int32 else \
+            (float("inf") if sr == MIN_PLUS else float("-inf"))
+        C = torch.full((m, n), fill, dtype=A.dtype, device=A.device)
+    if K is None:
+        K = torch.full((m, n), -1, dtype=torch.int32, device=A.device)
+    if A.dtype != B.dtype or A.dtype != C.dtype or K.dtype != torch.int32:
+        raise TypeError("A, B and C must share a dtype and K must be int32")
+    h = _handle_for(C, handle)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    pk, ldk = _mat(K, "K")
+    k = A.size(1)
+    if B.size(0) != k or C.shape != (m, n) or K.shape != (m, n):
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, "
+                         f"C {tuple(C.shape)}, K {tuple(K.shape)}")
+    h.check(lib().btas_tropical_gemm_witness(h.ptr, sr, _dt(A), m, n, k, pa, lda, pb, ldb,
+                                             pc, ldc, pk, ldk))
+    return C, K
+
+
+def apsp_successors(W, D, out=None, handle=None):
+    """Successor matrix S of a solved distance matrix D of W (min-plus):
+    S_ii = i; S_ij = the smallest u != i minimising W_iu (.) D_uj, -1 if
+    every term is absent."""
+    import torch
+    n = W.size(0)
+    if W.shape != (n, n) or D.shape != (n, n) or W.dtype != D.dtype:
+        raise ValueError("W and D must be square, of one shape and dtype")
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.int32, device=W.device)
+    if out.dtype != torch.int32 or out.shape != (n, n):
+        raise TypeError("out must be an n x n int32 tensor")
+    h = _handle_for(W, handle)
+    pw, ldw = _mat(W, "W")
+    pd, ldd = _mat(D, "D")
+    ps, lds = _mat(out, "S")
+    h.check(lib().btas_apsp_successors(h.ptr, _dt(W), n, pw, ldw, pd, ldd, ps, lds))
+    return out
+
+
+def shortest_path(S, i, j):
+    """The vertices of the path from i to j read off a successor matrix (a
+    host copy, numpy or nested lists); None if j is unreachable."""
+    path = [int(i)]
+    n = len(S)
+    while path[-1] != j:
+        nxt = int(S[path[-1]][j])
+        if nxt < 0 or len(path) > n:
+            return None
+        path.append(nxt)
+    return path
 
 
 def tropical_gemv(A, x, y, semiring="min", handle=None):

@@ -553,4 +553,69 @@ btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, 
     return BTAS_OK;
 }
 
+// ------------------------------------------------------------ witnesses ---
+btas_status_t btas_tropical_gemm_witness(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt,
+                                         int m, int n, int k, const void* A, int lda,
+                                         const void* B, int ldb, void* C, int ldc, int32_t* K,
+                                         int ldk) {
+    const char* fn = "btas_tropical_gemm_witness";
+    btas_status_t st = check_common(h, fn, sr, dt);
+    if (st != BTAS_OK) return st;
+    if (m < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (m=%d) < 0", fn, m);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (n=%d) < 0", fn, n);
+    if (k < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 6 (k=%d) < 0", fn, k);
+    if (lda < (k > 1 ? k : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (lda=%d) < max(1,k=%d)", fn, lda, k);
+    if (ldb < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 10 (ldb=%d) < max(1,n=%d)", fn, ldb, n);
+    if (ldc < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 12 (ldc=%d) < max(1,n=%d)", fn, ldc, n);
+    if (ldk < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 14 (ldk=%d) < max(1,n=%d)", fn, ldk, n);
+    if ((long)m * k > 0 && !A) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (A) is null", fn);
+    if ((long)k * n > 0 && !B) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (B) is null", fn);
+    if ((long)m * n > 0 && !C) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 11 (C) is null", fn);
+    if ((long)m * n > 0 && !K) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 13 (K) is null", fn);
+    const Span sc = mat_span(C, m, n, ldc), sk = mat_span(K, m, n, ldk);
+    const Span sa = mat_span(A, m, k, lda), sb = mat_span(B, k, n, ldb);
+    if (overlap(sc, sa) || overlap(sc, sb) || overlap(sk, sa) || overlap(sk, sb) || overlap(sk, sc))
+        return fail(h, BTAS_ERR_ALIAS, "%s: C or K overlaps another operand", fn);
+    if (m == 0 || n == 0 || k == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    const void* ps[2] = {A, B};
+    const long rows[2] = {m, k}, cols[2] = {k, n}, lds[2] = {lda, ldb};
+    st = validate_operands(h, fn, sr, dt, ps, rows, cols, lds, 2);
+    if (st != BTAS_OK) return st;
+    hipError_t e = btas::launch_gemm_witness(sr, dt, m, n, k, A, lda, B, ldb, C, ldc, K, ldk,
+                                             h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+btas_status_t btas_apsp_successors(btas_handle_t h, btas_dtype_t dt, int n, const void* W, int ldw,
+                                   const void* D, int ldd, int32_t* S, int lds) {
+    const char* fn = "btas_apsp_successors";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
+    if (ldw < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (ldw=%d) < max(1,n=%d)", fn, ldw, n);
+    if (ldd < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 7 (ldd=%d) < max(1,n=%d)", fn, ldd, n);
+    if (lds < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (lds=%d) < max(1,n=%d)", fn, lds, n);
+    if (n > 0 && (!W || !D || !S)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W, D or S is null", fn);
+    const Span ss = mat_span(S, n, n, lds);
+    if (overlap(ss, mat_span(W, n, n, ldw)) || overlap(ss, mat_span(D, n, n, ldd)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: S overlaps W or D", fn);
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    const void* ps[2] = {W, D};
+    const long rows[2] = {n, n}, cols[2] = {n, n}, ldv[2] = {ldw, ldd};
+    btas_status_t st = validate_operands(h, fn, BTAS_MIN_PLUS, dt, ps, rows, cols, ldv, 2);
+    if (st != BTAS_OK) return st;
+    hipError_t e = btas::launch_successors(dt, n, W, ldw, D, ldd, S, lds, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
 }  // extern "C"

@@ -105,6 +105,16 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
 // block (diagonal block, its block-row and block-column, the rest).
 int fw_block_size();
 hipError_t launch_floyd_warshall(int dt, int n, void* D, long ld, hipStream_t s);
+
+// Tropical product with witnesses (csrc/witness.hip): C <- C (+) A (.) B and,
+// where an entry strictly improves, K <- the smallest p attaining it.
+hipError_t launch_gemm_witness(int sr, int dt, int m, int n, int k, const void* A, long lda,
+                               const void* B, long ldb, void* C, long ldc, int32_t* K, long ldk,
+                               hipStream_t s);
+// Successors of a (min-plus) distance matrix: S_ii = i; for i != j the
+// smallest u != i minimising W_iu (.) D_uj, -1 if every term is absent.
+hipError_t launch_successors(int dt, int n, const void* W, long ldw, const void* D, long ldd,
+                             int32_t* S, long lds, hipStream_t s);
 // Domain scan (BTAS_VALIDATE=1): flag <- 1 if some element of the m x n matrix
 // is not a legal (.) operand of the semiring.
 hipError_t launch_domain_scan(int sr, int dt, int m, int n, const void* X, long ld, int* flag,

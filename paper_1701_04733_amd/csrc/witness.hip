@@ -1,0 +1,242 @@
+// Tropical product with witnesses: C <- C (+) A (.) B, and for every entry
+// whose value strictly improves, K <- the smallest p whose term A_ip (.) B_pj
+// attains it (the min over k of the Sec. IV product listing, with its
+// argument).  The same kernel computes successor matrices of APSP:
+// S_ij = the smallest u != i minimising W_iu (.) D_uj (i != j), S_ii = i,
+// -1 where every term is absent.
+//
+// Ties are decided on the terms' values in the kernel's arithmetic (binary32
+// adds for float32, clamped int32 adds mapped back to the absent value for
+// int32), which is the arithmetic of the value-only product, so C is the same
+// as that product's and K is unique.
+//
+// A 64x64 output tile per 256-thread workgroup, 4x4 outputs per thread, k in
+// blocks of 16 staged through LDS.  Each k-block is first reduced per output
+// with three-way min/max (the cost of the value-only product); only an output
+// whose block extreme strictly beats its running best searches the block
+// again for the first index attaining it.  The running best improves rarely
+// after the first blocks (about log(k) times per output for unordered data),
+// so the search costs a fraction of the main loop.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "kernels.h"
+#include "semiring.h"
+
+namespace btas {
+
+namespace {
+
+constexpr int WT_BM = 64, WT_BN = 64, WT_BK = 16;
+constexpr int WT_NT = 256;
+constexpr int WT_TM = 4, WT_TN = 4;
+constexpr int WT_APAD = 4;  // As rows padded: transposed stores hit 64 banks
+
+template <typename T>
+struct WitnessArgs {
+    int m, n, k;
+    const T* A;
+    long lda;
+    const T* B;
+    long ldb;
+    T* C;        // read and written in product mode; unused for successors
+    long ldc;
+    int32_t* K;  // witnesses (product mode) or successors
+    long ldk;
+};
+
+template <int SR, typename T>
+__device__ __forceinline__ bool better(T x, T y) {
+    if constexpr (SR == BTAS_MIN_PLUS) return x < y;
+    else return x > y;
+}
+
+// blockIdx -> (tile row, tile col): consecutive workgroups go to different
+// XCDs, so each XCD gets a contiguous range of tiles, walked in groups of 8
+// tile rows so that neighbouring workgroups share B panels in that XCD's L2.
+__device__ __forceinline__ void wt_tile_of(int bid, int nb, int nbm, int nbn, int& tm, int& tn) {
+    constexpr int NXCD = 8, GROUP_M = 8;
+    const int per = nb / NXCD;
+    if (bid < per * NXCD) bid = (bid % NXCD) * per + bid / NXCD;
+    const int group = GROUP_M * nbn;
+    const int gid = bid / group;
+    const int first_m = gid * GROUP_M;
+    const int gsz = min(nbm - first_m, GROUP_M);
+    const int in_g = bid - gid * group;
+    tm = first_m + in_g % gsz;
+    tn = in_g / gsz;
+}
+
+// SUCC: successor mode (A = W with its diagonal treated as absent, B = D,
+// output S); otherwise the witness product.
+template <typename T, int SR, bool VEC, bool SUCC>
+__global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
+    using R = Ring<SR, T>;
+    __shared__ __align__(16) T As[WT_BK][WT_BM + WT_APAD];
+    __shared__ __align__(16) T Bs[WT_BK][WT_BN];
+
+    const int nbm = (a.m + WT_BM - 1) / WT_BM, nbn = (a.n + WT_BN - 1) / WT_BN;
+    int tm, tn;
+    wt_tile_of(blockIdx.x, nbm * nbn, nbm, nbn, tm, tn);
+    const int m0 = tm * WT_BM, n0 = tn * WT_BN;
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+
+    // staging: A element (ar, ac4..ac4+3) of the 64x16 block, B (br, bc4..)
+    const int ar = tid / 4, ac4 = (tid % 4) * 4;
+    const int br = tid / 16, bc4 = (tid % 16) * 4;
+    T ra[4], rb[4];
+
+    auto load = [&](int k0) {
+        const int gi = m0 + ar, gp = k0 + ac4;
+        if (VEC && gi < a.m && gp + 4 <= a.k) {
+            const auto v = *reinterpret_cast<const HIP_vector_type<T, 4>*>(a.A + (long)gi * a.lda + gp);
+            ra[0] = v.x; ra[1] = v.y; ra[2] = v.z; ra[3] = v.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ra[q] = (gi < a.m && gp + q < a.k) ? a.A[(long)gi * a.lda + gp + q] : R::absent();
+        }
+        if constexpr (SUCC) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (gi == gp + q) ra[q] = R::absent();
+        }
+        const int gk = k0 + br, gj = n0 + bc4;
+        if (VEC && gk < a.k && gj + 4 <= a.n) {
+            const auto v = *reinterpret_cast<const HIP_vector_type<T, 4>*>(a.B + (long)gk * a.ldb + gj);
+            rb[0] = v.x; rb[1] = v.y; rb[2] = v.z; rb[3] = v.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                rb[q] = (gk < a.k && gj + q < a.n) ? a.B[(long)gk * a.ldb + gj + q] : R::absent();
+        }
+    };
+
+    T acc[WT_TM][WT_TN];
+    int idx[WT_TM][WT_TN];
+#pragma unroll
+    for (int r = 0; r < WT_TM; ++r)
+#pragma unroll
+        for (int c = 0; c < WT_TN; ++c) {
+            acc[r][c] = R::absent();
+            idx[r][c] = -1;
+        }
+
+    const int nkb = (a.k + WT_BK - 1) / WT_BK;
+    if (nkb > 0) load(0);
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int k0 = kb * WT_BK;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[ac4 + q][ar] = ra[q];
+        *reinterpret_cast<HIP_vector_type<T, 4>*>(&Bs[br][bc4]) = HIP_vector_type<T, 4>(rb[0], rb[1], rb[2], rb[3]);
+        __syncthreads();
+        if (kb + 1 < nkb) load(k0 + WT_BK);
+
+        // block extreme of every output over the 16 terms of this block
+        T bm[WT_TM][WT_TN];
+#pragma unroll
+        for (int r = 0; r < WT_TM; ++r)
+#pragma unroll
+            for (int c = 0; c < WT_TN; ++c) bm[r][c] = R::absent();
+// (two k-pairs per iteration: a full unroll hoists every LDS read and
+        // doubles the register count)
+#pragma unroll 2
+        for (int kk = 0; kk < WT_BK; kk += 2) {
+            const auto a0 = *reinterpret_cast<const HIP_vector_type<T, 4>*>(&As[kk][ty * WT_TM]);
+            const auto a1 = *reinterpret_cast<const HIP_vector_type<T, 4>*>(&As[kk + 1][ty * WT_TM]);
+            const auto b0 = *reinterpret_cast<const HIP_vector_type<T, 4>*>(&Bs[kk][tx * WT_TN]);
+            const auto b1 = *reinterpret_cast<const HIP_vector_type<T, 4>*>(&Bs[kk + 1][tx * WT_TN]);
+            const T av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
+            const T bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+            for (int r = 0; r < WT_TM; ++r)
+#pragma unroll
+                for (int c = 0; c < WT_TN; ++c)
+                    bm[r][c] = R::add3(bm[r][c], R::mul(av0[r], bv0[c]), R::mul(av1[r], bv1[c]));
+        }
+
+        // outputs whose block extreme strictly beats the running best: find
+        // the first index in the block that attains it
+#pragma unroll
+        for (int r = 0; r < WT_TM; ++r)
+#pragma unroll
+            for (int c = 0; c < WT_TN; ++c) {
+                const T v = R::finish(bm[r][c]);
+                if (better<SR>(v, acc[r][c])) {
+                    int kk = 0;
+                    T s = R::mul(As[0][ty * WT_TM + r], Bs[0][tx * WT_TN + c]);
+                    while (!(s == bm[r][c]) && kk + 1 < WT_BK) {
+                        ++kk;
+                        s = R::mul(As[kk][ty * WT_TM + r], Bs[kk][tx * WT_TN + c]);
+                    }
+                    acc[r][c] = s;
+                    idx[r][c] = k0 + kk;
+                }
+            }
+    }
+
+#pragma unroll
+    for (int r = 0; r < WT_TM; ++r) {
+        const int i = m0 + ty * WT_TM + r;
+        if (i >= a.m) continue;
+#pragma unroll
+        for (int c = 0; c < WT_TN; ++c) {
+            const int j = n0 + tx * WT_TN + c;
+            if (j >= a.n) continue;
+            if constexpr (SUCC) {
+                a.K[(long)i * a.ldk + j] = i == j ? i : idx[r][c];
+            } else {
+                const T cold = a.C[(long)i * a.ldc + j];
+                if (idx[r][c] >= 0 && better<SR>(acc[r][c], cold)) {
+                    a.C[(long)i * a.ldc + j] = acc[r][c];
+                    a.K[(long)i * a.ldk + j] = idx[r][c];
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int SR, bool SUCC>
+hipError_t launch_typed(WitnessArgs<T> a, hipStream_t s) {
+    if (a.m <= 0 || a.n <= 0) return hipSuccess;
+    const long tiles = (long)((a.m + WT_BM - 1) / WT_BM) * ((a.n + WT_BN - 1) / WT_BN);
+    if (tiles > 0x7FFFFFFFL) return hipErrorInvalidValue;
+    const bool vec = a.lda % 4 == 0 && a.ldb % 4 == 0 && (uintptr_t)a.A % 16 == 0 &&
+                     (uintptr_t)a.B % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL((witness_gemm_kernel<T, SR, true, SUCC>), dim3((unsigned)tiles),
+                           dim3(WT_NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((witness_gemm_kernel<T, SR, false, SUCC>), dim3((unsigned)tiles),
+                           dim3(WT_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_witness(int sr, int dt, int m, int n, int k, const void* A, long lda,
+                               const void* B, long ldb, void* C, long ldc, int32_t* K, long ldk,
+                               hipStream_t s) {
+    if (dt == BTAS_FLOAT32) {
+        WitnessArgs<float> a{m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc, K, ldk};
+        return sr == BTAS_MIN_PLUS ? launch_typed<float, BTAS_MIN_PLUS, false>(a, s)
+                                   : launch_typed<float, BTAS_MAX_PLUS, false>(a, s);
+    }
+    WitnessArgs<int32_t> a{m, n, k, (const int32_t*)A, lda, (const int32_t*)B, ldb, (int32_t*)C, ldc, K, ldk};
+    return sr == BTAS_MIN_PLUS ? launch_typed<int32_t, BTAS_MIN_PLUS, false>(a, s)
+                               : launch_typed<int32_t, BTAS_MAX_PLUS, false>(a, s);
+}
+
+hipError_t launch_successors(int dt, int n, const void* W, long ldw, const void* D, long ldd,
+                             int32_t* S, long lds, hipStream_t s) {
+    if (dt == BTAS_FLOAT32) {
+        WitnessArgs<float> a{n, n, n, (const float*)W, ldw, (const float*)D, ldd, nullptr, 0, S, lds};
+        return launch_typed<float, BTAS_MIN_PLUS, true>(a, s);
+    }
+    WitnessArgs<int32_t> a{n, n, n, (const int32_t*)W, ldw, (const int32_t*)D, ldd, nullptr, 0, S, lds};
+    return launch_typed<int32_t, BTAS_MIN_PLUS, true>(a, s);
+}
+
+}  // namespace btas
