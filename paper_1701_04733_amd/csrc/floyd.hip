@@ -4,22 +4,27 @@
 // pivot z, d(x,y) <- d(x,y) (+) d(x,z) (.) d(z,y)), grouped by pivot blocks of
 // FW_B = 64 consecutive vertices so that all but a thin strip of the work is a
 // tropical matrix product.  For pivot block K:
-//   1. one workgroup relaxes the diagonal block (K,K) in LDS, pivot by pivot;
+//   1. one workgroup relaxes the diagonal block (K,K) in registers, pivot by
+//      pivot;
 //   2. one workgroup per other block of block-row K and of block-column K
-//      relaxes it in LDS against the finished diagonal block, pivot by pivot;
+//      relaxes it in registers against the finished diagonal block;
 //   3. every block (I,J) with I != K and J != K gets
 //        D_IJ <- D_IJ (+) D_IK (.) D_KJ
-//      from blocks that this phase does not change: a tropical GEMM update with
-//      k = 64, run by the one-wave 64x64 tile of the product kernels (direct
-//      LDS loads for fp32 when n is a multiple of 64).
-// O(n^3) work in n/64 rounds of three launches, against O(n^3 log n) for
-// repeated squaring.  In exact arithmetic every order gives the shortest
-// distances; in binary32 the result is that of this order and block size.
+//      from blocks that this phase does not change: a tropical GEMM update.
+// Pivot blocks are taken in pairs so that phase 3 of both runs as one k=128
+// product on 128x128 tiles (the product kernels' large tile, direct LDS loads
+// for fp32 when n is a multiple of 128), with thin k=64 strip updates before
+// and after it that keep the sequential order's values exactly (fw_typed).
+// O(n^3) work, against O(n^3 log n) for repeated squaring.  In exact
+// arithmetic every order gives the shortest distances; in binary32 the result
+// is that of the blocked order with blocks of 64, which the pairing does not
+// change (min is exact, so one pass over 128 rounded terms equals two passes
+// over 64).
 //
 // Within one pivot z, the entries of row z and column z are relaxed against
 // d(z,z) = 0, which leaves them unchanged, so every other entry may be
-// relaxed concurrently with one barrier per pivot (graphs without negative
-// cycles; with one, the result is unspecified).
+// relaxed concurrently from the pivot's row and column as they stood before
+// it (graphs without negative cycles; with one, the result is unspecified).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -33,8 +38,6 @@ namespace btas {
 namespace {
 
 constexpr int FW_B = 64;      // pivot block edge
-constexpr int FW_NT = 256;    // threads of the phase-1/2 workgroups
-constexpr int FW_PER = FW_B * FW_B / FW_NT;  // block entries per thread
 
 // d <- d (+) a (.) b (min-plus).
 template <typename T>
@@ -43,147 +46,290 @@ __device__ __forceinline__ T relax(T a, T b, T d) {
     return R::add(d, R::finish(R::mul(a, b)));
 }
 
-template <typename T>
-__device__ __forceinline__ void load_block(T (*dst)[FW_B], const T* D, long ld, int r0, int c0,
-                                           int rows, int cols) {
-    for (int e = threadIdx.x; e < FW_B * FW_B; e += FW_NT) {
-        const int i = e / FW_B, j = e % FW_B;
-        dst[i][j] = (i < rows && j < cols) ? D[(long)(r0 + i) * ld + c0 + j]
-                                           : Ring<BTAS_MIN_PLUS, T>::absent();
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1: a loop whose index
+// is a constant in every copy of the body (register arrays stay in registers
+// where #pragma unroll would give up on a body this large).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
     }
 }
 
+// Phases 1 and 2: four waves per 64x64 block, the block in registers.  Lane
+// l of wave w holds 16 entries v[0..15] of line l (a row or a column of the
+// block), the 16 lines 16w..16w+15 of the other direction.  At pivot z the
+// entries of the pivot's line that a wave needs sit in its lane z
+// (readlane); the other operand is one value per lane.  The pivot loop is a
+// static_for, so register indices are constants.
+
 template <typename T>
-__device__ __forceinline__ void store_block(const T (*src)[FW_B], T* D, long ld, int r0, int c0,
-                                            int rows, int cols) {
-    for (int e = threadIdx.x; e < FW_B * FW_B; e += FW_NT) {
-        const int i = e / FW_B, j = e % FW_B;
-        if (i < rows && j < cols) D[(long)(r0 + i) * ld + c0 + j] = src[i][j];
-    }
+__device__ __forceinline__ T lane_value(T x, int lane) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
 }
 
 // Phase 1: the diagonal block of pivot block kb, pivots in ascending order.
-// Thread t owns entries (t/64 + 4r, t%64): a wave shares the row, so the
-// column-z operand is a broadcast and the row-z operand 64 consecutive words.
+// Lane j of wave w holds column j, rows 16w+r.  d(i,z) for the wave's rows is
+// in its lane z; d(z,j) is row z, held by wave z/16, passed through LDS.
 template <typename T>
-__global__ __launch_bounds__(FW_NT) void fw_phase1_kernel(int n, T* D, long ld, int kb) {
-    __shared__ T blk[FW_B][FW_B];
+__global__ __launch_bounds__(256) void fw_phase1_kernel(int n, T* D, long ld, int kb) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    __shared__ T rowz[2][FW_B];
     const int k0 = kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
-    load_block(blk, D, ld, k0, k0, ks, ks);
-    __syncthreads();
-    const int i0 = threadIdx.x / FW_B, j = threadIdx.x % FW_B;
-    for (int z = 0; z < ks; ++z) {
-        const T bz = blk[z][j];
+    const int j = threadIdx.x % 64, w = threadIdx.x / 64;
+    T v[16];
 #pragma unroll
-        for (int r = 0; r < FW_PER; ++r) {
-            const int i = i0 + r * (FW_NT / FW_B);
-            blk[i][j] = relax(blk[i][z], bz, blk[i][j]);
-        }
-        __syncthreads();
+    for (int r = 0; r < 16; ++r) {
+        const int i = 16 * w + r;
+        v[r] = (i < ks && j < ks) ? D[(long)(k0 + i) * ld + k0 + j] : R::absent();
     }
-    store_block(blk, D, ld, k0, k0, ks, ks);
+    static_for<0, FW_B>([&](auto zc) {
+        constexpr int z = decltype(zc)::value;
+        if (z < ks) {
+            if (w == z / 16) rowz[z & 1][j] = v[z % 16];
+            __syncthreads();  // this slot is written again two pivots later
+            const T dzj = rowz[z & 1][j];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = relax(lane_value(v[r], z), dzj, v[r]);
+        }
+    });
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 16 * w + r;
+        if (i < ks && j < ks) D[(long)(k0 + i) * ld + k0 + j] = v[r];
+    }
 }
 
-// Phase 2: workgroup w < nb-1 takes block (kb, J) of block-row kb, the others
+// Phase 2: workgroup b < nb-1 takes block (kb, J) of block-row kb, the others
 // block (I, kb) of block-column kb (J, I skip kb); each relaxes its block
 // against the finished diagonal block, pivots in ascending order.
+//   block-row:    own(x,j) <- own(x,j) (+) dia(x,z) (.) own(z,j): lane x holds
+//                 row x, columns 16w+c; own(z,j) is in lane z;
+//   block-column: own(i,x) <- own(i,x) (+) own(i,z) (.) dia(z,x): lane x holds
+//                 column x, rows 16w+c; own(i,z) is in lane z.
+// The per-lane operand L[z][x] (dia(x,z), resp. dia(z,x)) is constant, so no
+// wave waits for another after the set-up.
 template <typename T>
-__global__ __launch_bounds__(FW_NT) void fw_phase2_kernel(int n, T* D, long ld, int kb, int nb) {
-    __shared__ T dia[FW_B][FW_B];
-    __shared__ T own[FW_B][FW_B];
+__global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, int kb, int nb) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    constexpr int LP = FW_B + 1;  // the transposed fill walks a column
+    __shared__ T L[FW_B][LP];
     const int k0 = kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
     const bool row = blockIdx.x < (unsigned)(nb - 1);
     int b = row ? blockIdx.x : blockIdx.x - (nb - 1);
     b += b >= kb ? 1 : 0;
     const int o0 = b * FW_B, os = n - o0 < FW_B ? n - o0 : FW_B;
-    const int r0 = row ? k0 : o0, c0 = row ? o0 : k0;
-    const int rows = row ? ks : os, cols = row ? os : ks;
-    load_block(dia, D, ld, k0, k0, ks, ks);
-    load_block(own, D, ld, r0, c0, rows, cols);
-    __syncthreads();
-    const int i0 = threadIdx.x / FW_B, j = threadIdx.x % FW_B;
-    for (int z = 0; z < ks; ++z) {
-        if (row) {
-            // own(i,j) <- own(i,j) (+) dia(i,z) (.) own(z,j)
-            const T bz = own[z][j];
-#pragma unroll
-            for (int r = 0; r < FW_PER; ++r) {
-                const int i = i0 + r * (FW_NT / FW_B);
-                own[i][j] = relax(dia[i][z], bz, own[i][j]);
-            }
-        } else {
-            // own(i,j) <- own(i,j) (+) own(i,z) (.) dia(z,j)
-            const T bz = dia[z][j];
-#pragma unroll
-            for (int r = 0; r < FW_PER; ++r) {
-                const int i = i0 + r * (FW_NT / FW_B);
-                own[i][j] = relax(own[i][z], bz, own[i][j]);
-            }
-        }
-        __syncthreads();
+    const int x = threadIdx.x % 64, w = threadIdx.x / 64;
+    for (int e = threadIdx.x; e < FW_B * FW_B; e += 256) {
+        const int i = e / FW_B, c = e % FW_B;
+        const T d = (i < ks && c < ks) ? D[(long)(k0 + i) * ld + k0 + c] : R::absent();
+        if (row)
+            L[c][i] = d;
+        else
+            L[i][c] = d;
     }
-    store_block(own, D, ld, r0, c0, rows, cols);
+    T v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int o = 16 * w + c;
+        if (row)
+            v[c] = (x < ks && o < os) ? D[(long)(k0 + x) * ld + o0 + o] : R::absent();
+        else
+            v[c] = (o < os && x < ks) ? D[(long)(o0 + o) * ld + k0 + x] : R::absent();
+    }
+    __syncthreads();
+    static_for<0, FW_B>([&](auto zc) {
+        constexpr int z = decltype(zc)::value;
+        if (z < ks) {
+            const T lz = L[z][x];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) v[c] = relax(lz, lane_value(v[c], z), v[c]);
+        }
+    });
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int o = 16 * w + c;
+        if (row) {
+            if (x < ks && o < os) D[(long)(k0 + x) * ld + o0 + o] = v[c];
+        } else {
+            if (o < os && x < ks) D[(long)(o0 + o) * ld + k0 + x] = v[c];
+        }
+    }
 }
 
-// Tile (I, J) of phase 3 for workgroup t of (nb-1)^2 (I, J skip kb).
-__device__ __forceinline__ void phase3_tile(int t, int kb, int nb, int& m0, int& n0) {
-    int I = t / (nb - 1), J = t % (nb - 1);
-    I += I >= kb ? 1 : 0;
-    J += J >= kb ? 1 : 0;
-    m0 = I * FW_B;
-    n0 = J * FW_B;
+// Which 64x64 blocks an update launch covers; every covered block (I,J) gets
+// D_IJ <- D_IJ (+) D_I,kb (.) D_kb,J with the k-range of pivot block kb.
+//   full:  every I != kb, J != kb                       ((nb-1)^2 blocks)
+//   strip: block-row rb (J != skip) and block-column rb (I != rb, I != skip)
+//          (2nb-3 blocks; rb != skip)
+struct UpdateSel {
+    int kb, nb;
+    int rb, skip;  // rb < 0: full
+};
+
+__device__ __forceinline__ void select_block(const UpdateSel& u, int t, int& I, int& J) {
+    if (u.rb < 0) {
+        I = t / (u.nb - 1);
+        J = t % (u.nb - 1);
+        I += I >= u.kb ? 1 : 0;
+        J += J >= u.kb ? 1 : 0;
+    } else if (t < u.nb - 1) {
+        I = u.rb;
+        J = t + (t >= u.skip ? 1 : 0);
+    } else {
+        const int lo = u.rb < u.skip ? u.rb : u.skip, hi = u.rb < u.skip ? u.skip : u.rb;
+        I = t - (u.nb - 1);
+        I += I >= lo ? 1 : 0;
+        I += I >= hi ? 1 : 0;
+        J = u.rb;
+    }
 }
 
-// Phase 3, fp32 with n a multiple of 64: every tile full, direct LDS loads.
+__host__ __forceinline__ unsigned update_blocks(const UpdateSel& u) {
+    return u.rb < 0 ? (unsigned)((long)(u.nb - 1) * (u.nb - 1)) : (unsigned)(2 * u.nb - 3);
+}
+
+// fp32 with n a multiple of 64: every block full, direct LDS loads.
 template <int SR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_phase3_direct_kernel(
-    int n, float* D, long ld, int kb, int nb) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_update_direct_kernel(
+    int n, float* D, long ld, UpdateSel u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    int m0, n0;
-    phase3_tile(blockIdx.x, kb, nb, m0, n0);
-    const int k0 = kb * FW_B;
+    int I, J;
+    select_block(u, blockIdx.x, I, J);
+    const int k0 = u.kb * FW_B;
     TileArgs<float> a{n, n, FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
-    GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, SR>::run(a, m0, n0, smem_raw);
+    GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, SR>::run(a, I * FW_B, J * FW_B, smem_raw);
 }
 
-// Phase 3, general: the staged one-wave tile with bounds checks.
+// General: the staged one-wave tile with bounds checks.
 template <typename T, bool VEC>
-__global__ __launch_bounds__(64) void fw_phase3_kernel(int n, T* D, long ld, int kb, int nb) {
+__global__ __launch_bounds__(64) void fw_update_kernel(int n, T* D, long ld, UpdateSel u) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int I, J;
+    select_block(u, blockIdx.x, I, J);
+    const int k0 = u.kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
+    TileArgs<T> a{n, n, ks, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
+    GemmTile<GemmCfg<64, 64, 8, 8, 8>, T, T, BTAS_MIN_PLUS, VEC>::run(a, I * FW_B, J * FW_B, smem_raw);
+}
+
+// Pivot-pair update: every 128x128 tile (I,J) outside tile-row and
+// tile-column sb gets D_IJ <- D_IJ (+) D_I,P (.) D_P,J, P the 128 pivots of
+// blocks 2sb and 2sb+1 (fewer at a ragged end): both blocks' updates of
+// the same entries in one pass.
+__device__ __forceinline__ void pair_tile(int t, int sb, int nb2, int& m0, int& n0) {
+    int I = t / (nb2 - 1), J = t % (nb2 - 1);
+    I += I >= sb ? 1 : 0;
+    J += J >= sb ? 1 : 0;
+    m0 = I * 2 * FW_B;
+    n0 = J * 2 * FW_B;
+}
+
+template <int SR>
+__global__ __launch_bounds__(CfgL::NT) __attribute__((amdgpu_waves_per_eu(4))) void fw_pair_direct_kernel(
+    int n, float* D, long ld, int sb, int nb2) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int m0, n0;
-    phase3_tile(blockIdx.x, kb, nb, m0, n0);
-    const int k0 = kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
+    pair_tile(blockIdx.x, sb, nb2, m0, n0);
+    const int k0 = sb * 2 * FW_B;
+    TileArgs<float> a{n, n, 2 * FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
+    GemmTileDirect<CfgL, SR>::run(a, m0, n0, smem_raw);
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(CfgL::NT) void fw_pair_kernel(int n, T* D, long ld, int sb, int nb2) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int m0, n0;
+    pair_tile(blockIdx.x, sb, nb2, m0, n0);
+    const int k0 = sb * 2 * FW_B, ks = n - k0 < 2 * FW_B ? n - k0 : 2 * FW_B;
     TileArgs<T> a{n, n, ks, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
-    GemmTile<GemmCfg<64, 64, 8, 8, 8>, T, T, BTAS_MIN_PLUS, VEC>::run(a, m0, n0, smem_raw);
+    GemmTile<CfgL, T, T, BTAS_MIN_PLUS, VEC>::run(a, m0, n0, smem_raw);
 }
 
 template <typename T>
+struct FwLaunch {
+    int n, nb;
+    T* D;
+    long ld;
+    hipStream_t s;
+    bool vec;
+
+    void phase12(int kb) const {
+        hipLaunchKernelGGL(fw_phase1_kernel<T>, dim3(1), dim3(256), 0, s, n, D, ld, kb);
+        if (nb > 1)
+            hipLaunchKernelGGL(fw_phase2_kernel<T>, dim3(2 * (nb - 1)), dim3(256), 0, s, n, D, ld, kb,
+                               nb);
+    }
+
+    void update(const UpdateSel& u) const {
+        const unsigned blocks = update_blocks(u);
+        if (blocks == 0) return;
+        if constexpr (std::is_same_v<T, float>) {
+            if (vec && n % FW_B == 0) {
+                using DT = GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, BTAS_MIN_PLUS>;
+                hipLaunchKernelGGL((fw_update_direct_kernel<BTAS_MIN_PLUS>), dim3(blocks), dim3(64),
+                                   DT::lds_bytes, s, n, D, ld, u);
+                return;
+            }
+        }
+        using ST = GemmCfg<64, 64, 8, 8, 8>;
+        if (vec)
+            hipLaunchKernelGGL((fw_update_kernel<T, true>), dim3(blocks), dim3(64), ST::lds_bytes, s,
+                               n, D, ld, u);
+        else
+            hipLaunchKernelGGL((fw_update_kernel<T, false>), dim3(blocks), dim3(64), ST::lds_bytes,
+                               s, n, D, ld, u);
+    }
+
+    void pair_update(int sb) const {
+        const int nb2 = (n + 2 * FW_B - 1) / (2 * FW_B);
+        const unsigned tiles = (unsigned)((long)(nb2 - 1) * (nb2 - 1));
+        if (tiles == 0) return;
+        if constexpr (std::is_same_v<T, float>) {
+            if (vec && n % (2 * FW_B) == 0) {
+                using DT = GemmTileDirect<CfgL, BTAS_MIN_PLUS>;
+                hipLaunchKernelGGL((fw_pair_direct_kernel<BTAS_MIN_PLUS>), dim3(tiles), dim3(CfgL::NT),
+                                   DT::lds_bytes, s, n, D, ld, sb, nb2);
+                return;
+            }
+        }
+        if (vec)
+            hipLaunchKernelGGL((fw_pair_kernel<T, true>), dim3(tiles), dim3(CfgL::NT), CfgL::lds_bytes,
+                               s, n, D, ld, sb, nb2);
+        else
+            hipLaunchKernelGGL((fw_pair_kernel<T, false>), dim3(tiles), dim3(CfgL::NT), CfgL::lds_bytes,
+                               s, n, D, ld, sb, nb2);
+    }
+};
+
+// Pivot blocks in pairs (K, K+1).  The sequential order's effects are kept
+// exactly; only the two bulk updates of entries outside both blocks' rows
+// and columns are fused, which leaves every entry the same min of the same
+// rounded terms:
+//   phases 1-2 of K;
+//   K's update of block-row and block-column K+1 (they are K+1's pivots);
+//   phases 1-2 of K+1;
+//   one k=128 update of every tile outside rows/columns K, K+1, reading
+//     row/column K as phase 2 of K left them and row/column K+1 as phase 2
+//     of K+1 left them;
+//   then K+1's update of block-row and block-column K (deferred so that the
+//     fused update read their earlier values).
+// An odd last block runs the three plain phases.
+template <typename T>
 hipError_t fw_typed(int n, T* D, long ld, hipStream_t s) {
     const int nb = (n + FW_B - 1) / FW_B;
-    const bool vec = ld % 4 == 0 && (uintptr_t)D % 16 == 0;
-    const bool direct = std::is_same_v<T, float> && vec && n % FW_B == 0;
-    using DT = GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, BTAS_MIN_PLUS>;
-    using ST = GemmCfg<64, 64, 8, 8, 8>;
-    for (int kb = 0; kb < nb; ++kb) {
-        hipLaunchKernelGGL(fw_phase1_kernel<T>, dim3(1), dim3(FW_NT), 0, s, n, D, ld, kb);
-        if (nb > 1) {
-            hipLaunchKernelGGL(fw_phase2_kernel<T>, dim3(2 * (nb - 1)), dim3(FW_NT), 0, s, n, D, ld,
-                               kb, nb);
-            const unsigned tiles = (unsigned)((long)(nb - 1) * (nb - 1));
-            if constexpr (std::is_same_v<T, float>) {
-                if (direct) {
-                    hipLaunchKernelGGL((fw_phase3_direct_kernel<BTAS_MIN_PLUS>), dim3(tiles), dim3(64),
-                                       DT::lds_bytes, s, n, D, ld, kb, nb);
-                    continue;
-                }
-            }
-            if (vec)
-                hipLaunchKernelGGL((fw_phase3_kernel<T, true>), dim3(tiles), dim3(64), ST::lds_bytes,
-                                   s, n, D, ld, kb, nb);
-            else
-                hipLaunchKernelGGL((fw_phase3_kernel<T, false>), dim3(tiles), dim3(64), ST::lds_bytes,
-                                   s, n, D, ld, kb, nb);
-        }
+    const FwLaunch<T> L{n, nb, D, ld, s, ld % 4 == 0 && (uintptr_t)D % 16 == 0};
+    int kb = 0;
+    for (; kb + 1 < nb; kb += 2) {
+        L.phase12(kb);
+        L.update(UpdateSel{kb, nb, kb + 1, kb});
+        L.phase12(kb + 1);
+        L.pair_update(kb / 2);
+        L.update(UpdateSel{kb + 1, nb, kb, kb + 1});
+    }
+    if (kb < nb) {
+        L.phase12(kb);
+        if (nb > 1) L.update(UpdateSel{kb, nb, -1, -1});
     }
     return hipGetLastError();
 }

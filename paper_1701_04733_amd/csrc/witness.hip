@@ -11,12 +11,13 @@
 // as that product's and K is unique.
 //
 // A 64x64 output tile per 256-thread workgroup, 4x4 outputs per thread, k in
-// blocks of 16 staged through LDS.  Each k-block is first reduced per output
+// blocks of 8 staged through LDS.  Each k-block is first reduced per output
 // with three-way min/max (the cost of the value-only product); only an output
 // whose block extreme strictly beats its running best searches the block
-// again for the first index attaining it.  The running best improves rarely
-// after the first blocks (about log(k) times per output for unordered data),
-// so the search costs a fraction of the main loop.
+// again, branch-free, for the first index attaining it.  The running best of
+// one output improves in about log(k) blocks for unordered data; a wave
+// searches a slot when any of its 64 lanes needs it, which short blocks keep
+// rare (blocks of 8 and 4 measured equal at 8192^3, 16 slower).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -28,10 +29,12 @@ namespace btas {
 
 namespace {
 
-constexpr int WT_BM = 64, WT_BN = 64, WT_BK = 16;
+constexpr int WT_BM = 64, WT_BN = 64, WT_BK = 8;
 constexpr int WT_NT = 256;
 constexpr int WT_TM = 4, WT_TN = 4;
+constexpr int WT_VW = WT_BM * WT_BK / WT_NT;  // staged elements per thread and operand
 constexpr int WT_APAD = 4;  // As rows padded: transposed stores hit 64 banks
+static_assert(WT_VW >= 1 && WT_VW <= 4 && WT_BK % 2 == 0, "staging layout");
 
 template <typename T>
 struct WitnessArgs {
@@ -82,33 +85,37 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
     const int m0 = tm * WT_BM, n0 = tn * WT_BN;
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
 
-    // staging: A element (ar, ac4..ac4+3) of the 64x16 block, B (br, bc4..)
-    const int ar = tid / 4, ac4 = (tid % 4) * 4;
-    const int br = tid / 16, bc4 = (tid % 16) * 4;
-    T ra[4], rb[4];
+    // staging: each thread moves WT_VW consecutive elements of A (row ar,
+    // columns ac..) and of B (row br, columns bc..) per k-block
+    typedef T V __attribute__((ext_vector_type(WT_VW)));
+    const int ar = tid / (WT_BK / WT_VW), ac = (tid % (WT_BK / WT_VW)) * WT_VW;
+    const int br = tid / (WT_BN / WT_VW), bc = (tid % (WT_BN / WT_VW)) * WT_VW;
+    T ra[WT_VW], rb[WT_VW];
 
     auto load = [&](int k0) {
-        const int gi = m0 + ar, gp = k0 + ac4;
-        if (VEC && gi < a.m && gp + 4 <= a.k) {
-            const auto v = *reinterpret_cast<const HIP_vector_type<T, 4>*>(a.A + (long)gi * a.lda + gp);
-            ra[0] = v.x; ra[1] = v.y; ra[2] = v.z; ra[3] = v.w;
+        const int gi = m0 + ar, gp = k0 + ac;
+        if (VEC && gi < a.m && gp + WT_VW <= a.k) {
+            const V v = *reinterpret_cast<const V*>(a.A + (long)gi * a.lda + gp);
+#pragma unroll
+            for (int q = 0; q < WT_VW; ++q) ra[q] = v[q];
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < WT_VW; ++q)
                 ra[q] = (gi < a.m && gp + q < a.k) ? a.A[(long)gi * a.lda + gp + q] : R::absent();
         }
         if constexpr (SUCC) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < WT_VW; ++q)
                 if (gi == gp + q) ra[q] = R::absent();
         }
-        const int gk = k0 + br, gj = n0 + bc4;
-        if (VEC && gk < a.k && gj + 4 <= a.n) {
-            const auto v = *reinterpret_cast<const HIP_vector_type<T, 4>*>(a.B + (long)gk * a.ldb + gj);
-            rb[0] = v.x; rb[1] = v.y; rb[2] = v.z; rb[3] = v.w;
+        const int gk = k0 + br, gj = n0 + bc;
+        if (VEC && gk < a.k && gj + WT_VW <= a.n) {
+            const V v = *reinterpret_cast<const V*>(a.B + (long)gk * a.ldb + gj);
+#pragma unroll
+            for (int q = 0; q < WT_VW; ++q) rb[q] = v[q];
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < WT_VW; ++q)
                 rb[q] = (gk < a.k && gj + q < a.n) ? a.B[(long)gk * a.ldb + gj + q] : R::absent();
         }
     };
@@ -129,8 +136,10 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
         const int k0 = kb * WT_BK;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) As[ac4 + q][ar] = ra[q];
-        *reinterpret_cast<HIP_vector_type<T, 4>*>(&Bs[br][bc4]) = HIP_vector_type<T, 4>(rb[0], rb[1], rb[2], rb[3]);
+        for (int q = 0; q < WT_VW; ++q) {
+            As[ac + q][ar] = ra[q];
+            Bs[br][bc + q] = rb[q];
+        }
         __syncthreads();
         if (kb + 1 < nkb) load(k0 + WT_BK);
 
@@ -165,14 +174,20 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
             for (int c = 0; c < WT_TN; ++c) {
                 const T v = R::finish(bm[r][c]);
                 if (better<SR>(v, acc[r][c])) {
-                    int kk = 0;
-                    T s = R::mul(As[0][ty * WT_TM + r], Bs[0][tx * WT_TN + c]);
-                    while (!(s == bm[r][c]) && kk + 1 < WT_BK) {
-                        ++kk;
-                        s = R::mul(As[kk][ty * WT_TM + r], Bs[kk][tx * WT_TN + c]);
+                    // every term of the block, last to first, so the first
+                    // match is the one kept; no dependent LDS round trips
+                    int first = 0;
+                    T sf = bm[r][c];
+#pragma unroll
+                    for (int kk = WT_BK - 1; kk >= 0; --kk) {
+                        const T s = R::mul(As[kk][ty * WT_TM + r], Bs[kk][tx * WT_TN + c]);
+                        if (s == bm[r][c]) {
+                            first = kk;
+                            sf = s;
+                        }
                     }
-                    acc[r][c] = s;
-                    idx[r][c] = k0 + kk;
+                    acc[r][c] = sf;
+                    idx[r][c] = k0 + first;
                 }
             }
     }
