@@ -155,6 +155,14 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *   BTAS_APSP_EARLY_EXIT: stop after the first step whose output equals its
  *     input bit for bit (that step is counted).  Same result as fixed T.
  *     Reads a device flag back after every step (host synchronisation).
+ *     On this path, for 4096 <= n <= 16384, a squaring whose input has at
+ *     most n^2/8 finite entries and whose term count makes it cheaper runs
+ *     as a sparse product (the input compressed to rows of finite entries,
+ *     each output row accumulated in LDS); the result is bit-identical (the
+ *     same min of the same rounded terms).  Its workspace (n^2 + 8n bytes)
+ *     is kept by the handle; if it cannot be allocated the step runs dense.
+ *     BTAS_SPARSE_STEPS=0 in the environment disables it; =force uses it
+ *     for any n <= 16384 while the density limit holds.
  *   BTAS_APSP_CHECK_NEG_CYCLE: after the last step, return
  *     BTAS_WARN_NEG_CYCLE if some D_ii < 0 (synchronises).
  *   BTAS_APSP_GRAPH: capture the whole fixed-T solve into a hipGraph on the

@@ -47,6 +47,8 @@ struct btas_ctx {
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan
     // (dtype, size bucket, log2 of the plan's launch size) -> autotune result
     std::map<std::tuple<int, int, int>, btas::BucketTiming> tile_timing;
+    void* sp_ws = nullptr;               // sparse squarings: row counts, row pointers, CSR
+    size_t sp_bytes = 0;
     hipGraph_t apsp_graph = nullptr;     // last captured single-solve graph (BTAS_APSP_GRAPH)
     hipGraphExec_t apsp_exec = nullptr;
     uint64_t apsp_key = 0;
@@ -62,7 +64,10 @@ constexpr int FLAG_STEP_WIDE = 8;  // APSP: slot 8 + t describes D_t (t = 0..T <
 constexpr int FLAG_RESIDENT = 44;  // single-launch solve: +0 error, +1 steps, +1+t squaring t changed D
 constexpr int FLAG_BARRIER = 64;   // its device-wide barrier: 2 + (up to 64 groups) counters
 constexpr int FLAG_RESIDENT_END = FLAG_BARRIER + 2 + 64;
+constexpr int FLAG_SPARSE = 136;   // sparse squarings: two 64-bit counters (finite entries, terms)
 constexpr int kNumFlags = 192;
+static_assert(FLAG_RESIDENT_END <= FLAG_SPARSE && FLAG_SPARSE % 2 == 0 && FLAG_SPARSE + 4 <= kNumFlags,
+              "flag slots overlap");
 static_assert(FLAG_RESIDENT + 2 + 9 <= FLAG_BARRIER, "slots for T(500) = 9 squarings");
 
 struct DeviceGuard {

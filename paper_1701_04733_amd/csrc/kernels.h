@@ -106,6 +106,21 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
 int fw_block_size();
 hipError_t launch_floyd_warshall(int dt, int n, void* D, long ld, hipStream_t s);
 
+// Sparse-aware APSP squarings (csrc/sparse.hip), min-plus.  count: rownnz[i]
+// = finite entries of row i of D, counters[0] += total.  build: row pointers
+// (n + 1) and the CSR of D (capacity >= the total), counters[1] += the
+// squaring's term count.  square: E = D (+) D (.) D from the CSR, row by row
+// (LDS of sparse_step_lds_bytes(n) per workgroup), changed / wide_out flags
+// as in the dense product.
+size_t sparse_step_lds_bytes(int n);
+hipError_t launch_sparse_count(int dt, int n, const void* D, long ld, int* rownnz,
+                               unsigned long long* counters, hipStream_t s);
+hipError_t launch_sparse_build(int dt, int n, const void* D, long ld, const int* rownnz, int* rowptr,
+                               int* cols, void* vals, unsigned long long* counters, hipStream_t s);
+hipError_t launch_sparse_square(int dt, int n, const void* D, long ld, void* E, long lde,
+                                const int* rowptr, const int* cols, const void* vals, int* changed,
+                                int* wide_out, hipStream_t s);
+
 // Tropical product with witnesses (csrc/witness.hip): C <- C (+) A (.) B and,
 // where an entry strictly improves, K <- the smallest p attaining it.
 hipError_t launch_gemm_witness(int sr, int dt, int m, int n, int k, const void* A, long lda,
