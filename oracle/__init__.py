@@ -66,6 +66,11 @@ def _lib():
             getattr(lib, name).argtypes = [I, L, L, L, P, L, P, L, P, L, P, L]
         for name in ("or_successors_i32", "or_successors_f32"):
             getattr(lib, name).argtypes = [L, P, L, P, L, P, L]
+        for name in ("or_closure_i32", "or_closure_f32"):
+            getattr(lib, name).argtypes = [I, L, P, L, P, L, I, I, ctypes.POINTER(I)]
+        lib.or_cycle_mean_i32.argtypes = [L, P, L, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]
+        lib.or_cycle_mean_f32.argtypes = [L, P, L, ctypes.POINTER(ctypes.c_double)]
         lib.or_apsp_steps.argtypes = [L]
         lib.or_num_threads.restype = I
         lib.or_set_num_threads.argtypes = [I]
@@ -227,6 +232,40 @@ def apsp(W: np.ndarray, early_exit: bool = False, check_neg_cycle: bool = False)
             int(check_neg_cycle), ctypes.byref(steps))
     _check(st, "apsp", allow=(OK, WNEGCYCLE))
     return D, steps.value, st
+
+
+def closure(semiring: str, W: np.ndarray, early_exit: bool = False, check: bool = False):
+    """(I (+) W)^(2^s) by repeated squaring over the given semiring (min-plus:
+    shortest distances; max-plus: heaviest walks, the longest paths of a
+    graph without positive cycles).  Returns (D, steps, status)."""
+    W = _mat(W)
+    n = W.shape[0]
+    if W.shape != (n, n):
+        raise ValueError("W must be square")
+    D = np.empty((n, n), dtype=W.dtype)
+    steps = ctypes.c_int(0)
+    fn = getattr(_lib(), "or_closure_" + _sfx(W.dtype))
+    st = fn(SEMIRINGS[semiring], n, _ptr(W), max(1, _ld(W)), _ptr(D), max(1, n), int(early_exit),
+            int(check), ctypes.byref(steps))
+    _check(st, "closure", allow=(OK, WNEGCYCLE))
+    return D, steps.value, st
+
+
+def cycle_mean(A: np.ndarray):
+    """Maximum cycle mean of a max-plus matrix (Karp).  int32: (num, den)
+    exactly, den = 0 when there is no cycle; float32: a float (-inf: none)."""
+    A = _mat(A)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    if A.dtype == np.int32:
+        num, den = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib().or_cycle_mean_i32(n, _ptr(A), max(1, _ld(A)), ctypes.byref(num),
+                                        ctypes.byref(den)), "cycle_mean")
+        return num.value, den.value
+    lam = ctypes.c_double(0.0)
+    _check(_lib().or_cycle_mean_f32(n, _ptr(A), max(1, _ld(A)), ctypes.byref(lam)), "cycle_mean")
+    return lam.value
 
 
 def floyd_warshall(W: np.ndarray) -> np.ndarray:

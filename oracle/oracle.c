@@ -697,3 +697,179 @@ int or_successors_f32(long n, const float *W, long ldw, const float *D, long ldd
     }
     return OR_OK;
 }
+
+/* ============ Closure over either semiring (Sec. I semirings, Sec. III) ===
+ * (I (+) W)^(2^s) by repeated squaring, as or_apsp_* but for a chosen
+ * semiring.  Min-plus gives shortest distances; max-plus gives the heaviest
+ * walks of at most 2^s edges, which for a graph without positive cycles (a
+ * DAG, as in critical-path scheduling) are the longest paths.  I holds 0 on
+ * the diagonal and the absent value elsewhere, so D_ii starts at
+ * min(W_ii, 0), resp. max(W_ii, 0).  With check set, a diagonal entry past 0
+ * on the improving side (min-plus < 0, max-plus > 0) reports a cycle that
+ * makes the closure diverge (OR_WNEGCYCLE).
+ */
+static int improves_zero_i32(int sr, int32_t x) { return sr == OR_MIN_PLUS ? x < 0 : x > 0; }
+static int improves_zero_f32(int sr, float x) { return sr == OR_MIN_PLUS ? x < 0.0f : x > 0.0f; }
+
+int or_closure_i32(int sr, long n, const int32_t *W, long ldw, int32_t *D, long ldd,
+                   int early_exit, int check, int *steps_out) {
+    if (!sr_ok(sr) || n < 0 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (steps_out) *steps_out = 0;
+    if (n == 0) return OR_OK;
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * n * n);
+    int32_t *nxt = (int32_t *)malloc(sizeof(int32_t) * n * n);
+    if (!cur || !nxt) { free(cur); free(nxt); return OR_EARG; }
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) {
+            int32_t w = W[i * ldw + j];
+            if (i == j && improves_zero_i32(sr, 0 - w)) w = 0;   /* (+) with the identity's 0 */
+            cur[i * n + j] = w;
+        }
+    int T = or_apsp_steps(n), steps = 0, status = OR_OK;
+    for (int t = 0; t < T; ++t) {
+        memcpy(nxt, cur, sizeof(int32_t) * n * n);
+        status = or_gemm_i32(sr, n, n, n, cur, n, cur, n, nxt, n);
+        if (status != OR_OK) break;
+        ++steps;
+        int same = memcmp(nxt, cur, sizeof(int32_t) * n * n) == 0;
+        int32_t *tmp = cur; cur = nxt; nxt = tmp;
+        if (early_exit && same) break;
+    }
+    if (status == OR_OK) {
+        for (long i = 0; i < n; ++i)
+            for (long j = 0; j < n; ++j) D[i * ldd + j] = cur[i * n + j];
+        if (check)
+            for (long i = 0; i < n; ++i)
+                if (improves_zero_i32(sr, cur[i * n + i])) { status = OR_WNEGCYCLE; break; }
+    }
+    if (steps_out) *steps_out = steps;
+    free(cur); free(nxt);
+    return status;
+}
+
+int or_closure_f32(int sr, long n, const float *W, long ldw, float *D, long ldd,
+                   int early_exit, int check, int *steps_out) {
+    if (!sr_ok(sr) || n < 0 || (n > 0 && (ldw < n || ldd < n))) return OR_EARG;
+    if (steps_out) *steps_out = 0;
+    if (n == 0) return OR_OK;
+    float *cur = (float *)malloc(sizeof(float) * n * n);
+    float *nxt = (float *)malloc(sizeof(float) * n * n);
+    if (!cur || !nxt) { free(cur); free(nxt); return OR_EARG; }
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < n; ++j) {
+            float w = W[i * ldw + j];
+            if (i == j && improves_zero_f32(sr, -w)) w = 0.0f;
+            cur[i * n + j] = w;
+        }
+    int T = or_apsp_steps(n), steps = 0, status = OR_OK;
+    for (int t = 0; t < T; ++t) {
+        memcpy(nxt, cur, sizeof(float) * n * n);
+        status = or_gemm_f32(sr, n, n, n, cur, n, cur, n, nxt, n);
+        if (status != OR_OK) break;
+        ++steps;
+        int same = memcmp(nxt, cur, sizeof(float) * n * n) == 0;
+        float *tmp = cur; cur = nxt; nxt = tmp;
+        if (early_exit && same) break;
+    }
+    if (status == OR_OK) {
+        for (long i = 0; i < n; ++i)
+            for (long j = 0; j < n; ++j) D[i * ldd + j] = cur[i * n + j];
+        if (check)
+            for (long i = 0; i < n; ++i)
+                if (improves_zero_f32(sr, cur[i * n + i])) { status = OR_WNEGCYCLE; break; }
+    }
+    if (steps_out) *steps_out = steps;
+    free(cur); free(nxt);
+    return status;
+}
+
+/* ============ Maximum cycle mean (max-plus eigenvalue), Karp's theorem ====
+ * For a max-plus matrix A (A_vu the weight of edge v -> u), the largest mean
+ * weight of a cycle is the max-plus eigenvalue of A, the cycle time of the
+ * system x(k+1) = A (x) x(k).  With x_0 = 0 (every vertex a start) and
+ * x_{k+1} = A (x) x_k (x_k(v) = heaviest walk of exactly k edges from v):
+ *     lambda = max over v with x_n(v) present of
+ *              min over k < n with x_k(v) present of (x_n(v) - x_k(v)) / (n - k),
+ * and no v has x_n(v) present iff the graph has no cycle.  int32: exact
+ * integers, lambda returned as the fraction num/den in lowest terms (den = 0:
+ * no cycle);
+ * the walk weights x_k must stay within the domain bound (n * max|A| <=
+ * 2^29 - 1).  float32: every x_{k+1}(v) is a max of single binary32 adds, and
+ * lambda is evaluated in binary64 as ((double)x_n - (double)x_k) / (n - k)
+ * (-inf: no cycle).
+ */
+int or_cycle_mean_i32(long n, const int32_t *A, long lda, int64_t *num, int64_t *den) {
+    if (n < 0 || (n > 0 && lda < n)) return OR_EARG;
+    if (!scan_i32(OR_MAX_PLUS, n, n, A, lda)) return OR_EDOMAIN;
+    int64_t *x = (int64_t *)malloc(sizeof(int64_t) * (n + 1) * (n > 0 ? n : 1));
+    if (!x) return OR_EARG;
+    for (long v = 0; v < n; ++v) x[v] = 0;
+    for (long k = 0; k < n; ++k)
+        for (long v = 0; v < n; ++v) {
+            int64_t best = OR_NINF64;
+            for (long u = 0; u < n; ++u)
+                best = i64_oplus(OR_MAX_PLUS, best,
+                                 i64_otimes(OR_MAX_PLUS, i32_lift(OR_MAX_PLUS, A[v * lda + u]),
+                                            x[k * n + u]));
+            if (best != OR_NINF64 && (best > OR_FINITE_MAX || best < -OR_FINITE_MAX)) {
+                free(x);
+                return OR_EDOMAIN;
+            }
+            x[(k + 1) * n + v] = best;
+        }
+    int64_t bn = 0, bd = 0;  /* best lambda so far; bd = 0: none */
+    for (long v = 0; v < n; ++v) {
+        const int64_t xn = x[n * n + v];
+        if (xn == OR_NINF64) continue;
+        int64_t mn = 0, md = 0;  /* min over k */
+        for (long k = 0; k < n; ++k) {
+            const int64_t xk = x[k * n + v];
+            if (xk == OR_NINF64) continue;
+            const int64_t p = xn - xk, q = n - k;
+            if (md == 0 || p * md < mn * q) { mn = p; md = q; }
+        }
+        if (md != 0 && (bd == 0 || mn * bd > bn * md)) { bn = mn; bd = md; }
+    }
+    if (bd != 0) {  /* lowest terms, so that the fraction is unique */
+        int64_t a = bn < 0 ? -bn : bn, b = bd;
+        while (b != 0) { const int64_t r = a % b; a = b; b = r; }
+        if (a > 1) { bn /= a; bd /= a; }
+    }
+    *num = bn;
+    *den = bd;
+    free(x);
+    return OR_OK;
+}
+
+int or_cycle_mean_f32(long n, const float *A, long lda, double *lambda) {
+    if (n < 0 || (n > 0 && lda < n)) return OR_EARG;
+    if (!scan_f32(OR_MAX_PLUS, n, n, A, lda)) return OR_EDOMAIN;
+    float *x = (float *)malloc(sizeof(float) * (n + 1) * (n > 0 ? n : 1));
+    if (!x) return OR_EARG;
+    for (long v = 0; v < n; ++v) x[v] = 0.0f;
+    for (long k = 0; k < n; ++k)
+        for (long v = 0; v < n; ++v) {
+            double best = -INFINITY;
+            for (long u = 0; u < n; ++u) {
+                double term = (double)A[v * lda + u] + (double)x[k * n + u];
+                if (term > best) best = term;
+            }
+            x[(k + 1) * n + v] = (float)best;
+        }
+    double best = -INFINITY;
+    for (long v = 0; v < n; ++v) {
+        const float xn = x[n * n + v];
+        if (xn == -INFINITY) continue;
+        double mn = INFINITY;
+        for (long k = 0; k < n; ++k) {
+            const float xk = x[k * n + v];
+            if (xk == -INFINITY) continue;
+            const double r = ((double)xn - (double)xk) / (double)(n - k);
+            if (r < mn) mn = r;
+        }
+        if (mn > best) best = mn;
+    }
+    *lambda = best;
+    free(x);
+    return OR_OK;
+}

@@ -740,3 +740,174 @@ def test_successors_f32_general_weights_walks_reach_target():
             assert path is not None, (i, j)
             length = sum(float(W[a, b]) for a, b in zip(path, path[1:]))
             assert ref[i, j] <= length <= ref[i, j] * (1 + u) ** (2 * steps + 2) * (1 + u) ** len(path)
+
+
+# ------------------------------------------------- max-plus applications ---
+
+def _random_dag_i32(n, p, lo, hi, seed):
+    """Edges only from lower to higher index (acyclic); absent = NINF32."""
+    g = np.random.default_rng(seed)
+    W = np.full((n, n), NINF32, np.int32)
+    mask = np.triu(g.random((n, n)) < p, 1)
+    W[mask] = g.integers(lo, hi + 1, mask.sum())
+    return W
+
+
+def _dag_longest_dp(W):
+    """Longest paths of a DAG with edges i < j by dynamic programming in
+    reverse topological order (a textbook method, exact in Python ints)."""
+    n = W.shape[0]
+    L = [[None] * n for _ in range(n)]
+    for i in range(n - 1, -1, -1):
+        L[i][i] = 0
+        for k in range(i + 1, n):
+            if W[i, k] == NINF32:
+                continue
+            for j in range(k, n):
+                if L[k][j] is not None:
+                    cand = int(W[i, k]) + L[k][j]
+                    if L[i][j] is None or cand > L[i][j]:
+                        L[i][j] = cand
+    return np.array([[NINF32 if x is None else x for x in row] for row in L], np.int64)
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("n", [1, 2, 17, 64])
+def test_closure_min_plus_is_apsp(dt, n):
+    W = wl.er_digraph_i32(n, min(1.0, 4.0 / n), 1, 100, seed=n)
+    if dt == "f32":
+        W = np.where(W == INF32, np.inf, W * 0.37).astype(np.float32)
+        np.fill_diagonal(W, 0)
+    for ee in (False, True):
+        D, s, _ = oracle.closure("min", W, early_exit=ee)
+        D2, s2, _ = oracle.apsp(W, early_exit=ee)
+        assert s == s2 and np.array_equal(D.view(np.uint32), D2.view(np.uint32))
+
+
+@pytest.mark.parametrize("n,p", [(12, 0.4), (60, 0.1), (150, 0.05)])
+def test_closure_max_plus_dag_equals_dp(n, p):
+    W = _random_dag_i32(n, p, -20, 100, seed=n)
+    D, steps, st = oracle.closure("max", W, check=True)
+    assert st == oracle.OK and steps == oracle.apsp_steps(n)
+    assert np.array_equal(D.astype(np.int64), _dag_longest_dp(W))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_closure_max_plus_tiny_bruteforce(seed):
+    g = np.random.default_rng(seed)
+    n = int(g.integers(1, 7))
+    W = _random_dag_i32(n, 0.5, -5, 9, seed=40 + seed)
+    D, _, _ = oracle.closure("max", W)
+    for i in range(n):
+        for j in range(n):
+            best = None
+
+            def walk(v, acc, seen):
+                nonlocal best
+                if v == j and (best is None or acc > best):
+                    best = acc
+                for u in range(n):
+                    if u not in seen and W[v, u] != NINF32:
+                        walk(u, acc + int(W[v, u]), seen | {u})
+            walk(i, 0, {i})
+            assert D[i, j] == (NINF32 if best is None else best), (i, j)
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_closure_max_min_duality(dt):
+    """max-plus closure of W = -(min-plus closure of -W), absent values
+    swapped: negation is exact and commutes with rounding to nearest."""
+    n = 90
+    Wi = _random_dag_i32(n, 0.08, -50, 200, seed=3)
+    if dt == "i32":
+        W = Wi
+        neg = np.where(W == NINF32, INF32, -W.astype(np.int64)).astype(np.int32)
+        Dmax, s1, _ = oracle.closure("max", W, early_exit=True)
+        Dmin, s2, _ = oracle.closure("min", neg, early_exit=True)
+        back = np.where(Dmin == INF32, NINF32, -Dmin.astype(np.int64)).astype(np.int32)
+    else:
+        g = np.random.default_rng(4)
+        W = np.where(Wi == NINF32, -np.inf, Wi * g.random((n, n))).astype(np.float32)
+        Dmax, s1, _ = oracle.closure("max", W, early_exit=True)
+        Dmin, s2, _ = oracle.closure("min", -W, early_exit=True)
+        back = -Dmin
+    assert s1 == s2
+    assert np.array_equal(Dmax, back)
+
+
+def test_closure_max_plus_positive_cycle_flag_and_critical_path():
+    # chain 0 -> 1 -> ... -> 5 with durations: the critical path is the sum
+    n = 6
+    W = np.full((n, n), NINF32, np.int32)
+    dur = [3, 1, 4, 1, 5]
+    for i, d in enumerate(dur):
+        W[i, i + 1] = d
+    W[0, 5] = 10                              # a shortcut shorter than the chain
+    D, _, st = oracle.closure("max", W, check=True)
+    assert st == oracle.OK and D[0, 5] == sum(dur) and D[5, 0] == NINF32
+    W[5, 0] = 1                               # closes a positive cycle
+    _, _, st = oracle.closure("max", W, check=True)
+    assert st == oracle.WNEGCYCLE
+
+
+def _cycle_mean_bruteforce(A):
+    from fractions import Fraction
+    n = A.shape[0]
+    best = None
+    def walk(start, v, acc, length, seen):
+        nonlocal best
+        for u in range(n):
+            if A[v, u] == NINF32:
+                continue
+            if u == start:
+                m = Fraction(acc + int(A[v, u]), length + 1)
+                best = m if best is None or m > best else best
+            elif u > start and u not in seen:
+                walk(start, u, acc + int(A[v, u]), length + 1, seen | {u})
+    for s in range(n):
+        walk(s, s, 0, 0, {s})
+    return best
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_cycle_mean_tiny_bruteforce(seed):
+    """Karp's value equals the best mean over all simple cycles (each cycle
+    enumerated once from its smallest vertex), as an exact fraction."""
+    from fractions import Fraction
+    g = np.random.default_rng(seed)
+    n = int(g.integers(1, 7))
+    A = np.full((n, n), NINF32, np.int32)
+    mask = g.random((n, n)) < 0.45
+    A[mask] = g.integers(-9, 10, mask.sum())
+    num, den = oracle.cycle_mean(A)
+    best = _cycle_mean_bruteforce(A)
+    if best is None:
+        assert den == 0
+    else:
+        assert den > 0 and Fraction(num, den) == best and math.gcd(num, den) == 1
+
+
+def test_cycle_mean_closed_forms_and_f32():
+    from fractions import Fraction
+    n = 7
+    A = np.full((n, n), NINF32, np.int32)
+    w = [2, 9, -4, 6, 1, 3, 5]
+    for i in range(n):
+        A[i, (i + 1) % n] = w[i]             # one cycle through every vertex
+    num, den = oracle.cycle_mean(A)
+    assert Fraction(num, den) == Fraction(sum(w), n)
+    A[3, 3] = 7                               # a self loop with a larger mean
+    assert oracle.cycle_mean(A) == (7, 1)
+    dag = _random_dag_i32(20, 0.3, -5, 5, seed=1)
+    assert oracle.cycle_mean(dag)[1] == 0     # acyclic: no cycle
+    full = np.full((5, 5), 4, np.int32)
+    assert Fraction(*oracle.cycle_mean(full)) == 4
+    # float32 with integer weights: the same value, rounded once to binary64
+    g = np.random.default_rng(9)
+    Ai = np.full((40, 40), NINF32, np.int32)
+    mask = g.random((40, 40)) < 0.08
+    Ai[mask] = g.integers(-100, 100, mask.sum())
+    num, den = oracle.cycle_mean(Ai)
+    Af = np.where(Ai == NINF32, -np.inf, Ai).astype(np.float32)
+    lam = oracle.cycle_mean(Af)
+    assert (den == 0 and lam == -np.inf) or lam == num / den
