@@ -59,11 +59,13 @@ typedef enum {
     BTAS_OK = 0,
     BTAS_ERR_INVALID_ARG = 1, /* bad size, leading dimension, stride, enum or null pointer */
     BTAS_ERR_ALIAS = 2,       /* output overlaps an input where that is not allowed       */
-    BTAS_ERR_DOMAIN = 3,      /* BTAS_VALIDATE=1 found an element outside the domain      */
+    BTAS_ERR_DOMAIN = 3,      /* an element outside the domain (BTAS_VALIDATE=1 scans; a
+                                 few entry points check their own ranges always)           */
     BTAS_ERR_OOM = 4,         /* device workspace allocation failed                      */
     BTAS_ERR_DEVICE = 5,      /* HIP runtime error (launch, copy, synchronisation)         */
-    BTAS_ERR_UNSUPPORTED = 6, /* combination not provided (e.g. max-plus APSP)             */
-    BTAS_WARN_NEG_CYCLE = 7   /* APSP result has some D_ii < 0 (result unspecified)        */
+    BTAS_ERR_UNSUPPORTED = 6, /* combination not provided                                  */
+    BTAS_WARN_NEG_CYCLE = 7,  /* APSP result has some D_ii < 0 (result unspecified)        */
+    BTAS_WARN_POS_CYCLE = 8   /* max-plus closure has some D_ii > 0 (result unspecified)   */
 } btas_status_t;
 
 #define BTAS_I32_INF ((int32_t)0x7FFFFFFF)      /* min-plus absent value, +INF  */
@@ -237,6 +239,42 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
  * Asynchronous otherwise. */
 btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, const void *W,
                                        int ldw, void *D, int ldd, unsigned flags);
+
+/* Closure (I (+) W)^(2^s) by repeated squaring over either semiring of
+ * Sec. I: D_0 = I (+) W (I: 0 on the diagonal, the absent value elsewhere),
+ * D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1} for t = 1..T = ceil(log2(n-1)), as in
+ * Sec. III.  Min-plus is btas_apsp_squaring (shortest distances; this call
+ * forwards to it).  Max-plus gives the heaviest walks of up to n-1 edges; for
+ * a graph without positive cycles, such as the precedence DAG of a schedule,
+ * these are the longest paths (critical paths: D_ij is the latest start
+ * offset of j after i).  W absent entries: BTAS_I32_NEG_INF or -inf for
+ * max-plus.  Layout, in-place rule (W == D with ldw == ldd), aliasing and
+ * workspace as btas_apsp_squaring.  flags: BTAS_APSP_EARLY_EXIT (stop at the
+ * first unchanged step; host round trip per step) and
+ * BTAS_APSP_CHECK_NEG_CYCLE, which for max-plus reports a positive cycle (some
+ * D_ii > 0, result unspecified) as BTAS_WARN_POS_CYCLE.  int32 finite values
+ * along the way must stay within BTAS_I32_FINITE_MAX. */
+btas_status_t btas_tropical_closure(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                    const void *W, int ldw, void *D, int ldd, unsigned flags,
+                                    int *steps_out);
+
+/* Maximum cycle mean of the max-plus matrix A (n x n, row-major, lda; A_vu the
+ * weight of edge v -> u, absent BTAS_I32_NEG_INF / -inf): the largest mean
+ * weight of a cycle, which is the max-plus eigenvalue of A and the cycle time
+ * of the discrete-event system x(k+1) = A (x) x(k) (an application of the
+ * max-plus algebra of Sec. I).  Computed by Karp's theorem from the walk
+ * table x_0 = 0, x_{k+1} = A (x) x_k (n max-plus gemv launches, the table in
+ * the handle's workspace, (n+1) * n * 4 + 24 n bytes):
+ *   lambda = max_v min_{k<n, x_k(v) present} (x_n(v) - x_k(v)) / (n - k).
+ * int32: *num / *den is lambda exactly, in lowest terms (den > 0), and
+ * *lambda its binary64 rounding; den = 0 and lambda = -inf when A has no
+ * cycle.  n * max|A_ij| must not exceed BTAS_I32_FINITE_MAX (walk weights
+ * stay in the domain), else BTAS_ERR_DOMAIN (checked always).  float32: walk
+ * weights are maxima of single binary32 adds and the ratios are evaluated in
+ * binary64 as ((double)x_n - (double)x_k) / (n - k); *num = *den = 0.  Output
+ * pointers are host pointers, each may be NULL.  Synchronises. */
+btas_status_t btas_maxplus_cycle_mean(btas_handle_t h, btas_dtype_t dt, int n, const void *A,
+                                      int lda, int64_t *num, int64_t *den, double *lambda);
 
 /* Tropical product with witnesses: C <- C (+) A (.) B as btas_tropical_gemm
  * (the Sec. IV product, whose inner step is a min (max) over k), and K

@@ -32,8 +32,8 @@ APSP_EARLY_EXIT, APSP_CHECK_NEG_CYCLE, APSP_GRAPH, APSP_SINGLE_LAUNCH = 1, 2, 4,
 
 STATUS = {0: "BTAS_OK", 1: "BTAS_ERR_INVALID_ARG", 2: "BTAS_ERR_ALIAS", 3: "BTAS_ERR_DOMAIN",
           4: "BTAS_ERR_OOM", 5: "BTAS_ERR_DEVICE", 6: "BTAS_ERR_UNSUPPORTED",
-          7: "BTAS_WARN_NEG_CYCLE"}
-OK, WARN_NEG_CYCLE = 0, 7
+          7: "BTAS_WARN_NEG_CYCLE", 8: "BTAS_WARN_POS_CYCLE"}
+OK, WARN_NEG_CYCLE, WARN_POS_CYCLE = 0, 7, 8
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbtas.so")
@@ -92,6 +92,9 @@ def lib():
         L.btas_apsp_floyd_warshall.argtypes = [P, I, I, P, I, P, I, U]
         L.btas_tropical_gemm_witness.argtypes = [P, I, I, I, I, I, P, I, P, I, P, I, P, I]
         L.btas_apsp_successors.argtypes = [P, I, I, P, I, P, I, P, I]
+        L.btas_tropical_closure.argtypes = [P, I, I, I, P, I, P, I, U, ctypes.POINTER(I)]
+        I64P = ctypes.POINTER(ctypes.c_int64)
+        L.btas_maxplus_cycle_mean.argtypes = [P, I, I, P, I, I64P, I64P, ctypes.POINTER(ctypes.c_double)]
         L.btas_server_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.c_size_t, I, ctypes.c_double]
         L.btas_server_destroy.argtypes = [P]
         L.btas_server_now.argtypes = [P]
@@ -287,6 +290,46 @@ def apsp_successors(W, D, out=None, handle=None):
     ps, lds = _mat(out, "S")
     h.check(lib().btas_apsp_successors(h.ptr, _dt(W), n, pw, ldw, pd, ldd, ps, lds))
     return out
+
+
+def tropical_closure(W, semiring="max", out=None, early_exit=False, check_cycle=False,
+                     handle=None):
+    """(I (+) W)^(2^s) by repeated squaring over the semiring (min: shortest
+    distances; max: heaviest walks, the longest paths of a graph without
+    positive cycles).  Returns (D, steps, status)."""
+    import torch
+    n = W.size(0)
+    if W.shape != (n, n):
+        raise ValueError("W must be square")
+    if out is None:
+        out = torch.empty_like(W)
+    h = _handle_for(W, handle)
+    pw, ldw = _mat(W, "W")
+    pd, ldd = _mat(out, "D")
+    steps = ctypes.c_int(0)
+    flags = (APSP_EARLY_EXIT if early_exit else 0) | (APSP_CHECK_NEG_CYCLE if check_cycle else 0)
+    st = h.check(lib().btas_tropical_closure(h.ptr, _sr(semiring), _dt(W), n, pw, ldw, pd, ldd, flags,
+                                             ctypes.byref(steps)),
+                 allow=(OK, WARN_NEG_CYCLE, WARN_POS_CYCLE))
+    return out, steps.value, st
+
+
+def maxplus_cycle_mean(A, handle=None):
+    """Maximum cycle mean of a max-plus matrix (Karp).  int32: the exact
+    fraction (num, den) in lowest terms, den = 0 when acyclic; float32: a
+    float, -inf when acyclic."""
+    import torch
+    n = A.size(0)
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    h = _handle_for(A, handle)
+    pa, lda = _mat(A, "A")
+    num, den, lam = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_double(0.0)
+    h.check(lib().btas_maxplus_cycle_mean(h.ptr, _dt(A), n, pa, lda, ctypes.byref(num),
+                                          ctypes.byref(den), ctypes.byref(lam)))
+    if A.dtype == torch.int32:
+        return num.value, den.value
+    return lam.value
 
 
 def shortest_path(S, i, j):

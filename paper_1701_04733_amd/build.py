@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libbtas.so")
 INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"
 
-SOURCES = ["gemm.hip", "level12.hip", "aux.hip", "batched.hip", "resident.hip", "floyd.hip", "witness.hip", "sparse.hip", "api.cpp",
+SOURCES = ["gemm.hip", "level12.hip", "aux.hip", "batched.hip", "resident.hip", "floyd.hip", "witness.hip", "sparse.hip", "maxplus.hip", "api.cpp",
            "batched_api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

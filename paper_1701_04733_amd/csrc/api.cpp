@@ -113,6 +113,21 @@ hipError_t ensure_sparse_ws(btas_handle_t h, size_t need) {
     return e;
 }
 
+// The handle's matrix workspace (APSP ping-pong partner, cycle-mean table),
+// grown on demand.
+hipError_t ensure_ws(btas_handle_t h, size_t need) {
+    if (h->ws_bytes >= need) return hipSuccess;
+    if (h->ws) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    const hipError_t e = hipMalloc(&h->ws, need);
+    if (e == hipSuccess) h->ws_bytes = need;
+    return e;
+}
+
 uint64_t flag_u64(btas_handle_t h, int slot) {
     uint64_t v;
     memcpy(&v, h->hflags + slot, sizeof v);
@@ -180,6 +195,7 @@ const char* btas_status_string(btas_status_t s) {
         case BTAS_ERR_DEVICE: return "BTAS_ERR_DEVICE";
         case BTAS_ERR_UNSUPPORTED: return "BTAS_ERR_UNSUPPORTED";
         case BTAS_WARN_NEG_CYCLE: return "BTAS_WARN_NEG_CYCLE";
+        case BTAS_WARN_POS_CYCLE: return "BTAS_WARN_POS_CYCLE";
     }
     return "BTAS_UNKNOWN_STATUS";
 }
@@ -461,17 +477,8 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     }
     const int T = btas_apsp_num_steps(n);
     const size_t need = (size_t)n * n * 4;
-    if (T > 0 && h->ws_bytes < need) {
-        if (h->ws) {
-            (void)hipStreamSynchronize(h->stream);
-            (void)hipFree(h->ws);
-            h->ws = nullptr;
-            h->ws_bytes = 0;
-        }
-        if (hipMalloc(&h->ws, need) != hipSuccess)
-            return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
-        h->ws_bytes = need;
-    }
+    if (T > 0 && ensure_ws(h, need) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
     // Graphs of 24..192 vertices take the single-launch solve also without
     // the flag (it is faster there: one launch instead of one or two per
     // squaring) unless a captured graph was asked for or BTAS_SINGLE_LAUNCH=0.
@@ -712,6 +719,140 @@ btas_status_t btas_apsp_successors(btas_handle_t h, btas_dtype_t dt, int n, cons
     if (st != BTAS_OK) return st;
     hipError_t e = btas::launch_successors(dt, n, W, ldw, D, ldd, S, lds, h->stream);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+}
+
+// ------------------------------------------------------------- closure ---
+btas_status_t btas_tropical_closure(btas_handle_t h, btas_semiring_t sr, btas_dtype_t dt, int n,
+                                    const void* W, int ldw, void* D, int ldd, unsigned flags,
+                                    int* steps_out) {
+    const char* fn = "btas_tropical_closure";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (steps_out) *steps_out = 0;
+    if (sr != BTAS_MIN_PLUS && sr != BTAS_MAX_PLUS)
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (semiring=%d) unknown", fn, (int)sr);
+    if (flags & ~(BTAS_APSP_EARLY_EXIT | BTAS_APSP_CHECK_NEG_CYCLE))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 9 (flags=0x%x): EARLY_EXIT, CHECK_NEG_CYCLE",
+                    fn, flags);
+    if (sr == BTAS_MIN_PLUS) return btas_apsp_squaring(h, dt, n, W, ldw, D, ldd, flags, steps_out);
+    if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (dtype=%d) unknown", fn, (int)dt);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (n=%d) < 0", fn, n);
+    if (ldw < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 6 (ldw=%d) < max(1,n=%d)", fn, ldw, n);
+    if (ldd < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 8 (ldd=%d) < max(1,n=%d)", fn, ldd, n);
+    if (n > 0 && (!W || !D)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W or D is null", fn);
+    const bool in_place = W == D && ldw == ldd;
+    if (!in_place && overlap(mat_span(W, n, n, ldw), mat_span(D, n, n, ldd)))
+        return fail(h, BTAS_ERR_ALIAS, "%s: D partially overlaps W", fn);
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    {
+        const void* ps[1] = {W};
+        const long rows[1] = {n}, cols[1] = {n}, lds[1] = {ldw};
+        btas_status_t st = validate_operands(h, fn, BTAS_MAX_PLUS, dt, ps, rows, cols, lds, 1);
+        if (st != BTAS_OK) return st;
+    }
+    const int T = btas_apsp_num_steps(n);
+    if (T > 0 && ensure_ws(h, (size_t)n * n * 4) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, (size_t)n * n * 4);
+    if (T > 0 && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
+    const bool early = flags & BTAS_APSP_EARLY_EXIT;
+    void* bufs[2] = {D, h->ws};
+    long lds[2] = {ldd, n};
+    int cur = (T % 2 == 0) ? 0 : 1;
+    int* wide = dt == BTAS_INT32 ? h->dflags + FLAG_STEP_WIDE : nullptr;
+    hipError_t e = hipSuccess;
+    if (wide) e = btas::launch_clear_flags(wide, T + 1, h->stream);
+    if (e == hipSuccess)
+        e = btas::launch_closure_init(BTAS_MAX_PLUS, dt, n, W, ldw, bufs[cur], lds[cur], wide, h->stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    int steps = 0;
+    for (int t = 0; t < T; ++t) {
+        const int nxt = cur ^ 1;
+        int* changed = early ? h->dflags + FLAG_CHANGED : nullptr;
+        if (changed) e = btas::launch_clear_flags(changed, 1, h->stream);
+        btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
+                         bufs[nxt], lds[nxt], changed,
+                         wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr,
+                         h->skws, h->skws_bytes};
+        if (e == hipSuccess) e = btas::launch_gemm(BTAS_MAX_PLUS, dt, a, -1, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        ++steps;
+        cur = nxt;
+        if (early) {
+            btas_status_t st = sync_flags(h, fn, FLAG_CHANGED + 1);
+            if (st != BTAS_OK) return st;
+            if (h->hflags[FLAG_CHANGED] == 0) break;
+        }
+    }
+    if (cur != 0) {
+        e = btas::launch_copy_matrix(n, n, bufs[cur], lds[cur], D, ldd, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+    }
+    if (steps_out) *steps_out = steps;
+    if (flags & BTAS_APSP_CHECK_NEG_CYCLE) {
+        int* flag = h->dflags + FLAG_CHECK;
+        e = btas::launch_clear_flags(flag, 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_diag_check(BTAS_MAX_PLUS, dt, n, D, ldd, flag, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        btas_status_t st = sync_flags(h, fn, FLAG_CHECK + 1);
+        if (st != BTAS_OK) return st;
+        if (h->hflags[FLAG_CHECK]) return fail(h, BTAS_WARN_POS_CYCLE, "%s: positive cycle (some D_ii > 0)", fn);
+    }
+    return BTAS_OK;
+}
+
+// ---------------------------------------------------------- cycle mean ---
+btas_status_t btas_maxplus_cycle_mean(btas_handle_t h, btas_dtype_t dt, int n, const void* A, int lda,
+                                      int64_t* num, int64_t* den, double* lambda) {
+    const char* fn = "btas_maxplus_cycle_mean";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
+    if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
+    if (lda < (n > 1 ? n : 1))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 5 (lda=%d) < max(1,n=%d)", fn, lda, n);
+    if (n > 0 && !A) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 4 (A) is null", fn);
+    if (num) *num = 0;
+    if (den) *den = 0;
+    if (lambda) *lambda = -__builtin_inf();
+    if (n == 0) return BTAS_OK;
+    DeviceGuard g(h->device);
+    {
+        const void* ps[1] = {A};
+        const long rows[1] = {n}, cols[1] = {n}, lds[1] = {lda};
+        btas_status_t st = validate_operands(h, fn, BTAS_MAX_PLUS, dt, ps, rows, cols, lds, 1);
+        if (st != BTAS_OK) return st;
+    }
+    hipError_t e = hipSuccess;
+    if (dt == BTAS_INT32) {
+        // walks of up to n edges must stay inside the int32 domain bound
+        int* m = h->dflags + FLAG_CM_MAXABS;
+        e = btas::launch_clear_flags(m, 1, h->stream);
+        if (e == hipSuccess) e = btas::launch_cycle_mean_maxabs(n, A, lda, m, h->stream);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        btas_status_t st = sync_flags(h, fn, FLAG_CM_MAXABS + 1);
+        if (st != BTAS_OK) return st;
+        if ((long long)n * h->hflags[FLAG_CM_MAXABS] > (long long)BTAS_I32_FINITE_MAX)
+            return fail(h, BTAS_ERR_DOMAIN, "%s: n * max|A| = %lld exceeds 2^29-1 (walk weights overflow)",
+                        fn, (long long)n * h->hflags[FLAG_CM_MAXABS]);
+    }
+    const size_t need = btas::cycle_mean_ws_bytes(n);
+    if (ensure_ws(h, need) != hipSuccess)
+        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
+    long long* result = reinterpret_cast<long long*>(h->dflags + FLAG_CM_RESULT);
+    e = btas::launch_cycle_mean(dt, n, A, lda, h->ws, result, h->stream);
+    if (e != hipSuccess) return device_fail(h, fn, e);
+    btas_status_t st = sync_flags(h, fn, FLAG_CM_RESULT + 6);
+    if (st != BTAS_OK) return st;
+    int64_t r[3];
+    memcpy(r, h->hflags + FLAG_CM_RESULT, sizeof r);
+    if (num) *num = r[0];
+    if (den) *den = r[1];
+    if (lambda) memcpy(lambda, &r[2], sizeof(double));
+    return BTAS_OK;
 }
 
 }  // extern "C"

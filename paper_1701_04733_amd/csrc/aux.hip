@@ -13,10 +13,12 @@
 namespace btas {
 
 // D_0 = I (+) W (Sec. III starts the squaring from the adjacency matrix; the
-// tropical identity puts 0 on the diagonal, so D_ii = min(W_ii, 0)).
-template <typename T>
+// tropical identity puts 0 on the diagonal, so D_ii = min(W_ii, 0) for
+// min-plus and max(W_ii, 0) for max-plus).
+template <typename T, int SR>
 __global__ __launch_bounds__(256) void apsp_init_kernel(int n, const T* W, long ldw, T* D,
                                                          long ldd, int* wide) {
+    using R = Ring<SR, T>;
     const long total = (long)n * n;
     bool w_wide = false;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -24,10 +26,10 @@ __global__ __launch_bounds__(256) void apsp_init_kernel(int n, const T* W, long 
         long i, j;
         flat_to_rc(e, n, total, i, j);
         T w = W[i * ldw + j];
-        if (i == j && w > (T)0) w = (T)0;
+        if (i == j && (SR == BTAS_MIN_PLUS ? w > (T)0 : w < (T)0)) w = (T)0;
         D[i * ldd + j] = w;
         if constexpr (std::is_same_v<T, int32_t>)
-            w_wide |= w != BTAS_I32_INF && (w > FP32_EXACT_MAX || w < -FP32_EXACT_MAX);
+            w_wide |= w != R::absent() && (w > FP32_EXACT_MAX || w < -FP32_EXACT_MAX);
     }
     if (wide != nullptr && w_wide) *wide = 1;
 }
@@ -39,17 +41,29 @@ static unsigned blocks_for(long total) {
     return (unsigned)b;
 }
 
-hipError_t launch_apsp_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
-                            int* wide, hipStream_t s) {
+template <int SR>
+static hipError_t closure_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
+                               int* wide, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const unsigned g = blocks_for((long)n * n);
     if (dt == BTAS_FLOAT32)
-        hipLaunchKernelGGL(apsp_init_kernel<float>, dim3(g), dim3(256), 0, s, n, (const float*)W,
-                           ldw, (float*)dst, ldd, nullptr);
+        hipLaunchKernelGGL((apsp_init_kernel<float, SR>), dim3(g), dim3(256), 0, s, n,
+                           (const float*)W, ldw, (float*)dst, ldd, nullptr);
     else
-        hipLaunchKernelGGL(apsp_init_kernel<int32_t>, dim3(g), dim3(256), 0, s, n,
+        hipLaunchKernelGGL((apsp_init_kernel<int32_t, SR>), dim3(g), dim3(256), 0, s, n,
                            (const int32_t*)W, ldw, (int32_t*)dst, ldd, wide);
     return hipGetLastError();
+}
+
+hipError_t launch_apsp_init(int dt, int n, const void* W, long ldw, void* dst, long ldd,
+                            int* wide, hipStream_t s) {
+    return closure_init<BTAS_MIN_PLUS>(dt, n, W, ldw, dst, ldd, wide, s);
+}
+
+hipError_t launch_closure_init(int sr, int dt, int n, const void* W, long ldw, void* dst, long ldd,
+                               int* wide, hipStream_t s) {
+    return sr == BTAS_MIN_PLUS ? closure_init<BTAS_MIN_PLUS>(dt, n, W, ldw, dst, ldd, wide, s)
+                               : closure_init<BTAS_MAX_PLUS>(dt, n, W, ldw, dst, ldd, wide, s);
 }
 
 template <int SR>
@@ -89,23 +103,38 @@ hipError_t launch_clear_flags(int* flag, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void neg_diag_kernel(int n, const T* D, long ldd, int* flag) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        if (D[(long)i * ldd + i] < (T)0) *flag = 1;
+// flag <- 1 if some D_ii is past 0 on the semiring's improving side (min-plus
+// < 0: a negative cycle; max-plus > 0: a positive cycle).
+template <typename T, int SR>
+__global__ __launch_bounds__(256) void diag_check_kernel(int n, const T* D, long ldd, int* flag) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const T d = D[(long)i * ldd + i];
+        if (SR == BTAS_MIN_PLUS ? d < (T)0 : d > (T)0) *flag = 1;
+    }
+}
+
+template <int SR>
+static hipError_t diag_check(int dt, int n, const void* D, long ldd, int* flag, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (dt == BTAS_FLOAT32)
+        hipLaunchKernelGGL((diag_check_kernel<float, SR>), dim3(g), dim3(256), 0, s, n,
+                           (const float*)D, ldd, flag);
+    else
+        hipLaunchKernelGGL((diag_check_kernel<int32_t, SR>), dim3(g), dim3(256), 0, s, n,
+                           (const int32_t*)D, ldd, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_neg_diag_check(int dt, int n, const void* D, long ldd, int* flag,
                                  hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const unsigned g = (unsigned)((n + 255) / 256);
-    if (dt == BTAS_FLOAT32)
-        hipLaunchKernelGGL(neg_diag_kernel<float>, dim3(g), dim3(256), 0, s, n, (const float*)D,
-                           ldd, flag);
-    else
-        hipLaunchKernelGGL(neg_diag_kernel<int32_t>, dim3(g), dim3(256), 0, s, n,
-                           (const int32_t*)D, ldd, flag);
-    return hipGetLastError();
+    return diag_check<BTAS_MIN_PLUS>(dt, n, D, ldd, flag, s);
+}
+
+hipError_t launch_diag_check(int sr, int dt, int n, const void* D, long ldd, int* flag,
+                             hipStream_t s) {
+    return sr == BTAS_MIN_PLUS ? diag_check<BTAS_MIN_PLUS>(dt, n, D, ldd, flag, s)
+                               : diag_check<BTAS_MAX_PLUS>(dt, n, D, ldd, flag, s);
 }
 
 __global__ __launch_bounds__(256) void copy_matrix_kernel(int m, int n, const uint32_t* src,

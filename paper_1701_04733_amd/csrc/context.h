@@ -65,8 +65,11 @@ constexpr int FLAG_RESIDENT = 44;  // single-launch solve: +0 error, +1 steps, +
 constexpr int FLAG_BARRIER = 64;   // its device-wide barrier: 2 + (up to 64 groups) counters
 constexpr int FLAG_RESIDENT_END = FLAG_BARRIER + 2 + 64;
 constexpr int FLAG_SPARSE = 136;   // sparse squarings: two 64-bit counters (finite entries, terms)
+constexpr int FLAG_CM_MAXABS = 140;  // cycle mean: max |A| of int32 entries
+constexpr int FLAG_CM_RESULT = 144;  // cycle mean: num, den (int64), lambda bits (binary64)
 constexpr int kNumFlags = 192;
-static_assert(FLAG_RESIDENT_END <= FLAG_SPARSE && FLAG_SPARSE % 2 == 0 && FLAG_SPARSE + 4 <= kNumFlags,
+static_assert(FLAG_RESIDENT_END <= FLAG_SPARSE && FLAG_SPARSE % 2 == 0 && FLAG_SPARSE + 4 <= FLAG_CM_MAXABS &&
+                  FLAG_CM_MAXABS < FLAG_CM_RESULT && FLAG_CM_RESULT % 2 == 0 && FLAG_CM_RESULT + 6 <= kNumFlags,
               "flag slots overlap");
 static_assert(FLAG_RESIDENT + 2 + 9 <= FLAG_BARRIER, "slots for T(500) = 9 squarings");
 

@@ -79,6 +79,13 @@ hipError_t launch_clear_flags(int* flag, int count, hipStream_t s);
 // flag <- 1 if some D_ii < 0.
 hipError_t launch_neg_diag_check(int dt, int n, const void* D, long ldd, int* flag,
                                  hipStream_t s);
+// Either semiring: dst <- I (+) W (dst_ii = min(W_ii, 0), resp. max(W_ii, 0));
+// flag <- 1 if some D_ii is past 0 on the improving side (min-plus: < 0,
+// max-plus: > 0).
+hipError_t launch_closure_init(int sr, int dt, int n, const void* W, long ldw, void* dst, long ldd,
+                               int* wide, hipStream_t s);
+hipError_t launch_diag_check(int sr, int dt, int n, const void* D, long ldd, int* flag,
+                             hipStream_t s);
 // Copy an n-column, m-row matrix between leading dimensions (4-byte elements).
 hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst, long ldd,
                               hipStream_t s);
@@ -120,6 +127,16 @@ hipError_t launch_sparse_build(int dt, int n, const void* D, long ld, const int*
 hipError_t launch_sparse_square(int dt, int n, const void* D, long ld, void* E, long lde,
                                 const int* rowptr, const int* cols, const void* vals, int* changed,
                                 int* wide_out, hipStream_t s);
+
+// Maximum cycle mean of a max-plus matrix by Karp's theorem (csrc/maxplus.hip).
+// maxabs: *out = max |A_ij| over present int32 entries (atomicMax, clear first).
+// cycle_mean: ws of cycle_mean_ws_bytes(n) bytes; n max-plus gemv launches,
+// then result[0..1] = the int32 fraction in lowest terms (den = 0: no
+// cycle), result[2] = the bits of lambda as a binary64 (-inf: no cycle).
+size_t cycle_mean_ws_bytes(int n);
+hipError_t launch_cycle_mean_maxabs(int n, const void* A, long lda, int* out, hipStream_t s);
+hipError_t launch_cycle_mean(int dt, int n, const void* A, long lda, void* ws, long long* result,
+                             hipStream_t s);
 
 // Tropical product with witnesses (csrc/witness.hip): C <- C (+) A (.) B and,
 // where an entry strictly improves, K <- the smallest p attaining it.

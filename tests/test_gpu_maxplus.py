@@ -1,0 +1,128 @@
+"""Max-plus applications on the GPU, bit-exact against the oracle: the
+max-plus closure (longest paths of graphs without positive cycles, critical
+paths of DAGs) and the maximum cycle mean by Karp's theorem (int32 as an
+exact fraction, float32 as the same binary64 value)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import INF32, NINF32
+from paper_1701_04733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(x):
+    x = np.ascontiguousarray(x).copy()
+    if x.dtype == np.float32:
+        x[x == 0] = 0.0
+    return x.view(np.uint32)
+
+
+def _dev(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _dag(dt, n, p, seed):
+    """Edges from lower to higher index, in a random vertex order (so the
+    matrix is not triangular); int32 weights of both signs."""
+    g = np.random.default_rng(seed)
+    perm = g.permutation(n)
+    W = np.full((n, n), NINF32, np.int32)
+    mask = np.triu(g.random((n, n)) < p, 1)
+    W[mask] = g.integers(-30, 200, mask.sum())
+    W = W[np.ix_(perm, perm)]
+    if dt == "f32":
+        W = np.where(W == NINF32, -np.inf, W * 0.731).astype(np.float32)
+    return W
+
+
+def _digraph_maxplus(dt, n, p, seed, lo=-50, hi=100):
+    g = np.random.default_rng(seed)
+    A = np.full((n, n), NINF32, np.int32)
+    mask = g.random((n, n)) < p
+    A[mask] = g.integers(lo, hi + 1, mask.sum())
+    if dt == "f32":
+        A = np.where(A == NINF32, -np.inf, A * 0.5 + g.random((n, n)) * 0.25).astype(np.float32)
+    return A
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 65, 200, 257])
+def test_maxplus_closure_matches_oracle(dev, dt, n):
+    import paper_1701_04733_amd as btas
+    W = _dag(dt, n, min(1.0, 6.0 / max(n, 1)), seed=300 + n)
+    for ee in (False, True):
+        want, wsteps, _ = oracle.closure("max", W, early_exit=ee)
+        D, steps, st = btas.tropical_closure(_dev(W, dev), "max", early_exit=ee, check_cycle=True)
+        assert st == btas.OK and steps == wsteps
+        assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"{dt} n={n} early={ee}"
+
+
+def test_closure_min_plus_forwards_and_positive_cycle_and_views(dev):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    W = wl.er_digraph_i32(120, 0.04, 1, 50, seed=8)
+    D, s, _ = btas.tropical_closure(_dev(W, dev), "min", early_exit=True)
+    want, ws, _ = oracle.apsp(W, early_exit=True)
+    assert s == ws and np.array_equal(D.cpu().numpy(), want)
+    # a positive cycle is reported
+    n = 6
+    C = np.full((n, n), NINF32, np.int32)
+    for i in range(n - 1):
+        C[i, i + 1] = 2
+    C[n - 1, 0] = -12                     # cycle weight 2*5 - 12 < 0
+    _, _, st = btas.tropical_closure(_dev(C, dev), "max", check_cycle=True)
+    assert st == btas.OK
+    C[n - 1, 0] = -8                      # cycle weight 2*5 - 8 > 0
+    _, _, st = btas.tropical_closure(_dev(C, dev), "max", check_cycle=True)
+    assert st == btas.WARN_POS_CYCLE
+    # in place and with padded leading dimensions
+    W = _dag("i32", 150, 0.05, seed=2)
+    want, _, _ = oracle.closure("max", W)
+    t = _dev(W, dev)
+    btas.tropical_closure(t, "max", out=t)
+    assert np.array_equal(t.cpu().numpy(), want)
+    big = torch.full((150, 153), 9, dtype=torch.int32, device=dev)
+    big[:, :150] = _dev(W, dev)
+    out = torch.zeros((151, 160), dtype=torch.int32, device=dev)
+    btas.tropical_closure(big[:, :150], "max", out=out[:150, :150])
+    assert np.array_equal(out[:150, :150].cpu().numpy(), want)
+    assert (out[150, :] == 0).all() and (out[:, 150:] == 0).all() and (big[:, 150:] == 9).all()
+
+
+@pytest.mark.parametrize("n,p", [(1, 1.0), (2, 0.6), (7, 0.35), (64, 0.05), (200, 0.02), (500, 0.006)])
+def test_cycle_mean_i32_matches_oracle(dev, n, p):
+    import paper_1701_04733_amd as btas
+    A = _digraph_maxplus("i32", n, p, seed=n)
+    assert btas.maxplus_cycle_mean(_dev(A, dev)) == oracle.cycle_mean(A)
+
+
+@pytest.mark.parametrize("n,p", [(3, 0.5), (64, 0.05), (300, 0.01), (1024, 0.004)])
+def test_cycle_mean_f32_matches_oracle(dev, n, p):
+    import paper_1701_04733_amd as btas
+    A = _digraph_maxplus("f32", n, p, seed=50 + n)
+    got = btas.maxplus_cycle_mean(_dev(A, dev))
+    want = oracle.cycle_mean(A)
+    assert np.float64(got).view(np.uint64) == np.float64(want).view(np.uint64)
+
+
+def test_cycle_mean_acyclic_views_and_domain(dev):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    dag = _dag("i32", 90, 0.1, seed=4)
+    assert btas.maxplus_cycle_mean(_dev(dag, dev)) == (0, 0)
+    assert btas.maxplus_cycle_mean(_dev(_dag("f32", 90, 0.1, seed=4), dev)) == -np.inf
+    A = _digraph_maxplus("i32", 100, 0.05, seed=6)
+    big = torch.full((100, 104), 77, dtype=torch.int32, device=dev)
+    big[:, :100] = _dev(A, dev)
+    assert btas.maxplus_cycle_mean(big[:, :100]) == oracle.cycle_mean(A)
+    # walk weights would leave the int32 domain: rejected before any product
+    n = 1024
+    H = np.full((n, n), NINF32, np.int32)
+    H[0, 1] = H[1, 0] = 1 << 20
+    with pytest.raises(btas.BtasError, match="DOMAIN"):
+        btas.maxplus_cycle_mean(_dev(H, dev))
