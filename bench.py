@@ -248,6 +248,43 @@ def bench_witness(dev, operands, reps=3):
     return out
 
 
+def bench_maxplus(dev, reps=3):
+    """Max-plus applications: the maximum cycle mean (Karp: n max-plus gemv
+    steps, then the reduction) of a 4096-vertex digraph with int32 weights,
+    and the critical paths (max-plus closure with early exit) of a
+    4096-task precedence DAG."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    n = 4096
+    A = torch.from_numpy(wl.maxplus_digraph_i32(n, 8.0, -50, 100, seed=21)).to(dev)
+    btas.maxplus_cycle_mean(A)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        num, den = btas.maxplus_cycle_mean(A)
+        ts.append(time.perf_counter() - t0)
+    sec = float(np.median(ts))
+    out = {"cycle_mean": {"workload": "max cycle mean, n=4096 digraph, mean out-degree 8, int32 U{-50..100}",
+                          "ms": round(sec * 1e3, 2), "lambda": [num, den],
+                          "gemv_GB/s": round(n * n * 4.0 * n / sec / 1e9, 1)}}
+    del A
+    W = torch.from_numpy(wl.precedence_dag_f32(n, 8.0, seed=22)).to(dev)
+    btas.tropical_closure(W, "max", early_exit=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, steps, _ = btas.tropical_closure(W, "max", early_exit=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    out["critical_paths"] = {"workload": "max-plus closure, n=4096 precedence DAG, mean out-degree 8, "
+                                         "durations U(0,10] fp32, early exit",
+                             "ms": round(sec * 1e3, 2), "steps": steps,
+                             "Gop/s": round(2.0 * n ** 3 * steps / sec / 1e9, 1)}
+    return out
+
+
 def bench_batched(dev, reps=5):
     """4096 independent graphs, n log-uniform in [16,512], p = 8/n, int32
     weights U{1..1000}: one hipGraph launch vs 4096 plain solves."""
@@ -491,6 +528,7 @@ def main():
         extras["apsp_large"] = bench_apsp_large(dev)
         extras["witness"] = bench_witness(dev, witness_operands)
         del witness_operands
+        extras["maxplus"] = bench_maxplus(dev)
         torch.cuda.empty_cache()
         extras["batched"] = bench_batched(dev)
         torch.cuda.empty_cache()

@@ -190,3 +190,28 @@ def served_requests(count: int, rate: float, lo: int = 32, hi: int = 4096, deg: 
         w = (10.0 * (1.0 - g.random(r.size))).astype(np.float32)
         reqs.append(Request(i, float(arrivals[i]), n, r.astype(np.int32), c.astype(np.int32), w))
     return reqs
+
+
+# --------------------------------------------------------------------------
+# Max-plus inputs (absent entries -INF).
+
+def maxplus_digraph_i32(n: int, mean_degree: float, w_lo: int, w_hi: int, seed) -> np.ndarray:
+    """Directed graph as a max-plus matrix: each ordered pair (self loops
+    included) is an edge with probability mean_degree / n, integer weights
+    U{w_lo..w_hi}; absent = -INF.  Cycles of every length occur."""
+    g = rng(seed)
+    A = np.full((n, n), I32_NINF, np.int32)
+    mask = g.random((n, n)) < mean_degree / n
+    A[mask] = g.integers(w_lo, w_hi, mask.sum(), endpoint=True)
+    return A
+
+
+def precedence_dag_f32(n: int, mean_degree: float, seed) -> np.ndarray:
+    """Precedence DAG of a schedule as a max-plus matrix: edge i -> j only for
+    i < j in a random topological order, with probability mean_degree / n,
+    durations uniform in (0, 10]; absent = -inf."""
+    g = rng(seed)
+    perm = g.permutation(n)
+    mask = np.triu(g.random((n, n)) < mean_degree / n, 1)
+    A = np.where(mask, 10.0 * (1.0 - g.random((n, n))), -np.inf).astype(np.float32)
+    return A[np.ix_(perm, perm)]
