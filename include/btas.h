@@ -208,8 +208,12 @@ int btas_apsp_num_steps(int n);
  *   pointers to n[i] x n[i] row-major matrices with leading dimensions
  *   ldw[i], ldd[i] >= max(1, n[i]).  Every W[i] is read before any D[j] is
  *   written, so D[i] may equal W[i]; two outputs must not overlap
- *   (BTAS_ERR_ALIAS).  flags must be 0 (early exit is not offered here;
- *   it would not change the result).
+ *   (BTAS_ERR_ALIAS).  flags: 0 (every graph runs its T(n_i) squarings) or
+ *   BTAS_APSP_EARLY_EXIT: each squaring records per graph whether it changed
+ *   D, and the next squaring's tiles of a graph that did not change return at
+ *   once (the fixpoint then sits in both of its buffers).  Decided on the
+ *   device inside the captured graph, no host round trip; the results are
+ *   identical to flags = 0.  Any other flag: BTAS_ERR_UNSUPPORTED.
  * The first call with a given argument set builds a plan (device workspace of
  * two padded n_i x n_i buffers per graph, work lists, per-size-bucket tile
  * shapes chosen by timing every candidate shape of btas_tile_shape_t on this

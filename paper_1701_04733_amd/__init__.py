@@ -466,10 +466,11 @@ class BatchedAPSP:
 
     The first ``run()`` plans and captures the hipGraph; later calls replay it.
     ``Ws`` and ``Ds`` are lists of square device tensors of one dtype; D[i]
-    may be W[i] itself.
+    may be W[i] itself.  ``early_exit``: a graph's later squarings are skipped
+    on the device once one leaves it unchanged (same results).
     """
 
-    def __init__(self, Ws, Ds=None, handle=None):
+    def __init__(self, Ws, Ds=None, handle=None, early_exit=False):
         import torch
         if not Ws:
             raise ValueError("need at least one graph")
@@ -494,11 +495,12 @@ class BatchedAPSP:
             c, e = _mat(d, "D")
             ns.append(n); pw.append(a.value); lw.append(b); pd.append(c.value); ld.append(e)
         self._args = (IA(*ns), PA(*pw), IA(*lw), PA(*pd), IA(*ld))
+        self.flags = APSP_EARLY_EXIT if early_exit else 0
 
     def run(self):
         n, pw, lw, pd, ld = self._args
         self.h.check(lib().btas_apsp_squaring_batched(self.h.ptr, self.dt, len(self.Ws), n, pw, lw,
-                                                      pd, ld, 0))
+                                                      pd, ld, self.flags))
         return self.Ds
 
     def plan_info(self):
@@ -512,9 +514,9 @@ class BatchedAPSP:
         return lib().btas_batched_tile_choice(self.h.ptr, self.dt, int(n))
 
 
-def apsp_batched(Ws, Ds=None, handle=None):
+def apsp_batched(Ws, Ds=None, handle=None, early_exit=False):
     """Solve every graph in ``Ws`` by repeated squaring in one graph launch."""
-    return BatchedAPSP(Ws, Ds, handle).run()
+    return BatchedAPSP(Ws, Ds, handle, early_exit=early_exit).run()
 
 
 class Server:

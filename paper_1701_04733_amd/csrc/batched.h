@@ -203,10 +203,14 @@ struct BatchCopy {
 // 2^T * maxabs <= 2^23-1 is computed on the binary32 pipeline, reading int32
 // storage with conversions, or (float_storage) buffers that
 // launch_grouped_init filled with binary32 values.  changed (may be null):
-// per-graph flag set to 1 when a squaring changed some entry.
+// with early_stride == 0, changed[graph] is set to 1 when a squaring changed
+// some entry; with early_stride > 0 (early exit), squaring s sets
+// changed[s * early_stride + graph] and an item of squaring s >= 2 whose graph
+// left squaring s-1 unchanged returns at once (from then on both buffers
+// hold the fixpoint, so skipping is exact).
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
                                int nitems, const int* maxabs, int* changed, hipStream_t s,
-                               int family = 0, bool float_storage = false);
+                               int family = 0, bool float_storage = false, int early_stride = 0);
 // int32: maxabs[graph] <- max |finite element of I (+) W| (maxabs zeroed
 // first); the first pass of the float-storage mode.
 hipError_t launch_grouped_maxabs(const BatchGraph* graphs, const BatchCopy* jobs, int njobs,

@@ -45,12 +45,28 @@ struct FloatView {
     float* dst;
 };
 
+// The change flag an item writes (null: none); false when the item is to be
+// skipped because its graph reached the fixpoint at the previous squaring
+// (early exit; uniform over the workgroup).
+__device__ __forceinline__ bool step_flag(int* changed, const BatchItem& it, int early_stride,
+                                          int*& flag) {
+    flag = nullptr;
+    if (changed == nullptr) return true;
+    if (early_stride == 0) {
+        flag = changed + it.graph;
+        return true;
+    }
+    if (it.step >= 2 && changed[(it.step - 1) * early_stride + it.graph] == 0) return false;
+    flag = changed + it.step * early_stride + it.graph;
+    return true;
+}
+
 template <typename T, int SR>
 __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __restrict__ graphs,
                                                             const BatchItem* __restrict__ items,
                                                             const int* __restrict__ maxabs,
                                                             int* __restrict__ changed,
-                                                            int float_storage) {
+                                                            int float_storage, int early_stride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchItem it = items[blockIdx.x];
     if (it.kind == BATCH_TILE_NONE) return;
@@ -58,7 +74,8 @@ __global__ __launch_bounds__(256) void grouped_step_kernel(const BatchGraph* __r
     const bool odd = ((g.parity + it.step) & 1) != 0;  // squaring it.step writes buf[odd]
     const T* src = (const T*)(odd ? g.buf[0] : g.buf[1]);
     T* dst = (T*)(odd ? g.buf[1] : g.buf[0]);
-    int* chg = changed != nullptr ? changed + it.graph : nullptr;
+    int* chg;
+    if (!step_flag(changed, it, early_stride, chg)) return;
     TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
     const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
     if constexpr (std::is_same_v<T, int32_t>) {
@@ -88,7 +105,7 @@ __global__ __launch_bounds__(64) void grouped_wave_step_kernel(const BatchGraph*
                                                                 const BatchItem* __restrict__ items,
                                                                 const int* __restrict__ maxabs,
                                                                 int* __restrict__ changed,
-                                                                int float_storage) {
+                                                                int float_storage, int early_stride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchItem it = items[blockIdx.x];
     if (it.kind == BATCH_TILE_NONE) return;
@@ -96,7 +113,8 @@ __global__ __launch_bounds__(64) void grouped_wave_step_kernel(const BatchGraph*
     const bool odd = ((g.parity + it.step) & 1) != 0;  // squaring it.step writes buf[odd]
     const T* src = (const T*)(odd ? g.buf[0] : g.buf[1]);
     T* dst = (T*)(odd ? g.buf[1] : g.buf[0]);
-    int* chg = changed != nullptr ? changed + it.graph : nullptr;
+    int* chg;
+    if (!step_flag(changed, it, early_stride, chg)) return;
     TileArgs<T> a{g.n, g.n, g.n, src, g.ld, src, g.ld, src, g.ld, dst, g.ld, chg, nullptr};
     const bool narrow = graph_is_narrow<T>(g, maxabs, it.graph);
     if constexpr (std::is_same_v<T, int32_t>) {
@@ -129,7 +147,7 @@ template <typename T, int SR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
 grouped_direct_step_kernel(const BatchGraph* __restrict__ graphs, const BatchItem* __restrict__ items,
                            const int* __restrict__ maxabs, int* __restrict__ changed,
-                           int float_storage) {
+                           int float_storage, int early_stride) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchItem it = items[blockIdx.x];
     if (it.kind == BATCH_TILE_NONE) return;
@@ -137,7 +155,8 @@ grouped_direct_step_kernel(const BatchGraph* __restrict__ graphs, const BatchIte
     const bool odd = ((g.parity + it.step) & 1) != 0;
     const T* src = (const T*)(odd ? g.buf[0] : g.buf[1]);
     T* dst = (T*)(odd ? g.buf[1] : g.buf[0]);
-    int* chg = changed != nullptr ? changed + it.graph : nullptr;
+    int* chg;
+    if (!step_flag(changed, it, early_stride, chg)) return;
     const int np = g.np;
     if (std::is_same_v<T, float> || (float_storage && graph_is_narrow<T>(g, maxabs, it.graph))) {
         TileArgs<float> f{np, np, np, (const float*)src, np, (const float*)src, np,
@@ -153,7 +172,7 @@ grouped_direct_step_kernel(const BatchGraph* __restrict__ graphs, const BatchIte
 
 hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem* items,
                                int nitems, const int* maxabs, int* changed, hipStream_t s,
-                               int family, bool float_storage) {
+                               int family, bool float_storage, int early_stride) {
     if (nitems <= 0) return hipSuccess;
     const int fs = float_storage ? 1 : 0;
     if (family == 2) {
@@ -161,29 +180,29 @@ hipError_t launch_grouped_step(int dt, const BatchGraph* graphs, const BatchItem
                                ? GemmTileDirect<CfgWD, BTAS_MIN_PLUS>::lds_bytes : CfgW::lds_bytes;
         if (dt == BTAS_FLOAT32)
             hipLaunchKernelGGL((grouped_direct_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems),
-                               dim3(64), lds, s, graphs, items, nullptr, changed, 0);
+                               dim3(64), lds, s, graphs, items, nullptr, changed, 0, early_stride);
         else
             hipLaunchKernelGGL((grouped_direct_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems),
-                               dim3(64), lds, s, graphs, items, maxabs, changed, fs);
+                               dim3(64), lds, s, graphs, items, maxabs, changed, fs, early_stride);
         return hipGetLastError();
     }
     if (family == 1) {
         const size_t lds = CfgW::lds_bytes > CfgS::lds_bytes ? CfgW::lds_bytes : CfgS::lds_bytes;
         if (dt == BTAS_FLOAT32)
             hipLaunchKernelGGL((grouped_wave_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems),
-                               dim3(64), lds, s, graphs, items, nullptr, changed, 0);
+                               dim3(64), lds, s, graphs, items, nullptr, changed, 0, early_stride);
         else
             hipLaunchKernelGGL((grouped_wave_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems),
-                               dim3(64), lds, s, graphs, items, maxabs, changed, fs);
+                               dim3(64), lds, s, graphs, items, maxabs, changed, fs, early_stride);
         return hipGetLastError();
     }
     const size_t lds = CfgL::lds_bytes > CfgM::lds_bytes ? CfgL::lds_bytes : CfgM::lds_bytes;
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL((grouped_step_kernel<float, BTAS_MIN_PLUS>), dim3(nitems), dim3(256), lds,
-                           s, graphs, items, nullptr, changed, 0);
+                           s, graphs, items, nullptr, changed, 0, early_stride);
     else
         hipLaunchKernelGGL((grouped_step_kernel<int32_t, BTAS_MIN_PLUS>), dim3(nitems), dim3(256),
-                           lds, s, graphs, items, maxabs, changed, fs);
+                           lds, s, graphs, items, maxabs, changed, fs, early_stride);
     return hipGetLastError();
 }
 

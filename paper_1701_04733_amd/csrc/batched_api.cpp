@@ -46,6 +46,7 @@ struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     double terms = 0;                     // sum over graphs of T(n) * n^3
     int family = 0;                       // squaring kernel: 0 block, 1 wave, 2 direct
+    int* d_changed = nullptr;             // early exit: changed[s * ngraphs + g] for squaring s
 };
 
 void destroy_batch_plan(BatchPlan* p) {
@@ -53,7 +54,7 @@ void destroy_batch_plan(BatchPlan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     for (void* q : {(void*)p->d_graphs, (void*)p->d_items, (void*)p->d_init, (void*)p->d_out,
-                    (void*)p->d_maxabs, (void*)p->d_block_job, p->ws})
+                    (void*)p->d_maxabs, (void*)p->d_block_job, (void*)p->d_changed, p->ws})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -189,9 +190,9 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
     if (dt != BTAS_INT32 && dt != BTAS_FLOAT32)
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (count < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (count=%d) < 0", fn, count);
-    if (flags != 0)
-        return fail(h, BTAS_ERR_UNSUPPORTED, "%s: flags=0x%x; batched solves run the fixed T(n) squarings "
-                    "(early exit would give the same bits)", fn, flags);
+    if (flags & ~BTAS_APSP_EARLY_EXIT)
+        return fail(h, BTAS_ERR_UNSUPPORTED, "%s: flags=0x%x; only BTAS_APSP_EARLY_EXIT", fn, flags);
+    const bool early = flags & BTAS_APSP_EARLY_EXIT;
     if (count == 0) return BTAS_OK;
     if (!n || !W || !ldw || !D || !ldd)
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: a host array argument is null", fn);
@@ -214,6 +215,7 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
 
     DeviceGuard guard(h->device);
     uint64_t key = mix(0x42ull, (uint64_t)dt);
+    key = mix(key, early ? 1u : 0u);
     key = mix(key, (uint64_t)count);
     for (int i = 0; i < count; ++i) {
         key = mix(key, (uint64_t)n[i]);
@@ -339,6 +341,9 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         }
         st = upload(h, fn, (void**)&p->d_items, items.data(), sizeof(BatchItem) * items.size());
         if (st != BTAS_OK) return st;
+        const int nflags = early ? ng * (Tmax + 1) : 0;
+        if (nflags > 0 && hipMalloc((void**)&p->d_changed, sizeof(int) * nflags) != hipSuccess)
+            return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the change flags", fn);
         // Copy jobs (caller order is irrelevant: one job per graph).
         std::vector<BatchCopy> init(ng), out(ng);
         int blocks = 0;
@@ -373,9 +378,13 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         if (e == hipSuccess)
             e = launch_grouped_init(dt, p->d_graphs, p->d_init, ng, blocks, i32 ? p->d_maxabs : nullptr,
                                     h->aux_stream, i32, p->d_block_job);
+        // early exit: per squaring and graph, whether it changed D; an item
+        // whose graph did not change at the previous squaring is skipped
+        if (e == hipSuccess && nflags > 0) e = launch_clear_ints(p->d_changed, nflags, h->aux_stream);
         for (int t = 0; t < Tmax && e == hipSuccess; ++t)
             e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
-                                    i32 ? p->d_maxabs : nullptr, nullptr, h->aux_stream, p->family, i32);
+                                    i32 ? p->d_maxabs : nullptr, p->d_changed, h->aux_stream, p->family,
+                                    i32, nflags > 0 ? ng : 0);
         if (e == hipSuccess)
             e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream,
                                         i32 ? p->d_maxabs : nullptr, p->d_block_job);

@@ -171,3 +171,61 @@ def test_batched_full_config_vs_plain_and_oracle(dev):
     for i in sample:
         want, _, _ = oracle.apsp(Ws[i])
         assert np.array_equal(Ds[i].cpu().numpy(), want), f"graph {i}"
+
+
+def _convergence_mix(dt, seed):
+    """Graphs that reach their fixpoint at different squarings: complete
+    graphs (first squaring unchanged), long directed paths (need all T),
+    sparse random graphs in between."""
+    g = wl.rng(seed)
+    Ws = _mixed_graphs(dt, 20, seed=seed, lo=2, hi=260)
+    for n in (17, 64, 129):
+        W = np.full((n, n), 5, np.int32)
+        np.fill_diagonal(W, 0)
+        Ws.append(W)
+        P = np.full((n, n), wl.I32_INF, np.int32)
+        np.fill_diagonal(P, 0)
+        P[np.arange(n - 1), np.arange(1, n)] = g.integers(1, 9, n - 1)
+        Ws.append(P)
+    if dt == "f32":
+        Ws = [w if w.dtype == np.float32 else
+              np.where(w == wl.I32_INF, np.inf, w).astype(np.float32) for w in Ws]
+    return Ws
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+@pytest.mark.parametrize("tile", [None, "w64d", "128", "w64"])
+def test_batched_early_exit_matches_oracle(dev, dt, tile, monkeypatch):
+    """Early exit skips a graph's squarings after its fixpoint, on the
+    device; every result equals the oracle (fixed T) bit for bit, also on
+    replay, for each kernel family."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    if tile is not None:
+        monkeypatch.setenv("BTAS_BATCHED_TILE", tile)
+    Ws = _convergence_mix(dt, seed=11)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    runner = btas.BatchedAPSP(tW, early_exit=True)
+    for rep in range(2):
+        Ds = runner.run()
+        torch.cuda.synchronize()
+        for W, D in zip(Ws, Ds):
+            want, _, _ = oracle.apsp(W)
+            assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"rep {rep} n={W.shape[0]}"
+        for D in Ds:
+            D.fill_(0)
+
+
+def test_batched_early_exit_full_config_equals_fixed(dev):
+    """The 4096-graph workload with early exit gives the fixed-T bits."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = wl.batched_graphs_i32(count=4096, seed=5)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    fixed = btas.apsp_batched(tW)
+    early = btas.apsp_batched(tW, early_exit=True)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(fixed, early)):
+        assert torch.equal(a, b), f"graph {i} (n={Ws[i].shape[0]})"
