@@ -386,7 +386,7 @@ def bench_level12(dev, reps=10):
     return out
 
 
-def _serve_trace(reqs, mode):
+def _serve_trace(reqs, mode, early_exit=False):
     import threading
 
     import numpy as np
@@ -417,7 +417,7 @@ def _serve_trace(reqs, mode):
             if left <= 0:
                 break
             time.sleep(left if left > 0.002 else 0)
-        ids[i] = srv.submit(r.n, r.rows, r.cols, r.w, arrival=target)
+        ids[i] = srv.submit(r.n, r.rows, r.cols, r.w, early_exit=early_exit, arrival=target)
     th.join()
     st = srv.stats()
     srv.close()
@@ -431,14 +431,16 @@ def _serve_trace(reqs, mode):
 def bench_served(rates, count):
     """Open-loop Poisson trace of fp32 APSP requests (n log-uniform in
     [32,4096], out-degree 12, weights in (0,10], COO in, densified on the
-    device, fixed T(n)), served with continuous batching and with the plain
-    FIFO one-solve-per-launch path on the same trace."""
+    device, fixed T(n)), served with continuous batching (also with each
+    request's early exit: same bits) and with the plain FIFO
+    one-solve-per-launch path on the same trace."""
     from paper_1701_04733_amd import workloads as wl
     out = {"workload": f"served APSP fp32, {count} requests per rate, n log-uniform [32,4096], "
                        "out-degree 12, HBM budget 64 GiB"}
     for rate in rates:
         reqs = wl.served_requests(count, float(rate))
         out[f"rate_{rate}"] = {"continuous": _serve_trace(reqs, "continuous"),
+                               "continuous_early_exit": _serve_trace(reqs, "continuous", True),
                                "fifo": _serve_trace(reqs, "fifo")}
     return out
 

@@ -312,8 +312,12 @@ btas_status_t btas_tropical_gemm_witness(btas_handle_t h, btas_semiring_t sr, bt
  * btas_apsp_squaring (n x n, leading dimensions ldw, ldd; W and D may be the
  * same matrix only if the caller wants the successors of D itself); S is an
  * n x n int32 device matrix, leading dimension lds >= max(1,n),
- * caller-owned, and must not overlap W or D (BTAS_ERR_ALIAS).  One launch of
- * n^3 terms, asynchronous. */
+ * caller-owned, and must not overlap W or D (BTAS_ERR_ALIAS).  For n >= 256
+ * and W with at most n^2/32 edges off the diagonal (counted first, one host
+ * round trip) the argmin runs over each row's edges only, |row i| terms per
+ * entry, from a compressed copy of W in the handle's workspace; otherwise
+ * one witness product of n^3 terms.  Same S either way.  BTAS_SPARSE_STEPS=0
+ * forces the product, =force the edge lists at any n. */
 btas_status_t btas_apsp_successors(btas_handle_t h, btas_dtype_t dt, int n, const void *W, int ldw,
                                    const void *D, int ldd, int32_t *S, int lds);
 

@@ -2,6 +2,7 @@
 // kernels.  See include/btas.h for the contract of every entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -172,6 +173,43 @@ int sparse_step(btas_handle_t h, const char* fn, int dt, int n, const void* D, l
         return 0;
     e = btas::launch_sparse_square(dt, n, D, ld, E, lde, rowptr, cols, vals, changed, wide_out,
                                    h->stream);
+    if (e != hipSuccess) {
+        *st = device_fail(h, fn, e);
+        return -1;
+    }
+    return 1;
+}
+
+// Successors from W's edge lists when W is sparse: |row i| terms per entry
+// instead of n (the dense witness product's).  1 if done, 0 if W is too
+// dense (or no workspace), -1 on error (*st set).
+constexpr long SUCC_SPARSE_DIV = 32;  // sparse while W has <= n^2/32 edges
+
+int sparse_successors(btas_handle_t h, const char* fn, int dt, int n, const void* W, long ldw,
+                      const void* D, long ldd, int32_t* S, long lds, btas_status_t* st) {
+    const size_t head = ((size_t)(2 * n + 2) * 4 + 255) & ~(size_t)255;
+    const size_t cap = std::max<size_t>(1, (size_t)n * n / SUCC_SPARSE_DIV);
+    hipError_t e = ensure_sparse_ws(h, head + cap * 8 + 16);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    unsigned long long* counters = reinterpret_cast<unsigned long long*>(h->dflags + FLAG_SPARSE);
+    int* rownnz = reinterpret_cast<int*>(h->sp_ws);
+    int* rowptr = rownnz + n;
+    int* cols = reinterpret_cast<int*>(static_cast<char*>(h->sp_ws) + head);
+    void* vals = cols + cap;
+    if (e == hipSuccess) e = btas::launch_clear_flags(h->dflags + FLAG_SPARSE, 4, h->stream);
+    if (e == hipSuccess) e = btas::launch_sparse_count(dt, n, W, ldw, rownnz, counters, h->stream, true);
+    if (e != hipSuccess) {
+        *st = device_fail(h, fn, e);
+        return -1;
+    }
+    if ((*st = sync_flags(h, fn, FLAG_SPARSE + 4)) != BTAS_OK) return -1;
+    if (flag_u64(h, FLAG_SPARSE) > cap) return 0;
+    e = btas::launch_sparse_build(dt, n, W, ldw, rownnz, rowptr, cols, vals, counters, h->stream, true);
+    if (e == hipSuccess)
+        e = btas::launch_sparse_successors(dt, n, rowptr, cols, vals, D, ldd, S, lds, h->stream);
     if (e != hipSuccess) {
         *st = device_fail(h, fn, e);
         return -1;
@@ -717,6 +755,13 @@ btas_status_t btas_apsp_successors(btas_handle_t h, btas_dtype_t dt, int n, cons
     const long rows[2] = {n, n}, cols[2] = {n, n}, ldv[2] = {ldw, ldd};
     btas_status_t st = validate_operands(h, fn, BTAS_MIN_PLUS, dt, ps, rows, cols, ldv, 2);
     if (st != BTAS_OK) return st;
+    const SparseMode mode = n <= SPARSE_MAX_N ? sparse_mode(n) : SparseMode::Off;
+    const char* env = getenv("BTAS_SPARSE_STEPS");
+    if (!(env && env[0] == '0') && (n >= 256 || mode == SparseMode::Force)) {
+        const int r = sparse_successors(h, fn, dt, n, W, ldw, D, ldd, S, lds, &st);
+        if (r < 0) return st;
+        if (r == 1) return BTAS_OK;
+    }
     hipError_t e = btas::launch_successors(dt, n, W, ldw, D, ldd, S, lds, h->stream);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
 }

@@ -120,10 +120,18 @@ hipError_t launch_floyd_warshall(int dt, int n, void* D, long ld, hipStream_t s)
 // (LDS of sparse_step_lds_bytes(n) per workgroup), changed / wide_out flags
 // as in the dense product.
 size_t sparse_step_lds_bytes(int n);
+// skip_diag: leave out the diagonal (a graph's edges without self loops).
 hipError_t launch_sparse_count(int dt, int n, const void* D, long ld, int* rownnz,
-                               unsigned long long* counters, hipStream_t s);
+                               unsigned long long* counters, hipStream_t s, bool skip_diag = false);
 hipError_t launch_sparse_build(int dt, int n, const void* D, long ld, const int* rownnz, int* rowptr,
-                               int* cols, void* vals, unsigned long long* counters, hipStream_t s);
+                               int* cols, void* vals, unsigned long long* counters, hipStream_t s,
+                               bool skip_diag = false);
+// Successors from the CSR of W without its diagonal (column order kept):
+// the same S as launch_successors, one row per workgroup, |row i| terms per
+// entry instead of n.
+hipError_t launch_sparse_successors(int dt, int n, const int* rowptr, const int* cols,
+                                    const void* vals, const void* D, long ldd, int32_t* S, long lds,
+                                    hipStream_t s);
 hipError_t launch_sparse_square(int dt, int n, const void* D, long ld, void* E, long lde,
                                 const int* rowptr, const int* cols, const void* vals, int* changed,
                                 int* wide_out, hipStream_t s);

@@ -44,15 +44,16 @@ __device__ __forceinline__ long long block_sum(long long v, long long* red) {
     return t;
 }
 
-// rownnz[i] = finite entries of row i; counters[0] += their total.
+// rownnz[i] = finite entries of row i (off the diagonal if skip_diag);
+// counters[0] += their total.
 template <typename T>
 __global__ __launch_bounds__(SP_NT) void sp_count_kernel(int n, const T* D, long ld, int* rownnz,
-                                                        unsigned long long* counters) {
+                                                        unsigned long long* counters, int skip_diag) {
     __shared__ long long red[SP_NT / 64];
     const int i = blockIdx.x;
     const T* row = D + (long)i * ld;
     long long c = 0;
-    for (int j = threadIdx.x; j < n; j += SP_NT) c += present(row[j]) ? 1 : 0;
+    for (int j = threadIdx.x; j < n; j += SP_NT) c += present(row[j]) && !(skip_diag && j == i) ? 1 : 0;
     c = block_sum(c, red);
     if (threadIdx.x == 0) {
         rownnz[i] = (int)c;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(1024) void sp_scan_kernel(int n, const int* rownnz,
 template <typename T>
 __global__ __launch_bounds__(SP_NT) void sp_compact_kernel(int n, const T* D, long ld, const int* rownnz,
                                                           const int* rowptr, int* cols, T* vals,
-                                                          unsigned long long* counters) {
+                                                          unsigned long long* counters, int skip_diag) {
     __shared__ int wave_count[SP_NT / 64];
     __shared__ long long red[SP_NT / 64];
     const int i = blockIdx.x;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(SP_NT) void sp_compact_kernel(int n, const T* D, lo
     for (int j0 = 0; j0 < n; j0 += SP_NT) {
         const int j = j0 + threadIdx.x;
         const T x = j < n ? row[j] : Ring<BTAS_MIN_PLUS, T>::absent();
-        const bool f = j < n && present(x);
+        const bool f = j < n && present(x) && !(skip_diag && j == i);
         const unsigned long long mask = __ballot(f);
         const int before = __popcll(mask & ((1ull << lane) - 1));
         __syncthreads();  // wave_count of the previous chunk is consumed
@@ -158,30 +159,87 @@ __global__ __launch_bounds__(SP_NT) void sp_square_kernel(int n, const T* D, lon
     if (wide_out != nullptr && __any(wide) && lane == 0) *wide_out = 1;
 }
 
+// Successors from the CSR of W without its diagonal: S_ij = the first u (in
+// column order, so the smallest) of row i's edges minimising W_iu (.) D_uj,
+// -1 if every such term is absent; S_ii = i.  One workgroup per row, each
+// thread four consecutive columns per round.
+template <typename T>
+__global__ __launch_bounds__(SP_NT) void sp_successor_kernel(int n, const int* rowptr, const int* cols,
+                                                            const T* vals, const T* D, long ldd,
+                                                            int32_t* S, long lds) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    const int i = blockIdx.x;
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    int32_t* srow = S + (long)i * lds;
+    for (int j0 = threadIdx.x * 4; j0 < n; j0 += SP_NT * 4) {
+        T best[4];
+        int arg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            best[q] = R::absent();
+            arg[q] = -1;
+        }
+        for (int e = e0; e < e1; ++e) {
+            const int u = cols[e];
+            const T w = vals[e];
+            const T* drow = D + (long)u * ldd;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (j0 + q >= n) break;
+                const T d = drow[j0 + q];
+                if (!present(d)) continue;  // an absent D_uj never wins
+                const T t = R::mul(w, d);
+                if (t < best[q]) {
+                    best[q] = t;
+                    arg[q] = u;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (j0 + q < n) srow[j0 + q] = j0 + q == i ? i : arg[q];
+    }
+}
+
 }  // namespace
 
 size_t sparse_step_lds_bytes(int n) { return (size_t)n * 4; }
 
 hipError_t launch_sparse_count(int dt, int n, const void* D, long ld, int* rownnz,
-                               unsigned long long* counters, hipStream_t s) {
+                               unsigned long long* counters, hipStream_t s, bool skip_diag) {
+    const int sd = skip_diag ? 1 : 0;
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL(sp_count_kernel<float>, dim3(n), dim3(SP_NT), 0, s, n, (const float*)D, ld,
-                           rownnz, counters);
+                           rownnz, counters, sd);
     else
         hipLaunchKernelGGL(sp_count_kernel<int32_t>, dim3(n), dim3(SP_NT), 0, s, n, (const int32_t*)D,
-                           ld, rownnz, counters);
+                           ld, rownnz, counters, sd);
     return hipGetLastError();
 }
 
 hipError_t launch_sparse_build(int dt, int n, const void* D, long ld, const int* rownnz, int* rowptr,
-                               int* cols, void* vals, unsigned long long* counters, hipStream_t s) {
+                               int* cols, void* vals, unsigned long long* counters, hipStream_t s,
+                               bool skip_diag) {
+    const int sd = skip_diag ? 1 : 0;
     hipLaunchKernelGGL(sp_scan_kernel, dim3(1), dim3(1024), 0, s, n, rownnz, rowptr);
     if (dt == BTAS_FLOAT32)
         hipLaunchKernelGGL(sp_compact_kernel<float>, dim3(n), dim3(SP_NT), 0, s, n, (const float*)D, ld,
-                           rownnz, rowptr, cols, (float*)vals, counters);
+                           rownnz, rowptr, cols, (float*)vals, counters, sd);
     else
         hipLaunchKernelGGL(sp_compact_kernel<int32_t>, dim3(n), dim3(SP_NT), 0, s, n, (const int32_t*)D,
-                           ld, rownnz, rowptr, cols, (int32_t*)vals, counters);
+                           ld, rownnz, rowptr, cols, (int32_t*)vals, counters, sd);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_successors(int dt, int n, const int* rowptr, const int* cols,
+                                    const void* vals, const void* D, long ldd, int32_t* S, long lds,
+                                    hipStream_t s) {
+    if (dt == BTAS_FLOAT32)
+        hipLaunchKernelGGL(sp_successor_kernel<float>, dim3(n), dim3(SP_NT), 0, s, n, rowptr, cols,
+                           (const float*)vals, (const float*)D, ldd, S, lds);
+    else
+        hipLaunchKernelGGL(sp_successor_kernel<int32_t>, dim3(n), dim3(SP_NT), 0, s, n, rowptr, cols,
+                           (const int32_t*)vals, (const int32_t*)D, ldd, S, lds);
     return hipGetLastError();
 }
 

@@ -222,3 +222,24 @@ def test_successors_16384_f32_sampled_walks(dev):
         assert np.array_equal(cur[f], cols[f])
         assert np.all(length[f] >= exact[row][f] * (1 - 1e-12))
         assert np.all(length[f] <= exact[row][f] * (1 + 2.0 ** -12) + 1e-300)
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("n", [5, 65, 300, 700])
+def test_successors_sparse_and_dense_paths_match_oracle(dev, dt, n, monkeypatch):
+    """Successors from W's edge lists (the default for n >= 256 while W has at
+    most n^2/32 edges; forced here at every size) and from the dense witness
+    product (BTAS_SPARSE_STEPS=0) both equal the oracle."""
+    import paper_1701_04733_amd as btas
+    W = _graph(dt, n, seed=8800 + n, deg=5.0)
+    W[np.arange(n), np.arange(n)] = 0 if dt == "i32" else np.float32(0)
+    if n > 2:
+        W[1, 1] = 3 if dt == "i32" else np.float32(3)    # a self loop is not an edge to use
+    D, _, _ = oracle.apsp(W)
+    want = oracle.successors(W, D)
+    Wg = _dev(W, dev)
+    Dg, _, _ = btas.apsp(Wg)
+    for mode in ("force", "0"):
+        monkeypatch.setenv("BTAS_SPARSE_STEPS", mode)
+        S = btas.apsp_successors(Wg, Dg)
+        assert np.array_equal(S.cpu().numpy(), want), f"{dt} n={n} mode={mode}"
