@@ -244,6 +244,24 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
 btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, const void *W,
                                        int ldw, void *D, int ldd, unsigned flags);
 
+/* Blocked Floyd-Warshall (btas_apsp_floyd_warshall, pivot blocks of 64) of
+ * `count` independent graphs in one captured hipGraph: D[i] <- the result for
+ * I (+) W[i] (n[i] x n[i], row-major, leading dimensions ldw[i], ldd[i];
+ * device pointers in host arrays).  For every pivot block kb one launch per
+ * phase covers all graphs that have block kb, so the graph holds
+ * 1 + 3 * max_i ceil(n_i / 64) launches.  int32 results are the exact
+ * distances, bit-identical to btas_apsp_squaring and
+ * btas_apsp_squaring_batched; binary32 results equal btas_apsp_floyd_warshall
+ * graph by graph.  D[i] may be W[i] with ldd[i] == ldw[i] (in place); any
+ * other overlap of an output with any input or output is BTAS_ERR_ALIAS.
+ * flags must be 0.  Graphs must have no negative cycle (not checked; the
+ * result is unspecified otherwise).  The first call with an argument set
+ * builds and captures the plan (synchronises); identical later calls only
+ * launch it (asynchronous).  The handle keeps one such plan. */
+btas_status_t btas_apsp_floyd_warshall_batched(btas_handle_t h, btas_dtype_t dt, int count,
+                                               const int *n, const void *const *W, const int *ldw,
+                                               void *const *D, const int *ldd, unsigned flags);
+
 /* Closure (I (+) W)^(2^s) by repeated squaring over either semiring of
  * Sec. I: D_0 = I (+) W (I: 0 on the diagonal, the absent value elsewhere),
  * D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1} for t = 1..T = ceil(log2(n-1)), as in

@@ -93,6 +93,7 @@ def lib():
         L.btas_tropical_gemm_witness.argtypes = [P, I, I, I, I, I, P, I, P, I, P, I, P, I]
         L.btas_apsp_successors.argtypes = [P, I, I, P, I, P, I, P, I]
         L.btas_tropical_closure.argtypes = [P, I, I, I, P, I, P, I, U, ctypes.POINTER(I)]
+        L.btas_apsp_floyd_warshall_batched.argtypes = [P, I, I, IP, PP, IP, PP, IP, U]
         I64P = ctypes.POINTER(ctypes.c_int64)
         L.btas_maxplus_cycle_mean.argtypes = [P, I, I, P, I, I64P, I64P, ctypes.POINTER(ctypes.c_double)]
         L.btas_server_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.c_size_t, I, ctypes.c_double]
@@ -517,6 +518,52 @@ class BatchedAPSP:
 def apsp_batched(Ws, Ds=None, handle=None, early_exit=False):
     """Solve every graph in ``Ws`` by repeated squaring in one graph launch."""
     return BatchedAPSP(Ws, Ds, handle, early_exit=early_exit).run()
+
+
+class FloydWarshallBatched:
+    """Repeated blocked Floyd-Warshall solves of one fixed set of graphs
+    (square device tensors of one dtype; ``Ds[i]`` may be ``Ws[i]``).  The
+    argument arrays are prepared once; the first ``run()`` plans and captures
+    the launch sequence, later calls replay it.  int32 results equal the
+    squaring's; float32 results equal ``floyd_warshall`` graph by graph."""
+
+    def __init__(self, Ws, Ds=None, handle=None):
+        import torch
+        if not Ws:
+            raise ValueError("need at least one graph")
+        self.Ws = list(Ws)
+        self.Ds = list(Ds) if Ds is not None else [torch.empty_like(w) for w in self.Ws]
+        dts = {_dt(w) for w in self.Ws} | {_dt(d) for d in self.Ds}
+        if len(dts) != 1 or len(self.Ds) != len(self.Ws):
+            raise ValueError("one dtype for all graphs, and as many outputs as inputs")
+        self.dt = dts.pop()
+        self.h = handle if handle is not None else default_handle(self.Ws[0].device.index or 0)
+        cnt = len(self.Ws)
+        ns, pw, lw, pd, ld = [], [], [], [], []
+        for w, d in zip(self.Ws, self.Ds):
+            m = w.size(0)
+            if w.shape != (m, m) or d.shape != (m, m):
+                raise ValueError("graphs must be square and D must match W")
+            a, b = _mat(w, "W")
+            c, e = _mat(d, "D")
+            ns.append(m); pw.append(a.value); lw.append(b); pd.append(c.value); ld.append(e)
+        IA = ctypes.c_int * cnt
+        PA = ctypes.c_void_p * cnt
+        self._args = (IA(*ns), PA(*pw), IA(*lw), PA(*pd), IA(*ld))
+
+    def run(self):
+        n, pw, lw, pd, ld = self._args
+        self.h.check(lib().btas_apsp_floyd_warshall_batched(self.h.ptr, self.dt, len(self.Ws), n, pw,
+                                                            lw, pd, ld, 0))
+        return self.Ds
+
+
+def floyd_warshall_batched(Ws, Ds=None, handle=None):
+    """Blocked Floyd-Warshall of every graph in ``Ws`` in one captured launch
+    sequence (see FloydWarshallBatched).  Returns Ds."""
+    if not Ws:
+        return []
+    return FloydWarshallBatched(Ws, Ds, handle).run()
 
 
 class Server:

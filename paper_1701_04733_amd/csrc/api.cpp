@@ -281,6 +281,7 @@ btas_status_t btas_destroy(btas_handle_t h) {
     DeviceGuard g(h->device);
     (void)hipStreamSynchronize(h->stream);
     h->batch_plan.reset();
+    h->fw_batch_plan.reset();
     if (h->apsp_exec) (void)hipGraphExecDestroy(h->apsp_exec);
     if (h->apsp_graph) (void)hipGraphDestroy(h->apsp_graph);
     if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);

@@ -26,6 +26,7 @@
 
 #include "batched.h"
 #include "context.h"
+#include "kernels.h"
 
 namespace btas {
 
@@ -196,6 +197,22 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
     if (count == 0) return BTAS_OK;
     if (!n || !W || !ldw || !D || !ldd)
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: a host array argument is null", fn);
+    uint64_t key = mix(0x42ull, (uint64_t)dt);
+    key = mix(key, early ? 1u : 0u);
+    key = mix(key, (uint64_t)count);
+    for (int i = 0; i < count; ++i) {
+        key = mix(key, (uint64_t)n[i]);
+        key = mix(key, ((uint64_t)(uint32_t)ldw[i] << 32) | (uint32_t)ldd[i]);
+        key = mix(key, (uint64_t)(uintptr_t)W[i]);
+        key = mix(key, (uint64_t)(uintptr_t)D[i]);
+    }
+    if (h->batch_plan && h->batch_plan->key == key) {
+        // the arguments of the current plan (every argument is in the key),
+        // checked when it was built: replay it
+        DeviceGuard g(h->device);
+        const hipError_t e = hipGraphLaunch(h->batch_plan->exec, h->stream);
+        return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+    }
     std::vector<Span> dspans;
     for (int i = 0; i < count; ++i) {
         if (n[i] < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: n[%d]=%d < 0", fn, i, n[i]);
@@ -214,15 +231,6 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
             return fail(h, BTAS_ERR_ALIAS, "%s: two output matrices overlap", fn);
 
     DeviceGuard guard(h->device);
-    uint64_t key = mix(0x42ull, (uint64_t)dt);
-    key = mix(key, early ? 1u : 0u);
-    key = mix(key, (uint64_t)count);
-    for (int i = 0; i < count; ++i) {
-        key = mix(key, (uint64_t)n[i]);
-        key = mix(key, ((uint64_t)(uint32_t)ldw[i] << 32) | (uint32_t)ldd[i]);
-        key = mix(key, (uint64_t)(uintptr_t)W[i]);
-        key = mix(key, (uint64_t)(uintptr_t)D[i]);
-    }
 
     hipError_t e = hipSuccess;
     if (!h->aux_stream) {
@@ -418,4 +426,166 @@ extern "C" int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n)
     if (!h) return -1;
     auto it = h->tile_choice.find({(int)dt, size_bucket(n)});
     return it == h->tile_choice.end() ? -1 : it->second;
+}
+
+// ------------------------------------------------- batched Floyd-Warshall ---
+namespace btas {
+
+struct FwBatchPlan {
+    uint64_t key = 0;
+    int dt = 0;
+    FwGraph* d_graphs = nullptr;
+    FwItem* d_items = nullptr;
+    struct Launch {
+        int phase, kb, off, cnt;
+    };
+    std::vector<Launch> launches;
+    bool vec = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void destroy_fw_batch_plan(FwBatchPlan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_graphs) (void)hipFree(p->d_graphs);
+    if (p->d_items) (void)hipFree(p->d_items);
+    delete p;
+}
+
+}  // namespace btas
+
+extern "C" btas_status_t btas_apsp_floyd_warshall_batched(btas_handle_t h, btas_dtype_t dt, int count,
+                                                         const int* n, const void* const* W,
+                                                         const int* ldw, void* const* D,
+                                                         const int* ldd, unsigned flags) {
+    const char* fn = "btas_apsp_floyd_warshall_batched";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (dt != BTAS_INT32 && dt != BTAS_FLOAT32)
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
+    if (count < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (count=%d) < 0", fn, count);
+    if (flags != 0) return fail(h, BTAS_ERR_UNSUPPORTED, "%s: flags=0x%x; none are defined", fn, flags);
+    if (count == 0) return BTAS_OK;
+    if (!n || !W || !ldw || !D || !ldd)
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: a host array argument is null", fn);
+    uint64_t key = mix(0x46ull, (uint64_t)dt);
+    key = mix(key, (uint64_t)count);
+    for (int i = 0; i < count; ++i) {
+        key = mix(key, (uint64_t)n[i]);
+        key = mix(key, ((uint64_t)(uint32_t)ldw[i] << 32) | (uint32_t)ldd[i]);
+        key = mix(key, (uint64_t)(uintptr_t)W[i]);
+        key = mix(key, (uint64_t)(uintptr_t)D[i]);
+    }
+    if (h->fw_batch_plan && h->fw_batch_plan->key == key) {  // validated when it was built
+        DeviceGuard g(h->device);
+        const hipError_t e = hipGraphLaunch(h->fw_batch_plan->exec, h->stream);
+        return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
+    }
+    // D[i] may be W[i] with the same leading dimension (in place); no output
+    // may touch another graph's input or output, nor its own input otherwise
+    // (the first launch reads every W while it writes every D).
+    struct Tagged {
+        Span s;
+        int graph;
+        bool out;
+    };
+    std::vector<Tagged> spans;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: n[%d]=%d < 0", fn, i, n[i]);
+        if (ldw[i] < std::max(1, n[i]))
+            return fail(h, BTAS_ERR_INVALID_ARG, "%s: ldw[%d]=%d < max(1,n)", fn, i, ldw[i]);
+        if (ldd[i] < std::max(1, n[i]))
+            return fail(h, BTAS_ERR_INVALID_ARG, "%s: ldd[%d]=%d < max(1,n)", fn, i, ldd[i]);
+        if (n[i] == 0) continue;
+        if (!W[i] || !D[i]) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W[%d] or D[%d] is null", fn, i, i);
+        const bool in_place = W[i] == D[i] && ldw[i] == ldd[i];
+        spans.push_back({mat_span(D[i], n[i], n[i], ldd[i]), i, true});
+        if (!in_place) spans.push_back({mat_span(W[i], n[i], n[i], ldw[i]), i, false});
+    }
+    std::sort(spans.begin(), spans.end(), [](const Tagged& a, const Tagged& b) { return a.s.lo < b.s.lo; });
+    for (size_t i = 0; i < spans.size(); ++i)  // every overlapping pair that involves an output
+        for (size_t j = i + 1; j < spans.size() && spans[j].s.lo < spans[i].s.hi; ++j)
+            if (spans[i].out || spans[j].out)
+                return fail(h, BTAS_ERR_ALIAS, "%s: an output overlaps another matrix (graphs %d, %d)", fn,
+                            spans[i].graph, spans[j].graph);
+
+    DeviceGuard guard(h->device);
+    hipError_t e = hipSuccess;
+    if (!h->aux_stream) {
+        e = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+    }
+    FwBatchPlan* plan = h->fw_batch_plan.get();
+    if (!plan || plan->key != key) {
+        if (plan) {
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+        }
+        h->fw_batch_plan.reset();
+        std::unique_ptr<FwBatchPlan, FwBatchPlanDeleter> p(new FwBatchPlan);
+        p->key = key;
+        p->dt = dt;
+        const int B = fw_block_size();
+        std::vector<FwGraph> graphs;
+        bool vec = true;
+        int nbmax = 0;
+        for (int i = 0; i < count; ++i) {
+            if (n[i] == 0) continue;
+            const int nb = (n[i] + B - 1) / B;
+            graphs.push_back({W[i], (long)ldw[i], D[i], (long)ldd[i], n[i], nb});
+            vec = vec && ldd[i] % 4 == 0 && (uintptr_t)D[i] % 16 == 0;
+            nbmax = std::max(nbmax, nb);
+        }
+        p->vec = vec;
+        // work lists: init; then per pivot block kb, phases 1-3 of every graph
+        // that has block kb
+        std::vector<FwItem> items;
+        auto add_launch = [&](int phase, int kb, const std::vector<FwItem>& its) {
+            if (its.empty()) return;
+            p->launches.push_back({phase, kb, (int)items.size(), (int)its.size()});
+            items.insert(items.end(), its.begin(), its.end());
+        };
+        std::vector<FwItem> its;
+        for (int g = 0; g < (int)graphs.size(); ++g)
+            for (int r = 0; r < graphs[g].nb; ++r) its.push_back({g, r});
+        add_launch(0, 0, its);
+        for (int kb = 0; kb < nbmax; ++kb) {
+            std::vector<FwItem> p1, p2, p3;
+            for (int g = 0; g < (int)graphs.size(); ++g) {
+                const int nb = graphs[g].nb;
+                if (nb <= kb) continue;
+                p1.push_back({g, 0});
+                for (int b = 0; b < 2 * (nb - 1); ++b) p2.push_back({g, b});
+                for (int t = 0; t < (nb - 1) * (nb - 1); ++t) p3.push_back({g, t});
+            }
+            add_launch(1, kb, p1);
+            add_launch(2, kb, p2);
+            add_launch(3, kb, p3);
+        }
+        btas_status_t st = upload(h, fn, (void**)&p->d_graphs, graphs.data(), sizeof(FwGraph) * graphs.size());
+        if (st == BTAS_OK) st = upload(h, fn, (void**)&p->d_items, items.data(), sizeof(FwItem) * items.size());
+        if (st != BTAS_OK) return st;
+        e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        for (const auto& L : p->launches) {
+            e = launch_fw_batched(dt, L.phase, p->d_graphs, p->d_items + L.off, L.cnt, L.kb, p->vec,
+                                  h->aux_stream);
+            if (e != hipSuccess) break;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return device_fail(h, fn, e != hipSuccess ? e : e2);
+        }
+        p->graph = graph;
+        e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        h->fw_batch_plan = std::move(p);
+        plan = h->fw_batch_plan.get();
+    }
+    e = hipGraphLaunch(plan->exec, h->stream);
+    return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
 }

@@ -20,6 +20,11 @@ void destroy_batch_plan(BatchPlan* p);
 struct BatchPlanDeleter {
     void operator()(BatchPlan* p) const { destroy_batch_plan(p); }
 };
+struct FwBatchPlan;  // batched_api.cpp
+void destroy_fw_batch_plan(FwBatchPlan* p);
+struct FwBatchPlanDeleter {
+    void operator()(FwBatchPlan* p) const { destroy_fw_batch_plan(p); }
+};
 // Measured speed of one size bucket's squaring: for each tile family (0 =
 // four-wave blocks, 1 = single waves, 2 = single-wave direct loads on padded
 // buffers) the fastest shape and its seconds per useful term.
@@ -44,6 +49,7 @@ struct btas_ctx {
     int* dflags = nullptr;               // device flags [kNumFlags], see the FLAG_* slots
     int* hflags = nullptr;               // pinned host mirror
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
+    std::unique_ptr<btas::FwBatchPlan, btas::FwBatchPlanDeleter> fw_batch_plan;  // last batched FW plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan
     // (dtype, size bucket, log2 of the plan's launch size) -> autotune result
     std::map<std::tuple<int, int, int>, btas::BucketTiming> tile_timing;

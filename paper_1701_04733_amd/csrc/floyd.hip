@@ -73,7 +73,7 @@ __device__ __forceinline__ T lane_value(T x, int lane) {
 // Lane j of wave w holds column j, rows 16w+r.  d(i,z) for the wave's rows is
 // in its lane z; d(z,j) is row z, held by wave z/16, passed through LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void fw_phase1_kernel(int n, T* D, long ld, int kb) {
+__device__ __forceinline__ void phase1_block(int n, T* D, long ld, int kb) {
     using R = Ring<BTAS_MIN_PLUS, T>;
     __shared__ T rowz[2][FW_B];
     const int k0 = kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
@@ -101,6 +101,11 @@ __global__ __launch_bounds__(256) void fw_phase1_kernel(int n, T* D, long ld, in
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void fw_phase1_kernel(int n, T* D, long ld, int kb) {
+    phase1_block(n, D, ld, kb);
+}
+
 // Phase 2: workgroup b < nb-1 takes block (kb, J) of block-row kb, the others
 // block (I, kb) of block-column kb (J, I skip kb); each relaxes its block
 // against the finished diagonal block, pivots in ascending order.
@@ -111,13 +116,13 @@ __global__ __launch_bounds__(256) void fw_phase1_kernel(int n, T* D, long ld, in
 // The per-lane operand L[z][x] (dia(x,z), resp. dia(z,x)) is constant, so no
 // wave waits for another after the set-up.
 template <typename T>
-__global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, int kb, int nb) {
+__device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int nb, int bid) {
     using R = Ring<BTAS_MIN_PLUS, T>;
     constexpr int LP = FW_B + 1;  // the transposed fill walks a column
     __shared__ T L[FW_B][LP];
     const int k0 = kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
-    const bool row = blockIdx.x < (unsigned)(nb - 1);
-    int b = row ? blockIdx.x : blockIdx.x - (nb - 1);
+    const bool row = bid < nb - 1;
+    int b = row ? bid : bid - (nb - 1);
     b += b >= kb ? 1 : 0;
     const int o0 = b * FW_B, os = n - o0 < FW_B ? n - o0 : FW_B;
     const int x = threadIdx.x % 64, w = threadIdx.x / 64;
@@ -156,6 +161,11 @@ __global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, in
             if (o < os && x < ks) D[(long)(o0 + o) * ld + k0 + x] = v[c];
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, int kb, int nb) {
+    phase2_block(n, D, ld, kb, nb, (int)blockIdx.x);
 }
 
 // Which 64x64 blocks an update launch covers; every covered block (I,J) gets
@@ -334,7 +344,91 @@ hipError_t fw_typed(int n, T* D, long ld, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---- many graphs at once: one launch per phase and pivot block for all ----
+// graphs that still have that pivot block (work items name a graph and a
+// block index within that graph's phase).
+
+// D <- I (+) W, rows 64r .. 64r+63 of one graph per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void fwb_init_kernel(const FwGraph* __restrict__ gs,
+                                                       const FwItem* __restrict__ items) {
+    const FwItem it = items[blockIdx.x];
+    const FwGraph g = gs[it.graph];
+    const T* W = (const T*)g.W;
+    T* D = (T*)g.D;
+    const int r0 = it.idx * FW_B, rows = g.n - r0 < FW_B ? g.n - r0 : FW_B;
+    for (long e = threadIdx.x; e < (long)rows * g.n; e += 256) {
+        const int i = r0 + (int)(e / g.n), j = (int)(e % g.n);
+        T w = W[(long)i * g.ldw + j];
+        if (i == j && w > (T)0) w = (T)0;
+        D[(long)i * g.ldd + j] = w;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fwb_phase1_kernel(const FwGraph* __restrict__ gs,
+                                                         const FwItem* __restrict__ items, int kb) {
+    const FwItem it = items[blockIdx.x];
+    const FwGraph g = gs[it.graph];
+    phase1_block(g.n, (T*)g.D, g.ldd, kb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fwb_phase2_kernel(const FwGraph* __restrict__ gs,
+                                                         const FwItem* __restrict__ items, int kb) {
+    const FwItem it = items[blockIdx.x];
+    const FwGraph g = gs[it.graph];
+    phase2_block(g.n, (T*)g.D, g.ldd, kb, g.nb, it.idx);
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(64) void fwb_phase3_kernel(const FwGraph* __restrict__ gs,
+                                                        const FwItem* __restrict__ items, int kb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const FwItem it = items[blockIdx.x];
+    const FwGraph g = gs[it.graph];
+    int I, J;
+    select_block(UpdateSel{kb, g.nb, -1, -1}, it.idx, I, J);
+    T* D = (T*)g.D;
+    const int k0 = kb * FW_B, ks = g.n - k0 < FW_B ? g.n - k0 : FW_B;
+    TileArgs<T> a{g.n, g.n, ks, D + k0, g.ldd, D + (long)k0 * g.ldd, g.ldd, D, g.ldd, D, g.ldd,
+                  nullptr, nullptr};
+    GemmTile<GemmCfg<64, 64, 8, 8, 8>, T, T, BTAS_MIN_PLUS, VEC>::run(a, I * FW_B, J * FW_B, smem_raw);
+}
+
+template <typename T>
+hipError_t fwb_typed(int phase, const FwGraph* gs, const FwItem* items, int nitems, int kb, bool vec,
+                     hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    using ST = GemmCfg<64, 64, 8, 8, 8>;
+    switch (phase) {
+        case 0:
+            hipLaunchKernelGGL(fwb_init_kernel<T>, dim3(nitems), dim3(256), 0, s, gs, items);
+            break;
+        case 1:
+            hipLaunchKernelGGL(fwb_phase1_kernel<T>, dim3(nitems), dim3(256), 0, s, gs, items, kb);
+            break;
+        case 2:
+            hipLaunchKernelGGL(fwb_phase2_kernel<T>, dim3(nitems), dim3(256), 0, s, gs, items, kb);
+            break;
+        default:
+            if (vec)
+                hipLaunchKernelGGL((fwb_phase3_kernel<T, true>), dim3(nitems), dim3(64), ST::lds_bytes,
+                                   s, gs, items, kb);
+            else
+                hipLaunchKernelGGL((fwb_phase3_kernel<T, false>), dim3(nitems), dim3(64), ST::lds_bytes,
+                                   s, gs, items, kb);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fw_batched(int dt, int phase, const FwGraph* graphs, const FwItem* items, int nitems,
+                             int kb, bool vec, hipStream_t s) {
+    return dt == BTAS_FLOAT32 ? fwb_typed<float>(phase, graphs, items, nitems, kb, vec, s)
+                              : fwb_typed<int32_t>(phase, graphs, items, nitems, kb, vec, s);
+}
 
 int fw_block_size() { return FW_B; }
 

@@ -112,6 +112,26 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
 // block (diagonal block, its block-row and block-column, the rest).
 int fw_block_size();
 hipError_t launch_floyd_warshall(int dt, int n, void* D, long ld, hipStream_t s);
+// Blocked FW of many graphs: per graph its input, output (may be the input
+// with the same ld: in place), size and pivot-block count; work items name a
+// graph and a block index.  phase 0: D <- I (+) W, item idx = 64-row block;
+// phase 1: diagonal block kb (idx unused); phase 2: the 2(nb-1) panel blocks
+// of kb (idx); phase 3: the (nb-1)^2 other blocks (idx).  vec: every graph's
+// ldd is a multiple of 4 and D 16-byte aligned.
+struct FwGraph {
+    const void* W;
+    long ldw;
+    void* D;
+    long ldd;
+    int n;
+    int nb;
+};
+struct FwItem {
+    int graph;
+    int idx;
+};
+hipError_t launch_fw_batched(int dt, int phase, const FwGraph* graphs, const FwItem* items, int nitems,
+                             int kb, bool vec, hipStream_t s);
 
 // Sparse-aware APSP squarings (csrc/sparse.hip), min-plus.  count: rownnz[i]
 // = finite entries of row i of D, counters[0] += total.  build: row pointers

@@ -125,3 +125,69 @@ def test_fw_16384_f32_sampled_sources(dev):
     assert np.all(got[fin] >= exact[fin] * (1 - u) ** (n - 1) - 1e-300)
     del D
     torch.cuda.empty_cache()
+
+
+def _fw_mixed(dt, seed):
+    g = np.random.default_rng(seed)
+    sizes = [0, 1, 2, 63, 64, 65, 128, 200, 300, 513] + list(g.integers(3, 260, 14))
+    return [_graph(dt, int(n), seed=seed * 100 + i, deg=4.0) for i, n in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+def test_fw_batched_matches_oracle(dev, dt):
+    """Many graphs of mixed sizes in one captured launch sequence: int32 equals
+    the squaring oracle exactly, binary32 the blocked-FW oracle graph by graph,
+    also on replay."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = _fw_mixed(dt, seed=5)
+    tW = [_dev(W, dev) for W in Ws]
+    Ds = [torch.empty_like(t) for t in tW]
+    for rep in range(2):
+        btas.floyd_warshall_batched(tW, Ds)
+        torch.cuda.synchronize()
+        for W, D in zip(Ws, Ds):
+            n = W.shape[0]
+            if n == 0:
+                continue
+            want = oracle.apsp(W)[0] if dt == "i32" else oracle.floyd_warshall_blocked(W, BLOCK)
+            assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"rep {rep} {dt} n={n}"
+        for D in Ds:
+            D.fill_(0)
+
+
+def test_fw_batched_in_place_views_and_aliasing(dev):
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = [_graph("f32", n, seed=40 + n) for n in (70, 130, 5)]
+    want = [oracle.floyd_warshall_blocked(W, BLOCK) for W in Ws]
+    tW = [_dev(W, dev) for W in Ws]
+    btas.floyd_warshall_batched(tW, tW)                      # in place
+    for t, w in zip(tW, want):
+        assert np.array_equal(_bits(t.cpu().numpy()), _bits(w))
+    # outputs as padded views of one buffer (ld 140, not a multiple of 4 apart)
+    big = torch.full((300, 141), 3.0, device=dev)
+    outs = [big[0:70, :70], big[70:200, :130], big[200:205, :5]]
+    btas.floyd_warshall_batched([_dev(W, dev) for W in Ws], outs)
+    for o, w in zip(outs, want):
+        assert np.array_equal(_bits(o.cpu().numpy()), _bits(w))
+    assert (big[:, 130:] == 3.0).all() and (big[205:, :] == 3.0).all()
+    t = _dev(Ws[0], dev)
+    with pytest.raises(btas.BtasError, match="ALIAS"):
+        btas.floyd_warshall_batched([t, _dev(Ws[0], dev)], [torch.empty_like(t), t])
+
+
+def test_fw_batched_full_config_equals_batched_squaring(dev):
+    """The 4096-graph int32 workload: blocked FW gives the squaring's bits."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = wl.batched_graphs_i32(count=4096, seed=5)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    sq = btas.apsp_batched(tW, early_exit=True)
+    fw = btas.floyd_warshall_batched(tW)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(sq, fw)):
+        assert torch.equal(a, b), f"graph {i} (n={Ws[i].shape[0]})"
