@@ -294,7 +294,8 @@ def bench_maxplus(dev, reps=3):
 def bench_batched(dev, reps=5):
     """4096 independent graphs, n log-uniform in [16,512], p = 8/n, int32
     weights U{1..1000}: one hipGraph launch (fixed T(n), and with on-device
-    early exit) vs 4096 plain solves."""
+    early exit), the same graphs by batched blocked Floyd-Warshall, and 4096
+    plain solves."""
     import numpy as np
     import torch
 
@@ -339,9 +340,25 @@ def bench_batched(dev, reps=5):
         ms.append(e0.elapsed_time(e1))
     em = float(np.median(ms))
     same_early = all(torch.equal(a, b) for a, b in zip(re.Ds, outs))
+    # the same graphs by batched blocked Floyd-Warshall (int32: the same bits)
+    fw = btas.FloydWarshallBatched(Ws)
+    fw.run()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = _events()
+        e0.record()
+        fw.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    fm = float(np.median(ms))
+    same_fw = all(torch.equal(a, b) for a, b in zip(fw.Ds, outs))
     return {"workload": "batched APSP, 4096 graphs, n log-uniform [16,512], p=8/n, int32 U{1..1000}",
             "early_exit": {"batched_ms": round(em, 3), "batched_solves_per_s": round(4096 / (em / 1e3), 1),
                            "bit_identical_to_plain": same_early},
+            "floyd_warshall": {"batched_ms": round(fm, 3), "batched_solves_per_s": round(4096 / (fm / 1e3), 1),
+                               "bit_identical_to_plain": same_fw},
             "batched_ms": round(bm, 3), "batched_solves_per_s": round(4096 / (bm / 1e3), 1),
             "batched_Gop/s": round(2 * info["terms"] / (bm / 1e3) / 1e9, 1),
             "frac_valu_peak": round(2 * info["terms"] / (bm / 1e3) / 1e12 / PEAK_TOPS, 4),
