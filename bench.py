@@ -52,6 +52,8 @@ def parse():
                    help="rows of the 8192^3 min-plus fp32 product timed on the oracle")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the APSP workloads (small, large, batched, served)")
+    p.add_argument("--extras", default="level12,apsp_small,apsp_large,witness,maxplus,batched,served",
+                   help="comma-separated subset of the extra workloads to run")
     p.add_argument("--served-count", type=int, default=300,
                    help="requests per arrival rate in the served workload")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -109,10 +111,11 @@ def _events():
 
 def bench_apsp_small(dev, reps=200):
     """One APSP on an ER digraph, n=256, p=0.05, int32 weights U{1..100}, T=8:
-    per-solve latency of the plain path (init + 8 split-K squarings), of the
-    same sequence captured as one hipGraph launch, of the whole solve as one
-    cooperative kernel (fixed T, and with the early-exit test on the device),
-    and of the batched path with a single graph."""
+    per-solve latency of one launch per squaring (init + 8 split-K squarings),
+    of the same sequence captured as one hipGraph launch, of the whole solve
+    as one cooperative kernel (fixed T, the default at this size, and with
+    the early-exit test on the device), and of the batched path with a
+    single graph."""
     import numpy as np
     import torch
 
@@ -122,7 +125,18 @@ def bench_apsp_small(dev, reps=200):
     D = torch.empty_like(W)
     g = btas.BatchedAPSP([W], [D])
     out = {"workload": "APSP n=256 ER p=0.05 int32 U{1..100}, T=8 squarings"}
-    for name, fn in (("plain", lambda: btas.apsp(W, out=D, return_steps=False)),
+    def per_squaring():
+        prev = os.environ.get("BTAS_SINGLE_LAUNCH")
+        os.environ["BTAS_SINGLE_LAUNCH"] = "0"
+        try:
+            btas.apsp(W, out=D, return_steps=False)
+        finally:
+            if prev is None:
+                del os.environ["BTAS_SINGLE_LAUNCH"]
+            else:
+                os.environ["BTAS_SINGLE_LAUNCH"] = prev
+
+    for name, fn in (("per_squaring", per_squaring),
                      ("graph", lambda: btas.apsp(W, out=D, return_steps=False, graph=True)),
                      ("single_launch", lambda: btas.apsp(W, out=D, return_steps=False, single_launch=True)),
                      ("single_launch_early_exit",
@@ -565,18 +579,26 @@ def main():
     del host, tensors
     torch.cuda.empty_cache()
     if not args.no_extras:
+        want = {x for x in args.extras.split(",") if x}
         extras = {}
-        extras["level12"] = bench_level12(dev)
-        extras["apsp_small"] = bench_apsp_small(dev)
-        extras["apsp_large"] = bench_apsp_large(dev)
-        extras["witness"] = bench_witness(dev, witness_operands)
+        if "level12" in want:
+            extras["level12"] = bench_level12(dev)
+        if "apsp_small" in want:
+            extras["apsp_small"] = bench_apsp_small(dev)
+        if "apsp_large" in want:
+            extras["apsp_large"] = bench_apsp_large(dev)
+        if "witness" in want:
+            extras["witness"] = bench_witness(dev, witness_operands)
         del witness_operands
-        extras["maxplus"] = bench_maxplus(dev)
+        if "maxplus" in want:
+            extras["maxplus"] = bench_maxplus(dev)
         torch.cuda.empty_cache()
-        extras["batched"] = bench_batched(dev)
+        if "batched" in want:
+            extras["batched"] = bench_batched(dev)
         torch.cuda.empty_cache()
-        rates = [int(x) for x in args.served_rates.split(",") if x]
-        extras["served"] = bench_served(rates, args.served_count)
+        if "served" in want:
+            rates = [int(x) for x in args.served_rates.split(",") if x]
+            extras["served"] = bench_served(rates, args.served_count)
         out["extras"] = extras
     print(json.dumps(out), flush=True)
 

@@ -518,7 +518,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     const size_t need = (size_t)n * n * 4;
     if (T > 0 && ensure_ws(h, need) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
-    // Graphs of 24..192 vertices take the single-launch solve also without
+    // Graphs of 24..256 vertices take the single-launch solve also without
     // the flag (it is faster there: one launch instead of one or two per
     // squaring) unless a captured graph was asked for or BTAS_SINGLE_LAUNCH=0.
     const char* sl_env = getenv("BTAS_SINGLE_LAUNCH");
@@ -536,11 +536,10 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         // stop decision on the device; the host reads the step count only if
         // asked for it.
         int* rf = h->dflags + FLAG_RESIDENT;
-        unsigned* bar = reinterpret_cast<unsigned*>(h->dflags + FLAG_BARRIER);
         e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
         if (e == hipSuccess)
-            e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, bar, rf,
-                                           h->num_cus, 1 << 20, h->stream);
+            e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, rf, h->num_cus,
+                                           1 << 20, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
         steps = T;
         if (steps_out) {

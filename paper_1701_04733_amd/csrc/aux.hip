@@ -99,7 +99,7 @@ __global__ void clear_flags_kernel(int* flag, int count) {
 }
 
 hipError_t launch_clear_flags(int* flag, int count, hipStream_t s) {
-    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, s, flag, count);
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(256), 0, s, flag, count);
     return hipGetLastError();
 }
 

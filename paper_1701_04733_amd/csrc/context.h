@@ -13,6 +13,7 @@
 #include <utility>
 
 #include "btas.h"
+#include "kernels.h"
 
 namespace btas {
 struct BatchPlan;  // batched_api.cpp
@@ -67,17 +68,18 @@ constexpr int FLAG_CHANGED = 0;    // early exit: some output changed this step
 constexpr int FLAG_CHECK = 1;      // domain scan / negative-cycle check
 constexpr int FLAG_GEMM_WIDE = 2;  // int32 gemm operands exceed the binary32-exact range
 constexpr int FLAG_STEP_WIDE = 8;  // APSP: slot 8 + t describes D_t (t = 0..T <= 31)
-constexpr int FLAG_RESIDENT = 44;  // single-launch solve: +0 error, +1 steps, +1+t squaring t changed D
-constexpr int FLAG_BARRIER = 64;   // its device-wide barrier: 2 + (up to 64 groups) counters
-constexpr int FLAG_RESIDENT_END = FLAG_BARRIER + 2 + 64;
 constexpr int FLAG_SPARSE = 136;   // sparse squarings: two 64-bit counters (finite entries, terms)
 constexpr int FLAG_CM_MAXABS = 140;  // cycle mean: max |A| of int32 entries
 constexpr int FLAG_CM_RESULT = 144;  // cycle mean: num, den (int64), lambda bits (binary64)
-constexpr int kNumFlags = 192;
-static_assert(FLAG_RESIDENT_END <= FLAG_SPARSE && FLAG_SPARSE % 2 == 0 && FLAG_SPARSE + 4 <= FLAG_CM_MAXABS &&
-                  FLAG_CM_MAXABS < FLAG_CM_RESULT && FLAG_CM_RESULT % 2 == 0 && FLAG_CM_RESULT + 6 <= kNumFlags,
+// Single-launch solve: +0 error, +1 steps, then its barrier's arrival words
+// (two sets of RESIDENT_MAX_GRID, one per barrier parity).
+constexpr int FLAG_RESIDENT = 192;
+constexpr int FLAG_RESIDENT_END = FLAG_RESIDENT + 2 + 2 * RESIDENT_MAX_GRID;
+constexpr int kNumFlags = FLAG_RESIDENT_END;
+static_assert(FLAG_STEP_WIDE + 32 <= FLAG_SPARSE && FLAG_SPARSE % 2 == 0 && FLAG_SPARSE + 4 <= FLAG_CM_MAXABS &&
+                  FLAG_CM_MAXABS < FLAG_CM_RESULT && FLAG_CM_RESULT % 2 == 0 &&
+                  FLAG_CM_RESULT + 6 <= FLAG_RESIDENT,
               "flag slots overlap");
-static_assert(FLAG_RESIDENT + 2 + 9 <= FLAG_BARRIER, "slots for T(500) = 9 squarings");
 
 struct DeviceGuard {
     int prev = -1;

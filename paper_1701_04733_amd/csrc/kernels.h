@@ -92,21 +92,23 @@ hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst
 // Whole APSP solve in one cooperative launch (n <= RESIDENT_MAX_N): D_0 =
 // I (+) W, then T squarings (or fewer with early exit) separated by a
 // device-wide barrier, ping-ponging between D and ws (n x n, leading
-// dimension n); the result ends in D.  bar: 66 device words, zero at launch.
-// flags (device): [0] set on a barrier timeout, [1] <- the number of
-// squarings run, [1 + t] set if squaring t changed D; zero at launch.
+// dimension n); the result ends in D.  flags (device, 2 + 2 *
+// RESIDENT_MAX_GRID words, zero at launch): [0] set on a barrier timeout,
+// [1] <- the number of squarings run, [2..] the barrier's arrival words.
 // num_cus: compute units of the device; spin_limit: polls per barrier wait
 // before giving up.
 constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
+constexpr int RESIDENT_MAX_GRID = 1024;  // (500 / 16 rounded up)^2 tiles
 // Between these sizes the single-launch solve beats one launch per squaring
-// on MI355X (measured latency: n=9 49 us vs 37 us, n=33 62 us vs 81 us,
-// n=129 115 us vs 153 us, n=256 187 us vs 169 us).
+// on MI355X (measured latency, int32 ER graphs of mean degree 12.75, fixed T:
+// n=16 57 us vs 43 us, n=24 63 vs 65, n=129 96 vs 158, n=256 132 vs 174,
+// n=320 240 vs 209).
 constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 24;
-constexpr int AUTO_SINGLE_LAUNCH_N = 192;
+constexpr int AUTO_SINGLE_LAUNCH_N = 256;
 size_t resident_lds_bytes(int n);
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
-                                void* ws, int T, bool early, unsigned* bar, int* flags,
-                                int num_cus, int spin_limit, hipStream_t s);
+                                void* ws, int T, bool early, int* flags, int num_cus,
+                                int spin_limit, hipStream_t s);
 // Blocked Floyd-Warshall in place on D (n x n, leading dimension ld), which
 // holds I (+) W: pivot blocks of fw_block_size() vertices, three launches per
 // block (diagonal block, its block-row and block-column, the rest).

@@ -12,24 +12,32 @@
 // output tiles (one output per thread, full k): it stages the tile's 16 rows
 // of D_{t-1} and its 16 columns (transposed) in LDS, folds four k per pair of
 // three-input min/max, and writes D_t to the other buffer of the ping-pong
-// pair.  Early exit reads a per-step "changed" flag after the barrier, so
-// every workgroup takes the same decision.
+// pair.
 //
 // Coherence across the XCDs (each has its own L2) is obtained without cache
 // maintenance: every access to the matrices that another workgroup may touch
 // in the same launch is a device-scope (relaxed atomic) load or store, which
 // the hardware performs at the device's coherence point, and every wave waits
 // for its stores to complete before its workgroup arrives at the barrier.
-// The barrier counts arrivals per group of 16 workgroups and then per group,
-// so no single word takes more than 16 atomic increments per barrier; the
-// counters only grow within a launch (a group's last arrival is the one that
-// makes its count a multiple of the group size) and the caller zeroes them
-// before each launch.  The launch is cooperative, so every workgroup is
-// resident and the barrier cannot wait on one that has not started; each wait
-// is still bounded and, when the bound is hit, the kernel records an error
-// and runs to its end so that no wave is left spinning.
+// (Writing back and invalidating the L2 around plain loads measured slower.)
+//
+// The barrier: every workgroup stores one arrival word of its own, 2b | c for
+// barrier b, with c = 1 if its tiles changed D in the squaring just ended,
+// and then polls the words of all workgroups until each reads at least 2b.
+// The OR of the c bits is the early-exit decision, so every workgroup takes
+// the same one without a shared flag (256 workgroups storing to one word
+// serialise there: that cost several microseconds a squaring).  The words
+// come in two sets, used by barriers of odd and even b: a workgroup can only
+// arrive at barrier b + 2, and overwrite its word of barrier b, after every
+// workgroup has arrived at b + 1, that is after every poll of barrier b has
+// ended, so the bit read there is always the one of barrier b.  The caller
+// zeroes the words before each launch.  The launch is cooperative, so every
+// workgroup is resident and the barrier cannot wait on one that has not
+// started; each wait is still bounded and, when the bound is hit, the kernel
+// records an error and runs to its end so that no wave is left spinning.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "gemm_tile.h"
@@ -43,7 +51,7 @@ namespace {
 
 constexpr int RT = 16;        // output tile edge
 constexpr int RNT = RT * RT;  // threads per workgroup, one output each
-constexpr int PB = 8;         // panel loads in flight per thread
+constexpr int PB = 16;        // panel loads in flight per thread (one batch up to n = 256)
 
 template <typename T>
 struct ResidentArgs {
@@ -51,7 +59,7 @@ struct ResidentArgs {
     int nsq;          // squarings to run (the fixed count T)
     int early;        // stop after the first squaring that changes nothing
     int cur0;         // buffer index that receives D_0
-    int ls;           // LDS row stride in elements (>= n rounded to 4, plus padding)
+    int ls;           // LDS row stride in elements (>= n rounded to 8, plus padding)
     int spin_limit;   // bound on each barrier wait, in polls
     const T* W;
     long ldw;
@@ -59,11 +67,9 @@ struct ResidentArgs {
     long ld0;
     T* buf1;          // the handle's workspace, leading dimension n
     long ld1;
-    unsigned* bar;    // [0] barriers completed, [1] groups arrived, [2 + g] arrivals in group g
-    int* flags;       // [0] error, [1] steps executed, [1 + t] squaring t changed D
+    int* flags;       // [0] error, [1] steps executed
+    unsigned* arrive; // two sets of RESIDENT_MAX_GRID arrival words
 };
-
-constexpr unsigned BAR_GROUP = 16;  // workgroups per first-level barrier counter
 
 // Device-scope loads and stores (coherent across XCDs without cache flushes).
 template <typename T>
@@ -75,39 +81,32 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Device-wide barrier number `b` (1, 2, ... within a launch); returns false
-// if the wait bound was hit (then flags[0] is set).  Every thread of every
-// workgroup must call it with the same b.
-__device__ bool grid_barrier(unsigned* bar, unsigned b, int* err, int spin_limit) {
-    __shared__ int ok_s;
+// Device-wide barrier number b (1, 2, ... within a launch), carrying one bit
+// per workgroup; returns the OR of every workgroup's `changed`.  Every thread
+// of every workgroup calls it with the same b.  On a wait that hits the bound
+// flags[0] is set and the result is incomplete.
+__device__ int grid_barrier(unsigned* arrive, unsigned b, int changed, int* err, int spin_limit) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are performed
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    const int mine = __syncthreads_or(changed);
+    unsigned* words = arrive + (b & 1) * RESIDENT_MAX_GRID;
+    if (threadIdx.x == 0) st_dev(words + blockIdx.x, 2 * b | (mine ? 1u : 0u));
+    int any = 0;
+    for (int polls = 0;; ++polls) {
         int ok = 1;
-        const unsigned g = blockIdx.x / BAR_GROUP;
-        const unsigned rest = gridDim.x - g * BAR_GROUP;
-        const unsigned gsize = rest < BAR_GROUP ? rest : BAR_GROUP;
-        const unsigned ngroups = (gridDim.x + BAR_GROUP - 1) / BAR_GROUP;
-        const unsigned a1 =
-            __hip_atomic_fetch_add(bar + 2 + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if (a1 % gsize == 0) {
-            const unsigned a2 =
-                __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (a2 % ngroups == 0) st_dev(bar, a2 / ngroups);
+        any = 0;
+        for (unsigned i = threadIdx.x; i < gridDim.x; i += RNT) {
+            const unsigned w = ld_dev(words + i);
+            ok &= w >= 2 * b;
+            any |= w & 1;
         }
-        int polls = 0;
-        while (ld_dev(bar) < b) {
-            if (++polls > spin_limit) {
-                st_dev(err, 1);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
+        if (__syncthreads_and(ok)) break;
+        if (polls >= spin_limit) {
+            if (threadIdx.x == 0) st_dev(err, 1);
+            break;
         }
-        ok_s = ok;
+        __builtin_amdgcn_s_sleep(1);
     }
-    __syncthreads();
-    return ok_s != 0;
+    return __syncthreads_or(any);
 }
 
 template <typename T>
@@ -116,7 +115,6 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* As = reinterpret_cast<T*>(smem_raw);  // [RT][ls]: rows m0.. of D_{t-1}
     T* Bt = As + RT * a.ls;                  // [RT][ls]: columns n0.. of D_{t-1}, transposed
-    __shared__ int flag_s;
     const int n = a.n, tid = threadIdx.x;
     const long total = (long)n * n;
     const long gthreads = (long)gridDim.x * RNT;
@@ -128,14 +126,14 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
         const long ld0 = cur ? a.ld1 : a.ld0;
         for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
             long i, j;
-        flat_to_rc(e, n, total, i, j);
+            flat_to_rc(e, n, total, i, j);
             T w = a.W[i * a.ldw + j];
             if (i == j && w > (T)0) w = (T)0;
             st_dev(D0 + i * ld0 + j, w);
         }
     }
     unsigned bno = 1;
-    grid_barrier(a.bar, bno++, a.flags, a.spin_limit);
+    grid_barrier(a.arrive, bno++, 0, a.flags, a.spin_limit);
 
     const int nt = (n + RT - 1) / RT;
     const int kpad = (n + 7) & ~7;
@@ -196,29 +194,25 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
             const T acc = R::add(acc0, acc1);
             const int row = m0 + r, col = n0 + c;
             if (row < n && col < n) {
-                const T old = ld_dev(src + (long)row * lds + col);
+                // D_{t-1}[row][col] is in the staged row panel (k = col).
+                const T old = As[r * a.ls + col];
                 const T nv = R::add(old, R::finish(acc));
                 changed |= bits_of(nv) != bits_of(old);
                 st_dev(dst + (long)row * ldd + col, nv);
             }
             __syncthreads();  // LDS is reloaded for the next tile
         }
-        if (__syncthreads_or(changed) && tid == 0) st_dev(a.flags + 1 + t, 1);
-        grid_barrier(a.bar, bno++, a.flags, a.spin_limit);
+        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.spin_limit);
         cur ^= 1;
         steps = t;
-        if (a.early) {
-            if (tid == 0) flag_s = ld_dev(a.flags + 1 + t);
-            __syncthreads();
-            if (flag_s == 0) break;
-        }
+        if (a.early && !any) break;
     }
 
     // After an early exit the result may sit in the workspace: copy it to D.
     if (cur != 0) {
         for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
             long i, j;
-        flat_to_rc(e, n, total, i, j);
+            flat_to_rc(e, n, total, i, j);
             a.buf0[i * a.ld0 + j] = ld_dev(a.buf1 + i * a.ld1 + j);
         }
     }
@@ -227,8 +221,7 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
 
 template <typename T>
 hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void* ws, int T_,
-                        bool early, unsigned* bar, int* flags, int num_cus, int spin_limit,
-                        hipStream_t s) {
+                        bool early, int* flags, int num_cus, int spin_limit, hipStream_t s) {
     ResidentArgs<T> a;
     a.n = n;
     a.nsq = T_;
@@ -243,17 +236,25 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
     a.ld0 = ldd;
     a.buf1 = (T*)ws;
     a.ld1 = n;
-    a.bar = bar;
     a.flags = flags;
+    a.arrive = reinterpret_cast<unsigned*>(flags + 2);
     const size_t lds = resident_lds_bytes(n);
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(apsp_resident_kernel<T>), RNT, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    // Workgroups per CU depend only on the LDS size (k padded to 8): the
+    // occupancy query runs once per size, not on every call.
+    static std::atomic<int> per_cu_cache[RESIDENT_MAX_N / 8 + 2];
+    const int slot = ((n + 7) & ~7) / 8;
+    int per_cu = per_cu_cache[slot].load(std::memory_order_relaxed);
+    if (per_cu == 0) {
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(apsp_resident_kernel<T>), RNT, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) return hipErrorInvalidConfiguration;
+        per_cu_cache[slot].store(per_cu, std::memory_order_relaxed);
+    }
     const int nt = (n + RT - 1) / RT;
     long grid = (long)per_cu * num_cus;
     if (grid > (long)nt * nt) grid = (long)nt * nt;
+    if (grid > RESIDENT_MAX_GRID) grid = RESIDENT_MAX_GRID;
     void* args[] = {&a};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apsp_resident_kernel<T>),
                                       dim3((unsigned)grid), dim3(RNT), args, (unsigned)lds, s);
@@ -264,14 +265,12 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
 size_t resident_lds_bytes(int n) { return (size_t)2 * RT * (((n + 7) & ~7) + 4) * 4; }
 
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
-                                void* ws, int T, bool early, unsigned* bar, int* flags,
-                                int num_cus, int spin_limit, hipStream_t s) {
+                                void* ws, int T, bool early, int* flags, int num_cus,
+                                int spin_limit, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (dt == BTAS_FLOAT32)
-        return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, bar, flags, num_cus,
-                                   spin_limit, s);
-    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, bar, flags, num_cus, spin_limit,
-                                 s);
+        return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, flags, num_cus, spin_limit, s);
+    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, flags, num_cus, spin_limit, s);
 }
 
 }  // namespace btas

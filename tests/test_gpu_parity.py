@@ -291,7 +291,7 @@ def test_apsp_small_config_golden(btas, dev):
 
 @pytest.mark.parametrize("path", ["default", "per_squaring"])
 @pytest.mark.parametrize("dt", DT)
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 16, 32, 64, 128, 192, 193, 200, 201, 512])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 16, 23, 24, 32, 64, 128, 192, 193, 255, 256, 257, 512])
 def test_apsp_sizes(btas, dev, dt, n, path, monkeypatch):
     """Small n take the single-launch solve by default; BTAS_SINGLE_LAUNCH=0
     keeps them on one launch per squaring.  Both equal the oracle."""

@@ -1,7 +1,8 @@
 """APSP as one cooperative launch (BTAS_APSP_SINGLE_LAUNCH): bit-identical to
 the oracle and to the per-squaring path, with early exit decided on the
 device, in place and with padded leading dimensions, and stable over many
-launches in a row (the device-wide barrier's words return to zero)."""
+launches in a row (the barrier's arrival words are cleared before each
+launch and alternate between two sets within one)."""
 import hashlib
 import json
 import os
@@ -120,3 +121,25 @@ def test_single_launch_neg_cycle_large_n_and_errors(dev):
     assert steps == wsteps and np.array_equal(D.cpu().numpy(), want)
     with pytest.raises(btas.BtasError, match="INVALID_ARG"):
         btas.apsp(_dev(W[:10, :10], dev), single_launch=True, graph=True)
+
+
+def test_single_launch_repeated_small_config(dev):
+    """The n=256 workload solved 40 times back to back, alternating fixed T
+    and early exit: every result and step count equals the oracle's, so every
+    workgroup took the same early-exit decision in every launch."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)
+    want, wsteps, _ = oracle.apsp(W)
+    _, wsteps_e, _ = oracle.apsp(W, early_exit=True)
+    t = _dev(W, dev)
+    outs = [torch.empty_like(t) for _ in range(40)]
+    for i, o in enumerate(outs):
+        btas.apsp(t, out=o, single_launch=True, early_exit=bool(i & 1), return_steps=False)
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), want), f"launch {i}"
+    for ee, ws in ((False, wsteps), (True, wsteps_e)):
+        _, steps, st = btas.apsp(t, single_launch=True, early_exit=ee)
+        assert st == btas.OK and steps == ws
