@@ -46,6 +46,19 @@ __device__ __forceinline__ T relax(T a, T b, T d) {
     return R::add(d, R::finish(R::mul(a, b)));
 }
 
+// The same without mapping the sum back to the absent value: for int32 with
+// canonical operands (finite, or the absent value itself) a sum that
+// involves the absent value is >= 2^30, so an accumulator that only ever
+// takes minima of such sums holds either the exact finite value or some
+// value >= 2^30 that stands for "absent"; R::finish maps it back once where
+// it is read as an operand or stored.  Every entry ends equal to relax's.
+// (float32: R::finish is the identity and this is relax.)
+template <typename T>
+__device__ __forceinline__ T relax_raw(T a, T b, T d) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    return R::add(d, R::mul(a, b));
+}
+
 // Calls f(std::integral_constant<int, I>) for I = B .. E-1: a loop whose index
 // is a constant in every copy of the body (register arrays stay in registers
 // where #pragma unroll would give up on a body this large).
@@ -62,7 +75,10 @@ __device__ __forceinline__ void static_for(F&& f) {
 // block), the 16 lines 16w..16w+15 of the other direction.  At pivot z the
 // entries of the pivot's line that a wave needs sit in its lane z
 // (readlane); the other operand is one value per lane.  The pivot loop is a
-// static_for, so register indices are constants.
+// static_for, so register indices are constants.  The registers accumulate
+// with relax_raw: the readlane value is wave-uniform, so mapping it back to
+// the absent value is scalar work, and a term costs one add and one min on
+// the vector unit.
 
 template <typename T>
 __device__ __forceinline__ T lane_value(T x, int lane) {
@@ -87,17 +103,17 @@ __device__ __forceinline__ void phase1_block(int n, T* D, long ld, int kb) {
     static_for<0, FW_B>([&](auto zc) {
         constexpr int z = decltype(zc)::value;
         if (z < ks) {
-            if (w == z / 16) rowz[z & 1][j] = v[z % 16];
+            if (w == z / 16) rowz[z & 1][j] = R::finish(v[z % 16]);
             __syncthreads();  // this slot is written again two pivots later
             const T dzj = rowz[z & 1][j];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = relax(lane_value(v[r], z), dzj, v[r]);
+            for (int r = 0; r < 16; ++r) v[r] = relax_raw(R::finish(lane_value(v[r], z)), dzj, v[r]);
         }
     });
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int i = 16 * w + r;
-        if (i < ks && j < ks) D[(long)(k0 + i) * ld + k0 + j] = v[r];
+        if (i < ks && j < ks) D[(long)(k0 + i) * ld + k0 + j] = R::finish(v[r]);
     }
 }
 
@@ -149,16 +165,16 @@ __device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int n
         if (z < ks) {
             const T lz = L[z][x];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) v[c] = relax(lz, lane_value(v[c], z), v[c]);
+            for (int c = 0; c < 16; ++c) v[c] = relax_raw(lz, R::finish(lane_value(v[c], z)), v[c]);
         }
     });
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int o = 16 * w + c;
         if (row) {
-            if (x < ks && o < os) D[(long)(k0 + x) * ld + o0 + o] = v[c];
+            if (x < ks && o < os) D[(long)(k0 + x) * ld + o0 + o] = R::finish(v[c]);
         } else {
-            if (o < os && x < ks) D[(long)(o0 + o) * ld + k0 + x] = v[c];
+            if (o < os && x < ks) D[(long)(o0 + o) * ld + k0 + x] = R::finish(v[c]);
         }
     }
 }
