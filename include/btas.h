@@ -247,9 +247,11 @@ btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, 
 /* Blocked Floyd-Warshall (btas_apsp_floyd_warshall, pivot blocks of 64) of
  * `count` independent graphs in one captured hipGraph: D[i] <- the result for
  * I (+) W[i] (n[i] x n[i], row-major, leading dimensions ldw[i], ldd[i];
- * device pointers in host arrays).  For every pivot block kb one launch per
- * phase covers all graphs that have block kb, so the graph holds
- * 1 + 3 * max_i ceil(n_i / 64) launches.  int32 results are the exact
+ * device pointers in host arrays).  Pivot blocks go in pairs as in
+ * btas_apsp_floyd_warshall; each step of the pair schedule (phases 1 and 2
+ * of a block, a strip update, the k=128 update of a pair) is one launch
+ * over all graphs that have it, so the graph holds at most
+ * 1 + 8 * ceil(max_i ceil(n_i / 64) / 2) launches.  int32 results are the exact
  * distances, bit-identical to btas_apsp_squaring and
  * btas_apsp_squaring_batched; binary32 results equal btas_apsp_floyd_warshall
  * graph by graph.  D[i] may be W[i] with ldd[i] == ldw[i] (in place); any

@@ -539,8 +539,13 @@ extern "C" btas_status_t btas_apsp_floyd_warshall_batched(btas_handle_t h, btas_
             nbmax = std::max(nbmax, nb);
         }
         p->vec = vec;
-        // work lists: init; then per pivot block kb, phases 1-3 of every graph
-        // that has block kb
+        // Work lists: init; then per pair of pivot blocks (kb, kb+1) every
+        // graph that has both runs the single-graph pair schedule (phases 1-2
+        // of kb, kb's strip update of row/column kb+1, phases 1-2 of kb+1,
+        // the k=128 update of the tiles outside both, kb+1's deferred strip
+        // update of row/column kb); a graph whose last block is kb runs the
+        // three plain phases.  Graphs are independent, so each launch takes
+        // one step of every graph that has it.
         std::vector<FwItem> items;
         auto add_launch = [&](int phase, int kb, const std::vector<FwItem>& its) {
             if (its.empty()) return;
@@ -550,19 +555,33 @@ extern "C" btas_status_t btas_apsp_floyd_warshall_batched(btas_handle_t h, btas_
         std::vector<FwItem> its;
         for (int g = 0; g < (int)graphs.size(); ++g)
             for (int r = 0; r < graphs[g].nb; ++r) its.push_back({g, r});
-        add_launch(0, 0, its);
-        for (int kb = 0; kb < nbmax; ++kb) {
-            std::vector<FwItem> p1, p2, p3;
+        add_launch(FWB_INIT, 0, its);
+        for (int kb = 0; kb < nbmax; kb += 2) {
+            std::vector<FwItem> p1a, p2a, next, last, p1b, p2b, pair, prev;
             for (int g = 0; g < (int)graphs.size(); ++g) {
                 const int nb = graphs[g].nb;
                 if (nb <= kb) continue;
-                p1.push_back({g, 0});
-                for (int b = 0; b < 2 * (nb - 1); ++b) p2.push_back({g, b});
-                for (int t = 0; t < (nb - 1) * (nb - 1); ++t) p3.push_back({g, t});
+                p1a.push_back({g, 0});
+                for (int b = 0; b < 2 * (nb - 1); ++b) p2a.push_back({g, b});
+                if (nb == kb + 1) {  // last block, unpaired
+                    for (int t = 0; t < (nb - 1) * (nb - 1); ++t) last.push_back({g, t});
+                    continue;
+                }
+                for (int t = 0; t < 2 * nb - 3; ++t) next.push_back({g, t});
+                p1b.push_back({g, 0});
+                for (int b = 0; b < 2 * (nb - 1); ++b) p2b.push_back({g, b});
+                const int nb2 = (graphs[g].n + 2 * B - 1) / (2 * B);
+                for (int t = 0; t < (nb2 - 1) * (nb2 - 1); ++t) pair.push_back({g, t});
+                for (int t = 0; t < 2 * nb - 3; ++t) prev.push_back({g, t});
             }
-            add_launch(1, kb, p1);
-            add_launch(2, kb, p2);
-            add_launch(3, kb, p3);
+            add_launch(FWB_PHASE1, kb, p1a);
+            add_launch(FWB_PHASE2, kb, p2a);
+            add_launch(FWB_PHASE3, kb, last);
+            add_launch(FWB_STRIP_NEXT, kb, next);
+            add_launch(FWB_PHASE1, kb + 1, p1b);
+            add_launch(FWB_PHASE2, kb + 1, p2b);
+            add_launch(FWB_PAIR, kb, pair);
+            add_launch(FWB_STRIP_PREV, kb + 1, prev);
         }
         btas_status_t st = upload(h, fn, (void**)&p->d_graphs, graphs.data(), sizeof(FwGraph) * graphs.size());
         if (st == BTAS_OK) st = upload(h, fn, (void**)&p->d_items, items.data(), sizeof(FwItem) * items.size());

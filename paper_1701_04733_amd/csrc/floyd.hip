@@ -397,17 +397,23 @@ __global__ __launch_bounds__(256) void fwb_phase2_kernel(const FwGraph* __restri
     phase2_block(g.n, (T*)g.D, g.ldd, kb, g.nb, it.idx);
 }
 
-// Phase 3 of many small graphs: the four-wave 64x64 tile (4x4 per thread);
+// Updates of many small graphs on the four-wave 64x64 tile (4x4 per thread);
 // with k = 64 per tile more waves per tile hide the loads better than the
 // one-wave tile (measured 7.0 against 7.5 ms on 4096 graphs of 16..512).
+// mode 0: phase 3 of pivot block kb (every block outside its row and
+// column); mode 1: kb's update of block-row and block-column kb+1; mode 2:
+// kb's update of block-row and block-column kb-1 (the pair schedule's strips).
 template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void fwb_phase3_kernel(const FwGraph* __restrict__ gs,
-                                                        const FwItem* __restrict__ items, int kb) {
+__global__ __launch_bounds__(256) void fwb_update_kernel(const FwGraph* __restrict__ gs,
+                                                        const FwItem* __restrict__ items, int kb,
+                                                        int mode) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const FwItem it = items[blockIdx.x];
     const FwGraph g = gs[it.graph];
+    const UpdateSel u = mode == 0 ? UpdateSel{kb, g.nb, -1, -1}
+                                  : UpdateSel{kb, g.nb, mode == 1 ? kb + 1 : kb - 1, kb};
     int I, J;
-    select_block(UpdateSel{kb, g.nb, -1, -1}, it.idx, I, J);
+    select_block(u, it.idx, I, J);
     T* D = (T*)g.D;
     const int k0 = kb * FW_B, ks = g.n - k0 < FW_B ? g.n - k0 : FW_B;
     TileArgs<T> a{g.n, g.n, ks, D + k0, g.ldd, D + (long)k0 * g.ldd, g.ldd, D, g.ldd, D, g.ldd,
@@ -415,27 +421,69 @@ __global__ __launch_bounds__(256) void fwb_phase3_kernel(const FwGraph* __restri
     GemmTile<CfgM, T, T, BTAS_MIN_PLUS, VEC>::run(a, I * FW_B, J * FW_B, smem_raw);
 }
 
+// The pair update of many graphs: 128x128 tiles outside tile-row and
+// tile-column kb/2, k = the 128 pivots of blocks kb and kb+1.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(CfgL::NT) void fwb_pair_kernel(const FwGraph* __restrict__ gs,
+                                                           const FwItem* __restrict__ items, int kb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const FwItem it = items[blockIdx.x];
+    const FwGraph g = gs[it.graph];
+    const int sb = kb / 2, nb2 = (g.n + 2 * FW_B - 1) / (2 * FW_B);
+    int m0, n0;
+    pair_tile(it.idx, sb, nb2, m0, n0);
+    T* D = (T*)g.D;
+    const int k0 = sb * 2 * FW_B, ks = g.n - k0 < 2 * FW_B ? g.n - k0 : 2 * FW_B;
+    TileArgs<T> a{g.n, g.n, ks, D + k0, g.ldd, D + (long)k0 * g.ldd, g.ldd, D, g.ldd, D, g.ldd,
+                  nullptr, nullptr};
+    GemmTile<CfgL, T, T, BTAS_MIN_PLUS, VEC>::run(a, m0, n0, smem_raw);
+}
+
+template <typename T, bool VEC>
+void fwb_launch_update(const FwGraph* gs, const FwItem* items, int nitems, int kb, int mode,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((fwb_update_kernel<T, VEC>), dim3(nitems), dim3(256), CfgM::lds_bytes, s, gs,
+                       items, kb, mode);
+}
+
+template <typename T, bool VEC>
+void fwb_launch_pair(const FwGraph* gs, const FwItem* items, int nitems, int kb, hipStream_t s) {
+    hipLaunchKernelGGL((fwb_pair_kernel<T, VEC>), dim3(nitems), dim3(CfgL::NT), CfgL::lds_bytes, s,
+                       gs, items, kb);
+}
+
 template <typename T>
 hipError_t fwb_typed(int phase, const FwGraph* gs, const FwItem* items, int nitems, int kb, bool vec,
                      hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     switch (phase) {
-        case 0:
+        case FWB_INIT:
             hipLaunchKernelGGL(fwb_init_kernel<T>, dim3(nitems), dim3(256), 0, s, gs, items);
             break;
-        case 1:
+        case FWB_PHASE1:
             hipLaunchKernelGGL(fwb_phase1_kernel<T>, dim3(nitems), dim3(256), 0, s, gs, items, kb);
             break;
-        case 2:
+        case FWB_PHASE2:
             hipLaunchKernelGGL(fwb_phase2_kernel<T>, dim3(nitems), dim3(256), 0, s, gs, items, kb);
             break;
-        default:
+        case FWB_PHASE3:
+        case FWB_STRIP_NEXT:
+        case FWB_STRIP_PREV: {
+            const int mode = phase == FWB_PHASE3 ? 0 : (phase == FWB_STRIP_NEXT ? 1 : 2);
             if (vec)
-                hipLaunchKernelGGL((fwb_phase3_kernel<T, true>), dim3(nitems), dim3(256), CfgM::lds_bytes,
-                                   s, gs, items, kb);
+                fwb_launch_update<T, true>(gs, items, nitems, kb, mode, s);
             else
-                hipLaunchKernelGGL((fwb_phase3_kernel<T, false>), dim3(nitems), dim3(256), CfgM::lds_bytes,
-                                   s, gs, items, kb);
+                fwb_launch_update<T, false>(gs, items, nitems, kb, mode, s);
+            break;
+        }
+        case FWB_PAIR:
+            if (vec)
+                fwb_launch_pair<T, true>(gs, items, nitems, kb, s);
+            else
+                fwb_launch_pair<T, false>(gs, items, nitems, kb, s);
+            break;
+        default:
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -132,6 +132,13 @@ struct FwItem {
     int graph;
     int idx;
 };
+// Launch kinds of the batched blocked Floyd-Warshall (items name a graph and
+// a block or tile index within that launch's list for the graph): D = I (+) W
+// by 64-row slabs; phases 1 and 2 of pivot block kb; phase 3 of kb (every
+// block outside its row and column); kb's update of block-row and
+// block-column kb+1 (STRIP_NEXT) or kb-1 (STRIP_PREV); and the k=128 update of
+// the 128x128 tiles outside tile-row and tile-column kb/2 (PAIR, kb even).
+enum FwbPhase { FWB_INIT, FWB_PHASE1, FWB_PHASE2, FWB_PHASE3, FWB_STRIP_NEXT, FWB_STRIP_PREV, FWB_PAIR };
 hipError_t launch_fw_batched(int dt, int phase, const FwGraph* graphs, const FwItem* items, int nitems,
                              int kb, bool vec, hipStream_t s);
 
