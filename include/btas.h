@@ -178,7 +178,7 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     synchronises only if steps_out is not NULL).  Larger n ignore the flag.
  *     Not combinable with GRAPH.  BTAS_ERR_DEVICE if the device cannot launch
  *     it cooperatively, or (reported when steps_out is read) if a barrier
- *     wait timed out.  Calls without GRAPH take this path for 24 <= n <= 192
+ *     wait timed out.  Calls without GRAPH take this path for 24 <= n <= 256
  *     even without the flag (it is the faster one there), unless the
  *     environment variable BTAS_SINGLE_LAUNCH=0 is set.
  * steps_out: host int receiving the number of squarings executed (may be
