@@ -379,7 +379,12 @@ int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n);
  *     holding, for each active request, the next tiles of its current
  *     squaring up to quantum_terms (tile rows x tile cols x n) of work
  *     (<= 0 selects 6e10); requests admitted while others run join the next
- *     iteration (continuous batching);
+ *     iteration (continuous batching).  Two such engines (lanes) run side by
+ *     side on their own streams: one for requests of at most 1024 vertices
+ *     (the environment variable BTAS_SERVE_SMALL_N changes the bound; 0
+ *     keeps one lane) and one for the others, sharing the memory pool, so
+ *     small requests do not wait for the large ones' launches.  Admission is
+ *     in arrival order within each lane;
  *   BTAS_SERVE_FIFO: one request at a time, each squaring one plain GEMM
  *     launch (the one-solve-per-launch baseline).
  * Results are identical in both modes and to btas_apsp_squaring.  Times are

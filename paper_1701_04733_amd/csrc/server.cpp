@@ -25,6 +25,7 @@
 #include <string>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -70,16 +71,31 @@ class DevicePool {
     ~DevicePool() {
         if (base_) (void)hipFree(base_);
     }
-    size_t alloc(size_t bytes) { return ranges_.alloc(bytes); }
-    void release(size_t off, size_t bytes) { ranges_.release(off, bytes); }
+    // Shared by the engine lanes: each call takes the pool's own lock (always
+    // after a lane's lock, never the other way round).
+    size_t alloc(size_t bytes) {
+        std::lock_guard<std::mutex> g(m_);
+        return ranges_.alloc(bytes);
+    }
+    void release(size_t off, size_t bytes) {
+        std::lock_guard<std::mutex> g(m_);
+        ranges_.release(off, bytes);
+    }
     char* at(size_t off) const { return (char*)base_ + off; }
     size_t size() const { return ranges_.size(); }
-    size_t used() const { return ranges_.used(); }
-    size_t peak() const { return ranges_.peak(); }
+    size_t used() const {
+        std::lock_guard<std::mutex> g(m_);
+        return ranges_.used();
+    }
+    size_t peak() const {
+        std::lock_guard<std::mutex> g(m_);
+        return ranges_.peak();
+    }
 
    private:
     void* base_ = nullptr;
     RangeAllocator ranges_;
+    mutable std::mutex m_;
 };
 
 enum ReqState { PENDING = 0, ACTIVE = 1, DONE = 2, FAILED = 3 };
@@ -172,7 +188,8 @@ struct Server {
     int mode = 0;
     double quantum = 6e10;
     hipStream_t stream = nullptr;
-    DevicePool pool;
+    DevicePool* pool = nullptr;          // shared with the other lane
+    Server* peer = nullptr;              // the other lane (continuous mode), or null
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     std::mutex mu;
@@ -203,6 +220,17 @@ struct Server {
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    // Memory went back to the shared pool: let the other lane retry its
+    // admission.  Called without holding this lane's lock.
+    void wake_peer() {
+        if (!peer) return;
+        {
+            std::lock_guard<std::mutex> g(peer->mu);
+            peer->admission_blocked = false;
+        }
+        peer->cv_work.notify_all();
     }
 
     void free_staging() {
@@ -237,15 +265,15 @@ struct Server {
                 break;
             Request* r = pending.front();
             const size_t half = align_up((size_t)r->n * r->ld * 4, 256);
-            const size_t off = pool.alloc(2 * half);
+            const size_t off = pool->alloc(2 * half);
             if (off == SIZE_MAX) {
                 admission_blocked = true;
                 break;
             }
             const size_t coo = align_up((size_t)r->nnz * 4, 256) * 3;
-            const size_t coff = r->nnz > 0 ? pool.alloc(coo) : SIZE_MAX;
+            const size_t coff = r->nnz > 0 ? pool->alloc(coo) : SIZE_MAX;
             if (r->nnz > 0 && coff == SIZE_MAX) {
-                pool.release(off, 2 * half);
+                pool->release(off, 2 * half);
                 admission_blocked = true;
                 break;
             }
@@ -253,8 +281,8 @@ struct Server {
             r->bytes = 2 * half;
             r->coo_off = coff;
             r->coo_bytes = coo;
-            r->buf[0] = pool.at(off);
-            r->buf[1] = pool.at(off + half);
+            r->buf[0] = pool->at(off);
+            r->buf[1] = pool->at(off + half);
             r->state = ACTIVE;
             r->admitted = now();
             pending.pop_front();
@@ -267,7 +295,7 @@ struct Server {
     hipError_t densify(Request* r) {
         if (r->nnz > 0) {
             const size_t seg = align_up((size_t)r->nnz * 4, 256);
-            char* base = pool.at(r->coo_off);
+            char* base = pool->at(r->coo_off);
             hipError_t e = hipMemcpyAsync(base, r->rows.data(), r->nnz * 4, hipMemcpyHostToDevice, stream);
             if (e == hipSuccess) e = hipMemcpyAsync(base + seg, r->cols.data(), r->nnz * 4, hipMemcpyHostToDevice, stream);
             if (e == hipSuccess) e = hipMemcpyAsync(base + 2 * seg, r->w.data(), r->nnz * 4, hipMemcpyHostToDevice, stream);
@@ -385,32 +413,37 @@ struct Server {
         hipError_t e = hipEventSynchronize(L.ev);
         const double t = now();
         free_events.push_back(L.ev);
-        std::lock_guard<std::mutex> g(mu);
-        if (e != hipSuccess) return e;
-        for (Request* r : L.densified) {
-            if (r->coo_off != SIZE_MAX) {
-                pool.release(r->coo_off, r->coo_bytes);
-                r->coo_off = SIZE_MAX;
+        bool freed = false;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (e != hipSuccess) return e;
+            for (Request* r : L.densified) {
+                if (r->coo_off != SIZE_MAX) {
+                    pool->release(r->coo_off, r->coo_bytes);
+                    r->coo_off = SIZE_MAX;
+                    freed = true;
+                }
+                if (r->T == 0) finish_locked(r, t, 0);
             }
-            if (r->T == 0) finish_locked(r, t, 0);
-        }
-        for (Request* r : L.whole) finish_locked(r, t, r->T);
-        const int* chg = L.slot >= 0 ? staging[L.slot].h_changed : nullptr;
-        for (size_t i = 0; i < L.graphs.size(); ++i) {
-            Request* r = L.graphs[i];
-            if (r->early) r->changed_acc |= chg[i];
-            if (!L.ends_step[i]) continue;
-            r->done_steps += 1;
-            bool stop_early = false;
-            if (r->early) {
-                stop_early = r->changed_acc == 0;
-                r->changed_acc = 0;
-                r->hold = false;
+            for (Request* r : L.whole) finish_locked(r, t, r->T);
+            const int* chg = L.slot >= 0 ? staging[L.slot].h_changed : nullptr;
+            for (size_t i = 0; i < L.graphs.size(); ++i) {
+                Request* r = L.graphs[i];
+                if (r->early) r->changed_acc |= chg[i];
+                if (!L.ends_step[i]) continue;
+                r->done_steps += 1;
+                bool stop_early = false;
+                if (r->early) {
+                    stop_early = r->changed_acc == 0;
+                    r->changed_acc = 0;
+                    r->hold = false;
+                }
+                if (r->done_steps >= r->T || stop_early) finish_locked(r, t, r->done_steps);
             }
-            if (r->done_steps >= r->T || stop_early) finish_locked(r, t, r->done_steps);
+            cv_done.notify_all();
+            cv_work.notify_all();
         }
-        cv_done.notify_all();
-        cv_work.notify_all();
+        if (freed) wake_peer();
         return hipSuccess;
     }
 
@@ -503,9 +536,52 @@ struct Server {
 
 using btas::Server;
 
+// Continuous mode runs two lanes, each an engine thread with its own stream:
+// requests of at most small_n vertices go to the small lane, the others to
+// the large one.  Both share one memory pool (admission stays bounded by the
+// budget) and one clock; a small request's squarings then run in short
+// launches beside the large requests' instead of waiting for them.  A
+// request id carries its lane in bit 0.
 struct btas_server {
-    Server s;
+    btas::DevicePool pool;
+    Server lanes[2];
+    int nlanes = 1;
+    int small_n = 0;
 };
+
+namespace {
+
+Server* lane_of(btas_server_t srv, int64_t id, int64_t* local) {
+    const int l = (int)(id & 1);
+    if (id < 0 || l >= srv->nlanes) return nullptr;
+    *local = id >> 1;
+    return &srv->lanes[l];
+}
+
+void stop_lanes(btas_server_t srv) {
+    for (int l = 0; l < srv->nlanes; ++l) {
+        Server& s = srv->lanes[l];
+        {
+            std::lock_guard<std::mutex> g(s.mu);
+            s.stop = true;
+        }
+        s.cv_work.notify_all();
+    }
+    for (int l = 0; l < srv->nlanes; ++l)
+        if (srv->lanes[l].engine.joinable()) srv->lanes[l].engine.join();
+    for (int l = 0; l < srv->nlanes; ++l) {
+        Server& s = srv->lanes[l];
+        (void)hipSetDevice(s.device);
+        if (s.stream) {
+            (void)hipStreamSynchronize(s.stream);
+            (void)hipStreamDestroy(s.stream);
+            s.stream = nullptr;
+        }
+        s.free_staging();
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -521,46 +597,53 @@ btas_status_t btas_server_create(btas_server_t* out, int device, btas_dtype_t dt
         return BTAS_ERR_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return BTAS_ERR_DEVICE;
     std::unique_ptr<btas_server> srv(new btas_server);
-    Server& s = srv->s;
-    s.device = device;
-    s.dt = dt;
-    s.mode = mode;
-    if (quantum_terms > 0) s.quantum = quantum_terms;
-    if (!s.pool.init(budget_bytes)) return BTAS_ERR_OOM;
-    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return BTAS_ERR_DEVICE;
-    // Split-K workspace for the single-GEMM path (only products with fewer than
-    // 256 output tiles split, i.e. n < 512: at most a few MiB).
-    s.splitk_bytes = 16u << 20;
-    if (hipMalloc(&s.splitk_ws, s.splitk_bytes) != hipSuccess || hipMalloc((void**)&s.d_zero, 4) != hipSuccess ||
-        hipMemset(s.d_zero, 0, 4) != hipSuccess) {
-        s.free_staging();
-        return BTAS_ERR_OOM;
+    if (!srv->pool.init(budget_bytes)) return BTAS_ERR_OOM;
+    // The small lane (continuous mode only): graphs of up to 1024 vertices
+    // by default (one squaring <= 2.1e9 ops); BTAS_SERVE_SMALL_N overrides,
+    // 0 keeps a single lane.
+    int small_n = 1024;
+    if (const char* env = getenv("BTAS_SERVE_SMALL_N")) small_n = atoi(env);
+    srv->small_n = mode == BTAS_SERVE_CONTINUOUS && small_n > 0 ? small_n : 0;
+    srv->nlanes = srv->small_n > 0 ? 2 : 1;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < srv->nlanes; ++l) {
+        Server& s = srv->lanes[l];
+        s.device = device;
+        s.dt = dt;
+        s.mode = mode;
+        if (quantum_terms > 0) s.quantum = quantum_terms;
+        s.pool = &srv->pool;
+        s.t0 = srv->lanes[0].t0;
+        if (srv->nlanes == 2) s.peer = &srv->lanes[1 - l];
+        e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) break;
+        // Split-K workspace for the single-GEMM path (only products with fewer
+        // than 256 output tiles split, i.e. n < 512: at most a few MiB).
+        s.splitk_bytes = 16u << 20;
+        if ((e = hipMalloc(&s.splitk_ws, s.splitk_bytes)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&s.d_zero, 4)) != hipSuccess) break;
+        if ((e = hipMemset(s.d_zero, 0, 4)) != hipSuccess) break;
     }
-    s.engine = std::thread([p = &s] { p->run(); });
+    if (e != hipSuccess) {
+        stop_lanes(srv.get());
+        return e == hipErrorOutOfMemory ? BTAS_ERR_OOM : BTAS_ERR_DEVICE;
+    }
+    for (int l = 0; l < srv->nlanes; ++l) {
+        Server* p = &srv->lanes[l];
+        p->engine = std::thread([p] { p->run(); });
+    }
     *out = srv.release();
     return BTAS_OK;
 }
 
 btas_status_t btas_server_destroy(btas_server_t srv) {
     if (!srv) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
-    {
-        std::lock_guard<std::mutex> g(s.mu);
-        s.stop = true;
-    }
-    s.cv_work.notify_all();
-    if (s.engine.joinable()) s.engine.join();
-    (void)hipSetDevice(s.device);
-    if (s.stream) {
-        (void)hipStreamSynchronize(s.stream);
-        (void)hipStreamDestroy(s.stream);
-    }
-    s.free_staging();
+    stop_lanes(srv);
     delete srv;
     return BTAS_OK;
 }
 
-double btas_server_now(btas_server_t srv) { return srv ? srv->s.now() : -1.0; }
+double btas_server_now(btas_server_t srv) { return srv ? srv->lanes[0].now() : -1.0; }
 
 btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_t* rows,
                                  const int32_t* cols, const void* w, unsigned flags,
@@ -568,7 +651,8 @@ btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_
     if (!srv || n < 0 || nnz < 0 || (nnz > 0 && (!rows || !cols || !w)) || !id_out)
         return BTAS_ERR_INVALID_ARG;
     if (flags & ~(unsigned)BTAS_APSP_EARLY_EXIT) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
+    const int lane = srv->nlanes == 2 && n <= srv->small_n ? 1 : 0;
+    Server& s = srv->lanes[lane];
     try {
     std::unique_ptr<btas::Request> r(new btas::Request);
     r->n = n;
@@ -603,13 +687,13 @@ btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_
     r->ntiles = (int)r->tiles.size();
     const size_t need = 2 * btas::align_up((size_t)n * r->ld * 4, 256) +
                         3 * btas::align_up((size_t)nnz * 4, 256);
-    if (need > s.pool.size()) return BTAS_ERR_OOM;
+    if (need > s.pool->size()) return BTAS_ERR_OOM;
     {
         std::lock_guard<std::mutex> g(s.mu);
         if (!s.error.empty()) return BTAS_ERR_DEVICE;
         r->id = s.next_id++;
         r->arrival = arrival >= 0 ? arrival : s.now();
-        *id_out = r->id;
+        *id_out = r->id * 2 + lane;
         s.admission_blocked = false;
         s.pending.push_back(r.get());
         s.all[r->id] = std::move(r);
@@ -623,9 +707,12 @@ btas_status_t btas_server_submit(btas_server_t srv, int n, int nnz, const int32_
 
 btas_status_t btas_server_wait(btas_server_t srv, int64_t id, double timeout_s, int* done) {
     if (!srv) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
+    int64_t local = 0;
+    Server* sp = lane_of(srv, id, &local);
+    if (!sp) return BTAS_ERR_INVALID_ARG;
+    Server& s = *sp;
     std::unique_lock<std::mutex> lk(s.mu);
-    auto it = s.all.find(id);
+    auto it = s.all.find(local);
     if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
     btas::Request* r = it->second.get();
     auto ready = [&] { return r->state == btas::DONE || r->state == btas::FAILED; };
@@ -638,9 +725,12 @@ btas_status_t btas_server_wait(btas_server_t srv, int64_t id, double timeout_s, 
 btas_status_t btas_server_result(btas_server_t srv, int64_t id, const void** D_dev, int* ldd,
                                  int* steps) {
     if (!srv) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
+    int64_t local = 0;
+    Server* sp = lane_of(srv, id, &local);
+    if (!sp) return BTAS_ERR_INVALID_ARG;
+    Server& s = *sp;
     std::lock_guard<std::mutex> g(s.mu);
-    auto it = s.all.find(id);
+    auto it = s.all.find(local);
     if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
     btas::Request* r = it->second.get();
     if (r->state != btas::DONE) return BTAS_ERR_INVALID_ARG;
@@ -652,12 +742,15 @@ btas_status_t btas_server_result(btas_server_t srv, int64_t id, const void** D_d
 
 btas_status_t btas_server_copy_result(btas_server_t srv, int64_t id, void* D, int ldd) {
     if (!srv || !D) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
+    int64_t local = 0;
+    Server* sp = lane_of(srv, id, &local);
+    if (!sp) return BTAS_ERR_INVALID_ARG;
+    Server& s = *sp;
     const void* src;
     int n, ld;
     {
         std::lock_guard<std::mutex> g(s.mu);
-        auto it = s.all.find(id);
+        auto it = s.all.find(local);
         if (it == s.all.end() || it->second->state != btas::DONE) return BTAS_ERR_INVALID_ARG;
         btas::Request* r = it->second.get();
         src = r->buf[r->T & 1];
@@ -675,9 +768,12 @@ btas_status_t btas_server_copy_result(btas_server_t srv, int64_t id, void* D, in
 btas_status_t btas_server_times(btas_server_t srv, int64_t id, double* arrival, double* admitted,
                                 double* done) {
     if (!srv) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
+    int64_t local = 0;
+    Server* sp = lane_of(srv, id, &local);
+    if (!sp) return BTAS_ERR_INVALID_ARG;
+    Server& s = *sp;
     std::lock_guard<std::mutex> g(s.mu);
-    auto it = s.all.find(id);
+    auto it = s.all.find(local);
     if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
     btas::Request* r = it->second.get();
     if (arrival) *arrival = r->arrival;
@@ -688,34 +784,43 @@ btas_status_t btas_server_times(btas_server_t srv, int64_t id, double* arrival, 
 
 btas_status_t btas_server_release(btas_server_t srv, int64_t id) {
     if (!srv) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
+    int64_t local = 0;
+    Server* sp = lane_of(srv, id, &local);
+    if (!sp) return BTAS_ERR_INVALID_ARG;
+    Server& s = *sp;
     {
         std::lock_guard<std::mutex> g(s.mu);
-        auto it = s.all.find(id);
+        auto it = s.all.find(local);
         if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
         btas::Request* r = it->second.get();
         if (r->state != btas::DONE && r->state != btas::FAILED) return BTAS_ERR_INVALID_ARG;
-        if (r->off != SIZE_MAX) s.pool.release(r->off, r->bytes);
+        if (r->off != SIZE_MAX) s.pool->release(r->off, r->bytes);
         s.all.erase(it);
         s.admission_blocked = false;
     }
     s.cv_work.notify_all();
+    s.wake_peer();
     return BTAS_OK;
 }
 
 btas_status_t btas_server_stats(btas_server_t srv, btas_server_stats_t* out) {
     if (!srv || !out) return BTAS_ERR_INVALID_ARG;
-    Server& s = srv->s;
-    std::lock_guard<std::mutex> g(s.mu);
-    out->iterations = s.iterations.load();
-    out->launches = s.launches.load();
-    out->busy_seconds = s.busy_s;
-    out->pool_bytes = s.pool.size();
-    out->pool_used_bytes = s.pool.used();
-    out->pool_peak_bytes = s.pool.peak();
-    out->active = (int)s.active.size();
-    out->pending = (int)s.pending.size();
-    return s.error.empty() ? BTAS_OK : BTAS_ERR_DEVICE;
+    *out = btas_server_stats_t{};
+    bool ok = true;
+    for (int l = 0; l < srv->nlanes; ++l) {
+        Server& s = srv->lanes[l];
+        std::lock_guard<std::mutex> g(s.mu);
+        out->iterations += s.iterations.load();
+        out->launches += s.launches.load();
+        out->busy_seconds += s.busy_s;
+        out->active += (int)s.active.size();
+        out->pending += (int)s.pending.size();
+        ok = ok && s.error.empty();
+    }
+    out->pool_bytes = srv->pool.size();
+    out->pool_used_bytes = srv->pool.used();
+    out->pool_peak_bytes = srv->pool.peak();
+    return ok ? BTAS_OK : BTAS_ERR_DEVICE;
 }
 
 }  // extern "C"
