@@ -395,7 +395,7 @@ typedef struct btas_server *btas_server_t;
 #define BTAS_SERVE_CONTINUOUS 0
 #define BTAS_SERVE_FIFO 1
 
-typedef struct {
+typedef struct {           /* counts and times are summed over the lanes   */
     long iterations;        /* engine iterations run                        */
     long launches;          /* kernel launches issued for squarings          */
     double busy_seconds;    /* engine time spent with work on the device     */
