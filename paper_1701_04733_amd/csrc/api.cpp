@@ -888,10 +888,17 @@ btas_status_t btas_maxplus_cycle_mean(btas_handle_t h, btas_dtype_t dt, int n, c
     if (ensure_ws(h, need) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
     long long* result = reinterpret_cast<long long*>(h->dflags + FLAG_CM_RESULT);
-    e = btas::launch_cycle_mean(dt, n, A, lda, h->ws, result, h->stream);
+    int uses_err = 0;
+    e = btas::launch_cycle_mean(dt, n, A, lda, h->ws, result, h->num_cus, &uses_err, h->stream);
     if (e != hipSuccess) return device_fail(h, fn, e);
     btas_status_t st = sync_flags(h, fn, FLAG_CM_RESULT + 6);
     if (st != BTAS_OK) return st;
+    if (uses_err) {
+        int err = 0;
+        e = hipMemcpy(&err, btas::cycle_mean_error_word(n, h->ws), sizeof err, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return device_fail(h, fn, e);
+        if (err) return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
+    }
     int64_t r[3];
     memcpy(r, h->hflags + FLAG_CM_RESULT, sizeof r);
     if (num) *num = r[0];

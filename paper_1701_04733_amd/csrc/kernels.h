@@ -167,13 +167,18 @@ hipError_t launch_sparse_square(int dt, int n, const void* D, long ld, void* E, 
 
 // Maximum cycle mean of a max-plus matrix by Karp's theorem (csrc/maxplus.hip).
 // maxabs: *out = max |A_ij| over present int32 entries (atomicMax, clear first).
-// cycle_mean: ws of cycle_mean_ws_bytes(n) bytes; n max-plus gemv launches,
-// then result[0..1] = the int32 fraction in lowest terms (den = 0: no
-// cycle), result[2] = the bits of lambda as a binary64 (-inf: no cycle).
+// cycle_mean: ws of cycle_mean_ws_bytes(n) bytes; the n max-plus products
+// x_{k+1} = A (x) x_k as one cooperative launch (n <= 4096 and n/16 <=
+// num_cus; *uses_err = 1, and after synchronising the word at
+// cycle_mean_error_word(n, ws) is nonzero if a barrier wait timed out) or n
+// gemv launches (*uses_err = 0); then result[0..1] = the int32 fraction in
+// lowest terms (den = 0: no cycle), result[2] = the bits of lambda as a
+// binary64 (-inf: no cycle).
 size_t cycle_mean_ws_bytes(int n);
 hipError_t launch_cycle_mean_maxabs(int n, const void* A, long lda, int* out, hipStream_t s);
 hipError_t launch_cycle_mean(int dt, int n, const void* A, long lda, void* ws, long long* result,
-                             hipStream_t s);
+                             int num_cus, int* uses_err, hipStream_t s);
+const int* cycle_mean_error_word(int n, const void* ws);
 
 // Tropical product with witnesses (csrc/witness.hip): C <- C (+) A (.) B and,
 // where an entry strictly improves, K <- the smallest p attaining it.

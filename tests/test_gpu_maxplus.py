@@ -126,3 +126,22 @@ def test_cycle_mean_acyclic_views_and_domain(dev):
     H[0, 1] = H[1, 0] = 1 << 20
     with pytest.raises(btas.BtasError, match="DOMAIN"):
         btas.maxplus_cycle_mean(_dev(H, dev))
+
+
+@pytest.mark.parametrize("n", [4096, 4200])
+def test_cycle_mean_closed_form_both_paths(dev, n):
+    """A graph whose maximum cycle mean is known: a 2-cycle of weight 3 (mean
+    3/2), a 5-cycle of weight 7 (mean 7/5), and an acyclic chain through the
+    other vertices.  n = 4096 takes the single cooperative launch, n = 4200
+    the per-step products; both give exactly 3/2 (int32) and 1.5 (float32)."""
+    import paper_1701_04733_amd as btas
+    A = np.full((n, n), NINF32, np.int32)
+    A[0, 1], A[1, 0] = 1, 2
+    for i in range(5):
+        A[2 + i, 2 + (i + 1) % 5] = 1 if i < 3 else 2          # 1+1+1+2+2 = 7
+    for v in range(7, n - 1):
+        A[v, v + 1] = 50                                        # heavy, but no cycle
+    A[n - 1, 0] = -5                                            # enters the 2-cycle
+    assert btas.maxplus_cycle_mean(_dev(A, dev)) == (3, 2)
+    Af = np.where(A == NINF32, -np.inf, A).astype(np.float32)
+    assert btas.maxplus_cycle_mean(_dev(Af, dev)) == 1.5
