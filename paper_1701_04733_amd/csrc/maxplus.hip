@@ -256,10 +256,16 @@ hipError_t launch_cycle_mean(int dt, int n, const void* A, long lda, void* ws, l
         if (e == hipSuccess) {
             const void* fnp = dt == BTAS_FLOAT32 ? reinterpret_cast<const void*>(cm_persistent_kernel<float>)
                                                  : reinterpret_cast<const void*>(cm_persistent_kernel<int32_t>);
-            e = hipLaunchCooperativeKernel(fnp, dim3((unsigned)grid), dim3(CP_NT), args, 0, s);
+            // A refused cooperative launch (the workgroups cannot all be
+            // resident) falls back to one product launch per step.
+            if (hipLaunchCooperativeKernel(fnp, dim3((unsigned)grid), dim3(CP_NT), args, 0, s) != hipSuccess) {
+                (void)hipGetLastError();
+                persistent = false;
+            }
         }
-        if (err_out) *err_out = 1;  // the caller reads words[0] after synchronising
-    } else {
+        if (err_out) *err_out = persistent ? 1 : 0;  // the caller reads words[0] after synchronising
+    }
+    if (!persistent && e == hipSuccess) {
         if (err_out) *err_out = 0;
         for (int k = 0; k < n && e == hipSuccess; ++k)
             e = launch_gemv(BTAS_MAX_PLUS, dt, n, n, A, lda, base + (size_t)k * n * 4, 1,
