@@ -180,7 +180,8 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     it cooperatively, or (reported when steps_out is read) if a barrier
  *     wait timed out.  Calls without GRAPH take this path for 24 <= n <= 256
  *     even without the flag (it is the faster one there), unless the
- *     environment variable BTAS_SINGLE_LAUNCH=0 is set.
+ *     environment variable BTAS_SINGLE_LAUNCH=0 is set; such a call whose
+ *     cooperative launch is refused runs one launch per squaring instead.
  * steps_out: host int receiving the number of squarings executed (may be
  * NULL; when non-NULL the call synchronises).  Integer contract: all finite
  * path lengths must stay within +-BTAS_I32_FINITE_MAX.  The handle keeps an

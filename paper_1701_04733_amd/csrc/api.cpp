@@ -524,7 +524,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     const char* sl_env = getenv("BTAS_SINGLE_LAUNCH");
     const bool auto_single = !(sl_env && sl_env[0] == '0') && n >= btas::AUTO_SINGLE_LAUNCH_MIN_N &&
                              n <= btas::AUTO_SINGLE_LAUNCH_N && !(flags & BTAS_APSP_GRAPH);
-    const bool resident =
+    bool resident =
         n <= btas::RESIDENT_MAX_N && ((flags & BTAS_APSP_SINGLE_LAUNCH) || auto_single);
     if (T > 0 && !resident && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
@@ -537,18 +537,31 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         // asked for it.
         int* rf = h->dflags + FLAG_RESIDENT;
         e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
-        if (e == hipSuccess)
-            e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, rf, h->num_cus,
-                                           1 << 20, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
-        steps = T;
-        if (steps_out) {
-            btas_status_t st = sync_flags(h, fn, FLAG_RESIDENT + 2);
-            if (st != BTAS_OK) return st;
-            if (h->hflags[FLAG_RESIDENT] != 0)  // a barrier wait timed out: D is not valid
-                return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
-            steps = h->hflags[FLAG_RESIDENT + 1];
+        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, rf, h->num_cus,
+                                       1 << 20, h->stream);
+        if (e != hipSuccess && !(flags & BTAS_APSP_SINGLE_LAUNCH)) {
+            // Chosen automatically and refused (its workgroups cannot all be
+            // resident): one launch per squaring instead.
+            (void)hipGetLastError();
+            e = hipSuccess;
+            resident = false;
+            if (T > 0 && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
+                return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
+        } else {
+            if (e != hipSuccess) return device_fail(h, fn, e);
+            steps = T;
+            if (steps_out) {
+                btas_status_t st = sync_flags(h, fn, FLAG_RESIDENT + 2);
+                if (st != BTAS_OK) return st;
+                if (h->hflags[FLAG_RESIDENT] != 0)  // a barrier wait timed out: D is not valid
+                    return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
+                steps = h->hflags[FLAG_RESIDENT + 1];
+            }
         }
+    }
+    if (resident) {
+        // solved by the single launch above
     } else if (!early && (flags & BTAS_APSP_GRAPH)) {
         // One hipGraph per argument set: capture once on the auxiliary stream,
         // replay on the handle's stream.
