@@ -13,6 +13,7 @@
 // evaluated in binary64, as (double)x_n - (double)x_k divided by n - k.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
@@ -243,8 +244,10 @@ hipError_t launch_cycle_mean(int dt, int n, const void* A, long lda, void* ws, l
     e = hipGetLastError();
     // One cooperative launch when the rows fit the resident workgroups (one
     // per 16 rows, at most one per CU), else one gemv launch per step.
+    // (BTAS_CM_PERSISTENT=0 keeps the per-step launches at every size.)
     const int grid = (n + CP_ROWS - 1) / CP_ROWS;
-    bool persistent = n <= CP_MAX_N && grid <= num_cus && e == hipSuccess;
+    const char* pe = getenv("BTAS_CM_PERSISTENT");
+    bool persistent = n <= CP_MAX_N && grid <= num_cus && e == hipSuccess && !(pe && pe[0] == '0');
     if (persistent) {
         e = launch_clear_flags(words, 1 + 2 * CP_MAX_GRID, s);
         int* err = words;

@@ -145,3 +145,22 @@ def test_cycle_mean_closed_form_both_paths(dev, n):
     assert btas.maxplus_cycle_mean(_dev(A, dev)) == (3, 2)
     Af = np.where(A == NINF32, -np.inf, A).astype(np.float32)
     assert btas.maxplus_cycle_mean(_dev(Af, dev)) == 1.5
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+def test_cycle_mean_full_size_both_paths_agree(dev, dt, monkeypatch):
+    """The n=4096 workload of the benchmark (mean out-degree 8, int32
+    U{-50..100}; float32 the same values): the single cooperative launch and
+    the per-step products give the same exact fraction / binary64 value."""
+    import paper_1701_04733_amd as btas
+    A = wl.maxplus_digraph_i32(4096, 8.0, -50, 100, seed=9)
+    if dt == "f32":
+        A = np.where(A == NINF32, -np.inf, A).astype(np.float32)
+    t = _dev(A, dev)
+    one = btas.maxplus_cycle_mean(t)
+    monkeypatch.setenv("BTAS_CM_PERSISTENT", "0")
+    steps = btas.maxplus_cycle_mean(t)
+    if dt == "i32":
+        assert one == steps and steps[1] > 0
+    else:
+        assert np.float64(one).view(np.uint64) == np.float64(steps).view(np.uint64)
