@@ -172,13 +172,14 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     calls (one launch per solve; for latency-bound small n).  The handle
  *     keeps one such graph.  Not combinable with EARLY_EXIT.
  *   BTAS_APSP_SINGLE_LAUNCH: for n <= 500, run the whole solve (init, every
- *     squaring, and with EARLY_EXIT the stop test) as one cooperative kernel
- *     launch with a device-wide barrier between squarings: no per-step
+ *     squaring, and with EARLY_EXIT the stop test) as one kernel launch: one
+ *     workgroup with the matrices in LDS for n <= 64, else a cooperative
+ *     launch with a device-wide barrier between squarings.  No per-step
  *     launches and no host round trip, also with EARLY_EXIT (the host then
  *     synchronises only if steps_out is not NULL).  Larger n ignore the flag.
  *     Not combinable with GRAPH.  BTAS_ERR_DEVICE if the device cannot launch
  *     it cooperatively, or (reported when steps_out is read) if a barrier
- *     wait timed out.  Calls without GRAPH take this path for 24 <= n <= 256
+ *     wait timed out.  Calls without GRAPH take this path for n <= 256
  *     even without the flag (it is the faster one there), unless the
  *     environment variable BTAS_SINGLE_LAUNCH=0 is set; such a call whose
  *     cooperative launch is refused runs one launch per squaring instead.

@@ -518,7 +518,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     const size_t need = (size_t)n * n * 4;
     if (T > 0 && ensure_ws(h, need) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
-    // Graphs of 24..256 vertices take the single-launch solve also without
+    // Graphs of up to 256 vertices take the single-launch solve also without
     // the flag (it is faster there: one launch instead of one or two per
     // squaring) unless a captured graph was asked for or BTAS_SINGLE_LAUNCH=0.
     const char* sl_env = getenv("BTAS_SINGLE_LAUNCH");

@@ -89,21 +89,22 @@ hipError_t launch_diag_check(int sr, int dt, int n, const void* D, long ldd, int
 // Copy an n-column, m-row matrix between leading dimensions (4-byte elements).
 hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst, long ldd,
                               hipStream_t s);
-// Whole APSP solve in one cooperative launch (n <= RESIDENT_MAX_N): D_0 =
-// I (+) W, then T squarings (or fewer with early exit) separated by a
-// device-wide barrier, ping-ponging between D and ws (n x n, leading
-// dimension n); the result ends in D.  flags (device, 2 + 2 *
+// Whole APSP solve in one launch (n <= RESIDENT_MAX_N): D_0 = I (+) W, then
+// T squarings (or fewer with early exit); n <= 64: one workgroup with both
+// matrices in LDS; larger n: a cooperative launch with a device-wide barrier
+// between squarings, ping-ponging between D and ws (n x n, leading
+// dimension n).  The result ends in D.  flags (device, 2 + 2 *
 // RESIDENT_MAX_GRID words, zero at launch): [0] set on a barrier timeout,
 // [1] <- the number of squarings run, [2..] the barrier's arrival words.
 // num_cus: compute units of the device; spin_limit: polls per barrier wait
 // before giving up.
 constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
 constexpr int RESIDENT_MAX_GRID = 1024;  // (500 / 16 rounded up)^2 tiles
-// Between these sizes the single-launch solve beats one launch per squaring
-// on MI355X (measured latency, int32 ER graphs of mean degree 12.75, fixed T:
-// n=16 57 us vs 43 us, n=24 63 vs 65, n=129 96 vs 158, n=256 132 vs 174,
-// n=320 240 vs 209).
-constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 24;
+// Up to this size the single-launch solve beats one launch per squaring on
+// MI355X (measured latency, int32 ER graphs of mean degree 12.75, fixed T:
+// n=8 23 us vs 34 us, n=64 48 vs 93 (one workgroup, n <= 64), n=129 96 vs
+// 158, n=256 128 vs 176 (cooperative), n=320 235 vs 212).
+constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 1;
 constexpr int AUTO_SINGLE_LAUNCH_N = 256;
 size_t resident_lds_bytes(int n);
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,

@@ -260,6 +260,77 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
                                       dim3((unsigned)grid), dim3(RNT), args, (unsigned)lds, s);
 }
 
+// Graphs of at most 64 vertices: the whole solve in one workgroup, both
+// ping-pong matrices in LDS, a workgroup barrier between squarings (no
+// device-wide one).  Lane j of wave w computes column j of rows w, w+16,
+// w+32, w+48: per four k it reads the column's four entries once and each
+// row's four entries as one 16-byte broadcast read.  The early-exit decision
+// is the OR of the workgroup's change bits.  The same terms and the same
+// per-output mapping of int32 sums as the other squaring kernels, so the
+// same bits.
+constexpr int LDS_SOLVE_MAX_N = 64;
+constexpr int LDS_SOLVE_NT = 1024;
+constexpr int LDS_SOLVE_LS = LDS_SOLVE_MAX_N + 4;  // row stride: 16-byte aligned rows
+
+template <typename T>
+__global__ __launch_bounds__(LDS_SOLVE_NT) void apsp_lds_kernel(int n, const T* __restrict__ W, long ldw,
+                                                                T* D, long ldd, int nsq, int early,
+                                                                int* flags) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    __shared__ __align__(16) T buf[2][LDS_SOLVE_MAX_N * LDS_SOLVE_LS];
+    const int tid = threadIdx.x;
+    // both buffers absent outside n x n, so that k runs to n rounded up to 4
+    for (int e = tid; e < 2 * LDS_SOLVE_MAX_N * LDS_SOLVE_LS; e += LDS_SOLVE_NT) (&buf[0][0])[e] = R::absent();
+    __syncthreads();
+    for (int o = tid; o < n * n; o += LDS_SOLVE_NT) {
+        const int i = o / n, j = o - i * n;
+        T w = W[(long)i * ldw + j];
+        if (i == j && w > (T)0) w = (T)0;
+        buf[0][i * LDS_SOLVE_LS + j] = w;
+    }
+    __syncthreads();
+    const int j = tid & 63, ib = tid >> 6;
+    const int n4 = (n + 3) & ~3;
+    int cur = 0, steps = 0;
+    for (int t = 1; t <= nsq; ++t) {
+        const T* S = buf[cur];
+        T* Dn = buf[cur ^ 1];
+        T acc[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = R::absent();
+        for (int k = 0; k < n4; k += 4) {
+            const T b0 = S[k * LDS_SOLVE_LS + j], b1 = S[(k + 1) * LDS_SOLVE_LS + j];
+            const T b2 = S[(k + 2) * LDS_SOLVE_LS + j], b3 = S[(k + 3) * LDS_SOLVE_LS + j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const v4<T> a = *reinterpret_cast<const v4<T>*>(S + (ib + 16 * r) * LDS_SOLVE_LS + k);
+                acc[r][0] = R::add3(acc[r][0], R::mul(a[0], b0), R::mul(a[1], b1));
+                acc[r][1] = R::add3(acc[r][1], R::mul(a[2], b2), R::mul(a[3], b3));
+            }
+        }
+        bool changed = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = ib + 16 * r;
+            if (i < n && j < n) {
+                const T old = S[i * LDS_SOLVE_LS + j];
+                const T nv = R::add(old, R::finish(R::add(acc[r][0], acc[r][1])));
+                changed |= bits_of(nv) != bits_of(old);
+                Dn[i * LDS_SOLVE_LS + j] = nv;
+            }
+        }
+        const int any = __syncthreads_or(changed);  // also: Dn complete before it is read
+        cur ^= 1;
+        steps = t;
+        if (early && !any) break;
+    }
+    for (int o = tid; o < n * n; o += LDS_SOLVE_NT) {
+        const int i = o / n, jj = o - i * n;
+        D[(long)i * ldd + jj] = buf[cur][i * LDS_SOLVE_LS + jj];
+    }
+    if (tid == 0) flags[1] = steps;
+}
+
 }  // namespace
 
 size_t resident_lds_bytes(int n) { return (size_t)2 * RT * (((n + 7) & ~7) + 4) * 4; }
@@ -268,6 +339,15 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
                                 void* ws, int T, bool early, int* flags, int num_cus,
                                 int spin_limit, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (n <= LDS_SOLVE_MAX_N) {
+        if (dt == BTAS_FLOAT32)
+            hipLaunchKernelGGL(apsp_lds_kernel<float>, dim3(1), dim3(LDS_SOLVE_NT), 0, s, n,
+                               (const float*)W, ldw, (float*)D, ldd, T, early ? 1 : 0, flags);
+        else
+            hipLaunchKernelGGL(apsp_lds_kernel<int32_t>, dim3(1), dim3(LDS_SOLVE_NT), 0, s, n,
+                               (const int32_t*)W, ldw, (int32_t*)D, ldd, T, early ? 1 : 0, flags);
+        return hipGetLastError();
+    }
     if (dt == BTAS_FLOAT32)
         return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, flags, num_cus, spin_limit, s);
     return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, flags, num_cus, spin_limit, s);
