@@ -386,7 +386,10 @@ int btas_batched_tile_choice(btas_handle_t h, btas_dtype_t dt, int n);
  *     (the environment variable BTAS_SERVE_SMALL_N changes the bound; 0
  *     keeps one lane) and one for the others, sharing the memory pool, so
  *     small requests do not wait for the large ones' launches.  Admission is
- *     in arrival order within each lane;
+ *     in arrival order within each lane.  BTAS_SERVE_LAUNCH_TERMS (unset: no
+ *     cap) caps a large-lane launch at about that many terms, split evenly
+ *     over its requests: lower p50 at overload, at some cost in p99 and
+ *     throughput;
  *   BTAS_SERVE_FIFO: one request at a time, each squaring one plain GEMM
  *     launch (the one-solve-per-launch baseline).
  * Results are identical in both modes and to btas_apsp_squaring.  Times are

@@ -187,6 +187,8 @@ struct Server {
     int dt = BTAS_FLOAT32;
     int mode = 0;
     double quantum = 6e10;
+    double launch_terms = 0;             // > 0: a launch holds at most about this much work,
+                                         // split evenly over the requests it advances
     hipStream_t stream = nullptr;
     DevicePool* pool = nullptr;          // shared with the other lane
     Server* peer = nullptr;              // the other lane (continuous mode), or null
@@ -324,6 +326,7 @@ struct Server {
         // Few tiles in total: requests at a squaring boundary take the
         // single-GEMM path, one launch per request.
         const bool few = ni < (size_t)kMinGroupedItems;
+        const double q_each = launch_terms > 0 && ng > 0 ? std::min(quantum, launch_terms / (double)ng) : quantum;
         int nitems = 0;
         std::vector<Request*> single;
         for (Request* r : order) {
@@ -337,7 +340,7 @@ struct Server {
                 r->next_tile = r->ntiles;
             } else {
                 double work = 0;  // terms scheduled for this request in this launch
-                while (r->next_tile < r->ntiles && (work == 0 || work < quantum)) {
+                while (r->next_tile < r->ntiles && (work == 0 || work < q_each)) {
                     const TileRef& t = r->tiles[r->next_tile++];
                     st.h_items[nitems++] = {gi, t.m0, t.n0, t.kind, r->planned + 1, 0};
                     work += (t.kind == BATCH_TILE_128 ? 16384.0 : 4096.0) * r->n;
@@ -615,6 +618,8 @@ btas_status_t btas_server_create(btas_server_t* out, int device, btas_dtype_t dt
         s.pool = &srv->pool;
         s.t0 = srv->lanes[0].t0;
         if (srv->nlanes == 2) s.peer = &srv->lanes[1 - l];
+        if (const char* env = getenv("BTAS_SERVE_LAUNCH_TERMS"); env && l == 0 && srv->nlanes == 2)
+            s.launch_terms = atof(env);
         e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (e != hipSuccess) break;
         // Split-K workspace for the single-GEMM path (only products with fewer

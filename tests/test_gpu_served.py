@@ -168,13 +168,17 @@ def test_served_many_requests_share_grouped_launches(dev):
         assert np.array_equal(_bits(got[r.rid]), _bits(want))
 
 
-def test_served_two_lanes_large_and_small(dev):
+@pytest.mark.parametrize("cap", [None, "2e8"])
+def test_served_two_lanes_large_and_small(dev, cap, monkeypatch):
     """Requests above and below the small-lane bound (1024 vertices) served
     together: both lanes are used, the shared pool is empty afterwards, and
-    every result is the single-solve path's bits."""
+    every result is the single-solve path's bits (also with the large lane's
+    launches capped in size)."""
     import torch
 
     import paper_1701_04733_amd as btas
+    if cap is not None:
+        monkeypatch.setenv("BTAS_SERVE_LAUNCH_TERMS", cap)
     big = _requests(3, seed=35, lo=1100, hi=1400)
     small = _requests(10, seed=36, lo=32, hi=400)
     reqs = big + small
