@@ -9,6 +9,7 @@ import math
 import numpy as np
 import pytest
 
+import hand_cases
 import oracle
 from oracle import INF32, NINF32, FINITE_MAX
 from paper_1701_04733_amd import workloads as wl
@@ -563,6 +564,122 @@ def test_fw_blocked_f32_rounding_bound_vs_dijkstra():
     Dsq, _, _ = oracle.apsp(W)
     assert np.array_equal(np.isfinite(Dsq), fin)
 
+
+
+# --------------------------------------- blocked FW in binary32: hand pins ---
+
+def _fw_blocked_model(W, B, p1_desc=False, row_desc=False, col_desc=False, p2_pivot_inner=False,
+                      phase3_first=False):
+    """A scalar model of the blocked schedule with switches that plant the
+    plausible slips (pivot order inside phase 1 or phase 2, the pivot loop
+    inside the row loop in phase 2, phase 3 before phase 2); the default
+    switches are the order the hand-worked fixtures follow."""
+    n = W.shape[0]
+    d = W.astype(np.float32).copy()
+    np.fill_diagonal(d, np.minimum(np.diag(d), np.float32(0)))
+
+    def relax(x, y, z):
+        if not np.isfinite(d[x, z]):
+            return
+        s = np.float32(d[x, z]) + np.float32(d[z, y])
+        if s < d[x, y]:
+            d[x, y] = s
+
+    def sweep(z, rows, cols):
+        # pivot z over rows x cols; within one pivot no operand changes
+        # (d(z,z) = 0), so the row can be relaxed as a vector
+        c = np.array(cols, dtype=np.int64)
+        for x in rows:
+            if np.isfinite(d[x, z]):
+                d[x, c] = np.minimum(d[x, c], np.float32(d[x, z]) + d[z, c])
+
+    def panel(rows, cols, piv, desc):
+        pv = piv[::-1] if desc else piv
+        if p2_pivot_inner:
+            for x in rows:
+                for y in cols:
+                    for z in pv:
+                        relax(x, y, z)
+        else:
+            for z in pv:
+                sweep(z, rows, cols)
+
+    nb = (n + B - 1) // B
+    blk = [list(range(K * B, min(n, K * B + B))) for K in range(nb)]
+    for K in range(nb):
+        piv = blk[K]
+        others = [v for J in range(nb) if J != K for v in blk[J]]
+
+        def phase3():  # its operands, blocks (I,K) and (K,J), do not change here
+            oth = np.array(others, dtype=np.int64)
+            for z in piv:
+                for x in others:
+                    if np.isfinite(d[x, z]):
+                        s = np.float32(d[x, z]) + d[z, oth]
+                        d[x, oth] = np.minimum(d[x, oth], s)
+        for z in (piv[::-1] if p1_desc else piv):
+            sweep(z, piv, piv)
+        if phase3_first:
+            phase3()
+        panel(piv, others, piv, row_desc)
+        panel(others, piv, piv, col_desc)
+        if not phase3_first:
+            phase3()
+    return d
+
+
+def _bits(a):
+    return np.asarray(a, dtype=np.float32).view(np.uint32)
+
+
+def test_fw_blocked_f32_hand_golden():
+    """The oracle's binary32 blocked Floyd-Warshall at 1 < B < n equals the
+    values worked out by hand in tests/golden/fw_blocked_f32_hand.txt, each
+    case built so that one choice of relaxation order (blocked vs sequential,
+    pivot order in phase 1, in the block-row, in the block-column) decides
+    between 1 and 1 + 2^-23."""
+    cases = hand_cases.fw_blocked_f32_cases()
+    assert {c["name"] for c in cases} >= {"pair_order", "diagonal_block_pivots", "row_panel_pivots",
+                                          "column_panel_pivots", "pivot_block_64"}
+    for c in cases:
+        assert 1 < c["block"] < c["n"]
+        got = oracle.floyd_warshall_blocked(c["W"], c["block"])
+        assert np.array_equal(_bits(got), _bits(c["D"])), c["name"]
+
+
+def test_fw_blocked_f32_hand_golden_differs_from_sequential():
+    """Where the fixtures say so, the blocked result is not the sequential
+    one: numpy's binary32 sequential Floyd-Warshall and the oracle at B = 1
+    both give 1 + 2^-23 where the blocked order gives 1."""
+    for c in hand_cases.fw_blocked_f32_cases():
+        if c["name"] not in ("pair_order", "pivot_block_64", "pair_update_256", "later_block_pivots_128"):
+            continue
+        seq = _fw_f32_numpy(c["W"])
+        assert not np.array_equal(_bits(seq), _bits(c["D"])), c["name"]
+        assert np.array_equal(_bits(oracle.floyd_warshall_blocked(c["W"], 1)), _bits(seq))
+        diff = np.argwhere(seq != c["D"])
+        assert len(diff) == 1
+        i, j = diff[0]
+        assert float(c["D"][i, j]) == 1.0 and float(seq[i, j]) == 1.0 + 2.0 ** -23
+
+
+@pytest.mark.parametrize("slip", ["p1_desc", "row_desc", "col_desc", "p2_pivot_inner", "phase3_first",
+                                  "sequential"])
+def test_fw_blocked_f32_hand_golden_catches_order_slips(slip):
+    """The fixtures discriminate: the scalar model in the fixtures' order
+    reproduces every case, and each planted slip of the relaxation order
+    changes at least one of them."""
+    cases = hand_cases.fw_blocked_f32_cases()
+    for c in cases:
+        assert np.array_equal(_bits(_fw_blocked_model(c["W"], c["block"])), _bits(c["D"])), c["name"]
+    wrong = 0
+    for c in cases:
+        if slip == "sequential":
+            got = _fw_blocked_model(c["W"], c["n"])
+        else:
+            got = _fw_blocked_model(c["W"], c["block"], **{slip: True})
+        wrong += not np.array_equal(_bits(got), _bits(c["D"]))
+    assert wrong >= 1, slip
 
 # ------------------------------------------------------------ witnesses ---
 
