@@ -87,7 +87,11 @@ btas_status_t btas_destroy(btas_handle_t h);
  * stream) for all later work of this handle. */
 btas_status_t btas_set_stream(btas_handle_t h, void *hip_stream);
 
-/* Block the host until the handle's stream has drained. */
+/* Block the host until the handle's stream has drained.  Returns
+ * BTAS_ERR_DEVICE on a HIP error, or (once) when an earlier asynchronous
+ * single-launch APSP solve on this handle hit a device-wide barrier timeout
+ * (see BTAS_APSP_SINGLE_LAUNCH); every other entry point reports that latched
+ * error too, on its next call, instead of doing its work. */
 btas_status_t btas_synchronize(btas_handle_t h);
 
 /* Static text for a status code. */
@@ -178,8 +182,12 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     launches and no host round trip, also with EARLY_EXIT (the host then
  *     synchronises only if steps_out is not NULL).  Larger n ignore the flag.
  *     Not combinable with GRAPH.  BTAS_ERR_DEVICE if the device cannot launch
- *     it cooperatively, or (reported when steps_out is read) if a barrier
- *     wait timed out.  Calls without GRAPH take this path for n <= 256
+ *     it cooperatively, or if a barrier wait timed out (D is then not
+ *     valid): reported by this call when steps_out is not NULL, else latched
+ *     on the handle and reported by its next call or btas_synchronize.  The
+ *     environment variable BTAS_TEST_SPIN_LIMIT, read by btas_create, sets
+ *     the bound of each wait in polls (a negative value reports a timeout at
+ *     every wait, for tests of this path).  Calls without GRAPH take this path for n <= 256
  *     even without the flag (it is the faster one there), unless the
  *     environment variable BTAS_SINGLE_LAUNCH=0 is set; such a call whose
  *     cooperative launch is refused runs one launch per squaring instead.

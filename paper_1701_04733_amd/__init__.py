@@ -12,14 +12,17 @@ Semirings (Sec. I, eqs. (1)-(4)): ``"min"`` (min-plus) and ``"max"``
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
+import weakref
 
 __all__ = [
     "I32_INF", "I32_NEG_INF", "I32_FINITE_MAX", "BtasError", "lib", "library_path",
     "Handle", "default_handle", "tropical_gemm", "tropical_gemv", "vadd", "vmul", "dot",
     "axpy", "apsp", "apsp_num_steps", "version", "apsp_batched", "BatchedAPSP", "Server",
+    "close_all",
 ]
 
 I32_INF = 0x7FFFFFFF
@@ -39,6 +42,37 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbtas.so")
 _LIB = None
 _LOCK = threading.Lock()
+
+# Handles and servers still open at interpreter exit are closed by an atexit
+# hook, servers first (each owns a handle and a worker thread), while torch
+# and the HIP runtime are still up: destroying them later, from __del__
+# during module teardown, would synchronise streams and free graphs and
+# device memory after the runtime (or a profiler attached to it) has begun
+# its own shutdown.  The hook is registered on the first open, after torch
+# has been imported, so that it runs before torch's own exit hooks.
+_LIVE = weakref.WeakSet()
+_ATEXIT_DONE = False
+
+
+def _track(obj):
+    global _ATEXIT_DONE
+    with _LOCK:
+        _LIVE.add(obj)
+        if not _ATEXIT_DONE:
+            atexit.register(close_all)
+            _ATEXIT_DONE = True
+
+
+def close_all():
+    """Close every open Server, then every open Handle (idempotent)."""
+    objs = list(_LIVE)
+    for o in objs:
+        if isinstance(o, Server):
+            o.close()
+    for o in objs:
+        if isinstance(o, Handle):
+            o.close()
+    _HANDLES.clear()
 
 
 class ServerStats(ctypes.Structure):
@@ -132,6 +166,7 @@ class Handle:
         if st != OK:
             raise BtasError(st, f"btas_create(device={device}) failed")
         self._h = h
+        _track(self)
 
     @property
     def ptr(self):
@@ -149,6 +184,8 @@ class Handle:
         return st
 
     def synchronize(self):
+        """Wait for the handle's stream; raises BTAS_ERR_DEVICE if an earlier
+        asynchronous single-launch solve on this handle hit a barrier timeout."""
         self.check(lib().btas_synchronize(self._h))
 
     def close(self):
@@ -422,7 +459,9 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     Returns (D, steps, status); status is OK or WARN_NEG_CYCLE.  With
     ``return_steps=False`` steps is None and the call stays asynchronous unless
     a flag needs the host (early exit on the per-squaring path, the
-    negative-cycle check).  ``graph`` replays a captured hipGraph of the
+    negative-cycle check); a device-side failure of such a call (a barrier
+    timeout of the single-launch solve) is raised by the handle's next call
+    or ``synchronize()``.  ``graph`` replays a captured hipGraph of the
     fixed-T solve; ``single_launch`` runs the whole solve as one cooperative
     kernel (n <= 500).  ``out`` may be W itself (in place).
     """
@@ -596,6 +635,7 @@ class Server:
         if st != OK:
             raise BtasError(st, "btas_server_create failed")
         self._s = p
+        _track(self)
 
     def now(self) -> float:
         return lib().btas_server_now(self._s)

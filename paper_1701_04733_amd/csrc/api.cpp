@@ -25,7 +25,7 @@ bool dt_ok(btas_dtype_t dt) { return dt == BTAS_INT32 || dt == BTAS_FLOAT32; }
 btas_status_t check_common(btas_handle_t h, const char* fn, btas_semiring_t sr,
                            btas_dtype_t dt) {
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (!sr_ok(sr)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (semiring=%d) unknown", fn, (int)sr);
     if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (dtype=%d) unknown", fn, (int)dt);
     return BTAS_OK;
@@ -254,20 +254,29 @@ btas_status_t btas_create(btas_handle_t* out, int device) {
     h->device = device;
     const char* v = getenv("BTAS_VALIDATE");
     h->validate = v && v[0] == '1';
+    // BTAS_TEST_SPIN_LIMIT bounds each device-wide barrier wait of the
+    // single-launch solve (polls); a negative value makes every such wait
+    // report a timeout at once, so tests can reach the error path with every
+    // kernel still ending normally.
+    if (const char* sl = getenv("BTAS_TEST_SPIN_LIMIT")) h->spin_limit = atoi(sl);
     if (hipMalloc(&h->dflags, kNumFlags * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void**)&h->hflags, kNumFlags * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->hlatch, sizeof(int), hipHostMallocCoherent) != hipSuccess ||
         hipMalloc(&h->partials, (size_t)btas::dot_partials_needed(0) * 4) != hipSuccess) {
         if (h->dflags) (void)hipFree(h->dflags);
         if (h->hflags) (void)hipHostFree(h->hflags);
+        if (h->hlatch) (void)hipHostFree(h->hlatch);
         if (h->partials) (void)hipFree(h->partials);
         delete h;
         return BTAS_ERR_OOM;
     }
+    *h->hlatch = 0;
     if (hipMemset(h->dflags, 0, kNumFlags * sizeof(int)) != hipSuccess ||
         hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         h->num_cus < 1) {
         (void)hipFree(h->dflags);
         (void)hipHostFree(h->hflags);
+        (void)hipHostFree(h->hlatch);
         (void)hipFree(h->partials);
         delete h;
         return BTAS_ERR_DEVICE;
@@ -291,6 +300,7 @@ btas_status_t btas_destroy(btas_handle_t h) {
     if (h->partials) (void)hipFree(h->partials);
     if (h->dflags) (void)hipFree(h->dflags);
     if (h->hflags) (void)hipHostFree(h->hflags);
+    if (h->hlatch) (void)hipHostFree(h->hlatch);
     delete h;
     return BTAS_OK;
 }
@@ -305,7 +315,8 @@ btas_status_t btas_synchronize(btas_handle_t h) {
     if (!h) return BTAS_ERR_INVALID_ARG;
     DeviceGuard g(h->device);
     hipError_t e = hipStreamSynchronize(h->stream);
-    return e == hipSuccess ? BTAS_OK : device_fail(h, "btas_synchronize", e);
+    if (e != hipSuccess) return device_fail(h, "btas_synchronize", e);
+    return begin_call(h, "btas_synchronize");
 }
 
 // ------------------------------------------------------------- level 3 ---
@@ -487,7 +498,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
                                  void* D, int ldd, unsigned flags, int* steps_out) {
     const char* fn = "btas_apsp_squaring";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (steps_out) *steps_out = 0;
     if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
@@ -538,8 +549,8 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         int* rf = h->dflags + FLAG_RESIDENT;
         e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
-        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, rf, h->num_cus,
-                                       1 << 20, h->stream);
+        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, rf, h->hlatch,
+                                       h->num_cus, h->spin_limit, h->stream);
         if (e != hipSuccess && !(flags & BTAS_APSP_SINGLE_LAUNCH)) {
             // Chosen automatically and refused (its workgroups cannot all be
             // resident): one launch per squaring instead.
@@ -554,8 +565,10 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
             if (steps_out) {
                 btas_status_t st = sync_flags(h, fn, FLAG_RESIDENT + 2);
                 if (st != BTAS_OK) return st;
-                if (h->hflags[FLAG_RESIDENT] != 0)  // a barrier wait timed out: D is not valid
+                if (h->hflags[FLAG_RESIDENT] != 0) {  // a barrier wait timed out: D is not valid
+                    __atomic_store_n(h->hlatch, 0, __ATOMIC_RELEASE);  // reported here
                     return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
+                }
                 steps = h->hflags[FLAG_RESIDENT + 1];
             }
         }
@@ -671,7 +684,7 @@ btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, 
                                        int ldw, void* D, int ldd, unsigned flags) {
     const char* fn = "btas_apsp_floyd_warshall";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
     if (ldw < (n > 1 ? n : 1))
@@ -749,7 +762,7 @@ btas_status_t btas_apsp_successors(btas_handle_t h, btas_dtype_t dt, int n, cons
                                    const void* D, int ldd, int32_t* S, int lds) {
     const char* fn = "btas_apsp_successors";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
     if (ldw < (n > 1 ? n : 1))
@@ -785,7 +798,7 @@ btas_status_t btas_tropical_closure(btas_handle_t h, btas_semiring_t sr, btas_dt
                                     int* steps_out) {
     const char* fn = "btas_tropical_closure";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (steps_out) *steps_out = 0;
     if (sr != BTAS_MIN_PLUS && sr != BTAS_MAX_PLUS)
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (semiring=%d) unknown", fn, (int)sr);
@@ -867,7 +880,7 @@ btas_status_t btas_maxplus_cycle_mean(btas_handle_t h, btas_dtype_t dt, int n, c
                                       int64_t* num, int64_t* den, double* lambda) {
     const char* fn = "btas_maxplus_cycle_mean";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
     if (lda < (n > 1 ? n : 1))

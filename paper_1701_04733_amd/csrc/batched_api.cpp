@@ -187,7 +187,7 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
                                                     const int* ldd, unsigned flags) {
     const char* fn = "btas_apsp_squaring_batched";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (dt != BTAS_INT32 && dt != BTAS_FLOAT32)
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (count < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (count=%d) < 0", fn, count);
@@ -462,7 +462,7 @@ extern "C" btas_status_t btas_apsp_floyd_warshall_batched(btas_handle_t h, btas_
                                                          const int* ldd, unsigned flags) {
     const char* fn = "btas_apsp_floyd_warshall_batched";
     if (!h) return BTAS_ERR_INVALID_ARG;
-    h->last_error.clear();
+    if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (dt != BTAS_INT32 && dt != BTAS_FLOAT32)
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (count < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (count=%d) < 0", fn, count);

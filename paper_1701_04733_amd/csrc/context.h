@@ -49,6 +49,11 @@ struct btas_ctx {
     size_t skws_bytes = 0;
     int* dflags = nullptr;               // device flags [kNumFlags], see the FLAG_* slots
     int* hflags = nullptr;               // pinned host mirror
+    // Pinned host word that a single-launch solve sets (from the device) when
+    // one of its device-wide barrier waits hit its bound; reported and cleared
+    // by the next call on the handle or by btas_synchronize.
+    int* hlatch = nullptr;
+    int spin_limit = 1 << 20;            // polls per device-wide barrier wait
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
     std::unique_ptr<btas::FwBatchPlan, btas::FwBatchPlanDeleter> fw_batch_plan;  // last batched FW plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan
@@ -107,6 +112,21 @@ inline btas_status_t fail(btas_handle_t h, btas_status_t st, const char* fmt, ..
 
 inline btas_status_t device_fail(btas_handle_t h, const char* where, hipError_t e) {
     return fail(h, BTAS_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+// Start of every entry point on a handle: clears the last error and reports
+// (once) a barrier timeout latched by an earlier single-launch solve whose
+// caller did not synchronise on it.  The word is written by the device only
+// on that error path and is visible here once that kernel has ended.
+inline btas_status_t begin_call(btas_handle_t h, const char* fn) {
+    h->last_error.clear();
+    if (h->hlatch && __atomic_load_n(h->hlatch, __ATOMIC_ACQUIRE) != 0) {
+        __atomic_store_n(h->hlatch, 0, __ATOMIC_RELEASE);
+        return fail(h, BTAS_ERR_DEVICE,
+                    "%s: an earlier single-launch APSP solve on this handle timed out in a "
+                    "device-wide barrier; its D is not valid", fn);
+    }
+    return BTAS_OK;
 }
 
 // Byte span [lo, hi) touched by a row-major rows x cols matrix with leading

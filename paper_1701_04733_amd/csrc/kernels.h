@@ -96,8 +96,10 @@ hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst
 // dimension n).  The result ends in D.  flags (device, 2 + 2 *
 // RESIDENT_MAX_GRID words, zero at launch): [0] set on a barrier timeout,
 // [1] <- the number of squarings run, [2..] the barrier's arrival words.
-// num_cus: compute units of the device; spin_limit: polls per barrier wait
-// before giving up.
+// latch: a pinned host word also set to 1 on a barrier timeout (never
+// cleared by the kernel).  num_cus: compute units of the device; spin_limit:
+// polls per barrier wait before giving up (negative: every wait reports a
+// timeout at once, for tests of the error path).
 constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
 constexpr int RESIDENT_MAX_GRID = 1024;  // (500 / 16 rounded up)^2 tiles
 // Up to this size the single-launch solve beats one launch per squaring on
@@ -108,8 +110,8 @@ constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 1;
 constexpr int AUTO_SINGLE_LAUNCH_N = 256;
 size_t resident_lds_bytes(int n);
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
-                                void* ws, int T, bool early, int* flags, int num_cus,
-                                int spin_limit, hipStream_t s);
+                                void* ws, int T, bool early, int* flags, int* latch,
+                                int num_cus, int spin_limit, hipStream_t s);
 // Blocked Floyd-Warshall in place on D (n x n, leading dimension ld), which
 // holds I (+) W: pivot blocks of fw_block_size() vertices, three launches per
 // block (diagonal block, its block-row and block-column, the rest).

@@ -69,6 +69,7 @@ struct ResidentArgs {
     long ld1;
     int* flags;       // [0] error, [1] steps executed
     unsigned* arrive; // two sets of RESIDENT_MAX_GRID arrival words
+    int* latch;       // pinned host word, set with flags[0] on a timeout
 };
 
 // Device-scope loads and stores (coherent across XCDs without cache flushes).
@@ -81,15 +82,28 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A barrier wait hit its bound: the device flag for a caller that reads the
+// step count, and the handle's pinned host word for one that does not.
+__device__ __forceinline__ void report_timeout(int* err, int* latch) {
+    st_dev(err, 1);
+    __hip_atomic_store(latch, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Device-wide barrier number b (1, 2, ... within a launch), carrying one bit
 // per workgroup; returns the OR of every workgroup's `changed`.  Every thread
 // of every workgroup calls it with the same b.  On a wait that hits the bound
-// flags[0] is set and the result is incomplete.
-__device__ int grid_barrier(unsigned* arrive, unsigned b, int changed, int* err, int spin_limit) {
+// (at once when spin_limit < 0) the timeout is reported and the result is
+// incomplete.
+__device__ int grid_barrier(unsigned* arrive, unsigned b, int changed, int* err, int* latch,
+                            int spin_limit) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are performed
     const int mine = __syncthreads_or(changed);
     unsigned* words = arrive + (b & 1) * RESIDENT_MAX_GRID;
     if (threadIdx.x == 0) st_dev(words + blockIdx.x, 2 * b | (mine ? 1u : 0u));
+    if (spin_limit < 0) {
+        if (threadIdx.x == 0) report_timeout(err, latch);
+        return mine;
+    }
     int any = 0;
     for (int polls = 0;; ++polls) {
         int ok = 1;
@@ -101,7 +115,7 @@ __device__ int grid_barrier(unsigned* arrive, unsigned b, int changed, int* err,
         }
         if (__syncthreads_and(ok)) break;
         if (polls >= spin_limit) {
-            if (threadIdx.x == 0) st_dev(err, 1);
+            if (threadIdx.x == 0) report_timeout(err, latch);
             break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -133,7 +147,7 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
         }
     }
     unsigned bno = 1;
-    grid_barrier(a.arrive, bno++, 0, a.flags, a.spin_limit);
+    grid_barrier(a.arrive, bno++, 0, a.flags, a.latch, a.spin_limit);
 
     const int nt = (n + RT - 1) / RT;
     const int kpad = (n + 7) & ~7;
@@ -202,7 +216,7 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
             }
             __syncthreads();  // LDS is reloaded for the next tile
         }
-        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.spin_limit);
+        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.latch, a.spin_limit);
         cur ^= 1;
         steps = t;
         if (a.early && !any) break;
@@ -221,7 +235,8 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
 
 template <typename T>
 hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void* ws, int T_,
-                        bool early, int* flags, int num_cus, int spin_limit, hipStream_t s) {
+                        bool early, int* flags, int* latch, int num_cus, int spin_limit,
+                        hipStream_t s) {
     ResidentArgs<T> a;
     a.n = n;
     a.nsq = T_;
@@ -238,6 +253,7 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
     a.ld1 = n;
     a.flags = flags;
     a.arrive = reinterpret_cast<unsigned*>(flags + 2);
+    a.latch = latch;
     const size_t lds = resident_lds_bytes(n);
     // Workgroups per CU depend only on the LDS size (k padded to 8): the
     // occupancy query runs once per size, not on every call.
@@ -336,8 +352,8 @@ __global__ __launch_bounds__(LDS_SOLVE_NT) void apsp_lds_kernel(int n, const T* 
 size_t resident_lds_bytes(int n) { return (size_t)2 * RT * (((n + 7) & ~7) + 4) * 4; }
 
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
-                                void* ws, int T, bool early, int* flags, int num_cus,
-                                int spin_limit, hipStream_t s) {
+                                void* ws, int T, bool early, int* flags, int* latch,
+                                int num_cus, int spin_limit, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (n <= LDS_SOLVE_MAX_N) {
         if (dt == BTAS_FLOAT32)
@@ -349,8 +365,10 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
         return hipGetLastError();
     }
     if (dt == BTAS_FLOAT32)
-        return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, flags, num_cus, spin_limit, s);
-    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, flags, num_cus, spin_limit, s);
+        return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, flags, latch, num_cus,
+                                   spin_limit, s);
+    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, flags, latch, num_cus,
+                                 spin_limit, s);
 }
 
 }  // namespace btas

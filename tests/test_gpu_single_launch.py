@@ -143,3 +143,50 @@ def test_single_launch_repeated_small_config(dev):
     for ee, ws in ((False, wsteps), (True, wsteps_e)):
         _, steps, st = btas.apsp(t, single_launch=True, early_exit=ee)
         assert st == btas.OK and steps == ws
+
+
+@pytest.mark.parametrize("return_steps", [False, True])
+def test_single_launch_barrier_timeout_is_reported(dev, monkeypatch, return_steps):
+    """A barrier wait that hits its bound invalidates D and is reported also
+    when the caller does not read the step count: by the handle's next call
+    and by synchronize().  BTAS_TEST_SPIN_LIMIT=-1 makes every wait report a
+    timeout at once, so every kernel still runs to its end."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    monkeypatch.setenv("BTAS_TEST_SPIN_LIMIT", "-1")
+    h = btas.Handle(0)          # reads the bound at creation
+    monkeypatch.delenv("BTAS_TEST_SPIN_LIMIT")
+    try:
+        h.bind_stream()
+        W = _dev(_graph("i32", 200, seed=77), dev)
+        if return_steps:
+            with pytest.raises(btas.BtasError) as ei:
+                btas.apsp(W, handle=h)          # n=200 takes the single launch by default
+            assert ei.value.status == 5 and "timed out" in str(ei.value)
+            h.synchronize()                     # reported once, not again
+        else:
+            _, steps, st = btas.apsp(W, handle=h, return_steps=False)
+            assert steps is None and st == btas.OK
+            with pytest.raises(btas.BtasError) as ei:
+                h.synchronize()
+            assert ei.value.status == 5 and "timed out" in str(ei.value)
+            h.synchronize()
+            # the next call of any entry point reports it when the caller
+            # synchronised some other way
+            btas.apsp(W, handle=h, return_steps=False)
+            torch.cuda.synchronize()
+            C = torch.full((4, 4), btas.I32_INF, dtype=torch.int32, device=dev)
+            with pytest.raises(btas.BtasError) as ei:
+                btas.tropical_gemm(C.clone(), C.clone(), C, handle=h)
+            assert ei.value.status == 5
+        # with the normal bound, a fresh handle solves the same graph
+        ok = btas.Handle(0)
+        ok.bind_stream()
+        D, steps, _ = btas.apsp(W, handle=ok)
+        want, wsteps, _ = oracle.apsp(W.cpu().numpy())
+        assert steps == wsteps and np.array_equal(D.cpu().numpy(), want)
+        ok.close()
+    finally:
+        h.close()
+
