@@ -1,6 +1,7 @@
 """Write the stored expected values under tests/golden/ using only the oracle.
 
-Run:  python tests/golden/make_golden.py
+Run:  python tests/golden/make_golden.py            (apsp_er256.json)
+      python tests/golden/make_golden.py --large    (apsp_large4096.json)
 Every value here comes from oracle/ applied to inputs from the seeded
 generators; nothing is taken from the GPU path.
 """
@@ -23,7 +24,31 @@ def sha(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
+def large_4096():
+    """APSP-large generator at n=4096 (fp32, mean out-degree 16, exponential(1)
+    weights, seed 4) solved with early exit: the same code path as the
+    n=16384 workload on the GPU (sparse first squarings, then full 128x128
+    tiles).  Minutes on 8 host cores."""
+    W = wl.apsp_large_f32(4096, 16.0, seed=4)
+    D, steps, st = oracle.apsp(W, early_exit=True)
+    Dn = D.copy()
+    Dn[Dn == 0] = 0.0                      # -0 -> +0 before hashing
+    out = {"apsp_large_f32_n4096_seed4_early_exit": {
+        "recipe": "apsp_large_f32(4096, 16.0, seed=4); early exit capped at T",
+        "input_sha256": sha(W), "steps": steps, "T": oracle.apsp_steps(4096), "status": st,
+        "D_sha256": sha(Dn), "finite_pairs": int(np.isfinite(D).sum()),
+        "D_row0_first8_hex": [float(x).hex() for x in D[0, :8]],
+    }}
+    with open(os.path.join(HERE, "apsp_large4096.json"), "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
 def main():
+    if "--large" in sys.argv:
+        large_4096()
+        return
     out = {}
     # Small APSP workload: ER digraph n=256, p=0.05, int32 weights U{1..100}, seed 1.
     W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)

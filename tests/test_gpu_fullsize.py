@@ -47,7 +47,15 @@ def test_gemm_8192_sampled_rows(dev, sr, dt):
 
 
 def test_apsp_16384_f32_properties(dev):
-    """n=16384, mean out-degree 16, exponential(1) weights, early exit."""
+    """n=16384, mean out-degree 16, exponential(1) weights, early exit, on the
+    path the benchmark times (sparse first squarings, then 128x128 tiles).
+
+    Checked three ways: (1) 64 sampled sources against binary64 Dijkstra
+    within the (1 -+ u)^T rounding bound of a depth-T tree of binary32 adds;
+    (2) the same squarings chained through the GEMM entry point
+    (E = D (+) D (.) D, out of place) give the same bits; (3) the last
+    squaring of that chain, D_s = D_{s-1} (+) D_{s-1} (.) D_{s-1}, equals the
+    oracle's product bit for bit on 16 sampled rows, whatever s is."""
     import torch
     from scipy.sparse import csr_matrix
     from scipy.sparse.csgraph import dijkstra
@@ -62,7 +70,9 @@ def test_apsp_16384_f32_properties(dev):
     T = oracle.apsp_steps(n)
     assert 1 <= steps <= T
     assert (torch.diagonal(D) == 0).all()
-    sources = [0, 1, 8191, 16383]
+    g = np.random.default_rng(40)
+    sources = sorted({0, n - 1, *g.choice(n, size=62, replace=False).tolist()})
+    assert len(sources) == 64
     rows = D[sources].cpu().numpy().astype(np.float64)
     G = csr_matrix((w.astype(np.float64), (r, c)), shape=(n, n))
     exact = dijkstra(G, directed=True, indices=sources)
@@ -71,11 +81,61 @@ def test_apsp_16384_f32_properties(dev):
     u = 2.0 ** -24
     assert np.all(rows[fin] <= exact[fin] * (1 + u) ** T)
     assert np.all(rows[fin] >= exact[fin] * (1 - u) ** T)
-    # Early exit fired before T, so D is a fixpoint: D_i (+) D_i (.) D == D_i exactly.
+    del rows, exact, G
+    # (2) the squarings one product call at a time (W has a zero diagonal,
+    # so D_0 = I (+) W = W); keep D_{s-1} on the host for (3)
+    prev, Dh = tW, None
+    for t in range(steps):
+        cur = prev.clone()
+        btas.tropical_gemm(prev, prev, cur, semiring="min")
+        if t == steps - 1:
+            Dh = prev.cpu().numpy()
+        prev = cur
+    assert torch.equal(prev.view(torch.int32), D.view(torch.int32)), "chained products != apsp"
+    del prev, cur
+    # (3) the last squaring against the oracle on sampled rows
+    pick = [0, 1, 127, 128, 4096, 8191, 12000, n - 1] + g.choice(n, size=8, replace=False).tolist()
+    want = oracle.gemm("min", Dh[pick], Dh, Dh[pick])
+    got = D[pick].cpu().numpy()
+    assert np.array_equal(_bits(got), _bits(want))
+    # early exit fired before T: D is a fixpoint of one more squaring
     if steps < T:
-        Dn = D.cpu().numpy()
-        again = oracle.gemm("min", Dn[sources], Dn, Dn[sources])
-        assert np.array_equal(_bits(again), _bits(Dn[sources]))
+        assert np.array_equal(_bits(Dh[pick]), _bits(got))
+
+
+def test_apsp_large_generator_4096_golden(dev):
+    """The APSP-large generator at n=4096 (fp32, out-degree 16, exponential(1)
+    weights, seed 4) with early exit takes the code path of the n=16384
+    workload (sparse first squarings, then full 128x128 tiles with the
+    changed flag); the whole D equals the oracle's (digest written by
+    tests/golden/make_golden.py --large), and so does the dense-only path."""
+    import hashlib
+    import json
+    import os
+
+    import torch
+
+    import paper_1701_04733_amd as btas
+    with open(os.path.join(os.path.dirname(__file__), "golden", "apsp_large4096.json")) as f:
+        gold = json.load(f)["apsp_large_f32_n4096_seed4_early_exit"]
+    W = wl.apsp_large_f32(4096, 16.0, seed=4)
+    assert hashlib.sha256(W.tobytes()).hexdigest() == gold["input_sha256"]
+    tW = torch.from_numpy(W).to(dev)
+    for sparse in (None, "0"):
+        prev = os.environ.get("BTAS_SPARSE_STEPS")
+        if sparse is not None:
+            os.environ["BTAS_SPARSE_STEPS"] = sparse
+        try:
+            D, steps, _ = btas.apsp(tW, early_exit=True)
+        finally:
+            if sparse is not None:
+                if prev is None:
+                    del os.environ["BTAS_SPARSE_STEPS"]
+                else:
+                    os.environ["BTAS_SPARSE_STEPS"] = prev
+        Dn = _bits(D.cpu().numpy())
+        assert steps == gold["steps"], f"sparse={sparse}"
+        assert hashlib.sha256(Dn.tobytes()).hexdigest() == gold["D_sha256"], f"sparse={sparse}"
 
 
 @pytest.mark.parametrize("dt", ["f32", "i32"])
