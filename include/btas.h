@@ -204,6 +204,23 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n,
                                  const void *W, int ldw, void *D, int ldd,
                                  unsigned flags, int *steps_out);
 
+/* The same solve as btas_apsp_squaring, for callers that cannot allocate
+ * device memory during the call (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The call allocates nothing: the
+ * ping-pong partner matrix and split-K partial products live in a fixed
+ * 32 MiB device array held by the library on each GPU it runs on until the
+ * process ends, so n <= 2896 (larger n: BTAS_ERR_INVALID_ARG, nothing
+ * launched).  The caller passes W and D as for btas_apsp_squaring; flags as
+ * there except BTAS_APSP_GRAPH (BTAS_ERR_INVALID_ARG: capture allocates); the
+ * sparse first squarings are not used (same result).  Every call on one GPU
+ * shares that GPU's array: calls that may overlap in time on the same GPU
+ * (other handles or streams) race and must be serialised by the caller.  The
+ * array keeps the last call's contents; nothing in it has to start at zero.
+ * Results are bit-identical to btas_apsp_squaring's. */
+btas_status_t btas_apsp_squaring_noalloc(btas_handle_t h, btas_dtype_t dt, int n,
+                                         const void *W, int ldw, void *D, int ldd,
+                                         unsigned flags, int *steps_out);
+
 /* Number of squarings T for n vertices (0 for n <= 2). */
 int btas_apsp_num_steps(int n);
 

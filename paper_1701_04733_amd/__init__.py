@@ -22,7 +22,7 @@ __all__ = [
     "I32_INF", "I32_NEG_INF", "I32_FINITE_MAX", "BtasError", "lib", "library_path",
     "Handle", "default_handle", "tropical_gemm", "tropical_gemv", "vadd", "vmul", "dot",
     "axpy", "apsp", "apsp_num_steps", "version", "apsp_batched", "BatchedAPSP", "Server",
-    "close_all",
+    "close_all", "apsp_noalloc", "NOALLOC_MAX_N",
 ]
 
 I32_INF = 0x7FFFFFFF
@@ -118,6 +118,7 @@ def lib():
         L.btas_tropical_axpy.argtypes = [P, I, I, I, P, P, I, P, I]
         L.btas_apsp_squaring.argtypes = [P, I, I, P, I, P, I, U, ctypes.POINTER(I)]
         L.btas_apsp_num_steps.argtypes = [I]
+        L.btas_apsp_squaring_noalloc.argtypes = [P, I, I, P, I, P, I, U, ctypes.POINTER(I)]
         IP = ctypes.POINTER(I)
         PP = ctypes.POINTER(P)
         L.btas_apsp_squaring_batched.argtypes = [P, I, I, IP, PP, IP, PP, IP, U]
@@ -479,6 +480,30 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     steps = ctypes.c_int(0)
     sp = ctypes.byref(steps) if return_steps else None
     st = h.check(lib().btas_apsp_squaring(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
+                 allow=(OK, WARN_NEG_CYCLE))
+    return out, (steps.value if sp is not None else None), st
+
+
+NOALLOC_MAX_N = 2896
+
+
+def apsp_noalloc(W, out, early_exit=False, check_neg_cycle=False, return_steps=True,
+                 single_launch=False, handle=None):
+    """``apsp`` through the entry point that allocates nothing during the call
+    (its workspace is a fixed per-GPU array, n <= NOALLOC_MAX_N); ``out`` must
+    be given.  Calls that may overlap in time on one GPU race on that array.
+    Returns (D, steps, status) with the same bits as ``apsp``."""
+    n = W.size(0)
+    if W.shape != (n, n) or out.shape != (n, n) or out.dtype != W.dtype:
+        raise ValueError("W and out must be square, of one shape and dtype")
+    h = _handle_for(W, handle)
+    pw, ldw = _mat(W, "W")
+    pd, ldd = _mat(out, "D")
+    flags = (APSP_EARLY_EXIT if early_exit else 0) | (APSP_CHECK_NEG_CYCLE if check_neg_cycle else 0) \
+        | (APSP_SINGLE_LAUNCH if single_launch else 0)
+    steps = ctypes.c_int(0)
+    sp = ctypes.byref(steps) if return_steps else None
+    st = h.check(lib().btas_apsp_squaring_noalloc(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
                  allow=(OK, WARN_NEG_CYCLE))
     return out, (steps.value if sp is not None else None), st
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "btas.h"
@@ -18,6 +19,28 @@ using namespace btas;
 namespace {
 
 const char* kVersion = "btas-gfx950 0.1.0";
+
+// The no-allocation APSP entry point's workspace: one copy of this array per
+// GPU, held until the process ends.  In host code its name is only a
+// stand-in; kernels get the device address that btas_create looks up once
+// per device (kept in scratch_addr).
+__device__ __align__(256) unsigned char scratch[btas::NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices];
+
+// Device address of this device's copy of `scratch` (the device is
+// current); nullptr if the runtime cannot name it.
+void* scratch_for(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) scratch_addr[device] = p;
+        else (void)hipGetLastError();
+    }
+    return scratch_addr[device];
+}
 
 bool sr_ok(btas_semiring_t sr) { return sr == BTAS_MIN_PLUS || sr == BTAS_MAX_PLUS; }
 bool dt_ok(btas_dtype_t dt) { return dt == BTAS_INT32 || dt == BTAS_FLOAT32; }
@@ -60,8 +83,9 @@ btas_status_t validate_operands(btas_handle_t h, const char* fn, int sr, int dt,
 // I (+) W, T squarings ping-ponging between D and the workspace so that the
 // last one lands in D.
 hipError_t enqueue_fixed_apsp(btas_handle_t h, btas_dtype_t dt, int n, const void* W, int ldw,
-                              void* D, int ldd, int T, hipStream_t s) {
-    void* bufs[2] = {D, h->ws};
+                              void* D, int ldd, int T, void* ws, void* skws, size_t skws_bytes,
+                              hipStream_t s) {
+    void* bufs[2] = {D, ws};
     long lds[2] = {ldd, n};
     int cur = (T % 2 == 0) ? 0 : 1;
     // int32: slot FLAG_STEP_WIDE + t records whether D_t left the binary32-exact
@@ -75,7 +99,7 @@ hipError_t enqueue_fixed_apsp(btas_handle_t h, btas_dtype_t dt, int n, const voi
         btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
                          bufs[nxt], lds[nxt], nullptr,
                          wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr,
-                         h->skws, h->skws_bytes};
+                         skws, skws_bytes};
         e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, s);
         cur = nxt;
     }
@@ -271,6 +295,7 @@ btas_status_t btas_create(btas_handle_t* out, int device) {
         return BTAS_ERR_OOM;
     }
     *h->hlatch = 0;
+    h->scratch = scratch_for(device);
     if (hipMemset(h->dflags, 0, kNumFlags * sizeof(int)) != hipSuccess ||
         hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         h->num_cus < 1) {
@@ -494,9 +519,19 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
 }
 
 // ----------------------------------------------------------------- APSP ---
-btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const void* W, int ldw,
-                                 void* D, int ldd, unsigned flags, int* steps_out) {
-    const char* fn = "btas_apsp_squaring";
+namespace {
+
+// A caller-provided workspace for the squaring (the no-allocation entry
+// point): the ping-pong partner in [base, base + n*n*4), split-K partial
+// products in the rest.
+struct FixedWs {
+    unsigned char* base;
+    size_t bytes;
+};
+
+btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n, const void* W,
+                        int ldw, void* D, int ldd, unsigned flags, int* steps_out,
+                        const FixedWs* fixed) {
     if (!h) return BTAS_ERR_INVALID_ARG;
     if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (steps_out) *steps_out = 0;
@@ -514,6 +549,15 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
     if ((flags & BTAS_APSP_SINGLE_LAUNCH) && (flags & BTAS_APSP_GRAPH))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: SINGLE_LAUNCH and GRAPH cannot be combined", fn);
     if (n > 0 && (!W || !D)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: W or D is null", fn);
+    if (fixed && (flags & BTAS_APSP_GRAPH))
+        return fail(h, BTAS_ERR_INVALID_ARG, "%s: GRAPH needs allocations (graph capture); not "
+                    "available here", fn);
+    // The handle's (or the fixed) workspace: the n x n partner.
+    const size_t need = (size_t)n * n * 4;
+    if (fixed && (need + 255) / 256 * 256 > fixed->bytes)
+        return fail(h, BTAS_ERR_INVALID_ARG,
+                    "%s: argument 3 (n=%d) exceeds the fixed workspace (%zu bytes: n <= %d)", fn,
+                    n, fixed->bytes, btas::NOALLOC_MAX_N);
     const bool in_place = W == D && ldw == ldd;
     if (!in_place && overlap(mat_span(W, n, n, ldw), mat_span(D, n, n, ldd)))
         return fail(h, BTAS_ERR_ALIAS, "%s: D partially overlaps W", fn);
@@ -526,9 +570,30 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         if (st != BTAS_OK) return st;
     }
     const int T = btas_apsp_num_steps(n);
-    const size_t need = (size_t)n * n * 4;
-    if (T > 0 && ensure_ws(h, need) != hipSuccess)
-        return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
+    void* ws = nullptr;
+    void* skws = nullptr;
+    size_t skws_bytes = 0;
+    if (fixed) {
+        // No allocation: the partner matrix and the split-K partials come from
+        // the fixed workspace (a product whose partials do not fit runs
+        // without split-K: same bits).
+        const size_t part = (need + 255) & ~(size_t)255;  // fits: checked above
+        ws = fixed->base;
+        skws = fixed->base + part;
+        skws_bytes = fixed->bytes - part;
+    } else {
+        if (T > 0 && ensure_ws(h, need) != hipSuccess)
+            return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the %zu-byte workspace", fn, need);
+        ws = h->ws;
+    }
+    // Grow the handle's split-K workspace (not with a fixed workspace).
+    auto prepare_splitk = [&]() -> bool {
+        if (fixed) return true;
+        if (ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess) return false;
+        skws = h->skws;
+        skws_bytes = h->skws_bytes;
+        return true;
+    };
     // Graphs of up to 256 vertices take the single-launch solve also without
     // the flag (it is faster there: one launch instead of one or two per
     // squaring) unless a captured graph was asked for or BTAS_SINGLE_LAUNCH=0.
@@ -537,7 +602,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
                              n <= btas::AUTO_SINGLE_LAUNCH_N && !(flags & BTAS_APSP_GRAPH);
     bool resident =
         n <= btas::RESIDENT_MAX_N && ((flags & BTAS_APSP_SINGLE_LAUNCH) || auto_single);
-    if (T > 0 && !resident && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
+    if (T > 0 && !resident && !prepare_splitk())
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
     const bool early = flags & BTAS_APSP_EARLY_EXIT;
     hipError_t e = hipSuccess;
@@ -549,7 +614,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         int* rf = h->dflags + FLAG_RESIDENT;
         e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
-        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, h->ws, T, early, rf, h->hlatch,
+        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, ws, T, early, rf, h->hlatch,
                                        h->num_cus, h->spin_limit, h->stream);
         if (e != hipSuccess && !(flags & BTAS_APSP_SINGLE_LAUNCH)) {
             // Chosen automatically and refused (its workgroups cannot all be
@@ -557,7 +622,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
             (void)hipGetLastError();
             e = hipSuccess;
             resident = false;
-            if (T > 0 && ensure_splitk(h, btas::gemm_splitk_bytes(n, n, n)) != hipSuccess)
+            if (T > 0 && !prepare_splitk())
                 return fail(h, BTAS_ERR_OOM, "%s: cannot allocate the split-K workspace", fn);
         } else {
             if (e != hipSuccess) return device_fail(h, fn, e);
@@ -580,8 +645,8 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         // replay on the handle's stream.
         uint64_t key = 0x9E37ull;
         for (uint64_t v : {(uint64_t)dt, (uint64_t)n, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
-                           (uint64_t)(uintptr_t)D, (uint64_t)ldd, (uint64_t)(uintptr_t)h->ws,
-                           (uint64_t)(uintptr_t)h->skws, (uint64_t)h->skws_bytes})
+                           (uint64_t)(uintptr_t)D, (uint64_t)ldd, (uint64_t)(uintptr_t)ws,
+                           (uint64_t)(uintptr_t)skws, (uint64_t)skws_bytes})
             key = (key ^ (v + 0x9E3779B97F4A7C15ull + (key << 6) + (key >> 2)));
         if (!h->apsp_exec || h->apsp_key != key) {
             if (h->apsp_exec) {
@@ -598,7 +663,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
             }
             e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return device_fail(h, fn, e);
-            e = enqueue_fixed_apsp(h, dt, n, W, ldw, D, ldd, T, h->aux_stream);
+            e = enqueue_fixed_apsp(h, dt, n, W, ldw, D, ldd, T, ws, skws, skws_bytes, h->aux_stream);
             hipGraph_t graph = nullptr;
             const hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
             if (e == hipSuccess) e = e2;
@@ -615,19 +680,19 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         if (e != hipSuccess) return device_fail(h, fn, e);
         steps = T;
     } else if (!early) {
-        e = enqueue_fixed_apsp(h, dt, n, W, ldw, D, ldd, T, h->stream);
+        e = enqueue_fixed_apsp(h, dt, n, W, ldw, D, ldd, T, ws, skws, skws_bytes, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
         steps = T;
     } else {
         // Early exit: the same sequence, reading the change flag after each squaring.
-        void* bufs[2] = {D, h->ws};
+        void* bufs[2] = {D, ws};
         long lds[2] = {ldd, n};
         int cur = (T % 2 == 0) ? 0 : 1;
         int* wide = dt == BTAS_INT32 ? h->dflags + FLAG_STEP_WIDE : nullptr;
         if (wide) e = btas::launch_clear_flags(wide, T + 1, h->stream);
         if (e == hipSuccess) e = btas::launch_apsp_init(dt, n, W, ldw, bufs[cur], lds[cur], wide, h->stream);
         if (e != hipSuccess) return device_fail(h, fn, e);
-        const SparseMode smode = sparse_mode(n);
+        const SparseMode smode = fixed ? SparseMode::Off : sparse_mode(n);
         bool sparse_phase = smode != SparseMode::Off;
         for (int t = 0; t < T; ++t) {
             const int nxt = cur ^ 1;
@@ -646,7 +711,7 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
                 btas::GemmArgs a{n, n, n, bufs[cur], lds[cur], bufs[cur], lds[cur], bufs[cur], lds[cur],
                                  bufs[nxt], lds[nxt], changed,
                                  wide ? wide + t : nullptr, wide ? wide + t + 1 : nullptr,
-                                 h->skws, h->skws_bytes};
+                                 skws, skws_bytes};
                 e = btas::launch_gemm(BTAS_MIN_PLUS, dt, a, -1, h->stream);
                 if (e != hipSuccess) return device_fail(h, fn, e);
             }
@@ -677,6 +742,24 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const 
         *steps_out = steps;
     }
     return result;
+}
+
+}  // namespace
+
+btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n, const void* W, int ldw,
+                                 void* D, int ldd, unsigned flags, int* steps_out) {
+    return apsp_impl(h, "btas_apsp_squaring", dt, n, W, ldw, D, ldd, flags, steps_out, nullptr);
+}
+
+btas_status_t btas_apsp_squaring_noalloc(btas_handle_t h, btas_dtype_t dt, int n, const void* W,
+                                         int ldw, void* D, int ldd, unsigned flags,
+                                         int* steps_out) {
+    const char* fn = "btas_apsp_squaring_noalloc";
+    if (!h) return BTAS_ERR_INVALID_ARG;
+    if (!h->scratch)
+        return fail(h, BTAS_ERR_DEVICE, "%s: the device address of the fixed workspace is unknown", fn);
+    const FixedWs f{static_cast<unsigned char*>(h->scratch), btas::NOALLOC_SCRATCH_BYTES};
+    return apsp_impl(h, fn, dt, n, W, ldw, D, ldd, flags, steps_out, &f);
 }
 
 // ------------------------------------------------------ Floyd-Warshall ---

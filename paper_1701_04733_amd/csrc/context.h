@@ -54,6 +54,7 @@ struct btas_ctx {
     // by the next call on the handle or by btas_synchronize.
     int* hlatch = nullptr;
     int spin_limit = 1 << 20;            // polls per device-wide barrier wait
+    void* scratch = nullptr;             // this device's fixed no-allocation workspace
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
     std::unique_ptr<btas::FwBatchPlan, btas::FwBatchPlanDeleter> fw_batch_plan;  // last batched FW plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan

@@ -109,6 +109,14 @@ constexpr int RESIDENT_MAX_GRID = 1024;  // (500 / 16 rounded up)^2 tiles
 constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 1;
 constexpr int AUTO_SINGLE_LAUNCH_N = 256;
 size_t resident_lds_bytes(int n);
+// Fixed workspace of the no-allocation APSP entry point (per GPU): the
+// ping-pong partner (n*n*4 bytes, so n <= NOALLOC_MAX_N) and, in what is left,
+// split-K partial products.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+constexpr int NOALLOC_MAX_N = 2896;
+static_assert((size_t)NOALLOC_MAX_N * NOALLOC_MAX_N * 4 <= NOALLOC_SCRATCH_BYTES &&
+                  (size_t)(NOALLOC_MAX_N + 1) * (NOALLOC_MAX_N + 1) * 4 > NOALLOC_SCRATCH_BYTES,
+              "NOALLOC_MAX_N is the largest n whose partner matrix fits");
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
                                 void* ws, int T, bool early, int* flags, int* latch,
                                 int num_cus, int spin_limit, hipStream_t s);
