@@ -54,11 +54,12 @@ def parse():
                    help="skip the APSP workloads (small, large, batched, served)")
     p.add_argument("--extras", default="level12,apsp_small,apsp_large,witness,maxplus,batched,served",
                    help="comma-separated subset of the extra workloads to run")
-    p.add_argument("--served-count", type=int, default=300,
-                   help="requests per arrival rate in the served workload")
+    p.add_argument("--served-count", type=int, default=500,
+                   help="requests per arrival rate in the served workload (the stated "
+                        "configuration is 2000)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one plain 256 MiB device copy first (reference for HBM counters)")
-    p.add_argument("--served-rates", default="300,3000",
+    p.add_argument("--served-rates", default="100,300,1000,3000,10000",
                    help="comma-separated Poisson arrival rates (req/s) for the served workload")
     return p.parse_args()
 
@@ -480,6 +481,11 @@ def bench_served(rates, count):
         out[f"rate_{rate}"] = {"continuous": _serve_trace(reqs, "continuous"),
                                "continuous_early_exit": _serve_trace(reqs, "continuous", True),
                                "fifo": _serve_trace(reqs, "fifo")}
+    # The knee: the highest swept rate that a mode still serves at >= 90% of
+    # the arrival rate (above it the queue grows for as long as the trace lasts).
+    for mode in ("continuous", "continuous_early_exit", "fifo"):
+        keep = [r for r in rates if out[f"rate_{r}"][mode]["solves_per_s"] >= 0.9 * r]
+        out[f"knee_req_per_s[{mode}]"] = max(keep) if keep else None
     return out
 
 

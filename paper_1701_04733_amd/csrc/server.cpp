@@ -116,8 +116,9 @@ struct Request {
     int planned = 0;      // squarings whose tiles have all been enqueued
     int next_tile = 0;    // first tile of squaring planned+1 not yet enqueued
     int done_steps = 0;   // squarings known complete
-    bool hold = false;    // early exit: wait for the last squaring's flag before planning more
     int changed_acc = 0;  // some entry changed in the squaring in flight (early exit)
+    int refs = 0;         // launches in flight that name this request
+    bool released = false;  // the client released it while refs > 0: free at refs == 0
 };
 
 // Host-pinned and device copies of one launch's descriptors.
@@ -308,7 +309,14 @@ struct Server {
         return launch_densify(dt, r->buf[0], r->n, r->ld, 0, nullptr, nullptr, nullptr, stream);
     }
 
-    bool plannable(const Request* r) const { return !r->hold && r->planned < r->T; }
+    // Early-exit requests are planned speculatively: the next squaring is
+    // enqueued before the flag of the previous one is known.  When that flag
+    // says the previous squaring changed nothing, D_s is a fixpoint, so the
+    // speculative squaring s + 1 writes into the other buffer exactly the
+    // values of D_s (and never touches buf[s & 1], which holds the result);
+    // the request finishes with s steps, as with a wait per squaring, but
+    // without leaving the launches in between.
+    bool plannable(const Request* r) const { return r->planned < r->T; }
 
     // Fill a launch with, for every active request that can advance, the next
     // tiles of its next squaring (at most `quantum` terms of work each).
@@ -381,7 +389,6 @@ struct Server {
                 Request* r = L.graphs[i];
                 r->planned += 1;
                 r->next_tile = 0;
-                if (r->early) r->hold = true;
             }
         if (e == hipSuccess) e = hipMemcpyAsync(st.h_changed, st.d_changed, g * sizeof(int), hipMemcpyDeviceToHost, stream);
         return e;
@@ -409,6 +416,16 @@ struct Server {
         active.erase(std::remove(active.begin(), active.end(), r), active.end());
     }
 
+    // The distinct requests a launch names.
+    static std::vector<Request*> launch_requests(const Launch& L) {
+        std::vector<Request*> v(L.graphs);
+        v.insert(v.end(), L.densified.begin(), L.densified.end());
+        v.insert(v.end(), L.whole.begin(), L.whole.end());
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        return v;
+    }
+
     // Wait for the oldest launch and apply what its completion means.
     hipError_t retire_oldest() {
         Launch L = std::move(inflight.front());
@@ -432,6 +449,7 @@ struct Server {
             const int* chg = L.slot >= 0 ? staging[L.slot].h_changed : nullptr;
             for (size_t i = 0; i < L.graphs.size(); ++i) {
                 Request* r = L.graphs[i];
+                if (r->state != ACTIVE) continue;  // finished earlier: speculative work
                 if (r->early) r->changed_acc |= chg[i];
                 if (!L.ends_step[i]) continue;
                 r->done_steps += 1;
@@ -439,10 +457,19 @@ struct Server {
                 if (r->early) {
                     stop_early = r->changed_acc == 0;
                     r->changed_acc = 0;
-                    r->hold = false;
                 }
                 if (r->done_steps >= r->T || stop_early) finish_locked(r, t, r->done_steps);
             }
+            // Drop this launch's references; a request the client released
+            // while launches still named it is freed now.
+            for (Request* r : launch_requests(L))
+                if (--r->refs == 0 && r->released) {
+                    if (r->off != SIZE_MAX) pool->release(r->off, r->bytes);
+                    r->off = SIZE_MAX;
+                    freed = true;
+                    all.erase(r->id);
+                }
+            if (freed) admission_blocked = false;  // retry the head of the queue
             cv_done.notify_all();
             cv_work.notify_all();
         }
@@ -498,7 +525,11 @@ struct Server {
                 L.ev = get_event();
                 if (L.ev == nullptr) e = hipErrorOutOfMemory;
                 else e = hipEventRecord(L.ev, stream);
-                if (e == hipSuccess) inflight.push_back(std::move(L));
+                if (e == hipSuccess) {
+                    std::lock_guard<std::mutex> g(mu);
+                    for (Request* r : launch_requests(L)) ++r->refs;
+                    inflight.push_back(std::move(L));
+                }
             }
             // Keep at most kDepth launches in flight; when nothing new can be
             // planned, wait for the oldest so that its requests advance.
@@ -718,7 +749,7 @@ btas_status_t btas_server_wait(btas_server_t srv, int64_t id, double timeout_s, 
     Server& s = *sp;
     std::unique_lock<std::mutex> lk(s.mu);
     auto it = s.all.find(local);
-    if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+    if (it == s.all.end() || it->second->released) return BTAS_ERR_INVALID_ARG;
     btas::Request* r = it->second.get();
     auto ready = [&] { return r->state == btas::DONE || r->state == btas::FAILED; };
     if (timeout_s < 0) s.cv_done.wait(lk, ready);
@@ -736,7 +767,7 @@ btas_status_t btas_server_result(btas_server_t srv, int64_t id, const void** D_d
     Server& s = *sp;
     std::lock_guard<std::mutex> g(s.mu);
     auto it = s.all.find(local);
-    if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+    if (it == s.all.end() || it->second->released) return BTAS_ERR_INVALID_ARG;
     btas::Request* r = it->second.get();
     if (r->state != btas::DONE) return BTAS_ERR_INVALID_ARG;
     if (D_dev) *D_dev = r->buf[r->T & 1];
@@ -756,7 +787,8 @@ btas_status_t btas_server_copy_result(btas_server_t srv, int64_t id, void* D, in
     {
         std::lock_guard<std::mutex> g(s.mu);
         auto it = s.all.find(local);
-        if (it == s.all.end() || it->second->state != btas::DONE) return BTAS_ERR_INVALID_ARG;
+        if (it == s.all.end() || it->second->released || it->second->state != btas::DONE)
+            return BTAS_ERR_INVALID_ARG;
         btas::Request* r = it->second.get();
         src = r->buf[r->T & 1];
         n = r->n;
@@ -779,7 +811,7 @@ btas_status_t btas_server_times(btas_server_t srv, int64_t id, double* arrival, 
     Server& s = *sp;
     std::lock_guard<std::mutex> g(s.mu);
     auto it = s.all.find(local);
-    if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+    if (it == s.all.end() || it->second->released) return BTAS_ERR_INVALID_ARG;
     btas::Request* r = it->second.get();
     if (arrival) *arrival = r->arrival;
     if (admitted) *admitted = r->admitted;
@@ -796,9 +828,15 @@ btas_status_t btas_server_release(btas_server_t srv, int64_t id) {
     {
         std::lock_guard<std::mutex> g(s.mu);
         auto it = s.all.find(local);
-        if (it == s.all.end()) return BTAS_ERR_INVALID_ARG;
+        if (it == s.all.end() || it->second->released) return BTAS_ERR_INVALID_ARG;
         btas::Request* r = it->second.get();
         if (r->state != btas::DONE && r->state != btas::FAILED) return BTAS_ERR_INVALID_ARG;
+        if (r->refs > 0) {
+            // a speculative squaring still runs in its buffers: the engine
+            // frees them when that launch retires
+            r->released = true;
+            return BTAS_OK;
+        }
         if (r->off != SIZE_MAX) s.pool->release(r->off, r->bytes);
         s.all.erase(it);
         s.admission_blocked = false;

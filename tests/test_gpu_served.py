@@ -197,3 +197,81 @@ def test_served_two_lanes_large_and_small(dev, cap, monkeypatch):
         W = torch.from_numpy(_dense(r)).to(dev)
         want, _, _ = btas.apsp(W)
         assert np.array_equal(_bits(g), _bits(want.cpu().numpy())), f"request {r.rid} n={r.n}"
+
+
+def test_served_early_exit_release_while_speculating(dev):
+    """Early-exit requests are planned one squaring ahead; a request released
+    as soon as it finishes may still have that squaring in flight, so its
+    memory is handed back only when the launch retires.  Later requests
+    reuse the pool and every result equals the oracle; the pool drains to
+    zero once the engine is idle."""
+    import time
+
+    import torch
+
+    import paper_1701_04733_amd as btas
+    reqs = _requests(16, seed=37, lo=60, hi=500)
+    per = max(2 * ((r.n + 3) // 4 * 4) * r.n * 4 + 3 * 4 * (r.rows.size + 64) for r in reqs)
+    with btas.Server("f32", budget_bytes=3 * per, quantum_terms=2e7) as srv:
+        ids = [srv.submit(r.n, r.rows, r.cols, r.w, early_exit=True) for r in reqs]
+        for r, rid in zip(reqs, ids):
+            assert srv.wait(rid, 120)
+            got = _fetch(srv, rid, r.n, dev, torch.float32)
+            steps = srv.steps(rid)
+            srv.release(rid)                       # possibly before the last launch retired
+            with pytest.raises(btas.BtasError):
+                srv.release(rid)                   # released once only
+            want, wsteps, _ = oracle.apsp(_dense(r), early_exit=True)
+            assert steps == wsteps
+            assert np.array_equal(_bits(got), _bits(want)), f"request {r.rid} n={r.n}"
+        deadline = time.time() + 30
+        while srv.stats()["pool_used_bytes"] != 0 and time.time() < deadline:
+            time.sleep(0.01)
+        st = srv.stats()
+        assert st["pool_used_bytes"] == 0 and st["active"] == 0 and st["pending"] == 0
+
+
+def test_served_small_lane_not_behind_large(dev):
+    """A small request submitted right after several large ones, which need
+    far more device time, completes while every large one is still running:
+    the small lane does not wait for the large lane's squarings.  Ordering,
+    not a time bound: the large requests take tens of milliseconds on the
+    device, the small one a few launches."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    big = _requests(3, seed=38, lo=3000, hi=3500)
+    small = _requests(1, seed=39, lo=48, hi=64)[0]
+    with btas.Server("f32", budget_bytes=8 << 30) as srv:
+        bids = [srv.submit(r.n, r.rows, r.cols, r.w) for r in big]
+        sid = srv.submit(small.n, small.rows, small.cols, small.w)
+        assert sid & 1 == 1 and all(b & 1 == 0 for b in bids)
+        assert srv.wait(sid, 120)
+        done_small = srv.times(sid)[2]
+        for b in bids:
+            assert srv.wait(b, 120)
+        assert all(srv.times(b)[2] > done_small for b in bids)
+        got = _fetch(srv, sid, small.n, dev, torch.float32)
+        want, _, _ = oracle.apsp(_dense(small))
+        assert np.array_equal(_bits(got), _bits(want))
+        # the first large request against the oracle as well (n >= 3000 would
+        # take minutes on the host: compare its sampled rows with one more
+        # squaring's fixpoint instead)
+        r0 = big[0]
+        D = _fetch(srv, bids[0], r0.n, dev, torch.float32)
+        for b in bids:
+            srv.release(b)
+        srv.release(sid)
+    W = _dense(r0)
+    rows = [0, 1, r0.n // 2, r0.n - 1]
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra
+    G = csr_matrix((r0.w.astype(np.float64), (r0.rows, r0.cols)), shape=(r0.n, r0.n))
+    exact = dijkstra(G, directed=True, indices=rows)
+    T = oracle.apsp_steps(r0.n)
+    u = 2.0 ** -24
+    fin = np.isfinite(exact)
+    got = D[rows].astype(np.float64)
+    assert np.array_equal(fin, np.isfinite(got))
+    assert np.all(got[fin] <= exact[fin] * (1 + u) ** T) and np.all(got[fin] >= exact[fin] * (1 - u) ** T)
+    del W
