@@ -224,6 +224,19 @@ btas_status_t btas_apsp_squaring_noalloc(btas_handle_t h, btas_dtype_t dt, int n
 /* Number of squarings T for n vertices (0 for n <= 2). */
 int btas_apsp_num_steps(int n);
 
+/* 1 if the last btas_apsp_squaring / _noalloc call on this handle that read
+ * its step count (steps_out not NULL) ran the single-launch solve on packed
+ * 16-bit distances (Sec. I semirings evaluated two lanes per 32-bit
+ * register), else 0.  With BTAS_U16=1 in the environment that mode is taken
+ * on the device, for int32 graphs of 64 < n <= 500 solved by the single
+ * launch, when every finite off-diagonal weight lies in
+ * [0, floor(65534 / (2 (n - 1)))] and no diagonal weight is negative: every
+ * distance then fits 15 bits and every sum of two fits 16, so the result has
+ * the same bits as the int32 squarings.  It is off by default: at n=256 it
+ * measured slower than the int32 squarings (the solve is bound by load and
+ * barrier latency, not by bytes or instructions). */
+int btas_apsp_last_packed16(btas_handle_t h);
+
 /* ---------------------------------------------------------------------------
  * Batched APSP: `count` independent solves of btas_apsp_squaring (fixed
  * T(n_i) squarings each, same bits as one call per graph), executed as ONE

@@ -119,6 +119,7 @@ def lib():
         L.btas_apsp_squaring.argtypes = [P, I, I, P, I, P, I, U, ctypes.POINTER(I)]
         L.btas_apsp_num_steps.argtypes = [I]
         L.btas_apsp_squaring_noalloc.argtypes = [P, I, I, P, I, P, I, U, ctypes.POINTER(I)]
+        L.btas_apsp_last_packed16.argtypes = [P]
         IP = ctypes.POINTER(I)
         PP = ctypes.POINTER(P)
         L.btas_apsp_squaring_batched.argtypes = [P, I, I, IP, PP, IP, PP, IP, U]
@@ -506,6 +507,14 @@ def apsp_noalloc(W, out, early_exit=False, check_neg_cycle=False, return_steps=T
     st = h.check(lib().btas_apsp_squaring_noalloc(h.ptr, _dt(W), n, pw, ldw, pd, ldd, flags, sp),
                  allow=(OK, WARN_NEG_CYCLE))
     return out, (steps.value if sp is not None else None), st
+
+
+def apsp_last_packed16(handle=None) -> bool:
+    """Whether the handle's last APSP call that returned its step count ran
+    the single-launch solve on packed 16-bit distances."""
+    import torch
+    h = handle if handle is not None else default_handle(torch.cuda.current_device())
+    return bool(lib().btas_apsp_last_packed16(h.ptr))
 
 
 def floyd_warshall(W, out=None, check_neg_cycle=False, handle=None):

@@ -266,6 +266,8 @@ const char* btas_last_error(btas_handle_t h) { return h ? h->last_error.c_str() 
 
 int btas_apsp_num_steps(int n) { return btas::apsp_steps(n); }
 
+int btas_apsp_last_packed16(btas_handle_t h) { return h ? h->last_packed16 : 0; }
+
 btas_status_t btas_create(btas_handle_t* out, int device) {
     if (!out) return BTAS_ERR_INVALID_ARG;
     *out = nullptr;
@@ -535,6 +537,7 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
     if (!h) return BTAS_ERR_INVALID_ARG;
     if (btas_status_t l = begin_call(h, fn); l != BTAS_OK) return l;
     if (steps_out) *steps_out = 0;
+    h->last_packed16 = 0;
     if (!dt_ok(dt)) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 2 (dtype=%d) unknown", fn, (int)dt);
     if (n < 0) return fail(h, BTAS_ERR_INVALID_ARG, "%s: argument 3 (n=%d) < 0", fn, n);
     if (ldw < (n > 1 ? n : 1))
@@ -552,8 +555,9 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
     if (fixed && (flags & BTAS_APSP_GRAPH))
         return fail(h, BTAS_ERR_INVALID_ARG, "%s: GRAPH needs allocations (graph capture); not "
                     "available here", fn);
-    // The handle's (or the fixed) workspace: the n x n partner.
-    const size_t need = (size_t)n * n * 4;
+    // The handle's (or the fixed) workspace: the n x n partner, and for the
+    // single-launch solve of an int32 graph room for its packed 16-bit mode.
+    const size_t need = n <= btas::RESIDENT_MAX_N ? btas::resident_ws_bytes(dt, n) : (size_t)n * n * 4;
     if (fixed && (need + 255) / 256 * 256 > fixed->bytes)
         return fail(h, BTAS_ERR_INVALID_ARG,
                     "%s: argument 3 (n=%d) exceeds the fixed workspace (%zu bytes: n <= %d)", fn,
@@ -611,11 +615,23 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
         // One cooperative launch: init, every squaring and (early exit) the
         // stop decision on the device; the host reads the step count only if
         // asked for it.
+        // The barrier words carry the launch's epoch: they are cleared only
+        // before the first launch and when the count restarts.
         int* rf = h->dflags + FLAG_RESIDENT;
-        e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
-        if (e != hipSuccess) return device_fail(h, fn, e);
+        if (h->resident_epoch == 0 || h->resident_epoch >= (1u << 24) - 1) {
+            e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+            h->resident_epoch = 0;
+        }
+        const unsigned epoch = ++h->resident_epoch;
+        // BTAS_U16=1 lets int32 graphs that pass its gate run the packed
+        // 16-bit mode (same bits; measured slower than the int32 squarings
+        // at n=256, where panel-load and barrier latency, not bytes or
+        // instructions, set the time).
+        const char* u16_env = getenv("BTAS_U16");
         e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, ws, T, early, rf, h->hlatch,
-                                       h->num_cus, h->spin_limit, h->stream);
+                                       h->num_cus, h->spin_limit, u16_env && u16_env[0] == '1',
+                                       epoch, h->stream);
         if (e != hipSuccess && !(flags & BTAS_APSP_SINGLE_LAUNCH)) {
             // Chosen automatically and refused (its workgroups cannot all be
             // resident): one launch per squaring instead.
@@ -630,11 +646,12 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
             if (steps_out) {
                 btas_status_t st = sync_flags(h, fn, FLAG_RESIDENT + 2);
                 if (st != BTAS_OK) return st;
-                if (h->hflags[FLAG_RESIDENT] != 0) {  // a barrier wait timed out: D is not valid
+                if (h->hflags[FLAG_RESIDENT] == (int)epoch) {  // a barrier wait timed out: D is not valid
                     __atomic_store_n(h->hlatch, 0, __ATOMIC_RELEASE);  // reported here
                     return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
                 }
-                steps = h->hflags[FLAG_RESIDENT + 1];
+                steps = h->hflags[FLAG_RESIDENT + 1] & (btas::RESIDENT_PACKED16_BIT - 1);
+                h->last_packed16 = (h->hflags[FLAG_RESIDENT + 1] & btas::RESIDENT_PACKED16_BIT) != 0;
             }
         }
     }

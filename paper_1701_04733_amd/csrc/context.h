@@ -55,6 +55,8 @@ struct btas_ctx {
     int* hlatch = nullptr;
     int spin_limit = 1 << 20;            // polls per device-wide barrier wait
     void* scratch = nullptr;             // this device's fixed no-allocation workspace
+    int last_packed16 = 0;               // the last read single-launch solve ran 16-bit lanes
+    unsigned resident_epoch = 0;         // tag of the last single-launch solve's barrier words
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
     std::unique_ptr<btas::FwBatchPlan, btas::FwBatchPlanDeleter> fw_batch_plan;  // last batched FW plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan

@@ -94,10 +94,14 @@ hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst
 // matrices in LDS; larger n: a cooperative launch with a device-wide barrier
 // between squarings, ping-ponging between D and ws (n x n, leading
 // dimension n).  The result ends in D.  flags (device, 2 + 2 *
-// RESIDENT_MAX_GRID words, zero at launch): [0] set on a barrier timeout,
-// [1] <- the number of squarings run, [2..] the barrier's arrival words.
+// RESIDENT_MAX_GRID words): [0] <- epoch on a barrier timeout, [1] <- the
+// number of squarings run, [2..] the barrier's arrival words, tagged with
+// epoch (1 .. 2^24 - 1, larger than the tag of every word already there:
+// zero the words before the first epoch and whenever the count restarts).
 // latch: a pinned host word also set to 1 on a barrier timeout (never
-// cleared by the kernel).  num_cus: compute units of the device; spin_limit:
+// cleared by the kernel).  allow_u16 (int32, 64 < n): square in the packed
+// 16-bit mode when the weights pass its gate (checked on the device; ws
+// then needs resident_ws_bytes).  num_cus: compute units of the device; spin_limit:
 // polls per barrier wait before giving up (negative: every wait reports a
 // timeout at once, for tests of the error path).
 constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
@@ -109,6 +113,13 @@ constexpr int RESIDENT_MAX_GRID = 1024;  // (500 / 16 rounded up)^2 tiles
 constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 1;
 constexpr int AUTO_SINGLE_LAUNCH_N = 256;
 size_t resident_lds_bytes(int n);
+// Bytes of `ws` a single-launch solve uses: the n x n int32/fp32 partner and,
+// for int32 graphs that take the cooperative launch (64 < n <= RESIDENT_MAX_N),
+// two n x round_up(n, 8) matrices of 16-bit distances for the packed mode.
+size_t resident_ws_bytes(int dt, int n);
+// Set in flags[1] (beside the step count) by a solve that ran the packed
+// 16-bit mode.
+constexpr int RESIDENT_PACKED16_BIT = 1 << 16;
 // Fixed workspace of the no-allocation APSP entry point (per GPU): the
 // ping-pong partner (n*n*4 bytes, so n <= NOALLOC_MAX_N) and, in what is left,
 // split-K partial products.
@@ -119,7 +130,8 @@ static_assert((size_t)NOALLOC_MAX_N * NOALLOC_MAX_N * 4 <= NOALLOC_SCRATCH_BYTES
               "NOALLOC_MAX_N is the largest n whose partner matrix fits");
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
                                 void* ws, int T, bool early, int* flags, int* latch,
-                                int num_cus, int spin_limit, hipStream_t s);
+                                int num_cus, int spin_limit, bool allow_u16, unsigned epoch,
+                                hipStream_t s);
 // Blocked Floyd-Warshall in place on D (n x n, leading dimension ld), which
 // holds I (+) W: pivot blocks of fw_block_size() vertices, three launches per
 // block (diagonal block, its block-row and block-column, the rest).

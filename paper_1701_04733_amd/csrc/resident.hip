@@ -30,8 +30,11 @@
 // come in two sets, used by barriers of odd and even b: a workgroup can only
 // arrive at barrier b + 2, and overwrite its word of barrier b, after every
 // workgroup has arrived at b + 1, that is after every poll of barrier b has
-// ended, so the bit read there is always the one of barrier b.  The caller
-// zeroes the words before each launch.  The launch is cooperative, so every
+// ended, so the bit read there is always the one of barrier b.  Each launch
+// carries an epoch (a per-handle launch count, below 2^24) in the high bits
+// of its words, so the words a previous launch left behind read as "not
+// arrived" and nothing has to be cleared between launches; the host clears
+// them only when the count wraps.  The launch is cooperative, so every
 // workgroup is resident and the barrier cannot wait on one that has not
 // started; each wait is still bounded and, when the bound is hit, the kernel
 // records an error and runs to its end so that no wave is left spinning.
@@ -44,6 +47,7 @@
 #include "kernels.h"
 #include "semiring.h"
 #include "flat_index.h"
+#include "lds_solve.h"
 
 namespace btas {
 
@@ -67,10 +71,47 @@ struct ResidentArgs {
     long ld0;
     T* buf1;          // the handle's workspace, leading dimension n
     long ld1;
-    int* flags;       // [0] error, [1] steps executed
+    int* flags;       // [0] epoch of a launch that timed out, [1] steps executed
     unsigned* arrive; // two sets of RESIDENT_MAX_GRID arrival words
+    unsigned epoch;   // this launch's tag in the arrival words, 1 .. 2^24 - 1
     int* latch;       // pinned host word, set with flags[0] on a timeout
+    // Packed 16-bit mode (int32 only): gate_max >= 0 enables it for graphs
+    // whose finite off-diagonal weights lie in [0, gate_max] with no negative
+    // diagonal entry; u16[0..1] are two n x ld16 matrices of 16-bit distances.
+    int gate_max;
+    int ld16;
+    uint16_t* u16[2];
 };
+
+// ---- packed 16-bit mode ------------------------------------------------
+// An int32 graph whose weights are non-negative and at most gate_max =
+// floor(65534 / (2 (n - 1))) is squared on 16-bit distances, two per 32-bit
+// register: v_pk_add_u16 with clamp forms two terms, v_pk_min_u16 folds
+// them (Sec. I semirings on 16-bit lanes).  Exact: every finite entry of
+// every D_t is the length of a simple path (non-negative weights: dropping
+// a cycle never lengthens a walk), so it is at most (n - 1) * gate_max and
+// every sum of two finite entries is at most 65534; any sum that involves
+// the absent value 0xFFFF clamps to 0xFFFF, which is again absent.  The
+// output is mapped back to int32 (0xFFFF -> BTAS_I32_INF): the same bits as
+// the int32 squarings, with half the bytes per panel load and one VALU
+// instruction per term.
+using u16x2 = uint16_t __attribute__((ext_vector_type(2)));
+constexpr uint16_t U16_ABSENT = 0xFFFF;
+
+__device__ __forceinline__ uint32_t pk_add_sat(uint32_t x, uint32_t y) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, x),
+                                                                      __builtin_bit_cast(u16x2, y)));
+}
+__device__ __forceinline__ uint32_t pk_min(uint32_t x, uint32_t y) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, x),
+                                                                  __builtin_bit_cast(u16x2, y)));
+}
+// Absent in the halves whose column index (2 kp, 2 kp + 1) is >= n.
+__device__ __forceinline__ uint32_t mask_pair(uint32_t v, int k_lo, int n) {
+    if (k_lo + 1 >= n) v |= 0xFFFF0000u;
+    if (k_lo >= n) v |= 0x0000FFFFu;
+    return v;
+}
 
 // Device-scope loads and stores (coherent across XCDs without cache flushes).
 template <typename T>
@@ -84,8 +125,8 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
 
 // A barrier wait hit its bound: the device flag for a caller that reads the
 // step count, and the handle's pinned host word for one that does not.
-__device__ __forceinline__ void report_timeout(int* err, int* latch) {
-    st_dev(err, 1);
+__device__ __forceinline__ void report_timeout(int* err, int* latch, unsigned epoch) {
+    st_dev(err, (int)epoch);
     __hip_atomic_store(latch, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -95,13 +136,14 @@ __device__ __forceinline__ void report_timeout(int* err, int* latch) {
 // (at once when spin_limit < 0) the timeout is reported and the result is
 // incomplete.
 __device__ int grid_barrier(unsigned* arrive, unsigned b, int changed, int* err, int* latch,
-                            int spin_limit) {
+                            int spin_limit, unsigned epoch) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are performed
     const int mine = __syncthreads_or(changed);
     unsigned* words = arrive + (b & 1) * RESIDENT_MAX_GRID;
-    if (threadIdx.x == 0) st_dev(words + blockIdx.x, 2 * b | (mine ? 1u : 0u));
+    const unsigned tag = epoch << 8 | b << 1;  // b < 128: at most T + 2 barriers
+    if (threadIdx.x == 0) st_dev(words + blockIdx.x, tag | (mine ? 1u : 0u));
     if (spin_limit < 0) {
-        if (threadIdx.x == 0) report_timeout(err, latch);
+        if (threadIdx.x == 0) report_timeout(err, latch, epoch);
         return mine;
     }
     int any = 0;
@@ -110,17 +152,115 @@ __device__ int grid_barrier(unsigned* arrive, unsigned b, int changed, int* err,
         any = 0;
         for (unsigned i = threadIdx.x; i < gridDim.x; i += RNT) {
             const unsigned w = ld_dev(words + i);
-            ok &= w >= 2 * b;
+            ok &= w >= tag;
             any |= w & 1;
         }
         if (__syncthreads_and(ok)) break;
         if (polls >= spin_limit) {
-            if (threadIdx.x == 0) report_timeout(err, latch);
+            if (threadIdx.x == 0) report_timeout(err, latch, epoch);
             break;
         }
         __builtin_amdgcn_s_sleep(1);
     }
     return __syncthreads_or(any);
+}
+
+// The squarings of the 16-bit mode, then D <- the result as int32.  D_0 is
+// in u16[0]; every workgroup has passed barrier bno - 1.
+__device__ void solve_u16(const ResidentArgs<int32_t>& a, unsigned char* smem, unsigned bno) {
+    const int n = a.n, tid = threadIdx.x;
+    const int kpad = (n + 7) & ~7;           // k padded to 8 (one 16-byte LDS read)
+    const int kh = kpad / 2;                 // 32-bit pairs per staged row
+    const int ls16 = kpad + 8;               // LDS row stride (16-byte aligned rows)
+    uint16_t* As = reinterpret_cast<uint16_t*>(smem);  // [RT][ls16]: rows m0.. of D_{t-1}
+    uint16_t* Bt = As + RT * ls16;                       // [RT][ls16]: columns n0.., transposed
+    const int nt = (n + RT - 1) / RT;
+    const int r = tid / RT, c = tid % RT;
+    const long ld16 = a.ld16;
+    int cur = 0, steps = 0;
+    for (int t = 1; t <= a.nsq; ++t) {
+        const uint16_t* src = a.u16[cur];
+        uint16_t* dst = a.u16[cur ^ 1];
+        bool changed = false;
+        for (int tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
+            const int m0 = (tile / nt) * RT, n0 = (tile % nt) * RT;
+            // Rows m0..m0+15 as pairs along k, and columns n0..n0+15 as pairs
+            // of adjacent columns at one k (split into the transposed panel).
+            constexpr int PB16 = 8;
+            for (int e0 = 0; e0 < RT * kh; e0 += RNT * PB16) {
+                uint32_t va[PB16], vb[PB16];
+#pragma unroll
+                for (int u = 0; u < PB16; ++u) {
+                    const int e = e0 + u * RNT + tid;
+                    const int rr = e / kh, kp = e - rr * kh;
+                    const int kb = e / (RT / 2), cp = e - kb * (RT / 2);
+                    const int col = n0 + 2 * cp;
+                    va[u] = (e < RT * kh && m0 + rr < n)
+                                ? mask_pair(ld_dev(reinterpret_cast<const uint32_t*>(
+                                                src + (long)(m0 + rr) * ld16) + kp), 2 * kp, n)
+                                : 0xFFFFFFFFu;
+                    vb[u] = (e < RT * kh && kb < n && col < n)
+                                ? mask_pair(ld_dev(reinterpret_cast<const uint32_t*>(
+                                                src + (long)kb * ld16 + col)), col, n)
+                                : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int u = 0; u < PB16; ++u) {
+                    const int e = e0 + u * RNT + tid;
+                    if (e < RT * kh) {
+                        const int rr = e / kh, kp = e - rr * kh;
+                        const int kb = e / (RT / 2), cp = e - kb * (RT / 2);
+                        reinterpret_cast<uint32_t*>(As + rr * ls16)[kp] = va[u];
+                        Bt[(2 * cp) * ls16 + kb] = (uint16_t)(vb[u] & 0xFFFFu);
+                        Bt[(2 * cp + 1) * ls16 + kb] = (uint16_t)(vb[u] >> 16);
+                    }
+                }
+            }
+            __syncthreads();
+            // Eight k per pair of 16-byte LDS reads: four packed adds (two
+            // terms each) and four packed mins into two accumulators.
+            uint32_t acc0 = 0xFFFFFFFFu, acc1 = 0xFFFFFFFFu;
+            const uint32_t* ar = reinterpret_cast<const uint32_t*>(As + r * ls16);
+            const uint32_t* bc = reinterpret_cast<const uint32_t*>(Bt + c * ls16);
+#pragma unroll 4
+            for (int k2 = 0; k2 < kh; k2 += 4) {
+                const v4<uint32_t> x = *reinterpret_cast<const v4<uint32_t>*>(ar + k2);
+                const v4<uint32_t> y = *reinterpret_cast<const v4<uint32_t>*>(bc + k2);
+                acc0 = pk_min(acc0, pk_add_sat(x[0], y[0]));
+                acc1 = pk_min(acc1, pk_add_sat(x[1], y[1]));
+                acc0 = pk_min(acc0, pk_add_sat(x[2], y[2]));
+                acc1 = pk_min(acc1, pk_add_sat(x[3], y[3]));
+            }
+            const uint32_t m2 = pk_min(acc0, acc1);
+            const uint32_t lo = m2 & 0xFFFFu, hi = m2 >> 16;
+            const int row = m0 + r, col = n0 + c;
+            const uint32_t old = col < n ? As[r * ls16 + col] : U16_ABSENT;
+            const uint32_t acc = lo < hi ? lo : hi;
+            const uint32_t nv = acc < old ? acc : old;
+            changed |= row < n && col < n && nv != old;
+            // lanes c and c + 1 (adjacent) store one 32-bit pair; a pair whose
+            // second column is n writes into the row padding, never read as
+            // data (masked when staged)
+            const uint32_t nb = (uint32_t)__shfl_down((int)nv, 1);
+            if ((c & 1) == 0 && row < n && col < n)
+                st_dev(reinterpret_cast<uint32_t*>(dst + (long)row * ld16 + col), nv | (nb << 16));
+            __syncthreads();  // LDS is reloaded for the next tile
+        }
+        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.latch, a.spin_limit, a.epoch);
+        cur ^= 1;
+        steps = t;
+        if (a.early && !any) break;
+    }
+    // D <- the 16-bit result as int32
+    const long total = (long)n * n;
+    const long gthreads = (long)gridDim.x * RNT;
+    for (long e = (long)blockIdx.x * RNT + tid; e < total; e += gthreads) {
+        long i, j;
+        flat_to_rc(e, n, total, i, j);
+        const uint16_t v = ld_dev(a.u16[cur] + i * ld16 + j);
+        a.buf0[i * a.ld0 + j] = v == U16_ABSENT ? BTAS_I32_INF : (int32_t)v;
+    }
+    if (blockIdx.x == 0 && tid == 0) a.flags[1] = steps | RESIDENT_PACKED16_BIT;
 }
 
 template <typename T>
@@ -135,6 +275,10 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
     int cur = a.cur0;
 
     // D_0 = I (+) W (the diagonal gets min(W_ii, 0)); in place when W is D.
+    // With the 16-bit mode enabled, also a 16-bit copy of D_0 and the gate:
+    // the first barrier's OR tells every workgroup whether some entry falls
+    // outside it.
+    bool bad = false;
     {
         T* D0 = cur ? a.buf1 : a.buf0;
         const long ld0 = cur ? a.ld1 : a.ld0;
@@ -144,10 +288,25 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
             T w = a.W[i * a.ldw + j];
             if (i == j && w > (T)0) w = (T)0;
             st_dev(D0 + i * ld0 + j, w);
+            if constexpr (std::is_same_v<T, int32_t>) {
+                if (a.gate_max >= 0) {
+                    const bool absent = w == BTAS_I32_INF;
+                    bad |= !absent && (w < 0 || w > a.gate_max);
+                    st_dev(a.u16[0] + i * a.ld16 + j, absent ? U16_ABSENT : (uint16_t)w);
+                }
+            }
         }
     }
     unsigned bno = 1;
-    grid_barrier(a.arrive, bno++, 0, a.flags, a.latch, a.spin_limit);
+    const bool u16mode =
+        grid_barrier(a.arrive, bno++, bad, a.flags, a.latch, a.spin_limit, a.epoch) == 0 &&
+        a.gate_max >= 0;
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (u16mode) {
+            solve_u16(a, smem_raw, bno);
+            return;
+        }
+    }
 
     const int nt = (n + RT - 1) / RT;
     const int kpad = (n + 7) & ~7;
@@ -216,7 +375,7 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
             }
             __syncthreads();  // LDS is reloaded for the next tile
         }
-        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.latch, a.spin_limit);
+        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.latch, a.spin_limit, a.epoch);
         cur ^= 1;
         steps = t;
         if (a.early && !any) break;
@@ -236,8 +395,18 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
 template <typename T>
 hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void* ws, int T_,
                         bool early, int* flags, int* latch, int num_cus, int spin_limit,
-                        hipStream_t s) {
+                        bool allow_u16, unsigned epoch, hipStream_t s) {
     ResidentArgs<T> a;
+    a.gate_max = -1;
+    a.ld16 = (n + 7) & ~7;
+    a.u16[0] = a.u16[1] = nullptr;
+    if (std::is_same_v<T, int32_t> && allow_u16 && n >= 2) {
+        a.gate_max = 65534 / (2 * (n - 1));
+        const size_t part = ((size_t)n * n * 4 + 255) / 256 * 256;
+        const size_t half = ((size_t)n * a.ld16 * 2 + 255) / 256 * 256;
+        a.u16[0] = reinterpret_cast<uint16_t*>((char*)ws + part);
+        a.u16[1] = reinterpret_cast<uint16_t*>((char*)ws + part + half);
+    }
     a.n = n;
     a.nsq = T_;
     a.early = early ? 1 : 0;
@@ -254,6 +423,7 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
     a.flags = flags;
     a.arrive = reinterpret_cast<unsigned*>(flags + 2);
     a.latch = latch;
+    a.epoch = epoch;
     const size_t lds = resident_lds_bytes(n);
     // Workgroups per CU depend only on the LDS size (k padded to 8): the
     // occupancy query runs once per size, not on every call.
@@ -278,82 +448,31 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
 
 // Graphs of at most 64 vertices: the whole solve in one workgroup, both
 // ping-pong matrices in LDS, a workgroup barrier between squarings (no
-// device-wide one).  Lane j of wave w computes column j of rows w, w+16,
-// w+32, w+48: per four k it reads the column's four entries once and each
-// row's four entries as one 16-byte broadcast read.  The early-exit decision
-// is the OR of the workgroup's change bits.  The same terms and the same
-// per-output mapping of int32 sums as the other squaring kernels, so the
-// same bits.
-constexpr int LDS_SOLVE_MAX_N = 64;
-constexpr int LDS_SOLVE_NT = 1024;
-constexpr int LDS_SOLVE_LS = LDS_SOLVE_MAX_N + 4;  // row stride: 16-byte aligned rows
-
+// device-wide one).
 template <typename T>
 __global__ __launch_bounds__(LDS_SOLVE_NT) void apsp_lds_kernel(int n, const T* __restrict__ W, long ldw,
                                                                 T* D, long ldd, int nsq, int early,
                                                                 int* flags) {
-    using R = Ring<BTAS_MIN_PLUS, T>;
-    __shared__ __align__(16) T buf[2][LDS_SOLVE_MAX_N * LDS_SOLVE_LS];
-    const int tid = threadIdx.x;
-    // both buffers absent outside n x n, so that k runs to n rounded up to 4
-    for (int e = tid; e < 2 * LDS_SOLVE_MAX_N * LDS_SOLVE_LS; e += LDS_SOLVE_NT) (&buf[0][0])[e] = R::absent();
-    __syncthreads();
-    for (int o = tid; o < n * n; o += LDS_SOLVE_NT) {
-        const int i = o / n, j = o - i * n;
-        T w = W[(long)i * ldw + j];
-        if (i == j && w > (T)0) w = (T)0;
-        buf[0][i * LDS_SOLVE_LS + j] = w;
-    }
-    __syncthreads();
-    const int j = tid & 63, ib = tid >> 6;
-    const int n4 = (n + 3) & ~3;
-    int cur = 0, steps = 0;
-    for (int t = 1; t <= nsq; ++t) {
-        const T* S = buf[cur];
-        T* Dn = buf[cur ^ 1];
-        T acc[4][2];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = R::absent();
-        for (int k = 0; k < n4; k += 4) {
-            const T b0 = S[k * LDS_SOLVE_LS + j], b1 = S[(k + 1) * LDS_SOLVE_LS + j];
-            const T b2 = S[(k + 2) * LDS_SOLVE_LS + j], b3 = S[(k + 3) * LDS_SOLVE_LS + j];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const v4<T> a = *reinterpret_cast<const v4<T>*>(S + (ib + 16 * r) * LDS_SOLVE_LS + k);
-                acc[r][0] = R::add3(acc[r][0], R::mul(a[0], b0), R::mul(a[1], b1));
-                acc[r][1] = R::add3(acc[r][1], R::mul(a[2], b2), R::mul(a[3], b3));
-            }
-        }
-        bool changed = false;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = ib + 16 * r;
-            if (i < n && j < n) {
-                const T old = S[i * LDS_SOLVE_LS + j];
-                const T nv = R::add(old, R::finish(R::add(acc[r][0], acc[r][1])));
-                changed |= bits_of(nv) != bits_of(old);
-                Dn[i * LDS_SOLVE_LS + j] = nv;
-            }
-        }
-        const int any = __syncthreads_or(changed);  // also: Dn complete before it is read
-        cur ^= 1;
-        steps = t;
-        if (early && !any) break;
-    }
-    for (int o = tid; o < n * n; o += LDS_SOLVE_NT) {
-        const int i = o / n, jj = o - i * n;
-        D[(long)i * ldd + jj] = buf[cur][i * LDS_SOLVE_LS + jj];
-    }
-    if (tid == 0) flags[1] = steps;
+    __shared__ __align__(16) LdsSolveBuffers<T> sm;
+    const int steps = lds_solve_graph<T>(n, W, ldw, D, ldd, nsq, early, sm);
+    if (threadIdx.x == 0) flags[1] = steps;
 }
 
 }  // namespace
 
 size_t resident_lds_bytes(int n) { return (size_t)2 * RT * (((n + 7) & ~7) + 4) * 4; }
 
+size_t resident_ws_bytes(int dt, int n) {
+    const size_t part = ((size_t)n * n * 4 + 255) / 256 * 256;
+    if (dt != BTAS_INT32 || n <= 64 || n > RESIDENT_MAX_N) return part;
+    const size_t half = ((size_t)n * ((n + 7) & ~7) * 2 + 255) / 256 * 256;
+    return part + 2 * half;
+}
+
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
                                 void* ws, int T, bool early, int* flags, int* latch,
-                                int num_cus, int spin_limit, hipStream_t s) {
+                                int num_cus, int spin_limit, bool allow_u16, unsigned epoch,
+                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (n <= LDS_SOLVE_MAX_N) {
         if (dt == BTAS_FLOAT32)
@@ -366,9 +485,9 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
     }
     if (dt == BTAS_FLOAT32)
         return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, flags, latch, num_cus,
-                                   spin_limit, s);
+                                   spin_limit, false, epoch, s);
     return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, flags, latch, num_cus,
-                                 spin_limit, s);
+                                 spin_limit, allow_u16, epoch, s);
 }
 
 }  // namespace btas

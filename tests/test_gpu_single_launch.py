@@ -190,3 +190,94 @@ def test_single_launch_barrier_timeout_is_reported(dev, monkeypatch, return_step
     finally:
         h.close()
 
+
+def _u16_graph(n, seed, wmax, deg=4.0, zero_frac=0.1):
+    """int32 ER digraph with weights in [0, wmax] (some zero-weight edges)."""
+    g = wl.rng(seed)
+    W = np.full((n, n), wl.I32_INF, dtype=np.int32)
+    mask = g.random((n, n)) < min(1.0, deg / max(n - 1, 1))
+    w = g.integers(0, wmax, size=(n, n), endpoint=True).astype(np.int32)
+    w[g.random((n, n)) < zero_frac] = 0
+    W[mask] = w[mask]
+    np.fill_diagonal(W, 0)
+    return W
+
+
+def _gate(n):
+    return 65534 // (2 * (n - 1))
+
+
+@pytest.mark.parametrize("early", [False, True])
+@pytest.mark.parametrize("n", [65, 100, 129, 200, 255, 256, 301, 500])
+def test_single_launch_packed16_matches_oracle(dev, n, early, monkeypatch):
+    """With BTAS_U16=1, int32 graphs whose weights pass the 16-bit gate run the
+    packed mode (v_pk_add_u16 clamp + v_pk_min_u16) and give the oracle's
+    bits; without it the same call takes the int32 squarings, same bits."""
+    import paper_1701_04733_amd as btas
+    W = _u16_graph(n, 500 + n, _gate(n))
+    want, wsteps, _ = oracle.apsp(W, early_exit=early)
+    monkeypatch.setenv("BTAS_U16", "1")
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True, early_exit=early)
+    assert btas.apsp_last_packed16()
+    assert steps == wsteps and np.array_equal(D.cpu().numpy(), want), f"n={n} early={early}"
+    monkeypatch.delenv("BTAS_U16")
+    D2, steps2, _ = btas.apsp(_dev(W, dev), single_launch=True, early_exit=early)
+    assert not btas.apsp_last_packed16()
+    assert steps2 == wsteps and np.array_equal(D2.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("n", [80, 256])
+def test_single_launch_packed16_sums_at_the_limit(dev, n, monkeypatch):
+    """A directed cycle whose every edge weighs the gate's maximum: distances
+    reach (n-1) * gate and sums of two reach 2 (n-1) gate <= 65534, the top
+    of the 16-bit range below the absent value; plus one unreachable vertex
+    (absent rows and columns)."""
+    import paper_1701_04733_amd as btas
+    g = _gate(n)
+    W = np.full((n, n), wl.I32_INF, dtype=np.int32)
+    m = n - 1                                  # vertex n-1 is isolated
+    for i in range(m):
+        W[i, (i + 1) % m] = g
+    np.fill_diagonal(W, 0)
+    monkeypatch.setenv("BTAS_U16", "1")
+    want, wsteps, _ = oracle.apsp(W)
+    assert want.max(where=want != wl.I32_INF, initial=0) == (m - 1) * g
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True)
+    assert btas.apsp_last_packed16()
+    assert steps == wsteps and np.array_equal(D.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("case", ["above_gate", "negative_edge", "negative_diagonal"])
+def test_single_launch_packed16_gate_rejects(dev, case, monkeypatch):
+    """One weight outside the gate keeps the whole graph on the int32
+    squarings (decided on the device), with the oracle's bits."""
+    import paper_1701_04733_amd as btas
+    n = 200
+    W = _u16_graph(n, 77, _gate(n))
+    if case == "above_gate":
+        W[5, 17] = _gate(n) + 1
+    elif case == "negative_edge":
+        W[5, 17] = -1
+    else:
+        W[9, 9] = -3
+    monkeypatch.setenv("BTAS_U16", "1")
+    want, wsteps, _ = oracle.apsp(W)
+    D, steps, _ = btas.apsp(_dev(W, dev), single_launch=True)
+    assert not btas.apsp_last_packed16()
+    assert steps == wsteps and np.array_equal(D.cpu().numpy(), want)
+
+
+def test_small_workload_packed16_opt_in(dev, monkeypatch):
+    """The n=256 latency workload (weights U{1..100}) passes the gate
+    (floor(65534/510) = 128): the 16-bit mode with BTAS_U16=1, the int32
+    squarings by default, the oracle's bits either way."""
+    import paper_1701_04733_amd as btas
+    W = wl.er_digraph_i32(256, 0.05, 1, 100, seed=1)
+    want, _, _ = oracle.apsp(W)
+    D, steps, _ = btas.apsp(_dev(W, dev))
+    assert not btas.apsp_last_packed16() and steps == 8
+    assert np.array_equal(D.cpu().numpy(), want)
+    monkeypatch.setenv("BTAS_U16", "1")
+    D, steps, _ = btas.apsp(_dev(W, dev))
+    assert btas.apsp_last_packed16() and steps == 8
+    assert np.array_equal(D.cpu().numpy(), want)
