@@ -321,6 +321,9 @@ btas_status_t btas_destroy(btas_handle_t h) {
     if (h->apsp_exec) (void)hipGraphExecDestroy(h->apsp_exec);
     if (h->apsp_graph) (void)hipGraphDestroy(h->apsp_graph);
     if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+    if (h->fork_stream) (void)hipStreamDestroy(h->fork_stream);
+    if (h->fork_event) (void)hipEventDestroy(h->fork_event);
+    if (h->join_event) (void)hipEventDestroy(h->join_event);
     if (h->ws) (void)hipFree(h->ws);
     if (h->sp_ws) (void)hipFree(h->sp_ws);
     if (h->skws) (void)hipFree(h->skws);

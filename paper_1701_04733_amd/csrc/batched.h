@@ -237,6 +237,20 @@ inline int copy_blocks_for(int n) {
     return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
 }
 hipError_t launch_clear_ints(int* p, int count, hipStream_t s);
+
+// Graphs of at most BATCH_LDS_MAX_N vertices can be solved whole, one
+// workgroup each, with both ping-pong matrices in LDS: straight from the
+// caller's W to the caller's D, no internal buffers and no grid-wide launch
+// boundary between squarings (opt-in, BTAS_BATCH_LDS=1).
+constexpr int BATCH_LDS_MAX_N = 64;
+struct BatchSmall {
+    int n, T;
+    long ldw, ldd;
+    const void* W;
+    void* D;
+};
+hipError_t launch_batched_lds_solve(int dt, const BatchSmall* jobs, int njobs, bool early,
+                                    hipStream_t s);
 // D (n x n, leading dimension ld) <- I (+) W for a COO edge list W given by
 // device arrays rows/cols/w of length nnz (indices already range-checked);
 // duplicate edges keep the smallest weight.

@@ -48,6 +48,11 @@ struct BatchPlan {
     double terms = 0;                     // sum over graphs of T(n) * n^3
     int family = 0;                       // squaring kernel: 0 block, 1 wave, 2 direct
     int* d_changed = nullptr;             // early exit: changed[s * ngraphs + g] for squaring s
+    BatchSmall* d_small = nullptr;        // graphs solved whole in LDS, one workgroup each
+    int nsmall = 0;
+    bool early = false;
+    int nflags = 0;                       // early exit: entries of d_changed
+    bool direct = false;                  // no captured graph: launched in order on every call
 };
 
 void destroy_batch_plan(BatchPlan* p) {
@@ -55,7 +60,8 @@ void destroy_batch_plan(BatchPlan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     for (void* q : {(void*)p->d_graphs, (void*)p->d_items, (void*)p->d_init, (void*)p->d_out,
-                    (void*)p->d_maxabs, (void*)p->d_block_job, (void*)p->d_changed, p->ws})
+                    (void*)p->d_maxabs, (void*)p->d_block_job, (void*)p->d_changed,
+                    (void*)p->d_small, p->ws})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -87,10 +93,12 @@ void append_items(std::vector<BatchItem>& items, int graph_slot, int n, int shap
         items.push_back({graph_slot, t.m0, t.n0, t.kind, step, 0});
 }
 
+// An empty table still gets a small allocation (kernels take its address)
+// but nothing is copied into it.
 btas_status_t upload(btas_handle_t h, const char* fn, void** dst, const void* src, size_t bytes) {
-    if (bytes == 0) bytes = 16;
-    if (hipMalloc(dst, bytes) != hipSuccess)
+    if (hipMalloc(dst, bytes > 0 ? bytes : 16) != hipSuccess)
         return fail(h, BTAS_ERR_OOM, "%s: cannot allocate %zu bytes of descriptors", fn, bytes);
+    if (bytes == 0) return BTAS_OK;
     hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
 }
@@ -176,6 +184,55 @@ btas_status_t time_bucket(btas_handle_t h, const char* fn, int dt, BatchPlan* p,
     return BTAS_OK;
 }
 
+// The launch sequence of a plan on stream s: (int32) max |w| per graph,
+// then D_0 = I (+) W into the internal buffers, the squaring launches and the
+// copy-out; with fork, the small graphs' whole solves on a second stream
+// forked from s and joined back to it (so that, captured, they form a branch
+// of the graph), else on s first.
+hipError_t enqueue_batch(btas_handle_t h, const BatchPlan* p, hipStream_t s, bool fork) {
+    hipError_t e = hipSuccess;
+    const int ng = p->njobs, blocks = p->init_blocks;
+    if (p->nsmall > 0) {
+        if (fork) {
+            e = hipEventRecord(h->fork_event, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(h->fork_stream, h->fork_event, 0);
+            if (e == hipSuccess)
+                e = launch_batched_lds_solve(p->dt, p->d_small, p->nsmall, p->early, h->fork_stream);
+            if (e == hipSuccess) e = hipEventRecord(h->join_event, h->fork_stream);
+        } else {
+            e = launch_batched_lds_solve(p->dt, p->d_small, p->nsmall, p->early, s);
+        }
+    }
+    // int32: max |w| per graph first, so that graphs in the binary32-exact
+    // range are stored (and squared) as binary32 with no per-element
+    // conversions in the squarings.
+    const bool i32 = p->dt == BTAS_INT32;
+    if (e == hipSuccess && i32) e = launch_clear_ints(p->d_maxabs, std::max(ng, 1), s);
+    if (e == hipSuccess && i32)
+        e = launch_grouped_maxabs(p->d_graphs, p->d_init, ng, blocks, p->d_maxabs, s, p->d_block_job);
+    if (e == hipSuccess)
+        e = launch_grouped_init(p->dt, p->d_graphs, p->d_init, ng, blocks, i32 ? p->d_maxabs : nullptr,
+                                s, i32, p->d_block_job);
+    // early exit: per squaring and graph, whether it changed D; an item
+    // whose graph did not change at the previous squaring is skipped
+    if (e == hipSuccess && p->nflags > 0) e = launch_clear_ints(p->d_changed, p->nflags, s);
+    for (size_t t = 0; t < p->step_off.size() && e == hipSuccess; ++t)
+        e = launch_grouped_step(p->dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
+                                i32 ? p->d_maxabs : nullptr, p->d_changed, s, p->family, i32,
+                                p->nflags > 0 ? ng : 0);
+    if (e == hipSuccess)
+        e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, s, i32 ? p->d_maxabs : nullptr,
+                                    p->d_block_job);
+    if (e == hipSuccess && fork && p->nsmall > 0) e = hipStreamWaitEvent(s, h->join_event, 0);
+    return e;
+}
+
+// Run a built plan on the handle's stream: replay its captured graph, or
+// (BTAS_BATCH_GRAPH=0 when it was built) issue its launches in order.
+hipError_t run_batch(btas_handle_t h, const BatchPlan* p) {
+    return p->direct ? enqueue_batch(h, p, h->stream, false) : hipGraphLaunch(p->exec, h->stream);
+}
+
 }  // namespace
 }  // namespace btas
 
@@ -210,7 +267,7 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         // the arguments of the current plan (every argument is in the key),
         // checked when it was built: replay it
         DeviceGuard g(h->device);
-        const hipError_t e = hipGraphLaunch(h->batch_plan->exec, h->stream);
+        const hipError_t e = run_batch(h, h->batch_plan.get());
         return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
     }
     std::vector<Span> dspans;
@@ -250,10 +307,30 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         p->key = key;
         p->dt = dt;
         p->count = count;
-        // Order graphs: decreasing T, then decreasing n; drop n == 0.
+        // With BTAS_BATCH_LDS=1, graphs of at most BATCH_LDS_MAX_N vertices
+        // are solved whole in LDS by one workgroup each, on a branch of the
+        // captured graph (same bits; measured slower on the 4096-graph
+        // workload: those 1024-thread workgroups, bound by LDS bandwidth,
+        // take compute units from the squaring launches, which handle the
+        // small graphs' few tiles cheaply).  The rest, ordered by decreasing
+        // T, then decreasing n; n == 0 dropped.
+        const char* lds_env = getenv("BTAS_BATCH_LDS");
+        const bool lds_small = lds_env && lds_env[0] == '1';
         std::vector<HostGraph> hg;
-        for (int i = 0; i < count; ++i)
-            if (n[i] > 0) hg.push_back({i, n[i], apsp_steps(n[i]), padded_edge(n[i])});
+        std::vector<BatchSmall> small;
+        for (int i = 0; i < count; ++i) {
+            if (n[i] <= 0) continue;
+            if (lds_small && n[i] <= BATCH_LDS_MAX_N) {
+                small.push_back({n[i], apsp_steps(n[i]), (long)ldw[i], (long)ldd[i], W[i], D[i]});
+                p->terms += (double)apsp_steps(n[i]) * n[i] * (double)n[i] * n[i];
+            } else {
+                hg.push_back({i, n[i], apsp_steps(n[i]), padded_edge(n[i])});
+            }
+        }
+        // larger graphs first: their workgroups start before the short ones
+        std::stable_sort(small.begin(), small.end(),
+                         [](const BatchSmall& a, const BatchSmall& b) { return a.n > b.n; });
+        p->nsmall = (int)small.size();
         std::stable_sort(hg.begin(), hg.end(), [](const HostGraph& a, const HostGraph& b) {
             return a.T != b.T ? a.T > b.T : a.n > b.n;
         });
@@ -370,45 +447,42 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         if (st != BTAS_OK) return st;
         st = upload(h, fn, (void**)&p->d_init, init.data(), sizeof(BatchCopy) * ng);
         if (st == BTAS_OK) st = upload(h, fn, (void**)&p->d_out, out.data(), sizeof(BatchCopy) * ng);
+        if (st == BTAS_OK && p->nsmall > 0)
+            st = upload(h, fn, (void**)&p->d_small, small.data(), sizeof(BatchSmall) * p->nsmall);
         if (st != BTAS_OK) return st;
-
-        // Capture the whole solve.
-        e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return device_fail(h, fn, e);
-        // int32: max |w| per graph first, so that graphs in the binary32-exact
-        // range are stored (and squared) as binary32 with no per-element
-        // conversions in the squarings.
-        const bool i32 = dt == BTAS_INT32;
-        if (i32) e = launch_clear_ints(p->d_maxabs, std::max(ng, 1), h->aux_stream);
-        if (e == hipSuccess && i32)
-            e = launch_grouped_maxabs(p->d_graphs, p->d_init, ng, blocks, p->d_maxabs, h->aux_stream,
-                                      p->d_block_job);
-        if (e == hipSuccess)
-            e = launch_grouped_init(dt, p->d_graphs, p->d_init, ng, blocks, i32 ? p->d_maxabs : nullptr,
-                                    h->aux_stream, i32, p->d_block_job);
-        // early exit: per squaring and graph, whether it changed D; an item
-        // whose graph did not change at the previous squaring is skipped
-        if (e == hipSuccess && nflags > 0) e = launch_clear_ints(p->d_changed, nflags, h->aux_stream);
-        for (int t = 0; t < Tmax && e == hipSuccess; ++t)
-            e = launch_grouped_step(dt, p->d_graphs, p->d_items + p->step_off[t], p->step_cnt[t],
-                                    i32 ? p->d_maxabs : nullptr, p->d_changed, h->aux_stream, p->family,
-                                    i32, nflags > 0 ? ng : 0);
-        if (e == hipSuccess)
-            e = launch_grouped_copy_out(p->d_graphs, p->d_out, ng, blocks, h->aux_stream,
-                                        i32 ? p->d_maxabs : nullptr, p->d_block_job);
-        hipGraph_t graph = nullptr;
-        hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return device_fail(h, fn, e != hipSuccess ? e : e2);
+        if (p->nsmall > 0 && !h->fork_stream) {
+            e = hipStreamCreateWithFlags(&h->fork_stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming);
+            if (e != hipSuccess) return device_fail(h, fn, e);
         }
-        p->graph = graph;
-        e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return device_fail(h, fn, e);
+
+        p->early = early;
+        p->nflags = nflags;
+        // Capture the whole solve (the small graphs' solves as a branch of
+        // the captured graph), unless BTAS_BATCH_GRAPH=0 asks for the same
+        // launches issued in order on every call (for tools that cannot
+        // follow graph launches, such as counter collection).
+        const char* graph_env = getenv("BTAS_BATCH_GRAPH");
+        p->direct = graph_env && graph_env[0] == '0';
+        if (!p->direct) {
+            e = hipStreamBeginCapture(h->aux_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+            e = enqueue_batch(h, p.get(), h->aux_stream, true);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(h->aux_stream, &graph);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return device_fail(h, fn, e != hipSuccess ? e : e2);
+            }
+            p->graph = graph;
+            e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return device_fail(h, fn, e);
+        }
         h->batch_plan = std::move(p);
         plan = h->batch_plan.get();
     }
-    e = hipGraphLaunch(plan->exec, h->stream);
+    e = run_batch(h, plan);
     return e == hipSuccess ? BTAS_OK : device_fail(h, fn, e);
 }
 
@@ -417,7 +491,8 @@ extern "C" btas_status_t btas_batched_plan_info(btas_handle_t h, int* num_launch
     if (!h) return BTAS_ERR_INVALID_ARG;
     const BatchPlan* p = h->batch_plan.get();
     if (!p) return fail(h, BTAS_ERR_INVALID_ARG, "btas_batched_plan_info: no batched plan yet");
-    if (num_launches) *num_launches = (int)p->step_cnt.size() + (p->dt == BTAS_INT32 ? 4 : 2);
+    if (num_launches)
+        *num_launches = (int)p->step_cnt.size() + (p->dt == BTAS_INT32 ? 4 : 2) + (p->nsmall > 0 ? 1 : 0);
     if (total_terms) *total_terms = p->terms;
     return BTAS_OK;
 }

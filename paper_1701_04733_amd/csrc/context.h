@@ -64,6 +64,9 @@ struct btas_ctx {
     std::map<std::tuple<int, int, int>, btas::BucketTiming> tile_timing;
     void* sp_ws = nullptr;               // sparse squarings: row counts, row pointers, CSR
     size_t sp_bytes = 0;
+    hipStream_t fork_stream = nullptr;   // owned: second branch of a captured batched solve
+    hipEvent_t fork_event = nullptr;     // fork / join of that branch
+    hipEvent_t join_event = nullptr;
     hipGraph_t apsp_graph = nullptr;     // last captured single-solve graph (BTAS_APSP_GRAPH)
     hipGraphExec_t apsp_exec = nullptr;
     uint64_t apsp_key = 0;

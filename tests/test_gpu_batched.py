@@ -229,3 +229,83 @@ def test_batched_early_exit_full_config_equals_fixed(dev):
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(fixed, early)):
         assert torch.equal(a, b), f"graph {i} (n={Ws[i].shape[0]})"
+
+
+@pytest.mark.parametrize("dt", ["i32", "f32"])
+@pytest.mark.parametrize("early", [False, True])
+def test_batched_small_graphs_in_lds(dev, dt, early, monkeypatch):
+    """With BTAS_BATCH_LDS=1, graphs of at most 64 vertices are solved whole
+    by one workgroup each, on a branch of the captured graph beside the
+    squaring launches of the larger ones: the bits equal the oracle's and
+    those of the default plan (small graphs inside the grid-wide launches); a
+    batch of small graphs only (no grid-wide launch at all), in place, and
+    replays of the captured graph give the same bits."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = _mixed_graphs(dt, 40, seed=11, lo=1, hi=140)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    monkeypatch.setenv("BTAS_BATCH_LDS", "1")
+    h1 = btas.Handle(0)
+    h1.bind_stream()
+    D1 = btas.BatchedAPSP(tW, handle=h1, early_exit=early).run()
+    monkeypatch.delenv("BTAS_BATCH_LDS")
+    h0 = btas.Handle(0)
+    h0.bind_stream()
+    D0 = btas.BatchedAPSP(tW, handle=h0, early_exit=early).run()
+    torch.cuda.synchronize()
+    for W, a, b in zip(Ws, D1, D0):
+        assert np.array_equal(_bits(a.cpu().numpy()), _bits(b.cpu().numpy())), f"n={W.shape[0]}"
+        if W.shape[0] <= 64:
+            want, _, _ = oracle.apsp(W, early_exit=early)
+            assert np.array_equal(_bits(a.cpu().numpy()), _bits(want)), f"n={W.shape[0]}"
+    # small graphs only, solved in place, replayed three times
+    small = [w for w in Ws if w.shape[0] <= 64]
+    tS = [torch.from_numpy(w).to(dev) for w in small]
+    monkeypatch.setenv("BTAS_BATCH_LDS", "1")
+    runner = btas.BatchedAPSP(tS, Ds=tS, handle=h1, early_exit=early)
+    runner.run()                                   # plans with the LDS branch
+    monkeypatch.delenv("BTAS_BATCH_LDS")
+    for rep in range(3):
+        for t, w in zip(tS, small):
+            t.copy_(torch.from_numpy(w))
+        runner.run()
+        torch.cuda.synchronize()
+        for t, w in zip(tS, small):
+            want, _, _ = oracle.apsp(w, early_exit=early)
+            assert np.array_equal(_bits(t.cpu().numpy()), _bits(want)), f"replay {rep} n={w.shape[0]}"
+    # graphs needing no squaring only (n <= 2), inside the grid-wide path:
+    # empty work lists
+    tiny = [w for w in Ws if w.shape[0] <= 2] or [np.zeros((1, 1), Ws[0].dtype)]
+    tT = [torch.from_numpy(w).to(dev) for w in tiny]
+    DT = btas.BatchedAPSP(tT, handle=h0, early_exit=early).run()
+    torch.cuda.synchronize()
+    for w, d in zip(tiny, DT):
+        want, _, _ = oracle.apsp(w)
+        assert np.array_equal(_bits(d.cpu().numpy()), _bits(want))
+    h0.close()
+    h1.close()
+
+
+@pytest.mark.parametrize("early", [False, True])
+def test_batched_uncaptured_plan_same_bits(dev, early, monkeypatch):
+    """BTAS_BATCH_GRAPH=0 issues the plan's launches in order on every call
+    instead of replaying a captured graph: the same bits, call after call."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    Ws = _mixed_graphs("i32", 30, seed=21, lo=1, hi=300)
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    want = [d.cpu().numpy() for d in btas.BatchedAPSP(tW, early_exit=early).run()]
+    monkeypatch.setenv("BTAS_BATCH_GRAPH", "0")
+    h = btas.Handle(0)
+    h.bind_stream()
+    r = btas.BatchedAPSP(tW, handle=h, early_exit=early)
+    for _ in range(2):
+        for D in r.Ds:
+            D.fill_(0)
+        Ds = r.run()
+        torch.cuda.synchronize()
+        for a, b in zip(Ds, want):
+            assert np.array_equal(_bits(a.cpu().numpy()), _bits(b))
+    h.close()
