@@ -11,13 +11,17 @@
 // as that product's and K is unique.
 //
 // A 64x64 output tile per 256-thread workgroup, 4x4 outputs per thread, k in
-// blocks of 8 staged through LDS.  Each k-block is first reduced per output
-// with three-way min/max (the cost of the value-only product); only an output
-// whose block extreme strictly beats its running best searches the block
-// again, branch-free, for the first index attaining it.  The running best of
-// one output improves in about log(k) blocks for unordered data; a wave
-// searches a slot when any of its 64 lanes needs it, which short blocks keep
-// rare (blocks of 8 and 4 measured equal at 8192^3, 16 slower).
+// blocks of 16 staged through LDS.  Each k-block is reduced per output with
+// three-way min/max (the cost of the value-only product); an output whose
+// block extreme strictly beats its running best takes it and remembers the
+// block (a compare and two selects per output and block).  The index search
+// is deferred: after the k loop each output rereads, from global memory, the
+// 16 terms of the one block that holds its final value and takes the first
+// index attaining it.  Ties across blocks keep the earliest block (strict
+// comparison), ties inside it the earliest index, so the witness is the
+// smallest p, as with a search inside the loop, which measured 2.9 VALU
+// instructions per term against the 1.5 of the value product: a wave had to
+// search a block whenever any of its 64 lanes improved there.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -29,7 +33,7 @@ namespace btas {
 
 namespace {
 
-constexpr int WT_BM = 64, WT_BN = 64, WT_BK = 8;
+constexpr int WT_BM = 64, WT_BN = 64, WT_BK = 16;
 constexpr int WT_NT = 256;
 constexpr int WT_TM = 4, WT_TN = 4;
 constexpr int WT_VW = WT_BM * WT_BK / WT_NT;  // staged elements per thread and operand
@@ -121,13 +125,13 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
     };
 
     T acc[WT_TM][WT_TN];
-    int idx[WT_TM][WT_TN];
+    int blk[WT_TM][WT_TN];  // k-block where acc was first attained, -1 while absent
 #pragma unroll
     for (int r = 0; r < WT_TM; ++r)
 #pragma unroll
         for (int c = 0; c < WT_TN; ++c) {
             acc[r][c] = R::absent();
-            idx[r][c] = -1;
+            blk[r][c] = -1;
         }
 
     const int nkb = (a.k + WT_BK - 1) / WT_BK;
@@ -166,29 +170,16 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
                     bm[r][c] = R::add3(bm[r][c], R::mul(av0[r], bv0[c]), R::mul(av1[r], bv1[c]));
         }
 
-        // outputs whose block extreme strictly beats the running best: find
-        // the first index in the block that attains it
+        // outputs whose block extreme strictly beats the running best take
+        // it and remember the block
 #pragma unroll
         for (int r = 0; r < WT_TM; ++r)
 #pragma unroll
             for (int c = 0; c < WT_TN; ++c) {
                 const T v = R::finish(bm[r][c]);
-                if (better<SR>(v, acc[r][c])) {
-                    // every term of the block, last to first, so the first
-                    // match is the one kept; no dependent LDS round trips
-                    int first = 0;
-                    T sf = bm[r][c];
-#pragma unroll
-                    for (int kk = WT_BK - 1; kk >= 0; --kk) {
-                        const T s = R::mul(As[kk][ty * WT_TM + r], Bs[kk][tx * WT_TN + c]);
-                        if (s == bm[r][c]) {
-                            first = kk;
-                            sf = s;
-                        }
-                    }
-                    acc[r][c] = sf;
-                    idx[r][c] = k0 + first;
-                }
+                const bool imp = better<SR>(v, acc[r][c]);
+                acc[r][c] = imp ? v : acc[r][c];
+                blk[r][c] = imp ? kb : blk[r][c];
             }
     }
 
@@ -200,14 +191,33 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
         for (int c = 0; c < WT_TN; ++c) {
             const int j = n0 + tx * WT_TN + c;
             if (j >= a.n) continue;
+            bool store;
             if constexpr (SUCC) {
-                a.K[(long)i * a.ldk + j] = i == j ? i : idx[r][c];
+                store = i != j;
+                if (i == j) a.K[(long)i * a.ldk + j] = i;
             } else {
-                const T cold = a.C[(long)i * a.ldc + j];
-                if (idx[r][c] >= 0 && better<SR>(acc[r][c], cold)) {
-                    a.C[(long)i * a.ldc + j] = acc[r][c];
-                    a.K[(long)i * a.ldk + j] = idx[r][c];
+                store = blk[r][c] >= 0 && better<SR>(acc[r][c], a.C[(long)i * a.ldc + j]);
+            }
+            if (!store) continue;
+            // the first index of the remembered block whose term equals the
+            // value (a finite value is the raw block extreme, which one of the
+            // block's terms attains)
+            int first = -1;
+            if (blk[r][c] >= 0) {
+                const int p0 = blk[r][c] * WT_BK;
+                for (int q = WT_BK - 1; q >= 0; --q) {
+                    const int p = p0 + q;
+                    if (p >= a.k) continue;
+                    T x = a.A[(long)i * a.lda + p];
+                    if (SUCC && i == p) x = R::absent();
+                    if (R::mul(x, a.B[(long)p * a.ldb + j]) == acc[r][c]) first = p;
                 }
+            }
+            if constexpr (SUCC) {
+                a.K[(long)i * a.ldk + j] = first;
+            } else {
+                a.C[(long)i * a.ldc + j] = acc[r][c];
+                a.K[(long)i * a.ldk + j] = first;
             }
         }
     }
