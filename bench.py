@@ -52,7 +52,7 @@ def parse():
                    help="rows of the 8192^3 min-plus fp32 product timed on the oracle")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the APSP workloads (small, large, batched, served)")
-    p.add_argument("--extras", default="level12,apsp_small,apsp_large,witness,maxplus,batched,served",
+    p.add_argument("--extras", default="level12,int32_wide,apsp_small,apsp_large,witness,maxplus,batched,served",
                    help="comma-separated subset of the extra workloads to run")
     p.add_argument("--served-count", type=int, default=500,
                    help="requests per arrival rate in the served workload (the stated "
@@ -114,9 +114,9 @@ def bench_apsp_small(dev, reps=200):
     """One APSP on an ER digraph, n=256, p=0.05, int32 weights U{1..100}, T=8:
     per-solve latency of one launch per squaring (init + 8 split-K squarings),
     of the same sequence captured as one hipGraph launch, of the whole solve
-    as one cooperative kernel (fixed T, the default at this size, and with
-    the early-exit test on the device), and of the batched path with a
-    single graph."""
+    as one cooperative kernel (fixed T, the default at this size; with the
+    early-exit test on the device; and on packed 16-bit distances, which
+    these weights allow), and of the batched path with a single graph."""
     import numpy as np
     import torch
 
@@ -126,22 +126,32 @@ def bench_apsp_small(dev, reps=200):
     D = torch.empty_like(W)
     g = btas.BatchedAPSP([W], [D])
     out = {"workload": "APSP n=256 ER p=0.05 int32 U{1..100}, T=8 squarings"}
-    def per_squaring():
-        prev = os.environ.get("BTAS_SINGLE_LAUNCH")
-        os.environ["BTAS_SINGLE_LAUNCH"] = "0"
+    def with_env(var, val, fn):
+        prev = os.environ.get(var)
+        os.environ[var] = val
         try:
-            btas.apsp(W, out=D, return_steps=False)
+            fn()
         finally:
             if prev is None:
-                del os.environ["BTAS_SINGLE_LAUNCH"]
+                del os.environ[var]
             else:
-                os.environ["BTAS_SINGLE_LAUNCH"] = prev
+                os.environ[var] = prev
 
+    def per_squaring():
+        with_env("BTAS_SINGLE_LAUNCH", "0", lambda: btas.apsp(W, out=D, return_steps=False))
+
+    def single_packed16():
+        # the same single launch on packed 16-bit distances (opt-in)
+        with_env("BTAS_U16", "1", lambda: btas.apsp(W, out=D, return_steps=False, single_launch=True))
+
+    with_env("BTAS_U16", "1", lambda: btas.apsp(W, out=D, single_launch=True))
+    out["packed16_gate_passed"] = btas.apsp_last_packed16()
     for name, fn in (("per_squaring", per_squaring),
                      ("graph", lambda: btas.apsp(W, out=D, return_steps=False, graph=True)),
                      ("single_launch", lambda: btas.apsp(W, out=D, return_steps=False, single_launch=True)),
                      ("single_launch_early_exit",
                       lambda: btas.apsp(W, out=D, return_steps=False, single_launch=True, early_exit=True)),
+                     ("single_launch_packed16", single_packed16),
                      ("batched_one_graph", g.run)):
         for _ in range(10):
             fn()
@@ -356,6 +366,34 @@ def bench_batched(dev, reps=5):
         ms.append(e0.elapsed_time(e1))
     em = float(np.median(ms))
     same_early = all(torch.equal(a, b) for a, b in zip(re.Ds, outs))
+    # the same plan with the graphs of <= 64 vertices solved whole in LDS on
+    # their own branch of the captured graph (opt-in) instead of inside the
+    # grid-wide squaring launches
+    prev = os.environ.get("BTAS_BATCH_LDS")
+    os.environ["BTAS_BATCH_LDS"] = "1"
+    try:
+        h0 = btas.Handle(0)
+        h0.bind_stream()
+        rg = btas.BatchedAPSP(Ws, handle=h0)
+        rg.run()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = _events()
+            e0.record()
+            rg.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        gm = float(np.median(ms))
+        same_grid = all(torch.equal(a, b) for a, b in zip(rg.Ds, outs))
+        del rg
+        h0.close()
+    finally:
+        if prev is None:
+            del os.environ["BTAS_BATCH_LDS"]
+        else:
+            os.environ["BTAS_BATCH_LDS"] = prev
     # the same graphs by batched blocked Floyd-Warshall (int32: the same bits)
     fw = btas.FloydWarshallBatched(Ws)
     fw.run()
@@ -373,6 +411,8 @@ def bench_batched(dev, reps=5):
     return {"workload": "batched APSP, 4096 graphs, n log-uniform [16,512], p=8/n, int32 U{1..1000}",
             "early_exit": {"batched_ms": round(em, 3), "batched_solves_per_s": round(4096 / (em / 1e3), 1),
                            "bit_identical_to_plain": same_early},
+            "small_graphs_whole_in_lds": {"batched_ms": round(gm, 3),
+                                          "bit_identical_to_plain": same_grid},
             "floyd_warshall": {"batched_ms": round(fm, 3), "batched_solves_per_s": round(4096 / (fm / 1e3), 1),
                                "bit_identical_to_plain": same_fw},
             "batched_ms": round(bm, 3), "batched_solves_per_s": round(4096 / (bm / 1e3), 1),
@@ -381,6 +421,75 @@ def bench_batched(dev, reps=5):
             "graph_kernel_launches": info["launches"],
             "plain_ms": round(plain * 1e3, 3), "plain_solves_per_s": round(4096 / plain, 1),
             "speedup_vs_plain": round(plain * 1e3 / bm, 2), "bit_identical_to_plain": same}
+
+
+def bench_int32_wide(dev, reps=5):
+    """int32 min-plus products at 8192^3 beyond the binary32-exact range (the
+    clamped integer adds): entries uniform in [0, 2^28] and in [0, 2^29 - 1]
+    (the whole contract), 10% absent, C = INF."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    out = {"workload": "int32 min-plus 8192^3 beyond 2^23 (clamped integer adds)"}
+    for name, hi in (("values_le_2^28", 1 << 28), ("values_le_2^29-1", (1 << 29) - 1)):
+        ops = []
+        for seed in (2, 3):
+            g = wl.rng(seed)
+            X = g.integers(0, hi, size=(N, N), endpoint=True, dtype=np.int32)
+            X[g.random((N, N), dtype=np.float32) < 0.1] = wl.I32_INF
+            ops.append(torch.from_numpy(X).to(dev))
+            del X
+        C0 = torch.full((N, N), wl.I32_INF, dtype=torch.int32, device=dev)
+        btas.tropical_gemm(ops[0], ops[1], C0.clone())
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            C = C0.clone()
+            e0, e1 = _events()
+            e0.record()
+            btas.tropical_gemm(ops[0], ops[1], C)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        gops = 2.0 * N ** 3 / (ms / 1e3) / 1e9
+        out[name] = {"ms": round(ms, 3), "Gop/s": round(gops, 1),
+                     "frac_valu_peak": round(gops / 1e3 / PEAK_TOPS, 4)}
+        del ops, C0, C
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched_squaring(dev, reps=3):
+    """The 4096-graph batched squaring alone (fixed T, then early exit), with
+    no other solver in the process: the workload for counter collection
+    (run it with BTAS_BATCH_GRAPH=0 so that the launches are issued in order
+    instead of from a captured graph)."""
+    import numpy as np
+    import torch
+
+    import paper_1701_04733_amd as btas
+    from paper_1701_04733_amd import workloads as wl
+    Ws = [torch.from_numpy(w).to(dev) for w in wl.batched_graphs_i32(count=4096, seed=5)]
+    out = {"workload": "batched APSP squaring, 4096 graphs, n log-uniform [16,512], p=8/n, int32 U{1..1000}",
+           "captured": os.environ.get("BTAS_BATCH_GRAPH", "1") != "0"}
+    for name, early in (("fixed_T", False), ("early_exit", True)):
+        r = btas.BatchedAPSP(Ws, early_exit=early)
+        r.run()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = _events()
+            e0.record()
+            r.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        out[name] = {"batched_ms": round(float(np.median(ms)), 3)}
+        del r
+    return out
 
 
 def bench_level12(dev, reps=10):
@@ -590,6 +699,8 @@ def main():
         extras = {}
         if "level12" in want:
             extras["level12"] = bench_level12(dev)
+        if "int32_wide" in want:
+            extras["int32_wide"] = bench_int32_wide(dev)
         if "apsp_small" in want:
             extras["apsp_small"] = bench_apsp_small(dev)
         if "apsp_large" in want:
@@ -602,6 +713,8 @@ def main():
         torch.cuda.empty_cache()
         if "batched" in want:
             extras["batched"] = bench_batched(dev)
+        if "batched_squaring" in want:
+            extras["batched_squaring"] = bench_batched_squaring(dev)
         torch.cuda.empty_cache()
         if "served" in want:
             rates = [int(x) for x in args.served_rates.split(",") if x]

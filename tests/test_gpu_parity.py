@@ -395,6 +395,33 @@ def test_gemm_i32_exact_range_boundary(btas, dev, sr, edge):
     assert_same(to_np(Ct), want, f"edge={edge}")
 
 
+@pytest.mark.parametrize("sr", ["min", "max"])
+@pytest.mark.parametrize("edge", [1 << 28, (1 << 29) - 1])
+@pytest.mark.parametrize("shape", [(300, 260, 270), (130, 1000, 4100)])
+def test_gemm_i32_wide_values(btas, dev, sr, edge, shape):
+    """Beyond the binary32 range the int32 product runs on clamped integer
+    adds: operands up to the contract's 2^29 - 1 (finite sums reach
+    +-(2^30 - 2); a sum with the absent value must never win), with absent
+    rows and columns, give the oracle's bits.  The taller shape splits k."""
+    m, n, k = shape
+    g = wl.rng(edge % 997 + (sr == "max") + m)
+    A = g.integers(-edge, edge, size=(m, k), endpoint=True).astype(np.int32)
+    B = g.integers(-edge, edge, size=(k, n), endpoint=True).astype(np.int32)
+    A[0, 0], B[0, 0] = edge, edge                          # the largest finite sum
+    A[1, 0], B[0, 1] = -edge, -edge                        # the smallest
+    absent = wl.I32_INF if sr == "min" else wl.I32_NINF
+    A[g.random((m, k)) < 0.15] = absent
+    B[g.random((k, n)) < 0.15] = absent
+    A[2, :] = absent                                       # a row with no finite term
+    B[:, 3] = absent
+    A[3, :] = -edge if sr == "min" else edge               # terms that meet absent ones
+    C = wl.signed_operand((m, n), "i32", sr, seed=5, inf_frac=0.5)
+    want = oracle.gemm(sr, A, B, C)
+    Ct = to_dev(C, dev)
+    btas.tropical_gemm(to_dev(A, dev), to_dev(B, dev), Ct, semiring=sr)
+    assert_same(to_np(Ct), want, f"edge={edge}")
+
+
 def test_apsp_i32_distances_cross_exact_range(btas, dev):
     """A path graph with heavy edges: early squarings stay within +-(2^23-1),
     later ones exceed it and must switch to the integer pipeline."""
