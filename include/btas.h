@@ -89,8 +89,8 @@ btas_status_t btas_set_stream(btas_handle_t h, void *hip_stream);
 
 /* Block the host until the handle's stream has drained.  Returns
  * BTAS_ERR_DEVICE on a HIP error, or (once) when an earlier asynchronous
- * single-launch APSP solve on this handle hit a device-wide barrier timeout
- * (see BTAS_APSP_SINGLE_LAUNCH); every other entry point reports that latched
+ * single-launch APSP solve on this handle hit the bound of one of its waits
+ * on other workgroups (see BTAS_APSP_SINGLE_LAUNCH); every other entry point reports that latched
  * error too, on its next call, instead of doing its work. */
 btas_status_t btas_synchronize(btas_handle_t h);
 
@@ -178,11 +178,17 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *   BTAS_APSP_SINGLE_LAUNCH: for n <= 500, run the whole solve (init, every
  *     squaring, and with EARLY_EXIT the stop test) as one kernel launch: one
  *     workgroup with the matrices in LDS for n <= 64, else a cooperative
- *     launch with a device-wide barrier between squarings.  No per-step
+ *     launch.  When every 16x16 output tile can have a resident workgroup of
+ *     its own, squarings are ordered by the data alone: each workgroup
+ *     re-reads the entries of D_{t-1} it needs until their tags (64-bit words
+ *     of value and launch/step tag, in a tag buffer the handle allocates once,
+ *     about 6 MB) say they are current, and early exit reads one change word
+ *     per workgroup and squaring; otherwise a device-wide barrier separates
+ *     squarings.  No per-step
  *     launches and no host round trip, also with EARLY_EXIT (the host then
  *     synchronises only if steps_out is not NULL).  Larger n ignore the flag.
  *     Not combinable with GRAPH.  BTAS_ERR_DEVICE if the device cannot launch
- *     it cooperatively, or if a barrier wait timed out (D is then not
+ *     it cooperatively, or if a wait on other workgroups timed out (D is then not
  *     valid): reported by this call when steps_out is not NULL, else latched
  *     on the handle and reported by its next call or btas_synchronize.  The
  *     environment variable BTAS_TEST_SPIN_LIMIT, read by btas_create, sets
@@ -216,6 +222,9 @@ btas_status_t btas_apsp_squaring(btas_handle_t h, btas_dtype_t dt, int n,
  * shares that GPU's array: calls that may overlap in time on the same GPU
  * (other handles or streams) race and must be serialised by the caller.  The
  * array keeps the last call's contents; nothing in it has to start at zero.
+ * Without the handle's tag buffer (which this call does not allocate), a
+ * single-launch solve here orders fixed-T squarings by per-workgroup words
+ * of the row and column panels, and early exit by device-wide barriers.
  * Results are bit-identical to btas_apsp_squaring's. */
 btas_status_t btas_apsp_squaring_noalloc(btas_handle_t h, btas_dtype_t dt, int n,
                                          const void *W, int ldw, void *D, int ldd,
@@ -234,7 +243,8 @@ int btas_apsp_num_steps(int n);
  * distance then fits 15 bits and every sum of two fits 16, so the result has
  * the same bits as the int32 squarings.  It is off by default: at n=256 it
  * measured slower than the int32 squarings (the solve is bound by load and
- * barrier latency, not by bytes or instructions). */
+ * synchronisation latency, not by bytes or instructions; the packed mode
+ * keeps a device-wide barrier after its gate and between squarings). */
 int btas_apsp_last_packed16(btas_handle_t h);
 
 /* ---------------------------------------------------------------------------

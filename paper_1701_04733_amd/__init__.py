@@ -187,7 +187,8 @@ class Handle:
 
     def synchronize(self):
         """Wait for the handle's stream; raises BTAS_ERR_DEVICE if an earlier
-        asynchronous single-launch solve on this handle hit a barrier timeout."""
+        asynchronous single-launch solve on this handle timed out waiting on
+        other workgroups."""
         self.check(lib().btas_synchronize(self._h))
 
     def close(self):
@@ -461,7 +462,7 @@ def apsp(W, out=None, early_exit=False, check_neg_cycle=False, return_steps=True
     Returns (D, steps, status); status is OK or WARN_NEG_CYCLE.  With
     ``return_steps=False`` steps is None and the call stays asynchronous unless
     a flag needs the host (early exit on the per-squaring path, the
-    negative-cycle check); a device-side failure of such a call (a barrier
+    negative-cycle check); a device-side failure of such a call (a wait
     timeout of the single-launch solve) is raised by the handle's next call
     or ``synchronize()``.  ``graph`` replays a captured hipGraph of the
     fixed-T solve; ``single_launch`` runs the whole solve as one cooperative

@@ -325,6 +325,7 @@ btas_status_t btas_destroy(btas_handle_t h) {
     if (h->fork_event) (void)hipEventDestroy(h->fork_event);
     if (h->join_event) (void)hipEventDestroy(h->join_event);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->tagws) (void)hipFree(h->tagws);
     if (h->sp_ws) (void)hipFree(h->sp_ws);
     if (h->skws) (void)hipFree(h->skws);
     if (h->partials) (void)hipFree(h->partials);
@@ -620,9 +621,22 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
         // asked for it.
         // The barrier words carry the launch's epoch: they are cleared only
         // before the first launch and when the count restarts.
+        // The tag buffer of the tagged mode (the handle's own, not the
+        // caller's fixed workspace) follows the same rule.
         int* rf = h->dflags + FLAG_RESIDENT;
-        if (h->resident_epoch == 0 || h->resident_epoch >= (1u << 24) - 1) {
+        bool fresh_tags = false;
+        if (!fixed && !h->tagws) {
+            if (hipMalloc(&h->tagws, btas::resident_tag_bytes()) != hipSuccess) {
+                (void)hipGetLastError();
+                h->tagws = nullptr;  // solved without the tagged mode
+            } else {
+                fresh_tags = true;
+            }
+        }
+        if (fresh_tags || h->resident_epoch == 0 || h->resident_epoch >= (1u << 24) - 1) {
             e = btas::launch_clear_flags(rf, FLAG_RESIDENT_END - FLAG_RESIDENT, h->stream);
+            if (e == hipSuccess && h->tagws)
+                e = btas::launch_zero_words(h->tagws, btas::resident_tag_bytes() / 8, h->stream);
             if (e != hipSuccess) return device_fail(h, fn, e);
             h->resident_epoch = 0;
         }
@@ -632,7 +646,8 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
         // at n=256, where panel-load and barrier latency, not bytes or
         // instructions, set the time).
         const char* u16_env = getenv("BTAS_U16");
-        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, ws, T, early, rf, h->hlatch,
+        e = btas::launch_apsp_resident(dt, n, W, ldw, D, ldd, ws, fixed ? nullptr : h->tagws, T,
+                                       early, rf, h->hlatch,
                                        h->num_cus, h->spin_limit, u16_env && u16_env[0] == '1',
                                        epoch, h->stream);
         if (e != hipSuccess && !(flags & BTAS_APSP_SINGLE_LAUNCH)) {
@@ -649,9 +664,9 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
             if (steps_out) {
                 btas_status_t st = sync_flags(h, fn, FLAG_RESIDENT + 2);
                 if (st != BTAS_OK) return st;
-                if (h->hflags[FLAG_RESIDENT] == (int)epoch) {  // a barrier wait timed out: D is not valid
+                if (h->hflags[FLAG_RESIDENT] == (int)epoch) {  // a wait timed out: D is not valid
                     __atomic_store_n(h->hlatch, 0, __ATOMIC_RELEASE);  // reported here
-                    return fail(h, BTAS_ERR_DEVICE, "%s: device-wide barrier timed out", fn);
+                    return fail(h, BTAS_ERR_DEVICE, "%s: a wait on other workgroups timed out", fn);
                 }
                 steps = h->hflags[FLAG_RESIDENT + 1] & (btas::RESIDENT_PACKED16_BIT - 1);
                 h->last_packed16 = (h->hflags[FLAG_RESIDENT + 1] & btas::RESIDENT_PACKED16_BIT) != 0;

@@ -3,6 +3,7 @@
 // domain scan.  All are O(n^2) and HBM-bound.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "gemm_tile.h"
@@ -91,6 +92,20 @@ hipError_t launch_range_scan(int sr, int m, int n, const void* X, long ld, int* 
     else
         hipLaunchKernelGGL(range_scan_kernel<BTAS_MAX_PLUS>, g, b, 0, s, m, n, (const int32_t*)X,
                            ld, flag);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void zero_words_kernel(uint64_t* p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero_words(void* p, size_t words, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<uint64_t*>(p), words);
     return hipGetLastError();
 }
 

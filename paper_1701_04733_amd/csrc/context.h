@@ -57,6 +57,9 @@ struct btas_ctx {
     void* scratch = nullptr;             // this device's fixed no-allocation workspace
     int last_packed16 = 0;               // the last read single-launch solve ran 16-bit lanes
     unsigned resident_epoch = 0;         // tag of the last single-launch solve's barrier words
+    // Single-launch solve's tag buffer (btas::resident_tag_bytes()): written
+    // only by those launches, zeroed with the barrier words.
+    void* tagws = nullptr;
     std::unique_ptr<btas::BatchPlan, btas::BatchPlanDeleter> batch_plan;  // last batched plan
     std::unique_ptr<btas::FwBatchPlan, btas::FwBatchPlanDeleter> fw_batch_plan;  // last batched FW plan
     std::map<std::pair<int, int>, int> tile_choice;  // (dtype, size bucket) -> shape of the last plan
@@ -129,8 +132,8 @@ inline btas_status_t begin_call(btas_handle_t h, const char* fn) {
     if (h->hlatch && __atomic_load_n(h->hlatch, __ATOMIC_ACQUIRE) != 0) {
         __atomic_store_n(h->hlatch, 0, __ATOMIC_RELEASE);
         return fail(h, BTAS_ERR_DEVICE,
-                    "%s: an earlier single-launch APSP solve on this handle timed out in a "
-                    "device-wide barrier; its D is not valid", fn);
+                    "%s: an earlier single-launch APSP solve on this handle timed out "
+                    "waiting on other workgroups; its D is not valid", fn);
     }
     return BTAS_OK;
 }

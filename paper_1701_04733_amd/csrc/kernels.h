@@ -86,6 +86,8 @@ hipError_t launch_closure_init(int sr, int dt, int n, const void* W, long ldw, v
                                int* wide, hipStream_t s);
 hipError_t launch_diag_check(int sr, int dt, int n, const void* D, long ldd, int* flag,
                              hipStream_t s);
+// Zero `words` 64-bit words at p (8-byte aligned).
+hipError_t launch_zero_words(void* p, size_t words, hipStream_t s);
 // Copy an n-column, m-row matrix between leading dimensions (4-byte elements).
 hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst, long ldd,
                               hipStream_t s);
@@ -103,9 +105,16 @@ hipError_t launch_copy_matrix(int m, int n, const void* src, long lds, void* dst
 // 16-bit mode when the weights pass its gate (checked on the device; ws
 // then needs resident_ws_bytes).  num_cus: compute units of the device; spin_limit:
 // polls per barrier wait before giving up (negative: every wait reports a
-// timeout at once, for tests of the error path).
+// timeout at once, for tests of the error path).  tagws (may be null): a
+// buffer of resident_tag_bytes() that only these launches write, zeroed
+// like the arrival words; with it, a solve whose grid has one workgroup per
+// 16x16 tile runs the tagged mode (no device-wide barrier).  Without it, a
+// fixed-T solve of that shape waits per squaring for the workgroups of its
+// row and column panels only.
 constexpr int RESIDENT_MAX_N = 500;  // keeps the workgroup's LDS within 64 KB
 constexpr int RESIDENT_MAX_GRID = 1024;  // (500 / 16 rounded up)^2 tiles
+constexpr int RESIDENT_TAG_STEPS = 32;   // squarings the tagged mode's change words cover
+size_t resident_tag_bytes();
 // Up to this size the single-launch solve beats one launch per squaring on
 // MI355X (measured latency, int32 ER graphs of mean degree 12.75, fixed T:
 // n=8 23 us vs 34 us, n=64 48 vs 93 (one workgroup, n <= 64), n=129 96 vs
@@ -129,7 +138,7 @@ static_assert((size_t)NOALLOC_MAX_N * NOALLOC_MAX_N * 4 <= NOALLOC_SCRATCH_BYTES
                   (size_t)(NOALLOC_MAX_N + 1) * (NOALLOC_MAX_N + 1) * 4 > NOALLOC_SCRATCH_BYTES,
               "NOALLOC_MAX_N is the largest n whose partner matrix fits");
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
-                                void* ws, int T, bool early, int* flags, int* latch,
+                                void* ws, void* tagws, int T, bool early, int* flags, int* latch,
                                 int num_cus, int spin_limit, bool allow_u16, unsigned epoch,
                                 hipStream_t s);
 // Blocked Floyd-Warshall in place on D (n x n, leading dimension ld), which

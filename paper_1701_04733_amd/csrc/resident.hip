@@ -8,7 +8,9 @@
 //
 //   D_0 = I (+) W;  for t = 1..T:  D_t = D_{t-1} (+) D_{t-1} (.) D_{t-1}
 //
-// with a device-wide barrier between squarings.  Each workgroup owns 16x16
+// with, in the general case, a device-wide barrier between squarings (two
+// faster orderings for a grid of one workgroup per tile follow below: the
+// tagged mode and, without its buffer, the panel wait).  Each workgroup owns 16x16
 // output tiles (one output per thread, full k): it stages the tile's 16 rows
 // of D_{t-1} and its 16 columns (transposed) in LDS, folds four k per pair of
 // three-input min/max, and writes D_t to the other buffer of the ping-pong
@@ -81,6 +83,11 @@ struct ResidentArgs {
     int gate_max;
     int ld16;
     uint16_t* u16[2];
+    // Tagged mode (one tile per workgroup, a tag buffer of the handle's own):
+    // D_s as 64-bit words in tag[s % 3] (n x n), and per-squaring change
+    // words cw[s * RESIDENT_MAX_GRID + workgroup] for early exit.
+    uint64_t* tag[3];
+    uint64_t* cw;
 };
 
 // ---- packed 16-bit mode ------------------------------------------------
@@ -263,6 +270,196 @@ __device__ void solve_u16(const ResidentArgs<int32_t>& a, unsigned char* smem, u
     if (blockIdx.x == 0 && tid == 0) a.flags[1] = steps | RESIDENT_PACKED16_BIT;
 }
 
+// ---- tagged mode --------------------------------------------------------
+// One 16x16 tile per workgroup.  Every entry of D_s (s < T) is stored as one
+// 64-bit word, (epoch << 8 | s) << 32 | value bits, in buffer s mod 3 of a
+// tag buffer that only these launches write.  Squaring t loads its row and
+// column panels of D_{t-1} and loads again every word whose tag is not yet
+// that of D_{t-1}: the data says by itself that it has arrived, so nothing
+// (no flag, no wait for store completion, no barrier) separates squarings.
+// Three buffers suffice: squaring t overwrites this tile of D_{t-3}, which
+// the workgroups of the tile's row and column panel read in squaring t - 2;
+// the D_{t-1} entries just loaded were written by those same workgroups in
+// squaring t - 1, after their loads of squaring t - 2 had returned.  The
+// entry a thread owns stays in a register from squaring to squaring, and
+// the last one goes to D.
+//
+// Early exit without a barrier: each workgroup publishes one change word per
+// squaring (tagged the same way); after squaring t every workgroup reads the
+// words of squaring t - 1 of all workgroups, and if none changed, D_{t-1} is
+// the fixpoint (D_t equals it bit for bit) and all stop with the same step
+// count, t - 1, as the barrier path.  The extra squaring t is the price of
+// not waiting for the OR.
+__device__ __forceinline__ uint64_t tag_word(uint32_t tag, uint32_t bits) {
+    return (uint64_t)tag << 32 | bits;
+}
+
+template <typename T>
+__device__ __forceinline__ T word_value(uint64_t w) {
+    return __builtin_bit_cast(T, (uint32_t)w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(RNT) void apsp_tagged_kernel(ResidentArgs<T> a) {
+    using R = Ring<BTAS_MIN_PLUS, T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* As = reinterpret_cast<T*>(smem);  // [RT][ls]: rows m0.. of D_{t-1}
+    T* Bt = As + RT * a.ls;              // [RT][ls]: columns n0.. of D_{t-1}, transposed
+    const int n = a.n, tid = threadIdx.x;
+    const int nt = (n + RT - 1) / RT;
+    const int kpad = (n + 7) & ~7;
+    const int r = tid / RT, c = tid % RT;
+    const int m0 = (blockIdx.x / nt) * RT, n0 = (blockIdx.x % nt) * RT;
+    const int row = m0 + r, col = n0 + c;
+    const bool mine = row < n && col < n;
+    const uint32_t base = a.epoch << 8;
+    const uint32_t absent_bits = __builtin_bit_cast(uint32_t, R::absent());
+    int spin = a.spin_limit;
+    if (spin < 0) {
+        if (tid == 0) report_timeout(a.flags, a.latch, a.epoch);
+        spin = 0;
+    }
+
+    // D_0 = I (+) W, this tile only (W may be D: each entry is read and
+    // written by its own thread only).
+    T d = R::absent();
+    if (mine) {
+        T w = a.W[(long)row * a.ldw + col];
+        if (row == col && w > (T)0) w = (T)0;
+        d = w;
+        if (a.nsq > 0) st_dev(a.tag[0] + (long)row * n + col, tag_word(base, __builtin_bit_cast(uint32_t, w)));
+    }
+    int steps = 0;
+    for (int t = 1; t <= a.nsq; ++t) {
+        const uint64_t* src = a.tag[(t - 1) % 3];
+        const uint32_t want = base | (uint32_t)(t - 1);
+        const uint64_t pad = tag_word(want, absent_bits);
+        for (int e0 = 0; e0 < RT * kpad; e0 += RNT * PB) {
+            uint64_t va[PB], vb[PB];
+            auto load = [&](int u, bool a_side) -> uint64_t {
+                const int e = e0 + u * RNT + tid;
+                if (a_side) {
+                    const int rr = e / kpad, ka = e - rr * kpad;
+                    return (e < RT * kpad && m0 + rr < n && ka < n)
+                               ? ld_dev(src + (long)(m0 + rr) * n + ka) : pad;
+                }
+                const int kb = e / RT, cc = e - kb * RT;
+                return (e < RT * kpad && n0 + cc < n && kb < n) ? ld_dev(src + (long)kb * n + n0 + cc)
+                                                                : pad;
+            };
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                va[u] = load(u, true);
+                vb[u] = load(u, false);
+            }
+            for (int polls = 0;; ++polls) {
+                bool late = false;
+#pragma unroll
+                for (int u = 0; u < PB; ++u)
+                    late |= (uint32_t)(va[u] >> 32) != want || (uint32_t)(vb[u] >> 32) != want;
+                if (!late) break;
+                if (polls >= spin) {
+                    report_timeout(a.flags, a.latch, a.epoch);
+                    spin = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int u = 0; u < PB; ++u) {
+                    if ((uint32_t)(va[u] >> 32) != want) va[u] = load(u, true);
+                    if ((uint32_t)(vb[u] >> 32) != want) vb[u] = load(u, false);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int e = e0 + u * RNT + tid;
+                if (e < RT * kpad) {
+                    const int rr = e / kpad, ka = e - rr * kpad;
+                    const int kb = e / RT, cc = e - kb * RT;
+                    As[rr * a.ls + ka] = word_value<T>(va[u]);
+                    Bt[cc * a.ls + kb] = word_value<T>(vb[u]);
+                }
+            }
+        }
+        __syncthreads();
+        T acc0 = R::absent(), acc1 = R::absent();
+        const T* ar = As + r * a.ls;
+        const T* bc = Bt + c * a.ls;
+#pragma unroll 4
+        for (int k = 0; k < kpad; k += 8) {
+            const v4<T> x0 = *reinterpret_cast<const v4<T>*>(ar + k);
+            const v4<T> y0 = *reinterpret_cast<const v4<T>*>(bc + k);
+            const v4<T> x1 = *reinterpret_cast<const v4<T>*>(ar + k + 4);
+            const v4<T> y1 = *reinterpret_cast<const v4<T>*>(bc + k + 4);
+            acc0 = R::add3(acc0, R::mul(x0[0], y0[0]), R::mul(x0[1], y0[1]));
+            acc1 = R::add3(acc1, R::mul(x1[0], y1[0]), R::mul(x1[1], y1[1]));
+            acc0 = R::add3(acc0, R::mul(x0[2], y0[2]), R::mul(x0[3], y0[3]));
+            acc1 = R::add3(acc1, R::mul(x1[2], y1[2]), R::mul(x1[3], y1[3]));
+        }
+        const T nv = R::add(d, R::finish(R::add(acc0, acc1)));
+        const bool changed = mine && bits_of(nv) != bits_of(d);
+        d = nv;
+        steps = t;
+        if (t < a.nsq && mine)
+            st_dev(a.tag[t % 3] + (long)row * n + col, tag_word(base | (uint32_t)t, __builtin_bit_cast(uint32_t, nv)));
+        if (a.early) {
+            const int here = __syncthreads_or(changed);  // also: LDS is free for the next squaring
+            if (tid == 0)
+                st_dev(a.cw + (long)t * RESIDENT_MAX_GRID + blockIdx.x, tag_word(base | (uint32_t)t, here));
+            if (t >= 2) {
+                const uint32_t prev = base | (uint32_t)(t - 1);
+                int any = 0;
+                for (int i = tid; i < (int)gridDim.x; i += RNT) {
+                    const uint64_t* p = a.cw + (long)(t - 1) * RESIDENT_MAX_GRID + i;
+                    uint64_t w = ld_dev(p);
+                    for (int polls = 0; (uint32_t)(w >> 32) != prev; ++polls) {
+                        if (polls >= spin) {
+                            report_timeout(a.flags, a.latch, a.epoch);
+                            spin = 0;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        w = ld_dev(p);
+                    }
+                    any |= (int)(w & 1);
+                }
+                if (!__syncthreads_or(any)) {
+                    steps = t - 1;  // D_t == D_{t-1}: the fixpoint
+                    break;
+                }
+            }
+        } else {
+            __syncthreads();  // LDS is reloaded for the next squaring
+        }
+    }
+    if (mine) a.buf0[(long)row * a.ld0 + col] = d;
+    if (blockIdx.x == 0 && tid == 0) a.flags[1] = steps;
+}
+
+// Dataflow wait (fixed T, one tile per workgroup): before squaring t, wait
+// only for the workgroups that own the tiles of this tile's row panel and
+// column panel to have finished squaring t - 1 (their words, monotone within
+// a launch, reach `want`).  Those are also the only readers of this tile's
+// entries of D_{t-1}, so the overwrite of D_{t-1}'s buffer at t + 1 is safe.
+__device__ void panel_wait(const unsigned* words, unsigned want, int nt, int* err, int* latch,
+                           int spin_limit, unsigned epoch) {
+    const int I = blockIdx.x / nt, J = blockIdx.x % nt;
+    for (int polls = 0;; ++polls) {
+        int ok = 1;
+        if ((int)threadIdx.x < 2 * nt) {
+            const int src = (int)threadIdx.x < nt ? I * nt + (int)threadIdx.x
+                                                  : ((int)threadIdx.x - nt) * nt + J;
+            ok = ld_dev(words + src) >= want;
+        }
+        if (__syncthreads_and(ok)) break;
+        if (spin_limit < 0 || polls >= spin_limit) {
+            if (threadIdx.x == 0) report_timeout(err, latch, epoch);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
     using R = Ring<BTAS_MIN_PLUS, T>;
@@ -312,7 +509,12 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
     const int kpad = (n + 7) & ~7;
     const int r = tid / RT, c = tid % RT;
     int steps = 0;
+    const bool dataflow = !a.early && (int)gridDim.x == nt * nt && 2 * nt <= RNT;
+    unsigned* dwords = a.arrive;  // one word per workgroup, tags rising within the launch
     for (int t = 1; t <= a.nsq; ++t) {
+        if (dataflow && t > 1)
+            panel_wait(dwords, a.epoch << 8 | (unsigned)t << 1, nt, a.flags, a.latch, a.spin_limit,
+                       a.epoch);
         const T* src = cur ? a.buf1 : a.buf0;
         const long lds = cur ? a.ld1 : a.ld0;
         T* dst = cur ? a.buf0 : a.buf1;
@@ -375,7 +577,14 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
             }
             __syncthreads();  // LDS is reloaded for the next tile
         }
-        const int any = grid_barrier(a.arrive, bno++, changed, a.flags, a.latch, a.spin_limit, a.epoch);
+        int any = 1;
+        if (dataflow) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are performed
+            __syncthreads();
+            if (tid == 0) st_dev(dwords + blockIdx.x, a.epoch << 8 | (unsigned)(t + 1) << 1);
+        } else {
+            any = grid_barrier(a.arrive, bno++, changed, a.flags, a.latch, a.spin_limit, a.epoch);
+        }
         cur ^= 1;
         steps = t;
         if (a.early && !any) break;
@@ -393,10 +602,12 @@ __global__ __launch_bounds__(RNT) void apsp_resident_kernel(ResidentArgs<T> a) {
 }
 
 template <typename T>
-hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void* ws, int T_,
-                        bool early, int* flags, int* latch, int num_cus, int spin_limit,
+hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void* ws, void* tagws,
+                        int T_, bool early, int* flags, int* latch, int num_cus, int spin_limit,
                         bool allow_u16, unsigned epoch, hipStream_t s) {
     ResidentArgs<T> a;
+    a.tag[0] = a.tag[1] = a.tag[2] = nullptr;
+    a.cw = nullptr;
     a.gate_max = -1;
     a.ld16 = (n + 7) & ~7;
     a.u16[0] = a.u16[1] = nullptr;
@@ -427,12 +638,12 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
     const size_t lds = resident_lds_bytes(n);
     // Workgroups per CU depend only on the LDS size (k padded to 8): the
     // occupancy query runs once per size, not on every call.
+    const void* kernel = reinterpret_cast<const void*>(apsp_resident_kernel<T>);
     static std::atomic<int> per_cu_cache[RESIDENT_MAX_N / 8 + 2];
     const int slot = ((n + 7) & ~7) / 8;
     int per_cu = per_cu_cache[slot].load(std::memory_order_relaxed);
     if (per_cu == 0) {
-        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(apsp_resident_kernel<T>), RNT, lds);
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, RNT, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) return hipErrorInvalidConfiguration;
         per_cu_cache[slot].store(per_cu, std::memory_order_relaxed);
@@ -442,7 +653,28 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
     if (grid > (long)nt * nt) grid = (long)nt * nt;
     if (grid > RESIDENT_MAX_GRID) grid = RESIDENT_MAX_GRID;
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apsp_resident_kernel<T>),
+    if (tagws != nullptr && a.gate_max < 0 && T_ < RESIDENT_TAG_STEPS) {
+        // One workgroup per tile, if that many can be resident.
+        static std::atomic<int> tag_cu_cache[RESIDENT_MAX_N / 8 + 2];
+        int tag_cu = tag_cu_cache[slot].load(std::memory_order_relaxed);
+        if (tag_cu == 0) {
+            const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &tag_cu, reinterpret_cast<const void*>(apsp_tagged_kernel<T>), RNT, lds);
+            if (e != hipSuccess) return e;
+            tag_cu = tag_cu < 1 ? -1 : tag_cu;
+            tag_cu_cache[slot].store(tag_cu, std::memory_order_relaxed);
+        }
+        if ((long)tag_cu * num_cus >= (long)nt * nt && (long)nt * nt <= RESIDENT_MAX_GRID) {
+            uint64_t* tw = static_cast<uint64_t*>(tagws);
+            constexpr long region = (long)RESIDENT_MAX_N * RESIDENT_MAX_N;
+            for (int i = 0; i < 3; ++i) a.tag[i] = tw + i * region;
+            a.cw = tw + 3 * region;
+            return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apsp_tagged_kernel<T>),
+                                              dim3((unsigned)(nt * nt)), dim3(RNT), args,
+                                              (unsigned)lds, s);
+        }
+    }
+    return hipLaunchCooperativeKernel(kernel,
                                       dim3((unsigned)grid), dim3(RNT), args, (unsigned)lds, s);
 }
 
@@ -469,8 +701,12 @@ size_t resident_ws_bytes(int dt, int n) {
     return part + 2 * half;
 }
 
+size_t resident_tag_bytes() {
+    return ((size_t)3 * RESIDENT_MAX_N * RESIDENT_MAX_N + (size_t)RESIDENT_TAG_STEPS * RESIDENT_MAX_GRID) * 8;
+}
+
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
-                                void* ws, int T, bool early, int* flags, int* latch,
+                                void* ws, void* tagws, int T, bool early, int* flags, int* latch,
                                 int num_cus, int spin_limit, bool allow_u16, unsigned epoch,
                                 hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -484,9 +720,9 @@ hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D,
         return hipGetLastError();
     }
     if (dt == BTAS_FLOAT32)
-        return launch_typed<float>(n, W, ldw, D, ldd, ws, T, early, flags, latch, num_cus,
+        return launch_typed<float>(n, W, ldw, D, ldd, ws, tagws, T, early, flags, latch, num_cus,
                                    spin_limit, false, epoch, s);
-    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, T, early, flags, latch, num_cus,
+    return launch_typed<int32_t>(n, W, ldw, D, ldd, ws, tagws, T, early, flags, latch, num_cus,
                                  spin_limit, allow_u16, epoch, s);
 }
 

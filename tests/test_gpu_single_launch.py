@@ -1,8 +1,12 @@
 """APSP as one cooperative launch (BTAS_APSP_SINGLE_LAUNCH): bit-identical to
 the oracle and to the per-squaring path, with early exit decided on the
 device, in place and with padded leading dimensions, and stable over many
-launches in a row (the barrier's arrival words are cleared before each
-launch and alternate between two sets within one)."""
+launches in a row.  Sizes up to about 350 take the tagged mode (one
+workgroup per tile, squarings ordered by the launch/step tags of the data
+words, early exit from per-workgroup change words one squaring late); larger
+ones the device-wide barrier, whose arrival words alternate between two sets
+and carry the launch's epoch.  Launches of both kinds and of many sizes
+follow each other on one handle."""
 import hashlib
 import json
 import os
