@@ -14,9 +14,11 @@
 //    register tile split into 4-wide groups so that LDS reads are 128-bit.
 //  * A (BM x BK) and B (BK x BN) are staged row-major in padded LDS,
 //    double-buffered: the next k-block is fetched from HBM into registers
-//    while the current one is consumed, one barrier per block.  fp32
-//    products whose tiles are all full load the next k-block straight into
-//    LDS instead (no staging registers).
+//    while the current one is consumed, one barrier per block.  Products
+//    whose 128x128 tiles are all full load the next k-block straight into
+//    LDS instead (no staging registers): fp32, and int32 on the
+//    binary32-exact path (each lane converts the elements its own load
+//    wrote, in LDS, before the block's barrier).
 //  * Ragged m/n/k edges are filled with the absent value, which never wins
 //    the (+)-reduction, so tile boundaries need no special compute path.
 //  * Workgroup ids are remapped so that each XCD (own L2) receives a
@@ -51,9 +53,14 @@ __device__ __forceinline__ void tile_of(int bid, int nb, int nbm, int nbn, int& 
     tn = in_g / gsz;
 }
 
-template <typename Cfg, typename T, int SR, bool VEC>
+// WIDE_ONLY: the launch that follows a direct-load int32 launch; it does the
+// product only when the operands left the binary32-exact range.
+template <typename Cfg, typename T, int SR, bool VEC, bool WIDE_ONLY = false>
 __global__ __launch_bounds__(Cfg::NT) void tropical_gemm_kernel(TileArgs<T> a,
                                                                  const int* wide_in) {
+    if constexpr (WIDE_ONLY) {
+        if (*wide_in == 0) return;
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int nbm = (a.m + Cfg::BM - 1) / Cfg::BM;
     const int nbn = (a.n + Cfg::BN - 1) / Cfg::BN;
@@ -68,15 +75,21 @@ __global__ __launch_bounds__(Cfg::NT) void tropical_gemm_kernel(TileArgs<T> a,
     GemmTile<Cfg, T, T, SR, VEC>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
 }
 
-// fp32, every tile full and 16-byte aligned: direct global -> LDS loads.
-template <typename Cfg, int SR>
+// Every tile full and 16-byte aligned: direct global -> LDS loads.  fp32, or
+// int32 on the binary32-exact path (wide_in non-null: the workgroups return
+// at once when the operands left that range, and the WIDE_ONLY launch of the
+// staged kernel that follows does the product).
+template <typename Cfg, int SR, typename T = float>
 __global__ __launch_bounds__(Cfg::NT) __attribute__((amdgpu_waves_per_eu(4))) void tropical_gemm_direct_kernel(
-    TileArgs<float> a) {
+    TileArgs<T> a, const int* wide_in) {
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (*wide_in != 0) return;
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int nbm = a.m / Cfg::BM, nbn = a.n / Cfg::BN;
     int tm, tn;
     tile_of(blockIdx.x, nbm * nbn, nbm, nbn, tm, tn);
-    GemmTileDirect<Cfg, SR>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
+    GemmTileDirect<Cfg, SR, T>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
 }
 
 // Split-K: blockIdx.x = tile * S + chunk; the chunk's partial product goes to
@@ -207,11 +220,24 @@ static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
         return hipGetLastError();
     }
     dim3 grid((unsigned)nb), block(Cfg::NT);
-    if constexpr (std::is_same_v<T, float> && std::is_same_v<Cfg, CfgL>) {
-        if (vec && g.m % Cfg::BM == 0 && g.n % Cfg::BN == 0 && g.k % Cfg::BK == 0) {
-            hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR>), grid, block,
-                               (GemmTileDirect<Cfg, SR>::lds_bytes), s, a);
-            return hipGetLastError();
+    if constexpr (std::is_same_v<Cfg, CfgL>) {
+        const bool full = vec && g.m % Cfg::BM == 0 && g.n % Cfg::BN == 0 && g.k % Cfg::BK == 0;
+        if constexpr (std::is_same_v<T, float>) {
+            if (full) {
+                hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR>), grid, block,
+                                   (GemmTileDirect<Cfg, SR>::lds_bytes), s, a, nullptr);
+                return hipGetLastError();
+            }
+        } else {
+            // int32: the direct kernel runs the binary32-exact case and the
+            // staged kernel the wide one; the flag picks one on the device.
+            if (full && g.wide_in != nullptr) {
+                hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR, T>), grid, block,
+                                   (GemmTileDirect<Cfg, SR, T>::lds_bytes), s, a, g.wide_in);
+                hipLaunchKernelGGL((tropical_gemm_kernel<Cfg, T, SR, true, true>), grid, block,
+                                   Cfg::lds_bytes, s, a, g.wide_in);
+                return hipGetLastError();
+            }
         }
     }
     if (vec)

@@ -307,8 +307,18 @@ struct GemmTile {
 // consumed.  The LDS rows are therefore unpadded; with the register-row
 // mapping of GemmCfg::row_of the lanes of a wave still read A rows that start
 // in distinct banks, and B rows are read as contiguous 16-byte chunks.
-template <typename Cfg, int SR>
+//
+// int32 storage on the binary32-exact path (every finite operand within
+// +-(2^23-1)) uses the same kernel: the int32 bits land in LDS and each lane
+// turns the four elements its own load wrote into binary32 before the
+// k-block's barrier.  That conversion is a plain int-to-float of every
+// element, absent values included: an absent operand becomes -+2^31 (the
+// nearest binary32), so every term it enters has magnitude above 2^30 and
+// loses to every finite sum (|s| <= 2^24 - 2), and the epilogue maps any
+// accumulator of magnitude above 2^24 back to the absent value.
+template <typename Cfg, int SR, typename T = float>
 struct GemmTileDirect {
+    static_assert(std::is_same_v<T, float> || std::is_same_v<T, int32_t>, "fp32 or int32 storage");
     using R = Ring<SR, float>;
     static constexpr int LDA = Cfg::BK, LDB = Cfg::BN;  // unpadded LDS rows
     static constexpr int NW = Cfg::NT / 64;              // waves per workgroup
@@ -323,22 +333,55 @@ struct GemmTileDirect {
     using lds_ptr = __attribute__((address_space(3))) void*;
     using gbl_ptr = __attribute__((address_space(1))) void*;
 
-    __device__ __forceinline__ static void issue(const TileArgs<float>& a, int m0, int n0, int k0,
+    __device__ __forceinline__ static void issue(const TileArgs<T>& a, int m0, int n0, int k0,
                                                  float* As, float* Bs) {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
         for (int i = 0; i < AI; ++i) {
             const int rb = (w * AI + i) * A_ROWS;
             const int row = rb + lane / (Cfg::BK / 4), kq = lane % (Cfg::BK / 4);
-            const float* src = a.A + (long)(m0 + row) * a.lda + k0 + kq * 4;
+            const T* src = a.A + (long)(m0 + row) * a.lda + k0 + kq * 4;
             __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(As + rb * LDA), 16, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < BI; ++i) {
             const int rb = (w * BI + i) * B_ROWS;
             const int row = rb + lane / (Cfg::BN / 4), cq = lane % (Cfg::BN / 4);
-            const float* src = a.B + (long)(k0 + row) * a.ldb + n0 + cq * 4;
+            const T* src = a.B + (long)(k0 + row) * a.ldb + n0 + cq * 4;
             __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(Bs + rb * LDB), 16, 0, 0);
+        }
+    }
+
+    // int32 storage: the lanes of this wave convert, in place, the pieces their
+    // own loads wrote (lane L of an instruction wrote the 16 bytes at
+    // base + 16 L), once the wave's loads have completed.
+    __device__ __forceinline__ static void to_binary32(float* As, float* Bs) {
+        if constexpr (std::is_same_v<T, int32_t>) {
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            auto cvt = [](float* p) {
+                const v4<int32_t> x = __builtin_bit_cast(v4<int32_t>, *reinterpret_cast<v4<float>*>(p));
+                v4<float> f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) f[e] = (float)x[e];
+                *reinterpret_cast<v4<float>*>(p) = f;
+            };
+#pragma unroll
+            for (int i = 0; i < AI; ++i) cvt(As + (w * AI + i) * A_ROWS * LDA + lane * 4);
+#pragma unroll
+            for (int i = 0; i < BI; ++i) cvt(Bs + (w * BI + i) * B_ROWS * LDB + lane * 4);
+        }
+    }
+
+    // Output element from Cin and the binary32 accumulator.
+    __device__ __forceinline__ static T finish(T old, float acc, bool& wide) {
+        if constexpr (std::is_same_v<T, int32_t>) {
+            using RI = Ring<SR, int32_t>;
+            const int32_t v = __builtin_fabsf(acc) > 16777216.0f ? RI::absent() : (int32_t)acc;
+            const int32_t nv = RI::add(old, v);
+            wide |= nv != RI::absent() && (nv > FP32_EXACT_MAX || nv < -FP32_EXACT_MAX);
+            return nv;
+        } else {
+            return R::add(old, acc);
         }
     }
 
@@ -374,7 +417,7 @@ struct GemmTileDirect {
         }
     }
 
-    __device__ __forceinline__ static void run(const TileArgs<float>& a, int m0, int n0,
+    __device__ __forceinline__ static void run(const TileArgs<T>& a, int m0, int n0,
                                                unsigned char* smem) {
         float* As0 = reinterpret_cast<float*>(smem);
         float* Bs0 = As0 + Cfg::BM * LDA;
@@ -390,33 +433,37 @@ struct GemmTileDirect {
         const int nkb = a.k / Cfg::BK;
         if (nkb > 0) issue(a, m0, n0, 0, As0, Bs0);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's pieces are in LDS
+        if (nkb > 0) to_binary32(As0, Bs0);
         __syncthreads();                                   // and everyone else's
         for (int kb = 0; kb < nkb; ++kb) {
             const bool even = (kb & 1) == 0;
-            if (kb + 1 < nkb) issue(a, m0, n0, (kb + 1) * Cfg::BK, even ? As1 : As0, even ? Bs1 : Bs0);
+            const bool more = kb + 1 < nkb;
+            if (more) issue(a, m0, n0, (kb + 1) * Cfg::BK, even ? As1 : As0, even ? Bs1 : Bs0);
             compute(acc, even ? As0 : As1, even ? Bs0 : Bs1, tx, ty);
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (more) to_binary32(even ? As1 : As0, even ? Bs1 : Bs0);
             __syncthreads();
         }
         // Epilogue (every tile is interior): Cout = Cin (+) acc, changed flag.
-        bool diff = false;
+        bool diff = false, wide = false;
 #pragma unroll
         for (int r = 0; r < Cfg::TM; ++r) {
             const int row = m0 + Cfg::row_of(r, ty);
 #pragma unroll
             for (int g = 0; g < Cfg::CG; ++g) {
                 const int col = n0 + g * (Cfg::BN / Cfg::CG) + tx * 4;
-                const v4<float> old = *reinterpret_cast<const v4<float>*>(a.Cin + (long)row * a.ldci + col);
-                v4<float> nv;
+                const v4<T> old = *reinterpret_cast<const v4<T>*>(a.Cin + (long)row * a.ldci + col);
+                v4<T> nv;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    nv[e] = R::add(old[e], acc[r][g * 4 + e]);
+                    nv[e] = finish(old[e], acc[r][g * 4 + e], wide);
                     diff |= bits_of(nv[e]) != bits_of(old[e]);
                 }
-                *reinterpret_cast<v4<float>*>(a.Cout + (long)row * a.ldco + col) = nv;
+                *reinterpret_cast<v4<T>*>(a.Cout + (long)row * a.ldco + col) = nv;
             }
         }
         if (a.changed != nullptr && __any(diff) && (threadIdx.x & 63) == 0) *a.changed = 1;
+        if (a.wide_out != nullptr && __any(wide) && (threadIdx.x & 63) == 0) *a.wide_out = 1;
     }
 };
 

@@ -422,6 +422,41 @@ def test_gemm_i32_wide_values(btas, dev, sr, edge, shape):
     assert_same(to_np(Ct), want, f"edge={edge}")
 
 
+@pytest.mark.parametrize("sr", SR)
+def test_gemm_i32_full_tiles_direct_path(btas, dev, sr):
+    """int32 shapes whose 128x128 tiles are all full: operands within
+    +-(2^23-1) take the direct-load kernel (int32 bits converted to binary32
+    in LDS, absent values included), operands beyond it the integer kernel
+    launched after it; three calls in a row switch between the two on the
+    device.  Extremes, absent rows and columns, a partly absent C and padded
+    leading dimensions; every call gives the oracle's bits."""
+    torch = torch_mod()
+    m, n, k = 3200, 2688, 96                       # 525 full 128 x 128 tiles, k % 16 == 0
+    absent = wl.I32_INF if sr == "min" else wl.I32_NINF
+    for call, edge in enumerate([(1 << 23) - 1, 1 << 23, (1 << 23) - 1]):
+        g = wl.rng(300 + call + (sr == "max"))
+        A = g.integers(-edge, edge, size=(m, k), endpoint=True).astype(np.int32)
+        B = g.integers(-edge, edge, size=(k, n), endpoint=True).astype(np.int32)
+        A[0, 0], B[0, 0] = edge, edge                      # the largest finite sum
+        A[1, 0], B[0, 1] = -edge, -edge                    # the smallest
+        A[g.random((m, k)) < 0.1] = absent
+        B[g.random((k, n)) < 0.1] = absent
+        A[2, :] = absent                                   # a row with no finite term
+        B[:, 3] = absent
+        A[3, :] = -edge if sr == "min" else edge           # terms that meet absent ones
+        C = wl.signed_operand((m, n), "i32", sr, seed=6 + call, inf_frac=0.3)
+        want = oracle.gemm(sr, A, B, C)
+        Ap = torch.zeros((m, k + 4), dtype=torch.int32, device=dev)
+        Ap[:, :k] = to_dev(A, dev)
+        Bp = torch.zeros((k, n + 8), dtype=torch.int32, device=dev)
+        Bp[:, :n] = to_dev(B, dev)
+        Cp = torch.zeros((m, n + 4), dtype=torch.int32, device=dev)
+        Cp[:, :n] = to_dev(C, dev)
+        btas.tropical_gemm(Ap[:, :k], Bp[:, :n], Cp[:, :n], semiring=sr)
+        assert_same(to_np(Cp[:, :n]), want, f"{sr}/call {call}/edge={edge}")
+        assert (Cp[:, n:] == 0).all()
+
+
 def test_apsp_i32_distances_cross_exact_range(btas, dev):
     """A path graph with heavy edges: early squarings stay within +-(2^23-1),
     later ones exceed it and must switch to the integer pipeline."""
