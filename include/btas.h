@@ -193,8 +193,8 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     on the handle and reported by its next call or btas_synchronize.  The
  *     environment variable BTAS_TEST_SPIN_LIMIT, read by btas_create, sets
  *     the bound of each wait in polls (a negative value reports a timeout at
- *     every wait, for tests of this path).  Calls without GRAPH take this path for n <= 256
- *     even without the flag (it is the faster one there), unless the
+ *     every wait, for tests of this path).  Calls without GRAPH take this path
+ *     for n <= 352 (n <= 256 in btas_apsp_squaring_noalloc) even without the flag (it is the faster one there), unless the
  *     environment variable BTAS_SINGLE_LAUNCH=0 is set; such a call whose
  *     cooperative launch is refused runs one launch per squaring instead.
  * steps_out: host int receiving the number of squarings executed (may be
@@ -270,7 +270,10 @@ int btas_apsp_last_packed16(btas_handle_t h);
  * device, the captured graph) and synchronises; later calls with identical
  * arguments only launch the graph (asynchronous).  The environment variable
  * BTAS_BATCHED_TILE=128, 64, mixed, w64, wmix or w64d forces one tile shape;
- * BTAS_AUTOTUNE=0 uses a cost model instead of timing.
+ * BTAS_AUTOTUNE=0 uses a cost model instead of timing.  A batch of one or two
+ * graphs of n <= 352, whose earlier outputs do not overlap later inputs, is
+ * solved instead by one btas_apsp_squaring single launch per graph (faster
+ * at that size, same bits; no plan, unless BTAS_SINGLE_LAUNCH=0).
  */
 btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int count,
                                          const int *n, const void *const *W, const int *ldw,

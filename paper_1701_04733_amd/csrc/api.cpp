@@ -602,12 +602,15 @@ btas_status_t apsp_impl(btas_handle_t h, const char* fn, btas_dtype_t dt, int n,
         skws_bytes = h->skws_bytes;
         return true;
     };
-    // Graphs of up to 256 vertices take the single-launch solve also without
-    // the flag (it is faster there: one launch instead of one or two per
-    // squaring) unless a captured graph was asked for or BTAS_SINGLE_LAUNCH=0.
+    // Graphs of up to AUTO_SINGLE_LAUNCH_N vertices take the single-launch
+    // solve also without the flag (it is faster there: one launch instead of
+    // one or two per squaring) unless a captured graph was asked for or
+    // BTAS_SINGLE_LAUNCH=0.  Above 256 that holds for the tagged mode only,
+    // which needs the handle's tag buffer (not used with a fixed workspace).
     const char* sl_env = getenv("BTAS_SINGLE_LAUNCH");
+    const int auto_max = fixed ? btas::AUTO_SINGLE_LAUNCH_BARRIER_N : btas::AUTO_SINGLE_LAUNCH_N;
     const bool auto_single = !(sl_env && sl_env[0] == '0') && n >= btas::AUTO_SINGLE_LAUNCH_MIN_N &&
-                             n <= btas::AUTO_SINGLE_LAUNCH_N && !(flags & BTAS_APSP_GRAPH);
+                             n <= auto_max && !(flags & BTAS_APSP_GRAPH);
     bool resident =
         n <= btas::RESIDENT_MAX_N && ((flags & BTAS_APSP_SINGLE_LAUNCH) || auto_single);
     if (T > 0 && !resident && !prepare_splitk())

@@ -47,6 +47,9 @@ inline int tile_family(int kind) {
 inline bool tile_is_wave(int kind) { return tile_family(kind) == 1; }
 // Storage edge of a graph's padded buffers.
 inline int padded_edge(int n) { return (n + 63) / 64 * 64; }
+// Batches of at most this many graphs, all within the automatic single-launch
+// size, are solved one single launch per graph instead of by a batched plan.
+constexpr int BATCH_DIRECT_MAX_COUNT = 2;
 
 // One output tile of one squaring of one graph.
 struct BatchItem {

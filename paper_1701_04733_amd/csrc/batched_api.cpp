@@ -287,6 +287,31 @@ extern "C" btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_
         if (dspans[i].lo < dspans[i - 1].hi)
             return fail(h, BTAS_ERR_ALIAS, "%s: two output matrices overlap", fn);
 
+    // One or two graphs small enough for the automatic single-launch solve:
+    // that solve per graph is faster than a batched plan's dozen launches
+    // (n=256: 79 us against 233 us) and gives the same bits (early exit
+    // included); no plan is built.
+    {
+        const char* sl_env = getenv("BTAS_SINGLE_LAUNCH");
+        bool direct = count <= BATCH_DIRECT_MAX_COUNT && !(sl_env && sl_env[0] == '0');
+        for (int i = 0; i < count && direct; ++i) direct = n[i] <= AUTO_SINGLE_LAUNCH_N;
+        // Solved one after the other, so an earlier output must not overlap
+        // a later input (the batched contract reads every W first).
+        for (int i = 0; i < count && direct; ++i)
+            for (int j = i + 1; j < count && direct; ++j)
+                if (n[i] > 0 && n[j] > 0)
+                    direct = !overlap(mat_span(D[i], n[i], n[i], ldd[i]), mat_span(W[j], n[j], n[j], ldw[j]));
+        if (direct) {
+            for (int i = 0; i < count; ++i) {
+                if (n[i] == 0) continue;
+                const btas_status_t st =
+                    btas_apsp_squaring(h, dt, n[i], W[i], ldw[i], D[i], ldd[i], flags, nullptr);
+                if (st != BTAS_OK) return st;
+            }
+            return BTAS_OK;
+        }
+    }
+
     DeviceGuard guard(h->device);
 
     hipError_t e = hipSuccess;

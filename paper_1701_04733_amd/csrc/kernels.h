@@ -117,10 +117,12 @@ constexpr int RESIDENT_TAG_STEPS = 32;   // squarings the tagged mode's change w
 size_t resident_tag_bytes();
 // Up to this size the single-launch solve beats one launch per squaring on
 // MI355X (measured latency, int32 ER graphs of mean degree 12.75, fixed T:
-// n=8 23 us vs 34 us, n=64 48 vs 93 (one workgroup, n <= 64), n=129 96 vs
-// 158, n=256 128 vs 176 (cooperative), n=320 235 vs 212).
+// n=8 23 us vs 34 us, n=64 48 vs 93 (one workgroup, n <= 64); tagged mode:
+// n=129 64 vs 155, n=256 79 vs 171, n=288 132 vs 216, n=352 139 vs 240;
+// with the device-wide barrier, n=400 322 vs 251).
 constexpr int AUTO_SINGLE_LAUNCH_MIN_N = 1;
-constexpr int AUTO_SINGLE_LAUNCH_N = 256;
+constexpr int AUTO_SINGLE_LAUNCH_N = 352;
+constexpr int AUTO_SINGLE_LAUNCH_BARRIER_N = 256;  // without the tagged mode (barrier: n=320 235 vs 212)
 size_t resident_lds_bytes(int n);
 // Bytes of `ws` a single-launch solve uses: the n x n int32/fp32 partner and,
 // for int32 graphs that take the cooperative launch (64 < n <= RESIDENT_MAX_N),

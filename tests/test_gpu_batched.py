@@ -309,3 +309,44 @@ def test_batched_uncaptured_plan_same_bits(dev, early, monkeypatch):
         for a, b in zip(Ds, want):
             assert np.array_equal(_bits(a.cpu().numpy()), _bits(b))
     h.close()
+
+
+@pytest.mark.parametrize("early", [False, True])
+def test_batched_one_or_two_small_graphs(dev, early):
+    """A batch of one or two graphs of n <= 352 is solved by one single launch
+    per graph: the oracle's bits and step semantics (early exit included), in
+    place; with an earlier output overlapping a later input (allowed: the
+    batched contract reads every W first) or a larger graph, the batched plan
+    runs instead, with the same bits."""
+    import torch
+
+    import paper_1701_04733_amd as btas
+    kinds = [("i32", (256,)), ("f32", (100, 300)), ("i32", (352, 17))]
+    for dt, ns in kinds:
+        Ws = [_mixed_graphs(dt, 1, seed=60 + n, lo=n, hi=n)[0] for n in ns]
+        tW = [torch.from_numpy(w).to(dev) for w in Ws]
+        Ds = btas.apsp_batched(tW, early_exit=early)
+        torch.cuda.synchronize()
+        for W, D in zip(Ws, Ds):
+            want, _, _ = oracle.apsp(W, early_exit=early)
+            assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"{dt} n={W.shape[0]}"
+        btas.apsp_batched(tW, tW, early_exit=early)           # in place
+        torch.cuda.synchronize()
+        for W, D in zip(Ws, tW):
+            want, _, _ = oracle.apsp(W)
+            assert np.array_equal(_bits(D.cpu().numpy()), _bits(want)), f"{dt} n={W.shape[0]} in place"
+    # graph 0's output is graph 1's input buffer: every W must be read first
+    W0 = _mixed_graphs("i32", 1, seed=71, lo=200, hi=200)[0]
+    W1 = _mixed_graphs("i32", 1, seed=72, lo=200, hi=200)[0]
+    t0, t1 = torch.from_numpy(W0).to(dev), torch.from_numpy(W1).to(dev)
+    out1 = torch.empty_like(t1)
+    btas.apsp_batched([t0, t1], [t1, out1], early_exit=early)
+    torch.cuda.synchronize()
+    assert np.array_equal(t1.cpu().numpy(), oracle.apsp(W0)[0])
+    assert np.array_equal(out1.cpu().numpy(), oracle.apsp(W1)[0])
+    # above the single-launch size: the plan
+    Ws = [_mixed_graphs("i32", 1, seed=73, lo=400, hi=400)[0], W0]
+    Ds = btas.apsp_batched([torch.from_numpy(w).to(dev) for w in Ws], early_exit=early)
+    torch.cuda.synchronize()
+    for W, D in zip(Ws, Ds):
+        assert np.array_equal(D.cpu().numpy(), oracle.apsp(W)[0])

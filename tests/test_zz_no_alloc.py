@@ -31,9 +31,10 @@ def _bits(x):
 
 
 # (first n, second smaller n, flags): the pairs cover the one-workgroup LDS
-# solve (n <= 64), the cooperative single launch (n <= 256 by default, up to
-# 500 with single_launch), one launch per squaring with split-K partials in
-# the fixed array, and early exit on either path.  Without the handle's tag
+# solve (n <= 64), the cooperative single launch (by default n <= 256 here
+# and n <= 352 in the allocating call; up to 500 with single_launch), one
+# launch per squaring with split-K partials in the fixed array, and early
+# exit on either path.  Without the handle's tag
 # buffer a single launch here waits on panel words (fixed T) or device-wide
 # barriers (early exit) where the allocating call runs the tagged mode, so
 # the first two pairs also compare those orderings.
