@@ -409,7 +409,9 @@ typedef enum {
     BTAS_TILES_W64 = 3,    /* 64x64 tiles, one wave, 8x8 outputs per thread */
     BTAS_TILES_WMIX = 4,   /* one-wave 64x64 on the multiple-of-64 core, 32x32 on the edge */
     BTAS_TILES_W64_DIRECT = 5  /* one-wave 64x64 tiles over the matrix padded to a multiple of
-                                  64 with the absent value, operands loaded straight into LDS */
+                                  64 with the absent value, operands loaded straight into LDS;
+                                  when n mod 64 is 1..32 the last row and column strips use
+                                  64x32, 32x64 and 32x32 tiles (work up to n rounded to 32) */
 } btas_tile_shape_t;
 
 /* The btas_tile_shape_t the handle's most recent batched plan used for graphs

@@ -24,6 +24,11 @@ namespace btas {
 // kernel: operands go straight into LDS, so no staging registers; 8 KB of LDS
 // per workgroup.
 using CfgWD = GemmCfg<64, 64, 8, 8, 8>;
+// Edge strips of graphs with n mod 64 in 1..32 (one wave each as well):
+// 64x32, 32x64 and 32x32 outputs, 8x4 / 4x8 / 4x4 per lane.
+using CfgWD64x32 = GemmCfg<64, 32, 8, 8, 4>;
+using CfgWD32x64 = GemmCfg<32, 64, 8, 4, 8>;
+using CfgWD32 = GemmCfg<32, 32, 8, 4, 4>;
 
 // int32 graphs whose finite weights satisfy 2^T * max|w| <= FP32_EXACT_MAX
 // keep every finite distance of every step inside the binary32-exact range
@@ -167,7 +172,12 @@ grouped_direct_step_kernel(const BatchGraph* __restrict__ graphs, const BatchIte
     if (std::is_same_v<T, float> || (float_storage && graph_is_narrow<T>(g, maxabs, it.graph))) {
         TileArgs<float> f{np, np, kk, (const float*)src, np, (const float*)src, np,
                           (const float*)src, np, (float*)dst, np, chg, nullptr};
-        GemmTileDirect<CfgWD, SR>::run(f, it.m0, it.n0, smem_raw);
+        switch (it.kind) {
+            case BATCH_TILE_W64x32D: GemmTileDirect<CfgWD64x32, SR>::run(f, it.m0, it.n0, smem_raw); break;
+            case BATCH_TILE_W32x64D: GemmTileDirect<CfgWD32x64, SR>::run(f, it.m0, it.n0, smem_raw); break;
+            case BATCH_TILE_W32D: GemmTileDirect<CfgWD32, SR>::run(f, it.m0, it.n0, smem_raw); break;
+            default: GemmTileDirect<CfgWD, SR>::run(f, it.m0, it.n0, smem_raw); break;
+        }
         return;
     }
     if constexpr (std::is_same_v<T, int32_t>) {
@@ -299,7 +309,7 @@ __global__ __launch_bounds__(256) void grouped_maxabs_kernel(const BatchGraph* _
 // stay in the binary32-exact range are written as binary32 values (absent ->
 // +inf), so the squaring kernels read and write them without conversions.
 // Otherwise (int32) maxabs[graph] is accumulated here.  Padded graphs (np > 0)
-// get the absent value in rows and columns n..np-1.
+// get the absent value in rows and columns n..np-1, in both buffers.
 template <typename T>
 __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __restrict__ graphs,
                                                             const BatchCopy* __restrict__ jobs,
@@ -310,6 +320,7 @@ __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __r
     const int n = g.n;
     const T* W = (const T*)jb.ext;
     uint32_t* D = (uint32_t*)g.buf[g.parity & 1];
+    uint32_t* D1 = (uint32_t*)g.buf[(g.parity + 1) & 1];
     bool as_float = false;
     if constexpr (std::is_same_v<T, int32_t>) as_float = float_storage && graph_is_narrow<T>(g, maxabs, jb.graph);
     const uint32_t absent = as_float || std::is_same_v<T, float>
@@ -371,6 +382,12 @@ __global__ __launch_bounds__(256) void grouped_init_kernel(const BatchGraph* __r
                 out[u] = bits;
             }
             *reinterpret_cast<v4<uint32_t>*>(D + i * g.ld + qq[b] * 4) = out;
+            // The padding of the other buffer too: a plan whose edge tiles stop
+            // at n rounded up to 32 never writes rows or columns beyond that
+            // there, and a staged 64-wide tile may read them.  (Its entries
+            // below n are overwritten by the first squaring before any read.)
+            if (g.np > 0 && (i >= n || qq[b] * 4 + 3 >= n))
+                *reinterpret_cast<v4<uint32_t>*>(D1 + i * g.ld + qq[b] * 4) = out;
         }
     }
     if constexpr (std::is_same_v<T, int32_t>) {

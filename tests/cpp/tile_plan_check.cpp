@@ -12,14 +12,19 @@ int main() {
         for (int s = 0; s < btas::NUM_SHAPES; ++s) {
             std::vector<int> cov((size_t)n * n, 0);
             for (const btas::TileRef& t : btas::tile_plan(n, s)) {
-                const int sz = btas::tile_edge(t.kind);
+                const int rows = btas::tile_rows(t.kind), cols = btas::tile_cols(t.kind);
                 if (btas::tile_family(t.kind) != btas::shape_family(s)) ++bad;
                 if (t.m0 < 0 || t.n0 < 0 || t.m0 >= n || t.n0 >= n) {
                     ++bad;
                     continue;
                 }
-                for (int i = t.m0; i < t.m0 + sz && i < n; ++i)
-                    for (int j = t.n0; j < t.n0 + sz && j < n; ++j) cov[(size_t)i * n + j]++;
+                for (int i = t.m0; i < t.m0 + rows && i < n; ++i)
+                    for (int j = t.n0; j < t.n0 + cols && j < n; ++j) cov[(size_t)i * n + j]++;
+                // a direct-load tile stays inside the buffer padded to 64
+                if (btas::tile_family(t.kind) == 2 &&
+                    (t.m0 + rows > btas::padded_edge(n) || t.n0 + cols > btas::padded_edge(n) ||
+                     t.m0 % 32 || t.n0 % 32))
+                    ++bad;
             }
             for (int c : cov)
                 if (c != 1) {
