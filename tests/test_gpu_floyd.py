@@ -84,6 +84,21 @@ def test_fw_f32_larger_vs_oracle(dev):
     assert np.array_equal(_bits(D.cpu().numpy()), _bits(want))
 
 
+def test_fw_benchmark_generator_2048_bit_exact(dev):
+    """The n=16384 benchmark graph's generator (mean out-degree 16,
+    exponential(1) weights, seed 4) at n = 2048: every entry equals the
+    blocked-FW oracle bit for bit, through the same kernels as n = 16384
+    (n a multiple of 128: pivot pairs on the direct-load tiles)."""
+    import paper_1701_04733_amd as btas
+    n = 2048
+    r, c, w = wl.sparse_digraph_f32_exp(n, 16.0, seed=4)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    want = oracle.floyd_warshall_blocked(W, BLOCK)
+    D, st = btas.floyd_warshall(_dev(W, dev))
+    assert st == btas.OK
+    assert np.array_equal(_bits(D.cpu().numpy()), _bits(want))
+
+
 def test_fw_16384_f32_sampled_sources(dev):
     """The n=16384 benchmark graph (mean out-degree 16, exponential(1)
     weights): the diagonal is 0 and rows from sampled sources equal fp64

@@ -220,6 +220,38 @@ def test_gemv(btas, dev, sr, dt, mn):
 
 @pytest.mark.parametrize("sr", SR)
 @pytest.mark.parametrize("dt", DT)
+def test_gemv_long_rows_padded(btas, dev, sr, dt):
+    """Long rows with a leading dimension that is a multiple of 4 and
+    n % 4 == 2 (vector loads, then the scalar tail), and a row whose winning
+    term sits in that tail."""
+    torch = torch_mod()
+    m, n = 70, 1030
+    A = wl.signed_operand((m, n + 2), dt, sr, seed=11)
+    A[5, n - 1] = (-1 if sr == "min" else 1) * (2**28 if dt == "i32" else 1e30)
+    x = wl.signed_operand((n,), dt, sr, seed=12)
+    y = wl.signed_operand((m,), dt, sr, seed=13, inf_frac=0.3)
+    want = oracle.gemv(sr, A[:, :n].copy(), x, y)
+    tA, ty = to_dev(A, dev), to_dev(y, dev)
+    btas.tropical_gemv(tA[:, :n], to_dev(x, dev), ty, semiring=sr)
+    assert_same(to_np(ty), want, "long-row gemv")
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_dot_more_partials_than_one_pass(btas, dev, sr, dt):
+    """2^24 + 5 elements: more vectors than one pass of the largest partial
+    grid, so its loop and the final reduction over the full partial array
+    run; the winning term near the end."""
+    n = (1 << 24) + 5
+    x = wl.signed_operand((n,), dt, sr, seed=21)
+    y = wl.signed_operand((n,), dt, sr, seed=22)
+    x[n - 7] = (-1 if sr == "min" else 1) * (2**28 if dt == "i32" else 1e30)
+    d = to_np(btas.dot(to_dev(x, dev), to_dev(y, dev), semiring=sr))[0]
+    assert_same(np.array([d]), np.array([oracle.dot(sr, x, y)], dtype=x.dtype), "dot 2^24+5")
+
+
+@pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
 def test_gemv_strided(btas, dev, sr, dt):
     m, n = 77, 91
     A = wl.signed_operand((m, n + 3), dt, sr, seed=1)
