@@ -182,7 +182,7 @@ btas_status_t btas_tropical_axpy(btas_handle_t h, btas_semiring_t sr, btas_dtype
  *     its own, squarings are ordered by the data alone: each workgroup
  *     re-reads the entries of D_{t-1} it needs until their tags (64-bit words
  *     of value and launch/step tag, in a tag buffer the handle allocates once,
- *     about 6 MB) say they are current, and early exit reads one change word
+ *     about 4 MB) say they are current, and early exit reads one change word
  *     per workgroup and squaring; otherwise a device-wide barrier separates
  *     squarings.  No per-step
  *     launches and no host round trip, also with EARLY_EXIT (the host then

@@ -84,9 +84,9 @@ struct ResidentArgs {
     int ld16;
     uint16_t* u16[2];
     // Tagged mode (one tile per workgroup, a tag buffer of the handle's own):
-    // D_s as 64-bit words in tag[s % 3] (n x n), and per-squaring change
+    // D_s as 64-bit words in tag[s % 2] (n x n), and per-squaring change
     // words cw[s * RESIDENT_MAX_GRID + workgroup] for early exit.
-    uint64_t* tag[3];
+    uint64_t* tag[2];
     uint64_t* cw;
 };
 
@@ -272,17 +272,19 @@ __device__ void solve_u16(const ResidentArgs<int32_t>& a, unsigned char* smem, u
 
 // ---- tagged mode --------------------------------------------------------
 // One 16x16 tile per workgroup.  Every entry of D_s (s < T) is stored as one
-// 64-bit word, (epoch << 8 | s) << 32 | value bits, in buffer s mod 3 of a
+// 64-bit word, (epoch << 8 | s) << 32 | value bits, in buffer s mod 2 of a
 // tag buffer that only these launches write.  Squaring t loads its row and
 // column panels of D_{t-1} and loads again every word whose tag is not yet
 // that of D_{t-1}: the data says by itself that it has arrived, so nothing
 // (no flag, no wait for store completion, no barrier) separates squarings.
-// Three buffers suffice: squaring t overwrites this tile of D_{t-3}, which
-// the workgroups of the tile's row and column panel read in squaring t - 2;
-// the D_{t-1} entries just loaded were written by those same workgroups in
-// squaring t - 1, after their loads of squaring t - 2 had returned.  The
-// entry a thread owns stays in a register from squaring to squaring, and
-// the last one goes to D.
+// Two buffers suffice: squaring t overwrites this tile of D_{t-2}, which
+// only the workgroups of the tile's row and column panels read (a workgroup
+// reads tile (I, J) exactly when the owner of (I, J) reads the
+// workgroup's tile: same row or same column), in their squaring t - 1; the
+// D_{t-1} entries squaring t has just loaded were written by those same
+// workgroups at the end of their squaring t - 1, after its loads had
+// returned.  The entry a thread owns stays in a register from squaring to
+// squaring, and the last one goes to D.
 //
 // Early exit without a barrier: each workgroup publishes one change word per
 // squaring (tagged the same way); after squaring t every workgroup reads the
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(RNT) void apsp_tagged_kernel(ResidentArgs<T> a) {
     }
     int steps = 0;
     for (int t = 1; t <= a.nsq; ++t) {
-        const uint64_t* src = a.tag[(t - 1) % 3];
+        const uint64_t* src = a.tag[(t - 1) & 1];
         const uint32_t want = base | (uint32_t)(t - 1);
         const uint64_t pad = tag_word(want, absent_bits);
         for (int e0 = 0; e0 < RT * kpad; e0 += RNT * PB) {
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(RNT) void apsp_tagged_kernel(ResidentArgs<T> a) {
         d = nv;
         steps = t;
         if (t < a.nsq && mine)
-            st_dev(a.tag[t % 3] + (long)row * n + col, tag_word(base | (uint32_t)t, __builtin_bit_cast(uint32_t, nv)));
+            st_dev(a.tag[t & 1] + (long)row * n + col, tag_word(base | (uint32_t)t, __builtin_bit_cast(uint32_t, nv)));
         if (a.early) {
             const int here = __syncthreads_or(changed);  // also: LDS is free for the next squaring
             if (tid == 0)
@@ -606,7 +608,7 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
                         int T_, bool early, int* flags, int* latch, int num_cus, int spin_limit,
                         bool allow_u16, unsigned epoch, hipStream_t s) {
     ResidentArgs<T> a;
-    a.tag[0] = a.tag[1] = a.tag[2] = nullptr;
+    a.tag[0] = a.tag[1] = nullptr;
     a.cw = nullptr;
     a.gate_max = -1;
     a.ld16 = (n + 7) & ~7;
@@ -667,8 +669,8 @@ hipError_t launch_typed(int n, const void* W, long ldw, void* D, long ldd, void*
         if ((long)tag_cu * num_cus >= (long)nt * nt && (long)nt * nt <= RESIDENT_MAX_GRID) {
             uint64_t* tw = static_cast<uint64_t*>(tagws);
             constexpr long region = (long)RESIDENT_MAX_N * RESIDENT_MAX_N;
-            for (int i = 0; i < 3; ++i) a.tag[i] = tw + i * region;
-            a.cw = tw + 3 * region;
+            for (int i = 0; i < 2; ++i) a.tag[i] = tw + i * region;
+            a.cw = tw + 2 * region;
             return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apsp_tagged_kernel<T>),
                                               dim3((unsigned)(nt * nt)), dim3(RNT), args,
                                               (unsigned)lds, s);
@@ -702,7 +704,7 @@ size_t resident_ws_bytes(int dt, int n) {
 }
 
 size_t resident_tag_bytes() {
-    return ((size_t)3 * RESIDENT_MAX_N * RESIDENT_MAX_N + (size_t)RESIDENT_TAG_STEPS * RESIDENT_MAX_GRID) * 8;
+    return ((size_t)2 * RESIDENT_MAX_N * RESIDENT_MAX_N + (size_t)RESIDENT_TAG_STEPS * RESIDENT_MAX_GRID) * 8;
 }
 
 hipError_t launch_apsp_resident(int dt, int n, const void* W, long ldw, void* D, long ldd,
