@@ -92,6 +92,33 @@ __global__ __launch_bounds__(Cfg::NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     GemmTileDirect<Cfg, SR, T>::run(a, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
 }
 
+// Split-K on the direct-load tile (fp32, every 128x128 tile full): for
+// products with fewer tiles than the device holds workgroups (4 per CU), k
+// is cut into S chunks so that about a whole number of rounds of workgroups
+// runs; blockIdx.x = tile * S + chunk, the chunk's partial product goes to
+// ws[chunk] (m x n, leading dimension n) and splitk_reduce_kernel combines
+// them with Cin (bit-identical: the (+) is exact).
+template <typename Cfg, int SR>
+__global__ __launch_bounds__(Cfg::NT) __attribute__((amdgpu_waves_per_eu(4))) void tropical_gemm_direct_splitk_kernel(
+    TileArgs<float> a, int S, int kc, float* ws) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nbn = a.n / Cfg::BN;
+    const int tile = blockIdx.x / S, chunk = blockIdx.x - tile * S;
+    const int tm = tile / nbn, tn = tile - tm * nbn;
+    const int k0 = chunk * kc;
+    TileArgs<float> p = a;
+    p.A = a.A + k0;
+    p.B = a.B + (long)k0 * a.ldb;
+    p.k = min(kc, a.k - k0);
+    p.Cin = nullptr;
+    p.ldci = 0;
+    p.Cout = ws + (long)chunk * a.m * a.n;
+    p.ldco = a.n;
+    p.changed = nullptr;
+    p.wide_out = nullptr;
+    GemmTileDirect<Cfg, SR>::run(p, tm * Cfg::BM, tn * Cfg::BN, smem_raw);
+}
+
 // Split-K: blockIdx.x = tile * S + chunk; the chunk's partial product goes to
 // ws[chunk] (m x n, leading dimension n), Cin is not read.
 template <typename Cfg, typename T, int SR, bool VEC>
@@ -181,9 +208,41 @@ GemmPlan plan_gemm(int m, int n, int k) {
     return p;
 }
 
+// Workgroups of the 128x128 direct tile that the device holds at once (256
+// CUs, four per CU).
+constexpr long DIRECT_SLOTS = 1024;
+
+// Split factor of the direct-load split-K path for an m x n x k fp32 product
+// whose 128x128 tiles are all full (0: not used): when there are fewer tiles
+// than DIRECT_SLOTS, the S (2..16, chunks of at least 256 k, at least three
+// quarters of a round of workgroups) whose tiles * S fills the last round of
+// workgroups best.  Smaller products keep the 64x64 split-K plan.
+static int direct_split(int m, int n, int k) {
+    if (m % CfgL::BM || n % CfgL::BN || k % CfgL::BK || m == 0 || n == 0) return 0;
+    const long tiles = tiles_for<CfgL>(m, n);
+    if (tiles >= DIRECT_SLOTS || k < 512) return 0;
+    int best = 0;
+    double best_fill = 0;
+    for (int S = 2; S <= 16; ++S) {
+        int kc = (k + S - 1) / S;
+        kc = (kc + CfgL::BK - 1) / CfgL::BK * CfgL::BK;
+        if (kc < 256 || (k + kc - 1) / kc != S) continue;
+        const long wgs = tiles * S;
+        if (wgs * 4 < DIRECT_SLOTS * 3) continue;  // at least three quarters of one round
+        const double fill = (double)wgs / (double)(((wgs + DIRECT_SLOTS - 1) / DIRECT_SLOTS) * DIRECT_SLOTS);
+        if (fill > best_fill + 0.02) {
+            best_fill = fill;
+            best = S;
+        }
+    }
+    return best;
+}
+
 size_t gemm_splitk_bytes(int m, int n, int k) {
     const GemmPlan p = plan_gemm(m, n, k);
-    return p.splits > 1 ? (size_t)p.splits * m * n * 4 : 0;
+    const size_t staged = p.splits > 1 ? (size_t)p.splits * m * n * 4 : 0;
+    const size_t direct = (size_t)direct_split(m, n, k) * m * n * 4;
+    return staged > direct ? staged : direct;
 }
 
 template <typename Cfg, typename T, int SR>
@@ -249,8 +308,35 @@ static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int SR>
+static hipError_t launch_direct_split(const GemmArgs& g, int S, hipStream_t s) {
+    int kc = (g.k + S - 1) / S;
+    kc = (kc + CfgL::BK - 1) / CfgL::BK * CfgL::BK;
+    S = (g.k + kc - 1) / kc;
+    TileArgs<float> a{g.m, g.n, g.k, (const float*)g.A, g.lda, (const float*)g.B, g.ldb, (const float*)g.Cin,
+                      g.ldci, (float*)g.Cout, g.ldco, g.changed, g.wide_out};
+    const long nb = tiles_for<CfgL>(g.m, g.n);
+    hipLaunchKernelGGL((tropical_gemm_direct_splitk_kernel<CfgL, SR>), dim3((unsigned)(nb * S)),
+                       dim3(CfgL::NT), (GemmTileDirect<CfgL, SR>::lds_bytes), s, a, S, kc, (float*)g.ws);
+    long rb = ((long)g.m * g.n + 1023) / 1024;
+    rb = std::max<long>(1, std::min<long>(rb, 4096));
+    hipLaunchKernelGGL((splitk_reduce_kernel<float, SR>), dim3((unsigned)rb), dim3(256), 0, s, g.m, g.n, S,
+                       (const float*)g.ws, (const float*)g.Cin, g.ldci, (float*)g.Cout, g.ldco, g.changed,
+                       g.wide_out);
+    return hipGetLastError();
+}
+
 template <typename T, int SR>
 static hipError_t launch_typed(const GemmArgs& a, int cfg, hipStream_t s) {
+    if constexpr (std::is_same_v<T, float>) {
+        // mid-size fp32 products with full 128x128 tiles: direct loads, k split
+        const bool vec = (a.lda % 4 == 0) && (a.ldb % 4 == 0) && (a.ldci % 4 == 0) && (a.ldco % 4 == 0) &&
+                         (((uintptr_t)a.A | (uintptr_t)a.B | (uintptr_t)a.Cin | (uintptr_t)a.Cout |
+                           (uintptr_t)a.ws) % 16 == 0);
+        const int S = cfg < 0 && vec ? direct_split(a.m, a.n, a.k) : 0;
+        if (S > 1 && a.ws != nullptr && (size_t)S * a.m * a.n * 4 <= a.ws_bytes)
+            return launch_direct_split<SR>(a, S, s);
+    }
     GemmPlan p = plan_gemm(a.m, a.n, a.k);
     if (cfg >= 0 && cfg != p.cfg) p = GemmPlan{cfg, 1};  // a forced configuration does not split
     switch (p.cfg) {

@@ -444,7 +444,8 @@ struct GemmTileDirect {
             if (more) to_binary32(even ? As1 : As0, even ? Bs1 : Bs0);
             __syncthreads();
         }
-        // Epilogue (every tile is interior): Cout = Cin (+) acc, changed flag.
+        // Epilogue (every tile is interior): Cout = Cin (+) acc (Cin null: the
+        // absent value, a split-K partial), changed flag.
         bool diff = false, wide = false;
 #pragma unroll
         for (int r = 0; r < Cfg::TM; ++r) {
@@ -452,7 +453,13 @@ struct GemmTileDirect {
 #pragma unroll
             for (int g = 0; g < Cfg::CG; ++g) {
                 const int col = n0 + g * (Cfg::BN / Cfg::CG) + tx * 4;
-                const v4<T> old = *reinterpret_cast<const v4<T>*>(a.Cin + (long)row * a.ldci + col);
+                v4<T> old;
+                if (a.Cin != nullptr) {
+                    old = *reinterpret_cast<const v4<T>*>(a.Cin + (long)row * a.ldci + col);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) old[e] = Ring<SR, T>::absent();
+                }
                 v4<T> nv;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {

@@ -129,6 +129,23 @@ def test_gemm_full_tiles_direct_lds_path(btas, dev, sr, frac):
 
 
 @pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("shape", [(1536, 1536, 1536), (2048, 1024, 2048)])
+def test_gemm_mid_size_direct_split_k(btas, dev, sr, shape):
+    """fp32 products with full 128x128 tiles but fewer tiles than the device
+    holds workgroups: k is split over direct-load tiles (6 and 8 chunks here)
+    and the partials are combined with C; signed values, absent entries, a
+    partly absent C, and the winning term of some outputs in the last chunk."""
+    m, n, k = shape
+    A, B = operands(m, n, k, "f32", sr, seed=131, frac=0.1, signed=True)
+    A[:, -1] = (-1 if sr == "min" else 1) * 1e30                # the last chunk wins there
+    C = wl.signed_operand((m, n), "f32", sr, seed=132, inf_frac=0.3)
+    want = oracle.gemm(sr, A, B, C)
+    Ct = to_dev(C, dev)
+    btas.tropical_gemm(to_dev(A, dev), to_dev(B, dev), Ct, semiring=sr)
+    assert_same(to_np(Ct), want, f"{sr} {shape}")
+
+
+@pytest.mark.parametrize("sr", SR)
 @pytest.mark.parametrize("dt", DT)
 def test_gemm_leading_dimensions_and_alignment(btas, dev, sr, dt):
     """Sub-views with padded rows, including leading dimensions that are not a
