@@ -84,7 +84,11 @@ btas_status_t btas_create(btas_handle_t *h, int device);
 btas_status_t btas_destroy(btas_handle_t h);
 
 /* Use `hip_stream` (a hipStream_t, borrowed, not owned; NULL = default
- * stream) for all later work of this handle. */
+ * stream) for all later work of this handle.  The handle's workspaces (the
+ * APSP partner matrix, split-K partials, the single launch's tag buffer and
+ * barrier words) serve every call on it, so work still running on the
+ * previous stream must be ordered before the new stream's (for example by
+ * btas_synchronize) by the caller. */
 btas_status_t btas_set_stream(btas_handle_t h, void *hip_stream);
 
 /* Block the host until the handle's stream has drained.  Returns

@@ -11,12 +11,13 @@
 // as that product's and K is unique.
 //
 // A 64x64 output tile per 256-thread workgroup, 4x4 outputs per thread, k in
-// blocks of 16 staged through LDS.  Each k-block is reduced per output with
-// three-way min/max (the cost of the value-only product); an output whose
-// block extreme strictly beats its running best takes it and remembers the
-// block (a compare and two selects per output and block).  The index search
-// is deferred: after the k loop each output rereads, from global memory, the
-// 16 terms of the one block that holds its final value and takes the first
+// blocks of 16 staged through LDS.  Each witness block of 64 terms (four
+// k-blocks; 32 for successors) is reduced per output with three-way min/max
+// (the cost of the value-only product); an output whose block extreme
+// strictly beats its running best takes it and remembers the block (a
+// compare and two selects per output and block).  The index search is
+// deferred: after the k loop each output rereads, from global memory, the
+// terms of the one block that holds its final value and takes the first
 // index attaining it.  Ties across blocks keep the earliest block (strict
 // comparison), ties inside it the earliest index, so the witness is the
 // smallest p, as with a search inside the loop, which measured 2.9 VALU
@@ -34,6 +35,12 @@ namespace btas {
 namespace {
 
 constexpr int WT_BM = 64, WT_BN = 64, WT_BK = 16;
+// k-blocks per witness block: 4 (64 terms) for the product, 2 (32 terms) for
+// successors, whose every entry runs the deferred search (8192^3 product:
+// 17.5 ms with 32-term blocks, 17.0 with 64, 16.9 with 128; dense successors
+// n=16384: 135, 141, 239 ms).
+template <bool SUCC>
+constexpr int wt_wb() { return SUCC ? 2 : 4; }
 constexpr int WT_NT = 256;
 constexpr int WT_TM = 4, WT_TN = 4;
 constexpr int WT_VW = WT_BM * WT_BK / WT_NT;  // staged elements per thread and operand
@@ -125,7 +132,9 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
     };
 
     T acc[WT_TM][WT_TN];
-    int blk[WT_TM][WT_TN];  // k-block where acc was first attained, -1 while absent
+    int blk[WT_TM][WT_TN];  // witness block where acc was first attained, -1 while absent
+    T bm[WT_TM][WT_TN];     // extreme of the current witness block
+    constexpr int WT_WB = wt_wb<SUCC>();
 #pragma unroll
     for (int r = 0; r < WT_TM; ++r)
 #pragma unroll
@@ -147,12 +156,14 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
         __syncthreads();
         if (kb + 1 < nkb) load(k0 + WT_BK);
 
-        // block extreme of every output over the 16 terms of this block
-        T bm[WT_TM][WT_TN];
+        // block extreme of every output over the 32 terms of this witness
+        // block (two k-blocks)
+        if (kb % WT_WB == 0) {
 #pragma unroll
-        for (int r = 0; r < WT_TM; ++r)
+            for (int r = 0; r < WT_TM; ++r)
 #pragma unroll
-            for (int c = 0; c < WT_TN; ++c) bm[r][c] = R::absent();
+                for (int c = 0; c < WT_TN; ++c) bm[r][c] = R::absent();
+        }
 // (two k-pairs per iteration: a full unroll hoists every LDS read and
         // doubles the register count)
 #pragma unroll 2
@@ -170,17 +181,19 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
                     bm[r][c] = R::add3(bm[r][c], R::mul(av0[r], bv0[c]), R::mul(av1[r], bv1[c]));
         }
 
-        // outputs whose block extreme strictly beats the running best take
-        // it and remember the block
+        // at the end of a witness block, outputs whose block extreme strictly
+        // beats the running best take it and remember the block
+        if (kb % WT_WB == WT_WB - 1 || kb + 1 == nkb) {
 #pragma unroll
-        for (int r = 0; r < WT_TM; ++r)
+            for (int r = 0; r < WT_TM; ++r)
 #pragma unroll
-            for (int c = 0; c < WT_TN; ++c) {
-                const T v = R::finish(bm[r][c]);
-                const bool imp = better<SR>(v, acc[r][c]);
-                acc[r][c] = imp ? v : acc[r][c];
-                blk[r][c] = imp ? kb : blk[r][c];
-            }
+                for (int c = 0; c < WT_TN; ++c) {
+                    const T v = R::finish(bm[r][c]);
+                    const bool imp = better<SR>(v, acc[r][c]);
+                    acc[r][c] = imp ? v : acc[r][c];
+                    blk[r][c] = imp ? kb / WT_WB : blk[r][c];
+                }
+        }
     }
 
 #pragma unroll
@@ -204,8 +217,8 @@ __global__ __launch_bounds__(WT_NT) void witness_gemm_kernel(WitnessArgs<T> a) {
             // block's terms attains)
             int first = -1;
             if (blk[r][c] >= 0) {
-                const int p0 = blk[r][c] * WT_BK;
-                for (int q = WT_BK - 1; q >= 0; --q) {
+                const int p0 = blk[r][c] * (WT_WB * WT_BK);
+                for (int q = WT_WB * WT_BK - 1; q >= 0; --q) {
                     const int p = p0 + q;
                     if (p >= a.k) continue;
                     T x = a.A[(long)i * a.lda + p];
