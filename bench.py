@@ -687,7 +687,7 @@ def main():
                                "10% absent entries, C = (+)-identity",
                    "m": N, "n": N, "k": N, "products_per_step": len(VARIANTS)},
         "variants": variants,
-        "roofline": {"bound": "alu", "kernel": "tropical_gemm_direct_kernel<128x128x16,8x8> min-plus fp32 (direct global->LDS k-blocks)",
+        "roofline": {"bound": "alu", "kernel": "tropical_gemm_direct_kernel<256x256x16,8x8> min-plus fp32 (direct global->LDS k-blocks, 1024 threads)",
                      "achieved": round(achieved, 2), "peak": round(PEAK_TOPS, 2), "unit": "Top/s",
                      "frac": round(achieved / PEAK_TOPS, 4), "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",

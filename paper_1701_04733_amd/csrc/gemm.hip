@@ -18,7 +18,10 @@
 //    whose 128x128 tiles are all full load the next k-block straight into
 //    LDS instead (no staging registers): fp32, and int32 on the
 //    binary32-exact path (each lane converts the elements its own load
-//    wrote, in LDS, before the block's barrier).
+//    wrote, in LDS, before the block's barrier).  The largest such products
+//    (full 256x256 tiles, at least two rounds) use a 256x256 tile of 1024
+//    threads instead: half the panel traffic per output, and the panels a
+//    CU shares are read in step.
 //  * Ragged m/n/k edges are filled with the absent value, which never wins
 //    the (+)-reduction, so tile boundaries need no special compute path.
 //  * Workgroup ids are remapped so that each XCD (own L2) receives a
@@ -174,6 +177,9 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int m, int n, int S,
     if (wide_out != nullptr && __any(wide) && (threadIdx.x & 63) == 0) *wide_out = 1;
 }
 
+// Products with at least this many full 256x256 tiles take the XL tile.
+constexpr long XL_MIN_TILES = 512;
+
 template <typename Cfg>
 static long tiles_for(int m, int n) {
     return (long)((m + Cfg::BM - 1) / Cfg::BM) * ((n + Cfg::BN - 1) / Cfg::BN);
@@ -281,7 +287,15 @@ static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
     dim3 grid((unsigned)nb), block(Cfg::NT);
     if constexpr (std::is_same_v<Cfg, CfgL>) {
         const bool full = vec && g.m % Cfg::BM == 0 && g.n % Cfg::BN == 0 && g.k % Cfg::BK == 0;
+        // full 256x256 tiles, at least two rounds of them (one per CU): the XL tile
+        const long nbx = (long)(g.m / CfgXL::BM) * (g.n / CfgXL::BN);
+        const bool xl = full && g.m % CfgXL::BM == 0 && g.n % CfgXL::BN == 0 && nbx >= XL_MIN_TILES;
         if constexpr (std::is_same_v<T, float>) {
+            if (xl) {
+                hipLaunchKernelGGL((tropical_gemm_direct_kernel<CfgXL, SR>), dim3((unsigned)nbx),
+                                   dim3(CfgXL::NT), (GemmTileDirect<CfgXL, SR>::lds_bytes), s, a, nullptr);
+                return hipGetLastError();
+            }
             if (full) {
                 hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR>), grid, block,
                                    (GemmTileDirect<Cfg, SR>::lds_bytes), s, a, nullptr);
@@ -291,8 +305,13 @@ static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
             // int32: the direct kernel runs the binary32-exact case and the
             // staged kernel the wide one; the flag picks one on the device.
             if (full && g.wide_in != nullptr) {
-                hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR, T>), grid, block,
-                                   (GemmTileDirect<Cfg, SR, T>::lds_bytes), s, a, g.wide_in);
+                if (xl)
+                    hipLaunchKernelGGL((tropical_gemm_direct_kernel<CfgXL, SR, T>), dim3((unsigned)nbx),
+                                       dim3(CfgXL::NT), (GemmTileDirect<CfgXL, SR, T>::lds_bytes), s, a,
+                                       g.wide_in);
+                else
+                    hipLaunchKernelGGL((tropical_gemm_direct_kernel<Cfg, SR, T>), grid, block,
+                                       (GemmTileDirect<Cfg, SR, T>::lds_bytes), s, a, g.wide_in);
                 hipLaunchKernelGGL((tropical_gemm_kernel<Cfg, T, SR, true, true>), grid, block,
                                    Cfg::lds_bytes, s, a, g.wide_in);
                 return hipGetLastError();

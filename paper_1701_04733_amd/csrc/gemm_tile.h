@@ -58,6 +58,12 @@ struct GemmCfg {
 };
 
 using CfgL = GemmCfg<128, 128, 16, 8, 8>;  // large problems: 256 threads, 8x8 per thread
+// The largest products (full 256x256 tiles, at least two rounds of them):
+// 1024 threads, 8x8 per thread, direct loads only.  One workgroup per CU
+// whose 16 waves share each k-block through one barrier: the A and B panels
+// a CU reads per output halve, and the workgroups that share panels stay in
+// step (8192^3: 4.2 instead of 7.9 GB fetched from beyond the L2).
+using CfgXL = GemmCfg<256, 256, 16, 8, 8>;
 using CfgM = GemmCfg<64, 64, 16, 4, 4>;    // mid-size: 256 threads, 4x4 per thread
 using CfgS = GemmCfg<32, 32, 16, 4, 4>;    // small / latency-bound: 64 threads
 // One wave computes a 64x64 tile with the 8x8 register tile of CfgL.  The

@@ -129,6 +129,27 @@ def test_gemm_full_tiles_direct_lds_path(btas, dev, sr, frac):
 
 
 @pytest.mark.parametrize("sr", SR)
+@pytest.mark.parametrize("dt", DT)
+def test_gemm_xl_tiles(btas, dev, sr, dt):
+    """Products with at least 512 full 256x256 tiles take the 1024-thread XL
+    tile (6144 x 5632: 24 x 22 = 528 tiles); a short k (80: five k-blocks)
+    keeps the oracle quick.  Signed values, absent entries, a partly absent C;
+    int32 operands within +-(2^23-1) (the binary32-exact direct path)."""
+    m, n, k = 6144, 5632, 80
+    A, B = operands(m, n, k, dt, sr, seed=141, frac=0.1, signed=True)
+    if dt == "i32":
+        lim = (1 << 23) - 1
+        absent = wl.I32_INF if sr == "min" else wl.I32_NINF
+        A = np.where(A == absent, A, np.clip(A, -lim, lim)).astype(np.int32)
+        B = np.where(B == absent, B, np.clip(B, -lim, lim)).astype(np.int32)
+    C = wl.signed_operand((m, n), dt, sr, seed=142, inf_frac=0.3)
+    want = oracle.gemm(sr, A, B, C)
+    Ct = to_dev(C, dev)
+    btas.tropical_gemm(to_dev(A, dev), to_dev(B, dev), Ct, semiring=sr)
+    assert_same(to_np(Ct), want, f"{sr}/{dt} XL")
+
+
+@pytest.mark.parametrize("sr", SR)
 @pytest.mark.parametrize("shape", [(1536, 1536, 1536), (2048, 1024, 2048)])
 def test_gemm_mid_size_direct_split_k(btas, dev, sr, shape):
     """fp32 products with full 128x128 tiles but fewer tiles than the device
