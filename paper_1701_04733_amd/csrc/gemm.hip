@@ -18,8 +18,8 @@
 //    whose 128x128 tiles are all full load the next k-block straight into
 //    LDS instead (no staging registers): fp32, and int32 on the
 //    binary32-exact path (each lane converts the elements its own load
-//    wrote, in LDS, before the block's barrier).  The largest such products
-//    (full 256x256 tiles, at least two rounds) use a 256x256 tile of 1024
+//    wrote, in LDS, before the block's barrier).  Large such products whose
+//    full 256x256 tiles fill rounds of one per CU use a 256x256 tile of 1024
 //    threads instead: half the panel traffic per output, and the panels a
 //    CU shares are read in step.
 //  * Ragged m/n/k edges are filled with the absent value, which never wins
@@ -177,8 +177,17 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int m, int n, int S,
     if (wide_out != nullptr && __any(wide) && (threadIdx.x & 63) == 0) *wide_out = 1;
 }
 
-// Products with at least this many full 256x256 tiles take the XL tile.
-constexpr long XL_MIN_TILES = 512;
+// The XL tile runs one workgroup per CU (256 at once): products whose full
+// 256x256 tiles fill their rounds of 256 to at least 90% take it.  A ragged
+// last round leaves CUs idle that 128x128 tiles (four per CU) would still
+// occupy: fp32 n=4096 (256 tiles) 72.4 against 68.4 Top/s, n=5120 (400)
+// 58.5 against 62.6, n=8192 (1024) 73-75 against 71-72.
+constexpr long XL_SLOTS = 256;
+static bool xl_fills(long tiles) {
+    if (tiles < XL_SLOTS) return false;
+    const long rounds = (tiles + XL_SLOTS - 1) / XL_SLOTS;
+    return tiles * 10 >= rounds * XL_SLOTS * 9;
+}
 
 template <typename Cfg>
 static long tiles_for(int m, int n) {
@@ -287,9 +296,9 @@ static hipError_t launch_cfg(const GemmArgs& g, int S, hipStream_t s) {
     dim3 grid((unsigned)nb), block(Cfg::NT);
     if constexpr (std::is_same_v<Cfg, CfgL>) {
         const bool full = vec && g.m % Cfg::BM == 0 && g.n % Cfg::BN == 0 && g.k % Cfg::BK == 0;
-        // full 256x256 tiles, at least two rounds of them (one per CU): the XL tile
+        // full 256x256 tiles that fill their rounds (one per CU): the XL tile
         const long nbx = (long)(g.m / CfgXL::BM) * (g.n / CfgXL::BN);
-        const bool xl = full && g.m % CfgXL::BM == 0 && g.n % CfgXL::BN == 0 && nbx >= XL_MIN_TILES;
+        const bool xl = full && g.m % CfgXL::BM == 0 && g.n % CfgXL::BN == 0 && xl_fills(nbx);
         if constexpr (std::is_same_v<T, float>) {
             if (xl) {
                 hipLaunchKernelGGL((tropical_gemm_direct_kernel<CfgXL, SR>), dim3((unsigned)nbx),

@@ -58,7 +58,7 @@ struct GemmCfg {
 };
 
 using CfgL = GemmCfg<128, 128, 16, 8, 8>;  // large problems: 256 threads, 8x8 per thread
-// The largest products (full 256x256 tiles, at least two rounds of them):
+// Large products whose full 256x256 tiles fill rounds of one per CU:
 // 1024 threads, 8x8 per thread, direct loads only.  One workgroup per CU
 // whose 16 waves share each k-block through one barrier: the A and B panels
 // a CU reads per output halve, and the workgroups that share panels stay in

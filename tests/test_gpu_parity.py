@@ -131,11 +131,12 @@ def test_gemm_full_tiles_direct_lds_path(btas, dev, sr, frac):
 @pytest.mark.parametrize("sr", SR)
 @pytest.mark.parametrize("dt", DT)
 def test_gemm_xl_tiles(btas, dev, sr, dt):
-    """Products with at least 512 full 256x256 tiles take the 1024-thread XL
-    tile (6144 x 5632: 24 x 22 = 528 tiles); a short k (80: five k-blocks)
-    keeps the oracle quick.  Signed values, absent entries, a partly absent C;
-    int32 operands within +-(2^23-1) (the binary32-exact direct path)."""
-    m, n, k = 6144, 5632, 80
+    """Products whose full 256x256 tiles fill rounds of one per CU take the
+    1024-thread XL tile (8192 x 2048: 32 x 8 = 256 tiles); a short k (80: five
+    k-blocks) keeps the oracle quick.  Signed values, absent entries, a partly
+    absent C; int32 operands within +-(2^23-1) (the binary32-exact direct
+    path)."""
+    m, n, k = 8192, 2048, 80
     A, B = operands(m, n, k, dt, sr, seed=141, frac=0.1, signed=True)
     if dt == "i32":
         lim = (1 << 23) - 1
