@@ -11,15 +11,17 @@
 //   3. every block (I,J) with I != K and J != K gets
 //        D_IJ <- D_IJ (+) D_IK (.) D_KJ
 //      from blocks that this phase does not change: a tropical GEMM update.
-// Pivot blocks are taken in pairs so that phase 3 of both runs as one k=128
-// product on 128x128 tiles (the product kernels' large tile, direct LDS loads
-// for fp32 when n is a multiple of 128), with thin k=64 strip updates before
-// and after it that keep the sequential order's values exactly (fw_typed).
-// O(n^3) work, against O(n^3 log n) for repeated squaring.  In exact
-// arithmetic every order gives the shortest distances; in binary32 the result
-// is that of the blocked order with blocks of 64, which the pairing does not
-// change (min is exact, so one pass over 128 rounded terms equals two passes
-// over 64).
+// Pivot blocks are taken in groups (four for fp32 when n is a multiple of
+// 128, else pairs) so that phase 3 of the whole group, outside the group's
+// own block-rows and block-columns, runs as one k=256 (k=128) product on
+// 128x128 tiles (the product kernels' large tile, direct LDS loads for fp32
+// when n is a multiple of 128), with thin k=64 strip updates before and after
+// it that keep the sequential order's values exactly (fw_typed).  O(n^3)
+// work, against O(n^3 log n) for repeated squaring.  In exact arithmetic
+// every order gives the shortest distances; in binary32 the result is that
+// of the blocked order with blocks of 64, which the grouping does not change
+// (min is exact, so one pass over 256 rounded terms equals four passes over
+// 64).
 //
 // Within one pivot z, the entries of row z and column z are relaxed against
 // d(z,z) = 0, which leaves them unchanged, so every other entry may be
@@ -27,8 +29,10 @@
 // it (graphs without negative cycles; with one, the result is unspecified).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <type_traits>
 
+#include "fw_schedule.h"
 #include "gemm_tile.h"
 #include "kernels.h"
 #include "semiring.h"
@@ -37,7 +41,6 @@ namespace btas {
 
 namespace {
 
-constexpr int FW_B = 64;      // pivot block edge
 
 // d <- d (+) a (.) b (min-plus).
 template <typename T>
@@ -184,39 +187,18 @@ __global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, in
     phase2_block(n, D, ld, kb, nb, (int)blockIdx.x);
 }
 
-// Which 64x64 blocks an update launch covers; every covered block (I,J) gets
-// D_IJ <- D_IJ (+) D_I,kb (.) D_kb,J with the k-range of pivot block kb.
-//   full:  every I != kb, J != kb                       ((nb-1)^2 blocks)
-//   strip: block-row rb (J != skip) and block-column rb (I != rb, I != skip)
-//          (2nb-3 blocks; rb != skip)
-struct UpdateSel {
-    int kb, nb;
-    int rb, skip;  // rb < 0: full
-};
-
-__device__ __forceinline__ void select_block(const UpdateSel& u, int t, int& I, int& J) {
-    if (u.rb < 0) {
-        I = t / (u.nb - 1);
-        J = t % (u.nb - 1);
-        I += I >= u.kb ? 1 : 0;
-        J += J >= u.kb ? 1 : 0;
-    } else if (t < u.nb - 1) {
-        I = u.rb;
-        J = t + (t >= u.skip ? 1 : 0);
-    } else {
-        const int lo = u.rb < u.skip ? u.rb : u.skip, hi = u.rb < u.skip ? u.skip : u.rb;
-        I = t - (u.nb - 1);
-        I += I >= lo ? 1 : 0;
-        I += I >= hi ? 1 : 0;
-        J = u.rb;
-    }
-}
-
-__host__ __forceinline__ unsigned update_blocks(const UpdateSel& u) {
-    return u.rb < 0 ? (unsigned)((long)(u.nb - 1) * (u.nb - 1)) : (unsigned)(2 * u.nb - 3);
-}
-
 // fp32 with n a multiple of 64: every block full, direct LDS loads.
+template <int SR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_band_direct_kernel(
+    int n, float* D, long ld, BandSel u) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int I, J;
+    select_band(u, blockIdx.x, I, J);
+    const int k0 = u.kb * FW_B;
+    TileArgs<float> a{n, n, FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
+    GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, SR>::run(a, I * FW_B, J * FW_B, smem_raw);
+}
+
 template <int SR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_update_direct_kernel(
     int n, float* D, long ld, UpdateSel u) {
@@ -239,18 +221,6 @@ __global__ __launch_bounds__(64) void fw_update_kernel(int n, T* D, long ld, Upd
     GemmTile<GemmCfg<64, 64, 8, 8, 8>, T, T, BTAS_MIN_PLUS, VEC>::run(a, I * FW_B, J * FW_B, smem_raw);
 }
 
-// Pivot-pair update: every 128x128 tile (I,J) outside tile-row and
-// tile-column sb gets D_IJ <- D_IJ (+) D_I,P (.) D_P,J, P the 128 pivots of
-// blocks 2sb and 2sb+1 (fewer at a ragged end): both blocks' updates of
-// the same entries in one pass.
-__device__ __forceinline__ void pair_tile(int t, int sb, int nb2, int& m0, int& n0) {
-    int I = t / (nb2 - 1), J = t % (nb2 - 1);
-    I += I >= sb ? 1 : 0;
-    J += J >= sb ? 1 : 0;
-    m0 = I * 2 * FW_B;
-    n0 = J * 2 * FW_B;
-}
-
 template <int SR>
 __global__ __launch_bounds__(CfgL::NT) __attribute__((amdgpu_waves_per_eu(4))) void fw_pair_direct_kernel(
     int n, float* D, long ld, int sb, int nb2) {
@@ -259,6 +229,17 @@ __global__ __launch_bounds__(CfgL::NT) __attribute__((amdgpu_waves_per_eu(4))) v
     pair_tile(blockIdx.x, sb, nb2, m0, n0);
     const int k0 = sb * 2 * FW_B;
     TileArgs<float> a{n, n, 2 * FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
+    GemmTileDirect<CfgL, SR>::run(a, m0, n0, smem_raw);
+}
+
+template <int SR>
+__global__ __launch_bounds__(CfgL::NT) __attribute__((amdgpu_waves_per_eu(4))) void fw_quad_direct_kernel(
+    int n, float* D, long ld, int q, int nt) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int m0, n0;
+    quad_tile(blockIdx.x, q, nt, m0, n0);
+    const int k0 = q * 4 * FW_B;
+    TileArgs<float> a{n, n, 4 * FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
     GemmTileDirect<CfgL, SR>::run(a, m0, n0, smem_raw);
 }
 
@@ -271,6 +252,8 @@ __global__ __launch_bounds__(CfgL::NT) void fw_pair_kernel(int n, T* D, long ld,
     TileArgs<T> a{n, n, ks, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
     GemmTile<CfgL, T, T, BTAS_MIN_PLUS, VEC>::run(a, m0, n0, smem_raw);
 }
+
+constexpr int FW_QUAD_MIN_N = 12288;
 
 template <typename T>
 struct FwLaunch {
@@ -307,6 +290,43 @@ struct FwLaunch {
                                s, n, D, ld, u);
     }
 
+    // fp32 with every 128x128 tile full and n >= FW_QUAD_MIN_N: groups of
+    // four pivot blocks.  Each group adds two strip launches and three times
+    // the strip work of two pairs, which its k=256 update repays only on
+    // large graphs (n=16384: 138 against 147 ms; n=8192: 23.7 against 23.3;
+    // n=4096: 6.6 against 6.1).  BTAS_FW_GROUP=2 or 4 forces pairs or
+    // groups of four.
+    bool quads() const {
+        if constexpr (!std::is_same_v<T, float>) return false;
+        if (!vec || n % (2 * FW_B) != 0) return false;
+        const char* e = getenv("BTAS_FW_GROUP");
+        if (e && e[0] == '2') return false;
+        if (e && e[0] == '4') return true;
+        return n >= FW_QUAD_MIN_N;
+    }
+
+    // (only reached when quads() holds: fp32, every 128x128 tile full)
+    void band(const BandSel& u) const {
+        if constexpr (std::is_same_v<T, float>) {
+            const long blocks = band_blocks(u);
+            if (blocks <= 0) return;
+            using DT = GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, BTAS_MIN_PLUS>;
+            hipLaunchKernelGGL((fw_band_direct_kernel<BTAS_MIN_PLUS>), dim3((unsigned)blocks), dim3(64),
+                               DT::lds_bytes, s, n, D, ld, u);
+        }
+    }
+
+    void quad_update(int q) const {
+        if constexpr (std::is_same_v<T, float>) {
+            const int nt = n / (2 * FW_B);
+            const unsigned tiles = (unsigned)((long)(nt - 2) * (nt - 2));
+            if (tiles == 0) return;
+            using DT = GemmTileDirect<CfgL, BTAS_MIN_PLUS>;
+            hipLaunchKernelGGL((fw_quad_direct_kernel<BTAS_MIN_PLUS>), dim3(tiles), dim3(CfgL::NT),
+                               DT::lds_bytes, s, n, D, ld, q, nt);
+        }
+    }
+
     void pair_update(int sb) const {
         const int nb2 = (n + 2 * FW_B - 1) / (2 * FW_B);
         const unsigned tiles = (unsigned)((long)(nb2 - 1) * (nb2 - 1));
@@ -328,34 +348,22 @@ struct FwLaunch {
     }
 };
 
-// Pivot blocks in pairs (K, K+1).  The sequential order's effects are kept
-// exactly; only the two bulk updates of entries outside both blocks' rows
-// and columns are fused, which leaves every entry the same min of the same
-// rounded terms:
-//   phases 1-2 of K;
-//   K's update of block-row and block-column K+1 (they are K+1's pivots);
-//   phases 1-2 of K+1;
-//   one k=128 update of every tile outside rows/columns K, K+1, reading
-//     row/column K as phase 2 of K left them and row/column K+1 as phase 2
-//     of K+1 left them;
-//   then K+1's update of block-row and block-column K (deferred so that the
-//     fused update read their earlier values).
-// An odd last block runs the three plain phases.
+// The launches of fw_schedule (fw_schedule.h), in order on one stream.  The
+// sequential blocked order's effects are kept exactly; only the updates of
+// entries outside a pair's (group's) rows and columns are fused, which leaves
+// every entry the same min of the same rounded terms.
 template <typename T>
 hipError_t fw_typed(int n, T* D, long ld, hipStream_t s) {
     const int nb = (n + FW_B - 1) / FW_B;
     const FwLaunch<T> L{n, nb, D, ld, s, ld % 4 == 0 && (uintptr_t)D % 16 == 0};
-    int kb = 0;
-    for (; kb + 1 < nb; kb += 2) {
-        L.phase12(kb);
-        L.update(UpdateSel{kb, nb, kb + 1, kb});
-        L.phase12(kb + 1);
-        L.pair_update(kb / 2);
-        L.update(UpdateSel{kb + 1, nb, kb, kb + 1});
-    }
-    if (kb < nb) {
-        L.phase12(kb);
-        if (nb > 1) L.update(UpdateSel{kb, nb, -1, -1});
+    for (const FwStep& st : fw_schedule(nb, L.quads())) {
+        switch (st.kind) {
+            case FW_PHASE12: L.phase12(st.kb); break;
+            case FW_UPDATE: L.update(st.u); break;
+            case FW_BAND: L.band(st.b); break;
+            case FW_PAIR: L.pair_update(st.q); break;
+            case FW_QUAD: L.quad_update(st.q); break;
+        }
     }
     return hipGetLastError();
 }

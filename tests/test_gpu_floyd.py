@@ -99,6 +99,36 @@ def test_fw_benchmark_generator_2048_bit_exact(dev):
     assert np.array_equal(_bits(D.cpu().numpy()), _bits(want))
 
 
+@pytest.mark.parametrize("n", [384, 640, 1536])
+def test_fw_groups_of_four_equal_pairs_and_oracle(dev, n):
+    """fp32 with n a multiple of 128 can take pivot blocks in groups of four
+    (one k=256 update per group; a last pair when n/64 is not a multiple of
+    4: n = 384, 640), the default from n = 12288 on and forced here with
+    BTAS_FW_GROUP=4: the same bits as pivot pairs (BTAS_FW_GROUP=2) and as
+    the oracle's blocked order."""
+    import os
+
+    import paper_1701_04733_amd as btas
+    r, c, w = wl.sparse_digraph_f32_exp(n, 12.0, seed=n)
+    W = wl.coo_to_dense_f32(n, r, c, w)
+    want = _bits(oracle.floyd_warshall_blocked(W, BLOCK))
+    prev = os.environ.get("BTAS_FW_GROUP")
+    got = {}
+    try:
+        for mode in ("4", "2"):
+            os.environ["BTAS_FW_GROUP"] = mode
+            D, st = btas.floyd_warshall(_dev(W, dev))
+            assert st == btas.OK
+            got[mode] = _bits(D.cpu().numpy())
+    finally:
+        if prev is None:
+            del os.environ["BTAS_FW_GROUP"]
+        else:
+            os.environ["BTAS_FW_GROUP"] = prev
+    assert np.array_equal(got["4"], want)
+    assert np.array_equal(got["2"], want)
+
+
 def test_fw_16384_f32_sampled_sources(dev):
     """The n=16384 benchmark graph (mean out-degree 16, exponential(1)
     weights): the diagonal is 0 and rows from sampled sources equal fp64

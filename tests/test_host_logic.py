@@ -23,6 +23,15 @@ def test_tile_plans_cover_every_output_once():
     assert "tile plan failures: 0" in r.stdout
 
 
+def test_floyd_warshall_schedule_keeps_the_blocked_order():
+    """Pairs and groups of four pivot blocks, nb = 1..40 and 256: every block
+    gets every pivot block's update once, in order, from operands in the
+    blocked order's state, and no launch writes a block it reads."""
+    r = _run_cpp("fw_schedule_check.cpp")
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "fw schedule failures: 0" in r.stdout
+
+
 def test_pool_allocator_never_overlaps_and_coalesces():
     r = _run_cpp("range_alloc_check.cpp")
     assert r.returncode == 0, r.stdout + r.stderr
