@@ -188,6 +188,10 @@ __global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, in
 }
 
 // fp32 with n a multiple of 64: every block full, direct LDS loads.
+// The k=64 strip updates on the direct-load path: one wave per 64x64 block,
+// 8x8 outputs per lane.
+using FwStripCfg = GemmCfg<64, 64, 8, 8, 8>;
+
 template <int SR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_band_direct_kernel(
     int n, float* D, long ld, BandSel u) {
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw
     select_band(u, blockIdx.x, I, J);
     const int k0 = u.kb * FW_B;
     TileArgs<float> a{n, n, FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
-    GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, SR>::run(a, I * FW_B, J * FW_B, smem_raw);
+    GemmTileDirect<FwStripCfg, SR>::run(a, I * FW_B, J * FW_B, smem_raw);
 }
 
 template <int SR>
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw
     select_block(u, blockIdx.x, I, J);
     const int k0 = u.kb * FW_B;
     TileArgs<float> a{n, n, FW_B, D + k0, ld, D + (long)k0 * ld, ld, D, ld, D, ld, nullptr, nullptr};
-    GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, SR>::run(a, I * FW_B, J * FW_B, smem_raw);
+    GemmTileDirect<FwStripCfg, SR>::run(a, I * FW_B, J * FW_B, smem_raw);
 }
 
 // General: the staged one-wave tile with bounds checks.
@@ -275,7 +279,7 @@ struct FwLaunch {
         if (blocks == 0) return;
         if constexpr (std::is_same_v<T, float>) {
             if (vec && n % FW_B == 0) {
-                using DT = GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, BTAS_MIN_PLUS>;
+                using DT = GemmTileDirect<FwStripCfg, BTAS_MIN_PLUS>;
                 hipLaunchKernelGGL((fw_update_direct_kernel<BTAS_MIN_PLUS>), dim3(blocks), dim3(64),
                                    DT::lds_bytes, s, n, D, ld, u);
                 return;
@@ -310,7 +314,7 @@ struct FwLaunch {
         if constexpr (std::is_same_v<T, float>) {
             const long blocks = band_blocks(u);
             if (blocks <= 0) return;
-            using DT = GemmTileDirect<GemmCfg<64, 64, 8, 8, 8>, BTAS_MIN_PLUS>;
+            using DT = GemmTileDirect<FwStripCfg, BTAS_MIN_PLUS>;
             hipLaunchKernelGGL((fw_band_direct_kernel<BTAS_MIN_PLUS>), dim3((unsigned)blocks), dim3(64),
                                DT::lds_bytes, s, n, D, ld, u);
         }
