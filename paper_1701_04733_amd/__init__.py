@@ -168,6 +168,7 @@ class Handle:
         if st != OK:
             raise BtasError(st, f"btas_create(device={device}) failed")
         self._h = h
+        self._bound = None  # the stream last handed to btas_set_stream
         _track(self)
 
     @property
@@ -175,9 +176,12 @@ class Handle:
         return self._h
 
     def bind_stream(self, stream=None):
-        import torch
-        s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        lib().btas_set_stream(self._h, ctypes.c_void_p(s.cuda_stream))
+        """Make the handle launch on ``stream`` (torch's current stream of the
+        handle's device if None); skips the library call when unchanged."""
+        raw = stream.cuda_stream if stream is not None else _current_raw_stream(self.device)
+        if raw != self._bound:
+            lib().btas_set_stream(self._h, ctypes.c_void_p(raw))
+            self._bound = raw
 
     def check(self, st: int, allow=(OK,)) -> int:
         if st not in allow:
@@ -204,6 +208,17 @@ class Handle:
 
 
 _HANDLES: dict = {}
+_RAW_STREAM = None
+
+
+def _current_raw_stream(device: int) -> int:
+    """torch's current stream on ``device`` as a raw pointer value."""
+    global _RAW_STREAM
+    if _RAW_STREAM is None:
+        import torch
+        fast = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        _RAW_STREAM = fast if fast is not None else (lambda d: torch.cuda.current_stream(d).cuda_stream)
+    return _RAW_STREAM(device)
 
 
 def default_handle(device: int | None = None) -> Handle:
@@ -241,11 +256,13 @@ def _mat(t, name):
         raise ValueError(f"{name} must be a matrix")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
-    if t.numel() == 0:
-        return ctypes.c_void_p(t.data_ptr() or None), max(1, t.size(1))
-    if t.size(1) > 1 and t.stride(1) != 1:
+    rows, cols = t.shape
+    if rows == 0 or cols == 0:
+        return ctypes.c_void_p(t.data_ptr() or None), max(1, cols)
+    s0, s1 = t.stride()
+    if cols > 1 and s1 != 1:
         raise ValueError(f"{name} must have unit column stride (row-major with leading dimension)")
-    ld = t.stride(0) if t.size(0) > 1 else max(1, t.size(1))
+    ld = s0 if rows > 1 else max(1, cols)
     return ctypes.c_void_p(t.data_ptr()), max(1, ld)
 
 
@@ -260,7 +277,7 @@ def _vec(t, name):
 
 
 def _handle_for(t, handle):
-    return handle if handle is not None else default_handle(t.device.index or 0)
+    return handle if handle is not None else default_handle(max(t.get_device(), 0))
 
 
 def tropical_gemm(A, B, C=None, semiring="min", handle=None):
