@@ -287,7 +287,11 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
  * paper's sequential algorithm (Sec. IV, Algorithm 2), d(x,y) <- d(x,y) (+)
  * d(x,z) (.) d(z,y) for every pivot z, grouped into pivot blocks of 64
  * vertices (diagonal block, then its block-row and block-column, then every
- * other block as a tropical product with k = 64).  O(n^3) work instead of
+ * other block as a tropical product with k = 64).  Consecutive pivot blocks
+ * are fused in pairs (in fours for fp32 with n a multiple of 128 and
+ * n >= 12288) into one k = 128 (k = 256) product over the blocks outside
+ * their own rows and columns, with strip updates that keep the values of
+ * the unfused order exactly.  O(n^3) work instead of
  * the O(n^3 log n) of repeated squaring.  D (leading dimension ldd) receives
  * the result of I (+) W (the same reading of the diagonal as
  * btas_apsp_squaring); W == D (same ld) runs in place, any other overlap is
@@ -304,8 +308,9 @@ btas_status_t btas_apsp_floyd_warshall(btas_handle_t h, btas_dtype_t dt, int n, 
 /* Blocked Floyd-Warshall (btas_apsp_floyd_warshall, pivot blocks of 64) of
  * `count` independent graphs in one captured hipGraph: D[i] <- the result for
  * I (+) W[i] (n[i] x n[i], row-major, leading dimensions ldw[i], ldd[i];
- * device pointers in host arrays).  Pivot blocks go in pairs as in
- * btas_apsp_floyd_warshall; each step of the pair schedule (phases 1 and 2
+ * device pointers in host arrays).  Pivot blocks go in pairs (the pair
+ * schedule of btas_apsp_floyd_warshall, which gives the same values as its
+ * groups of four); each step of the pair schedule (phases 1 and 2
  * of a block, a strip update, the k=128 update of a pair) is one launch
  * over all graphs that have it, so the graph holds at most
  * 1 + 8 * ceil(max_i ceil(n_i / 64) / 2) launches.  int32 results are the exact
