@@ -127,6 +127,23 @@ def test_fw_groups_of_four_equal_pairs_and_oracle(dev, n):
             os.environ["BTAS_FW_GROUP"] = prev
     assert np.array_equal(got["4"], want)
     assert np.array_equal(got["2"], want)
+    if n == 384:
+        # groups of four in place in a padded matrix (ld = n + 16)
+        import torch
+        big = torch.full((n, n + 16), 7.0, dtype=torch.float32, device=dev)
+        big[:, :n] = _dev(W, dev)
+        prev = os.environ.get("BTAS_FW_GROUP")
+        os.environ["BTAS_FW_GROUP"] = "4"
+        try:
+            _, st = btas.floyd_warshall(big[:, :n], out=big[:, :n])
+        finally:
+            if prev is None:
+                del os.environ["BTAS_FW_GROUP"]
+            else:
+                os.environ["BTAS_FW_GROUP"] = prev
+        assert st == btas.OK
+        assert np.array_equal(_bits(big[:, :n].cpu().numpy()), want)
+        assert (big[:, n:] == 7.0).all()
 
 
 def test_fw_16384_f32_sampled_sources(dev):

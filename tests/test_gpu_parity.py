@@ -566,3 +566,34 @@ def test_apsp_graph_mode_replays_current_inputs(btas, dev, dt):
             outs.append(want)
     with pytest.raises(btas.BtasError, match="INVALID_ARG"):
         btas.apsp(t, early_exit=True, graph=True)
+
+
+def test_calls_follow_torch_current_stream(btas, dev):
+    """The default handle launches on torch's current stream: a chain of
+    products alternating between two streams (ordered with wait_stream) gives
+    the oracle's bits, and after each call the handle is bound to the stream
+    that was current."""
+    torch = torch_mod()
+    g = np.random.default_rng(5)
+    A = g.random((96, 80), dtype=np.float32)
+    B = g.random((80, 80), dtype=np.float32)
+    want = oracle.gemm("min", A, B, np.full((96, 80), np.inf, np.float32))
+    want = oracle.gemm("min", want, B, np.full((96, 80), np.inf, np.float32))
+    want = oracle.gemm("min", want, B, np.full((96, 80), np.inf, np.float32))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    tA = torch.from_numpy(A).to(dev)
+    tB = torch.from_numpy(B).to(dev)
+    torch.cuda.synchronize()
+    h = btas.default_handle(0)
+    cur = tA
+    for s in (s1, s2, s1):
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            s.wait_stream(s1 if s is s2 else s2)
+            cur = btas.tropical_gemm(cur, tB, semiring="min")
+            assert h._bound == s.cuda_stream
+    torch.cuda.synchronize()
+    got = cur.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    btas.default_handle(0)  # back on the default stream
+    assert h._bound == torch.cuda.current_stream().cuda_stream
