@@ -289,7 +289,7 @@ btas_status_t btas_apsp_squaring_batched(btas_handle_t h, btas_dtype_t dt, int c
  * vertices (diagonal block, then its block-row and block-column, then every
  * other block as a tropical product with k = 64).  Consecutive pivot blocks
  * are fused in pairs (in fours for fp32 with n a multiple of 128 and
- * n >= 12288) into one k = 128 (k = 256) product over the blocks outside
+ * n >= 8192) into one k = 128 (k = 256) product over the blocks outside
  * their own rows and columns, with strip updates that keep the values of
  * the unfused order exactly.  O(n^3) work instead of
  * the O(n^3 log n) of repeated squaring.  D (leading dimension ldd) receives

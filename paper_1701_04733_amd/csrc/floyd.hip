@@ -188,12 +188,14 @@ __global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, in
 }
 
 // fp32 with n a multiple of 64: every block full, direct LDS loads.
-// The k=64 strip updates on the direct-load path: one wave per 64x64 block,
-// 8x8 outputs per lane.
-using FwStripCfg = GemmCfg<64, 64, 8, 8, 8>;
+// The k=64 strip updates on the direct-load path: four waves per 64x64
+// block, 4x4 outputs per thread.  (With one wave per block and 8x8 outputs
+// per lane each workgroup ran 64^3 terms through one SIMD, 22-40 us per
+// launch.)
+using FwStripCfg = GemmCfg<64, 64, 16, 4, 4>;
 
 template <int SR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_band_direct_kernel(
+__global__ __launch_bounds__(FwStripCfg::NT) void fw_band_direct_kernel(
     int n, float* D, long ld, BandSel u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int I, J;
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw
 }
 
 template <int SR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void fw_update_direct_kernel(
+__global__ __launch_bounds__(FwStripCfg::NT) void fw_update_direct_kernel(
     int n, float* D, long ld, UpdateSel u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int I, J;
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(CfgL::NT) void fw_pair_kernel(int n, T* D, long ld,
     GemmTile<CfgL, T, T, BTAS_MIN_PLUS, VEC>::run(a, m0, n0, smem_raw);
 }
 
-constexpr int FW_QUAD_MIN_N = 12288;
+constexpr int FW_QUAD_MIN_N = 8192;
 
 template <typename T>
 struct FwLaunch {
@@ -280,7 +282,7 @@ struct FwLaunch {
         if constexpr (std::is_same_v<T, float>) {
             if (vec && n % FW_B == 0) {
                 using DT = GemmTileDirect<FwStripCfg, BTAS_MIN_PLUS>;
-                hipLaunchKernelGGL((fw_update_direct_kernel<BTAS_MIN_PLUS>), dim3(blocks), dim3(64),
+                hipLaunchKernelGGL((fw_update_direct_kernel<BTAS_MIN_PLUS>), dim3(blocks), dim3(FwStripCfg::NT),
                                    DT::lds_bytes, s, n, D, ld, u);
                 return;
             }
@@ -297,9 +299,9 @@ struct FwLaunch {
     // fp32 with every 128x128 tile full and n >= FW_QUAD_MIN_N: groups of
     // four pivot blocks.  Each group adds two strip launches and three times
     // the strip work of two pairs, which its k=256 update repays only on
-    // large graphs (n=16384: 138 against 147 ms; n=8192: 23.7 against 23.3;
-    // n=4096: 6.6 against 6.1).  BTAS_FW_GROUP=2 or 4 forces pairs or
-    // groups of four.
+    // large graphs (n=16384: 141 against 146-147 ms; n=8192: 21.6 against
+    // 21.9; n=4096: 5.4-5.5 against 5.3).  BTAS_FW_GROUP=2 or 4 forces pairs
+    // or groups of four.
     bool quads() const {
         if constexpr (!std::is_same_v<T, float>) return false;
         if (!vec || n % (2 * FW_B) != 0) return false;
@@ -315,7 +317,7 @@ struct FwLaunch {
             const long blocks = band_blocks(u);
             if (blocks <= 0) return;
             using DT = GemmTileDirect<FwStripCfg, BTAS_MIN_PLUS>;
-            hipLaunchKernelGGL((fw_band_direct_kernel<BTAS_MIN_PLUS>), dim3((unsigned)blocks), dim3(64),
+            hipLaunchKernelGGL((fw_band_direct_kernel<BTAS_MIN_PLUS>), dim3((unsigned)blocks), dim3(FwStripCfg::NT),
                                DT::lds_bytes, s, n, D, ld, u);
         }
     }

@@ -103,7 +103,7 @@ def test_fw_benchmark_generator_2048_bit_exact(dev):
 def test_fw_groups_of_four_equal_pairs_and_oracle(dev, n):
     """fp32 with n a multiple of 128 can take pivot blocks in groups of four
     (one k=256 update per group; a last pair when n/64 is not a multiple of
-    4: n = 384, 640), the default from n = 12288 on and forced here with
+    4: n = 384, 640), the default from n = 8192 on and forced here with
     BTAS_FW_GROUP=4: the same bits as pivot pairs (BTAS_FW_GROUP=2) and as
     the oracle's blocked order."""
     import os
