@@ -89,53 +89,59 @@ __device__ __forceinline__ T lane_value(T x, int lane) {
 }
 
 // Phase 1: the diagonal block of pivot block kb, pivots in ascending order.
-// Lane j of wave w holds column j, rows 16w+r.  d(i,z) for the wave's rows is
-// in its lane z; d(z,j) is row z, held by wave z/16, passed through LDS.
-template <typename T>
+// NW waves, E = 64/NW rows each: lane j of wave w holds column j, rows E*w+r.
+// d(i,z) for the wave's rows is in its lane z; d(z,j) is row z, held by wave
+// z/E, passed through LDS.
+template <typename T, int NW = 4>
 __device__ __forceinline__ void phase1_block(int n, T* D, long ld, int kb) {
     using R = Ring<BTAS_MIN_PLUS, T>;
+    constexpr int E = FW_B / NW;
     __shared__ T rowz[2][FW_B];
     const int k0 = kb * FW_B, ks = n - k0 < FW_B ? n - k0 : FW_B;
     const int j = threadIdx.x % 64, w = threadIdx.x / 64;
-    T v[16];
+    T v[E];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = 16 * w + r;
+    for (int r = 0; r < E; ++r) {
+        const int i = E * w + r;
         v[r] = (i < ks && j < ks) ? D[(long)(k0 + i) * ld + k0 + j] : R::absent();
     }
     static_for<0, FW_B>([&](auto zc) {
         constexpr int z = decltype(zc)::value;
         if (z < ks) {
-            if (w == z / 16) rowz[z & 1][j] = R::finish(v[z % 16]);
+            if (w == z / E) rowz[z & 1][j] = R::finish(v[z % E]);
             __syncthreads();  // this slot is written again two pivots later
             const T dzj = rowz[z & 1][j];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = relax_raw(R::finish(lane_value(v[r], z)), dzj, v[r]);
+            for (int r = 0; r < E; ++r) v[r] = relax_raw(R::finish(lane_value(v[r], z)), dzj, v[r]);
         }
     });
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = 16 * w + r;
+    for (int r = 0; r < E; ++r) {
+        const int i = E * w + r;
         if (i < ks && j < ks) D[(long)(k0 + i) * ld + k0 + j] = R::finish(v[r]);
     }
 }
 
+constexpr int FW_P1_WAVES = 16;  // phase 1 of single graphs: 16 waves, 4 rows each
+
 template <typename T>
-__global__ __launch_bounds__(256) void fw_phase1_kernel(int n, T* D, long ld, int kb) {
-    phase1_block(n, D, ld, kb);
+__global__ __launch_bounds__(FW_P1_WAVES * 64) void fw_phase1_kernel(int n, T* D, long ld, int kb) {
+    phase1_block<T, FW_P1_WAVES>(n, D, ld, kb);
 }
 
 // Phase 2: workgroup b < nb-1 takes block (kb, J) of block-row kb, the others
 // block (I, kb) of block-column kb (J, I skip kb); each relaxes its block
 // against the finished diagonal block, pivots in ascending order.
 //   block-row:    own(x,j) <- own(x,j) (+) dia(x,z) (.) own(z,j): lane x holds
-//                 row x, columns 16w+c; own(z,j) is in lane z;
+//                 row x, columns E*w+c; own(z,j) is in lane z;
 //   block-column: own(i,x) <- own(i,x) (+) own(i,z) (.) dia(z,x): lane x holds
-//                 column x, rows 16w+c; own(i,z) is in lane z.
-// The per-lane operand L[z][x] (dia(x,z), resp. dia(z,x)) is constant, so no
-// wave waits for another after the set-up.
-template <typename T>
+//                 column x, rows E*w+c; own(i,z) is in lane z.
+// NW waves per block, E = 64/NW entries per lane.  The per-lane operand
+// L[z][x] (dia(x,z), resp. dia(z,x)) is constant, so no wave waits for
+// another after the set-up.
+template <typename T, int NW = 4>
 __device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int nb, int bid) {
+    constexpr int E = FW_B / NW;
     using R = Ring<BTAS_MIN_PLUS, T>;
     constexpr int LP = FW_B + 1;  // the transposed fill walks a column
     __shared__ T L[FW_B][LP];
@@ -145,7 +151,7 @@ __device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int n
     b += b >= kb ? 1 : 0;
     const int o0 = b * FW_B, os = n - o0 < FW_B ? n - o0 : FW_B;
     const int x = threadIdx.x % 64, w = threadIdx.x / 64;
-    for (int e = threadIdx.x; e < FW_B * FW_B; e += 256) {
+    for (int e = threadIdx.x; e < FW_B * FW_B; e += NW * 64) {
         const int i = e / FW_B, c = e % FW_B;
         const T d = (i < ks && c < ks) ? D[(long)(k0 + i) * ld + k0 + c] : R::absent();
         if (row)
@@ -153,10 +159,10 @@ __device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int n
         else
             L[i][c] = d;
     }
-    T v[16];
+    T v[E];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int o = 16 * w + c;
+    for (int c = 0; c < E; ++c) {
+        const int o = E * w + c;
         if (row)
             v[c] = (x < ks && o < os) ? D[(long)(k0 + x) * ld + o0 + o] : R::absent();
         else
@@ -168,12 +174,12 @@ __device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int n
         if (z < ks) {
             const T lz = L[z][x];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) v[c] = relax_raw(lz, R::finish(lane_value(v[c], z)), v[c]);
+            for (int c = 0; c < E; ++c) v[c] = relax_raw(lz, R::finish(lane_value(v[c], z)), v[c]);
         }
     });
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int o = 16 * w + c;
+    for (int c = 0; c < E; ++c) {
+        const int o = E * w + c;
         if (row) {
             if (x < ks && o < os) D[(long)(k0 + x) * ld + o0 + o] = R::finish(v[c]);
         } else {
@@ -182,9 +188,11 @@ __device__ __forceinline__ void phase2_block(int n, T* D, long ld, int kb, int n
     }
 }
 
+constexpr int FW_P2_WAVES = 16;  // phase 2 of single graphs: 16 waves per block
+
 template <typename T>
-__global__ __launch_bounds__(256) void fw_phase2_kernel(int n, T* D, long ld, int kb, int nb) {
-    phase2_block(n, D, ld, kb, nb, (int)blockIdx.x);
+__global__ __launch_bounds__(FW_P2_WAVES * 64) void fw_phase2_kernel(int n, T* D, long ld, int kb, int nb) {
+    phase2_block<T, FW_P2_WAVES>(n, D, ld, kb, nb, (int)blockIdx.x);
 }
 
 // fp32 with n a multiple of 64: every block full, direct LDS loads.
@@ -270,9 +278,9 @@ struct FwLaunch {
     bool vec;
 
     void phase12(int kb) const {
-        hipLaunchKernelGGL(fw_phase1_kernel<T>, dim3(1), dim3(256), 0, s, n, D, ld, kb);
+        hipLaunchKernelGGL(fw_phase1_kernel<T>, dim3(1), dim3(FW_P1_WAVES * 64), 0, s, n, D, ld, kb);
         if (nb > 1)
-            hipLaunchKernelGGL(fw_phase2_kernel<T>, dim3(2 * (nb - 1)), dim3(256), 0, s, n, D, ld, kb,
+            hipLaunchKernelGGL(fw_phase2_kernel<T>, dim3(2 * (nb - 1)), dim3(FW_P2_WAVES * 64), 0, s, n, D, ld, kb,
                                nb);
     }
 
